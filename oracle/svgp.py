@@ -1,0 +1,210 @@
+"""Inverse-free SVGP (R-SVGP with inducing-mean preconditioning) in float64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Notation follows the paper:
+  K_uu = k(Z, Z), K_uf = k(Z, X_b), k_nn = sigma_f^2          (Section 2, M-SVGP)
+  K~ = K_uu + S~,  S~ = diag(s~)                               (Section 2, L-SVGP)
+  T = L L^T, L lower triangular                                (Section 3.1)
+  P = 2 T - T K~ T                                             (Section 3.2)
+  mu_n = k_nu P m~,  sigma_n^2 = k_nn - k_nu P k_un             (eq. rsvgp_precond)
+  KL <= 1/2 ( -tr(P K_uu) + tr(K~ T) - M + m~^T P K_uu P m~
+              - log|T| - log|S~| )                             (eq. rsvgp_precond)
+  F = (N / B) sum_{n in batch} E_n - KL                        (eq. elbo, mini-batch)
+
+Natural-gradient step on L (Prop. 1, eq. natgrad; alternating scheme of
+Section 3.1):
+  W = L^T K~ L,  L <- L - gamma L [ tril(W) - 1/2 (I + diag(W)) ],
+with tril keeping the diagonal, and the stopping residual of eq.
+stopping_frobenius:  r = ||W - I||_F / sqrt(M).
+
+The gradient of F with respect to xi = {lengthscales, sigma_f^2, noise
+variance, Z, m~, s~} holds T fixed (stopgrad, Section 3.1 and the proof of
+Prop. 2 in Section S2).  It is written here as the adjoint of the literal
+formulas above (explicit P, T), not in any factored form.
+"""
+import numpy as np
+
+from .quadrature import expectation
+
+
+# ----------------------------------------------------------------------------
+# Covariance (ARD RBF kernel, Section 4 and Section S5)
+# ----------------------------------------------------------------------------
+def sq_dist_scaled(A, Bm, ell):
+    """sum_d (a_d - b_d)^2 / ell_d^2 for every pair of rows, chunked over A."""
+    A = np.asarray(A, np.float64) / ell
+    Bm = np.asarray(Bm, np.float64) / ell
+    out = np.empty((A.shape[0], Bm.shape[0]))
+    step = max(1, int(2**24 // max(1, Bm.shape[0] * A.shape[1])))
+    for i0 in range(0, A.shape[0], step):
+        diff = A[i0:i0 + step, None, :] - Bm[None, :, :]
+        out[i0:i0 + step] = np.sum(diff * diff, axis=-1)
+    return out
+
+
+def se_ard(A, Bm, ell, sf2):
+    """k(a, b) = sigma_f^2 exp(-1/2 sum_d (a_d - b_d)^2 / ell_d^2)."""
+    return sf2 * np.exp(-0.5 * sq_dist_scaled(A, Bm, ell))
+
+
+def ktilde(Z, ell, sf2, s):
+    """K~ = K_uu + diag(s~) (Section 2, L-SVGP)."""
+    return se_ard(Z, Z, ell, sf2) + np.diag(np.asarray(s, np.float64))
+
+
+# ----------------------------------------------------------------------------
+# Natural gradient for T = L L^T (Prop. 1, Section 3.1)
+# ----------------------------------------------------------------------------
+def natgrad_direction(L, A):
+    """L [tril(L^T A L) - 1/2 (I + diag(L^T A L))]  (eq. natgrad)."""
+    L = np.asarray(L, np.float64)
+    W = L.T @ A @ L
+    M = L.shape[0]
+    X = np.tril(W) - 0.5 * (np.eye(M) + np.diag(np.diag(W)))
+    return L @ X
+
+
+def ng_residual(L, A):
+    """||L^T A L - I||_F / sqrt(M)  (eq. stopping_frobenius)."""
+    L = np.asarray(L, np.float64)
+    M = L.shape[0]
+    return np.linalg.norm(L.T @ A @ L - np.eye(M), "fro") / np.sqrt(M)
+
+
+def ng_steps(L, A, gammas):
+    """Run len(gammas) NG steps L <- L - gamma_t * natgrad; returns (L, residuals).
+
+    residuals[t] is measured at the iterate *before* step t, from the same
+    W = L^T A L that the step uses.
+    """
+    L = np.array(L, np.float64)
+    res = []
+    for g in gammas:
+        res.append(ng_residual(L, A))
+        L = L - g * natgrad_direction(L, A)
+    return L, np.array(res)
+
+
+def loglinear_gammas(n, g0=1e-5, g1=1.0, ramp=10, start=0):
+    """Log-linear step-size schedule of Section 3.4: g0 -> g1 over `ramp` steps.
+
+    Step t (counting from the start of training) uses
+    10^(log10 g0 + (log10 g1 - log10 g0) * min(t, ramp-1)/(ramp-1)).
+    """
+    out = []
+    for t in range(start, start + n):
+        f = min(t, ramp - 1) / (ramp - 1)
+        out.append(10.0 ** (np.log10(g0) + (np.log10(g1) - np.log10(g0)) * f))
+    return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# The preconditioned R-SVGP bound (eq. rsvgp_precond)
+# ----------------------------------------------------------------------------
+def _as64(*xs):
+    return [np.asarray(x, np.float64) for x in xs]
+
+
+def rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
+                n_gh=20, return_parts=False):
+    """Evaluate F = (N/B) sum_n E_n - KL at T = L L^T, literally.
+
+    Returns a dict with F, data (the scaled expected log likelihood), KL,
+    sum_var (sum_n sigma_n^2), mu (B), var (B), and the per-datum E_n.
+    """
+    X, y, ell, Z, m, s, L = _as64(X, y, ell, Z, m, s, L)
+    sf2 = float(sf2)
+    B = X.shape[0]
+    M = Z.shape[0]
+    Kuu = se_ard(Z, Z, ell, sf2)
+    Kuf = se_ard(Z, X, ell, sf2)
+    Kt = Kuu + np.diag(s)
+    T = L @ L.T
+    P = 2.0 * T - T @ Kt @ T
+    mu = Kuf.T @ (P @ m)
+    var = sf2 - np.sum(Kuf * (P @ Kuf), axis=0)
+    E, _, _, _ = expectation(lik, y, mu, var, noise_var, n_gh)
+    data = (N / B) * np.sum(E)
+    logdetT = 2.0 * np.sum(np.log(np.abs(np.diag(L))))
+    KL = 0.5 * (-np.trace(P @ Kuu) + np.trace(Kt @ T) - M
+                + m @ P @ Kuu @ P @ m - logdetT - np.sum(np.log(s)))
+    out = dict(F=data - KL, data=data, KL=KL, sum_var=np.sum(var),
+               mu=mu, var=var, E=E)
+    if return_parts:
+        out.update(Kuu=Kuu, Kuf=Kuf, Kt=Kt, T=T, P=P)
+    return out
+
+
+def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
+                     n_gh=20):
+    """Gradient of rsvgp_bound w.r.t. xi at fixed T (adjoint of the literal form).
+
+    Returns dict: ell (D), sf2, noise_var (Gaussian only, else 0), Z (MxD),
+    m (M), s (M), plus the bound dict under key 'bound'.
+    """
+    X, y, ell, Z, m, s, L = _as64(X, y, ell, Z, m, s, L)
+    sf2 = float(sf2)
+    B, D = X.shape
+    c = N / B
+    bd = rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik, n_gh,
+                     return_parts=True)
+    Kuu, Kuf, T, P = bd["Kuu"], bd["Kuf"], bd["T"], bd["P"]
+    mu, var = bd["mu"], bd["var"]
+    _, dmu, dv, ds2 = expectation(lik, y, mu, var, noise_var, n_gh)
+    alpha = c * dmu            # dF/dmu_n
+    beta = c * dv              # dF/dsigma_n^2
+
+    Pm = P @ m
+    # Coefficient of dP in dF (symmetrised), collecting:
+    #   data:  sum_n alpha_n k_n^T dP m~  -  sum_n beta_n k_n^T dP k_n
+    #   -KL:   +1/2 tr(dP K_uu)  -  1/2 d(m~^T P K_uu P m~)|_P
+    Ka = Kuf @ alpha
+    G_P = 0.5 * (np.outer(Ka, m) + np.outer(m, Ka))
+    G_P -= (Kuf * beta[None, :]) @ Kuf.T
+    G_P += 0.5 * Kuu
+    KPm = Kuu @ Pm
+    G_P -= 0.5 * (np.outer(KPm, m) + np.outer(m, KPm))
+    # dP = -T dK~ T (T fixed); plus -KL's -1/2 tr(T dK~)
+    G_Kt = -T @ G_P @ T - 0.5 * T
+    # direct K_uu dependence of -KL: +1/2 tr(P dK_uu) - 1/2 (Pm)^T dK_uu (Pm)
+    G_Kuu = 0.5 * P - 0.5 * np.outer(Pm, Pm) + G_Kt
+    # K_uf: alpha_n (P m~)^T dk_n  - 2 beta_n (P k_n)^T dk_n
+    G_Kuf = np.outer(Pm, alpha) - 2.0 * (P @ Kuf) * beta[None, :]
+    # m~: sum_n alpha_n k_n^T P dm~  - (P K_uu P m~)^T dm~
+    g_m = P @ Ka - P @ KPm
+    # s~: through K~ (diagonal) and -KL's +1/2 sum log s~
+    g_s = np.diag(G_Kt) + 0.5 / s
+
+    # SE-ARD chain rule.  dK/dsf2 = K/sf2; dK/dell_d = K (a_d-b_d)^2/ell_d^3;
+    # dK_ab/da_d = -K (a_d - b_d)/ell_d^2.
+    Huu = G_Kuu * Kuu
+    Huf = G_Kuf * Kuf
+    g_sf2 = (np.sum(Huu) + np.sum(Huf)) / sf2 + np.sum(beta)
+    g_ell = np.zeros(D)
+    g_Z = np.zeros_like(Z)
+    for d in range(D):
+        dzz = Z[:, d][:, None] - Z[:, d][None, :]
+        dzx = Z[:, d][:, None] - X[:, d][None, :]
+        g_ell[d] = (np.sum(Huu * dzz**2) + np.sum(Huf * dzx**2)) / ell[d]**3
+        # K_uu[i,j] depends on Z_i through row i and column i
+        g_Z[:, d] = -(np.sum((Huu + Huu.T) * dzz, axis=1)
+                      + np.sum(Huf * dzx, axis=1)) / ell[d]**2
+    g_noise = c * np.sum(ds2) if ds2 is not None else 0.0
+    return dict(ell=g_ell, sf2=g_sf2, noise_var=g_noise, Z=g_Z, m=g_m, s=g_s,
+                bound=bd, alpha=alpha, beta=beta)
+
+
+def training_iteration(X, y, N, ell, sf2, noise_var, Z, m, s, L, gammas,
+                       lik="gaussian", n_gh=20, with_grad=True):
+    """One iteration in the order of Section 3.1: NG steps on L with K~(xi),
+    then bound (and gradient) at the updated L.  Returns (L_new, res, out)."""
+    Kt = ktilde(Z, ell, sf2, s)
+    L_new, res = ng_steps(L, Kt, gammas)
+    if with_grad:
+        out = rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L_new,
+                               lik, n_gh)
+    else:
+        out = dict(bound=rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s,
+                                     L_new, lik, n_gh))
+    return L_new, res, out

@@ -1,0 +1,347 @@
+"""Pins of the float64 oracle against what the paper and the mathematics fix.
+
+No test here re-types an oracle formula and compares it with itself.  Each
+one checks the oracle against an independent quantity: a Cholesky-based ELBO,
+the exact GP evidence, a textbook Fisher natural gradient built by brute
+force, adaptive quadrature, finite differences, or an identity the paper
+proves (equality at T = K~^{-1}, bound validity, Newton-Schulz error
+squaring, Prop. 2, Prop. 3).
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import gamma as gamma_fn, log_ndtr
+
+from oracle import svgp, references as ref, quadrature as quad
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def small_problem(seed=0, M=6, B=9, D=2, N=40.0, lik="gaussian"):
+    g = _rng(seed)
+    X = g.standard_normal((B, D))
+    if lik == "gaussian":
+        y = np.sin(X.sum(1)) + 0.1 * g.standard_normal(B)
+    else:
+        y = np.where(g.standard_normal(B) > 0, 1.0, -1.0)
+    Z = g.standard_normal((M, D))
+    ell = g.uniform(0.7, 1.5, D)
+    sf2 = g.uniform(0.6, 1.6)
+    noise = g.uniform(0.05, 0.4)
+    m = g.standard_normal(M)
+    s = g.uniform(0.05, 0.5, M)
+    return dict(X=X, y=y, N=N, ell=ell, sf2=sf2, noise_var=noise, Z=Z, m=m,
+                s=s, lik=lik)
+
+
+def chol_Kinv(p):
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    return np.linalg.cholesky(np.linalg.inv(Kt))
+
+
+def random_L(M, seed, scale=0.5):
+    g = _rng(seed)
+    L = np.tril(scale * g.standard_normal((M, M)), -1)
+    L += np.diag(g.uniform(0.2, 1.5, M))
+    return L
+
+
+def bound(p, L):
+    return svgp.rsvgp_bound(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                            p["noise_var"], p["Z"], p["m"], p["s"], L,
+                            lik=p["lik"])
+
+
+# ---------------------------------------------------------------- covariance
+def test_se_ard_closed_form_values():
+    # k(0, 1) with ell=1, sf2=2 is 2 exp(-1/2); k(x, x) = sf2
+    K = svgp.se_ard(np.array([[0.0]]), np.array([[1.0], [0.0]]), np.array([1.0]), 2.0)
+    assert np.allclose(K, [[2.0 * np.exp(-0.5), 2.0]], rtol=0, atol=1e-15)
+    # ARD: distance along d is measured in units of ell_d
+    K = svgp.se_ard(np.array([[0.0, 0.0]]), np.array([[3.0, 4.0]]),
+                    np.array([3.0, 2.0]), 1.0)
+    assert np.isclose(K[0, 0], np.exp(-0.5 * (1.0 + 4.0)), rtol=1e-15)
+    # an infinitely long lengthscale removes that input dimension
+    g = _rng(1)
+    A, Bm = g.standard_normal((5, 2)), g.standard_normal((4, 2))
+    K2 = svgp.se_ard(A, Bm, np.array([0.8, 1e12]), 1.3)
+    K1 = svgp.se_ard(A[:, :1], Bm[:, :1], np.array([0.8]), 1.3)
+    assert np.allclose(K2, K1, rtol=1e-12)
+
+
+def test_se_ard_symmetric_psd():
+    g = _rng(2)
+    Z = g.standard_normal((12, 3))
+    K = svgp.se_ard(Z, Z, np.array([0.5, 1.0, 2.0]), 1.7)
+    assert np.allclose(K, K.T, atol=0)
+    assert np.allclose(np.diag(K), 1.7, atol=1e-15)
+    assert np.linalg.eigvalsh(K).min() > -1e-12
+
+
+# ---------------------------------------------------------------- expectations
+def test_gaussian_expectation_vs_adaptive_quadrature():
+    for (y, mu, v, s2) in [(0.3, -0.2, 0.5, 0.1), (2.0, 1.0, 0.01, 1.0),
+                           (-1.0, 0.5, 2.0, 0.3)]:
+        def integrand(f):
+            logp = -0.5 * np.log(2 * np.pi * s2) - (y - f) ** 2 / (2 * s2)
+            return logp * np.exp(-(f - mu) ** 2 / (2 * v)) / np.sqrt(2 * np.pi * v)
+        val, _ = integrate.quad(integrand, -np.inf, np.inf, epsabs=1e-13, epsrel=1e-13)
+        E, _, _, _ = quad.gaussian_expectation(np.array([y]), np.array([mu]),
+                                               np.array([v]), s2)
+        assert np.isclose(E[0], val, rtol=1e-10, atol=1e-12)
+
+
+def test_gh_rule_integrates_polynomials_exactly():
+    t, w = quad.gh_rule(20)
+    for j in range(20):  # degree 2j <= 38 < 40
+        assert np.isclose(np.sum(w * t ** (2 * j)), gamma_fn(j + 0.5), rtol=1e-11)
+        assert abs(np.sum(w * t ** (2 * j + 1))) < 1e-8 * gamma_fn(j + 1.0)
+
+
+def test_probit_expectation_vs_adaptive_quadrature():
+    # 20-point Gauss-Hermite vs adaptive quadrature of E[log Phi(y f)]
+    for (y, mu, v) in [(1.0, 0.3, 0.2), (-1.0, 0.3, 0.2), (1.0, -2.0, 0.05),
+                       (1.0, 1.5, 1.0), (-1.0, 0.0, 0.5)]:
+        def integrand(f):
+            return log_ndtr(y * f) * np.exp(-(f - mu) ** 2 / (2 * v)) / np.sqrt(2 * np.pi * v)
+        val, _ = integrate.quad(integrand, mu - 40 * np.sqrt(v), mu + 40 * np.sqrt(v),
+                                epsabs=1e-13, epsrel=1e-12, limit=200)
+        E, _, _ = quad.probit_expectation(np.array([y]), np.array([mu]), np.array([v]))
+        assert np.isclose(E[0], val, rtol=2e-6, atol=1e-8)
+
+
+def test_probit_partials_match_finite_differences_of_gh_sum():
+    g = _rng(3)
+    y = np.where(g.standard_normal(7) > 0, 1.0, -1.0)
+    mu = g.standard_normal(7)
+    v = g.uniform(0.05, 2.0, 7)
+    E, dmu, dv = quad.probit_expectation(y, mu, v)
+    h = 1e-6
+    Ep, _, _ = quad.probit_expectation(y, mu + h, v)
+    Em, _, _ = quad.probit_expectation(y, mu - h, v)
+    assert np.allclose(dmu, (Ep - Em) / (2 * h), rtol=1e-6, atol=1e-9)
+    Ep, _, _ = quad.probit_expectation(y, mu, v + h)
+    Em, _, _ = quad.probit_expectation(y, mu, v - h)
+    assert np.allclose(dv, (Ep - Em) / (2 * h), rtol=1e-6, atol=1e-9)
+
+
+def test_gh_on_gaussian_loglik_reproduces_closed_form():
+    # GH is exact for the quadratic Gaussian log-density
+    t, w = quad.gh_rule(20)
+    y, mu, v, s2 = 0.7, -0.4, 0.3, 0.2
+    f = mu + np.sqrt(2 * v) * t
+    gh = np.sum(w * (-0.5 * np.log(2 * np.pi * s2) - (y - f) ** 2 / (2 * s2))) / np.sqrt(np.pi)
+    E, _, _, _ = quad.gaussian_expectation(np.array([y]), np.array([mu]), np.array([v]), s2)
+    assert np.isclose(gh, E[0], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- the bound
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bound_equals_cholesky_elbo_at_Ktilde_inverse(lik, seed):
+    """At T = K~^{-1} the bound is the L-SVGP (preconditioned) ELBO, i.e. the
+    Cholesky ELBO of q(u) = N(K_uu K~^{-1} m~, (K_uu^{-1} + S~^{-1})^{-1})."""
+    p = small_problem(seed, lik=lik)
+    out = bound(p, chol_Kinv(p))
+    qm, qS = ref.lsvgp_q(p["ell"], p["sf2"], p["Z"], p["m"], p["s"])
+    ch = ref.cholesky_elbo(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                           p["noise_var"], p["Z"], qm, qS, lik=lik)
+    assert np.isclose(out["F"], ch["F"], rtol=1e-10, atol=1e-10)
+    assert np.isclose(out["KL"], ch["KL"], rtol=1e-9, atol=1e-10)
+    assert np.allclose(out["var"], ch["var"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(out["mu"], ch["mu"], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_bound_never_exceeds_elbo_of_induced_q(lik):
+    """Validity (Section 2, R-SVGP): for any T the bound is an ELBO of the
+    q(u) it induces, so it never exceeds that q's exact Cholesky ELBO."""
+    p = small_problem(4, lik=lik)
+    worst = -np.inf
+    for k in range(150):
+        L = random_L(6, 100 + k, scale=0.6)
+        out = bound(p, L)
+        qm, qS = ref.induced_q(p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L)
+        ch = ref.cholesky_elbo(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                               p["noise_var"], p["Z"], qm, qS, lik=lik)
+        # same predictive marginals: the variance bound is attained by this q
+        assert np.allclose(out["var"], ch["var"], rtol=1e-8, atol=1e-10)
+        worst = max(worst, out["F"] - ch["F"])
+    assert worst <= 1e-9
+
+
+def test_bound_below_log_marginal_likelihood_full_batch():
+    g = _rng(5)
+    X = g.standard_normal((10, 2))
+    y = np.cos(X[:, 0]) + 0.2 * g.standard_normal(10)
+    Z = g.standard_normal((5, 2))
+    ell, sf2, noise = np.array([0.9, 1.2]), 1.1, 0.15
+    lml = ref.log_marginal_likelihood(X, y, ell, sf2, noise)
+    for k in range(100):
+        L = random_L(5, 300 + k, 0.5)
+        m = g.standard_normal(5)
+        s = g.uniform(0.01, 1.0, 5)
+        F = svgp.rsvgp_bound(X, y, 10, ell, sf2, noise, Z, m, s, L)["F"]
+        assert F <= lml + 1e-9
+
+
+def test_unpreconditioned_bound_is_maximised_over_T_at_Ktilde_inverse():
+    p = small_problem(6)
+    args = (p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"], p["Z"],
+            p["m"], p["s"])
+    Fstar = ref.rsvgp_bound_unpreconditioned(*args, chol_Kinv(p))
+    for k in range(100):
+        assert ref.rsvgp_bound_unpreconditioned(*args, random_L(6, 500 + k)) <= Fstar + 1e-9
+
+
+def test_preconditioner_is_one_newton_schulz_step():
+    """P = 2T - T K~ T satisfies I - K~ P = (I - K~ T)^2 (error squaring)."""
+    p = small_problem(7)
+    L = random_L(6, 7, 0.3)
+    out = svgp.rsvgp_bound(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                           p["noise_var"], p["Z"], p["m"], p["s"], L,
+                           return_parts=True)
+    I = np.eye(6)
+    E = I - out["Kt"] @ (L @ L.T)
+    assert np.allclose(I - out["Kt"] @ out["P"], E @ E, atol=1e-10)
+    assert np.allclose(out["P"], out["P"].T, atol=1e-12)
+
+
+def test_prop3_variance_sandwich():
+    """L_n <= sigma_n^2(L-SVGP) <= U_n = oracle variance, and
+    U_n - L_n = ||(I - K~ T) k_n||^2 / sigma^2 (Prop. 3, Section S3)."""
+    p = small_problem(8)
+    L = random_L(6, 8, 0.4)
+    out = svgp.rsvgp_bound(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                           p["noise_var"], p["Z"], p["m"], p["s"], L,
+                           return_parts=True)
+    Kt, T, Kuf = out["Kt"], out["T"], out["Kuf"]
+    sig2 = 0.5 * p["s"].min()               # S~ = S~' + sig2 I with S~' PD
+    Ktm = Kt - sig2 * np.eye(6)
+    var_L = p["sf2"] - np.sum(Kuf * np.linalg.solve(Kt, Kuf), axis=0)
+    Ln = p["sf2"] - (np.sum(Kuf * Kuf, 0) - 2 * np.sum(Kuf * (T @ Ktm @ Kuf), 0)
+                     + np.sum(Kuf * (T @ Ktm @ Kt @ T @ Kuf), 0)) / sig2
+    assert np.all(Ln <= var_L + 1e-10)
+    assert np.all(var_L <= out["var"] + 1e-10)
+    R = (np.eye(6) - Kt @ T) @ Kuf
+    assert np.allclose(out["var"] - Ln, np.sum(R * R, 0) / sig2, rtol=1e-8, atol=1e-10)
+
+
+def test_logdet_T_from_cholesky_diagonal():
+    L = random_L(7, 9)
+    L[2, 2] *= -1.0                          # sign flips keep T = L L^T
+    assert np.isclose(2 * np.sum(np.log(np.abs(np.diag(L)))),
+                      np.linalg.slogdet(L @ L.T)[1], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- natural gradient
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_natgrad_equals_textbook_fisher_natural_gradient(seed):
+    g = _rng(10 + seed)
+    M = 4
+    R = g.standard_normal((M, M))
+    A = R @ R.T + 0.5 * np.eye(M)
+    L = random_L(M, 20 + seed, 0.4)
+    G = svgp.natgrad_direction(L, A)
+    Gb = ref.fisher_natgrad(L, A)
+    assert np.allclose(np.triu(G, 1), 0.0)
+    assert np.allclose(G, Gb, rtol=1e-6, atol=1e-7)
+
+
+def test_natgrad_fixed_point_and_quadratic_convergence():
+    p = small_problem(11, M=8)
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    Ls = np.linalg.cholesky(np.linalg.inv(Kt))
+    assert np.abs(svgp.natgrad_direction(Ls, Kt)).max() < 1e-10
+    assert svgp.ng_residual(Ls, Kt) < 1e-12
+    # from a nearby start, unit steps converge quadratically to chol(K~^{-1})
+    L = Ls + 0.02 * np.tril(_rng(12).standard_normal((8, 8)))
+    _, res = svgp.ng_steps(L, Kt, [1.0] * 5)
+    assert res[0] > 1e-3
+    for a, b in zip(res[:-1], res[1:]):
+        if a > 1e-7:
+            assert b < 10.0 * a * a
+    Ln, _ = svgp.ng_steps(L, Kt, [1.0] * 8)
+    assert np.allclose(Ln @ Ln.T, np.linalg.inv(Kt), rtol=1e-9, atol=1e-9)
+
+
+def test_loglinear_schedule_endpoints():
+    gm = svgp.loglinear_gammas(12)
+    assert np.isclose(gm[0], 1e-5) and np.isclose(gm[9], 1.0) and np.isclose(gm[11], 1.0)
+    assert np.all(np.diff(np.log10(gm[:10])) > 0)
+
+
+def test_schedule_converges_from_identity_on_snelson_like_grid():
+    """From T0 = I/sf2 the unit step diverges when lambda_max(K~) is large;
+    the log-linear schedule converges (Section 3.4)."""
+    x = np.linspace(0.0, 6.0, 16)[:, None]
+    Kt = svgp.ktilde(x, np.array([1.0]), 1.0, np.full(16, 1e-4))
+    _, res_unit = svgp.ng_steps(np.eye(16), Kt, [1.0] * 6)
+    assert res_unit[-1] > 1e2
+    Lc, res = svgp.ng_steps(np.eye(16), Kt, svgp.loglinear_gammas(60))
+    assert res[-1] < 1e-8
+    assert np.allclose(Lc @ Lc.T @ Kt, np.eye(16), atol=1e-6)
+
+
+# ---------------------------------------------------------------- gradient
+def _flat_fd(p, L, key, idx, h=1e-5):
+    def f(v):
+        q = dict(p)
+        q[key] = v if np.ndim(p[key]) else float(v.reshape(()))
+        return bound(q, L)["F"]
+    return ref.central_fd(f, np.asarray(p[key], np.float64), idx, h)
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_gradient_matches_central_differences(lik):
+    p = small_problem(13, M=7, B=11, D=3, lik=lik)
+    L = random_L(7, 14, 0.3)
+    gr = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                               p["noise_var"], p["Z"], p["m"], p["s"], L, lik=lik)
+    for key in ["ell", "Z", "m", "s"]:
+        n = np.size(p[key])
+        fd = _flat_fd(p, L, key, list(range(n)))
+        an = np.ravel(gr[key])
+        assert np.allclose(an, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max()), key
+    fd = _flat_fd(p, L, "sf2", [0])
+    assert np.isclose(gr["sf2"], fd[0], rtol=1e-6)
+    if lik == "gaussian":
+        fd = _flat_fd(p, L, "noise_var", [0], h=1e-6)
+        assert np.isclose(gr["noise_var"], fd[0], rtol=1e-6)
+
+
+def test_prop2_gradient_equals_lsvgp_gradient_at_stopgrad_inverse():
+    """Prop. 2: with T = stopgrad(K~^{-1}) the R-SVGP gradient w.r.t. xi equals
+    the gradient of the preconditioned L-SVGP bound (exact inverse inside)."""
+    p = small_problem(15, M=6, B=8, D=2)
+    L = chol_Kinv(p)
+    gr = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                               p["noise_var"], p["Z"], p["m"], p["s"], L)
+
+    def lsvgp(q):
+        return ref.lsvgp_precond_bound(q["X"], q["y"], q["N"], q["ell"], q["sf2"],
+                                       q["noise_var"], q["Z"], q["m"], q["s"])
+    for key in ["ell", "Z", "m", "s", "sf2"]:
+        x0 = np.atleast_1d(np.asarray(p[key], np.float64))
+
+        def f(v, key=key):
+            q = dict(p)
+            q[key] = v if np.ndim(p[key]) else float(v[0])
+            return lsvgp(q)
+        fd = ref.central_fd(f, x0, list(range(x0.size)), 1e-5)
+        assert np.allclose(np.ravel(gr[key]), fd, rtol=1e-6,
+                           atol=1e-6 * np.abs(fd).max()), key
+
+
+def test_minibatch_scaling_of_data_term():
+    """F = (N/B) sum_batch E_n - KL: doubling N doubles the data term only."""
+    p = small_problem(16)
+    L = random_L(6, 16)
+    a = bound(p, L)
+    q = dict(p)
+    q["N"] = 2 * p["N"]
+    b = bound(q, L)
+    assert np.isclose(b["data"], 2 * a["data"], rtol=1e-14)
+    assert np.isclose(b["KL"], a["KL"], rtol=1e-14)
