@@ -1,0 +1,182 @@
+/*
+ * ifsvgp.h -- C ABI of the MI355X (gfx950) inverse-free sparse variational GP
+ * training iteration.
+ *
+ * Method: Cortinovis, Aitchison, Eleftheriadis, van der Wilk, "Inverse-Free
+ * Sparse Variational Gaussian Processes".  One training iteration is
+ *   (1) t* natural-gradient steps on the factor L of the auxiliary matrix
+ *       T = L L^T towards chol(K~^{-1}), K~ = K_uu + diag(s~)
+ *       (Prop. 1, eq. natgrad; alternating scheme of Section 3.1);
+ *   (2) the preconditioned inverse-free bound at the updated L
+ *       (Section 3.2, eq. rsvgp_precond), with the mini-batch data term
+ *       F = (N/B) sum_n E_q[log p(y_n | f_n)] - KL;
+ *   (3) the gradient of that bound with respect to the kernel lengthscales,
+ *       signal variance, noise variance, inducing inputs Z, inducing mean m~
+ *       (and optionally s~), with T held fixed (stopgrad, Section 3.1 and the
+ *       proof of Prop. 2 in Section S2).
+ * Kernel: ARD squared exponential k(x,x') = sf2 exp(-1/2 sum_d (x_d-x'_d)^2/ell_d^2)
+ * (Section 4, Section S5).  Likelihoods: Gaussian with variance noise_var, or
+ * Bernoulli with probit link p(y|f) = Phi(y f), y in {-1,+1}, whose expectation
+ * is the n_gh-point Gauss-Hermite rule over q(f_n) (Section S5, Model Setup).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - All tensor arguments are DEVICE pointers to caller-owned, contiguous,
+ *   row-major arrays on the device that was current when the context was
+ *   created.  float = IEEE fp32, double = fp64.  The library keeps no pointer
+ *   past the return of a call.
+ * - Shapes: X is B x D, y is B, ell is D, sf2/noise_var are 1 element,
+ *   Z is M x D, m_tilde and s_tilde are M, L is M x M.
+ * - L is the lower-triangular factor of T.  Only its lower triangle
+ *   (diagonal included) is read; updated values are written to the lower
+ *   triangle only; the strict upper triangle is never read or written.
+ * - Work is enqueued asynchronously on the context's HIP stream
+ *   (ifsvgp_set_stream); no call synchronises the device except
+ *   ifsvgp_status and ifsvgp_timing_read.
+ * - Return codes: IFSVGP_OK or a negative IFSVGP_E* code.  Argument errors
+ *   are detected on the host before any work is enqueued (IFSVGP_EINVAL).
+ *   Value errors that live in device memory (non-positive ell, sf2, noise_var
+ *   or s~, a zero diagonal entry of L, a non-finite bound) set a sticky
+ *   device flag; ifsvgp_status reports and clears it.  Nothing throws across
+ *   the ABI.
+ * - A context is bound to one stream and is not thread-safe.  Calls on one
+ *   context run in stream order and reuse its workspace.
+ */
+#ifndef IFSVGP_H
+#define IFSVGP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifsvgp_ctx ifsvgp_ctx;
+
+/* GEMM operand precision.  FP32: every product in fp32 on fp32 MFMA.
+ * BF16 / FP16: the cubic and B*M^2 products take bf16 / fp16 operands with
+ * fp32 accumulation; L, the kernel-matrix exponentials, the likelihood terms
+ * and all reductions stay fp32 and the final scalar sums are fp64. */
+enum ifsvgp_prec { IFSVGP_PREC_FP32 = 0, IFSVGP_PREC_BF16 = 1, IFSVGP_PREC_FP16 = 2 };
+
+enum ifsvgp_lik { IFSVGP_LIK_GAUSSIAN = 0, IFSVGP_LIK_PROBIT = 1 };
+
+enum ifsvgp_status_code {
+  IFSVGP_OK = 0,
+  IFSVGP_EINVAL = -1,      /* bad argument (null pointer, size, enum)          */
+  IFSVGP_EDOMAIN = -2,     /* ell, sf2, noise_var or s~ <= 0, or L_ii == 0     */
+  IFSVGP_EHIP = -3,        /* a HIP runtime call failed                        */
+  IFSVGP_ENONFINITE = -4,  /* the bound or the updated L is not finite         */
+  IFSVGP_ENOMEM = -5,      /* workspace allocation failed                      */
+  IFSVGP_ESTATE = -6       /* ifsvgp_bound_bwd without a matching forward      */
+};
+
+/* Indices into out_terms[IFSVGP_N_TERMS] (device fp64). */
+enum ifsvgp_term {
+  IFSVGP_TERM_DATA = 0,    /* (N/B) sum_n E_n                                  */
+  IFSVGP_TERM_KL = 1,      /* KL upper bound of eq. rsvgp_precond              */
+  IFSVGP_TERM_SUMVAR = 2,  /* sum_n sigma_n^2                                  */
+  IFSVGP_TERM_RESID = 3,   /* ||L^T K~ L - I||_F / sqrt(M) at the bound's L    */
+  IFSVGP_TERM_TRW = 4,     /* tr(K~ T)                                         */
+  IFSVGP_TERM_TRPK = 5,    /* tr(P K_uu), P = 2T - T K~ T                      */
+  IFSVGP_TERM_QUAD = 6,    /* m~^T P K_uu P m~                                 */
+  IFSVGP_TERM_LOGDET = 7,  /* log|T| = 2 sum_i log|L_ii|                       */
+  IFSVGP_N_TERMS = 8
+};
+
+/* Library version as an integer (major*10000 + minor*100 + patch). */
+int ifsvgp_version(void);
+
+/* Human-readable text for a status code.  Never NULL. */
+const char *ifsvgp_strerror(int code);
+
+/* Create a context for problems of M inducing points, mini-batches of at
+ * most B_max rows and D input dimensions.  prec: enum ifsvgp_prec.  lik:
+ * enum ifsvgp_lik.  n_gh: Gauss-Hermite points for the probit likelihood
+ * (1..64; ignored for Gaussian).  Allocates the whole device workspace on the
+ * current device (sizes grow as M^2 + M*B_max).  Stream: the null stream
+ * until ifsvgp_set_stream.  *out is set only on IFSVGP_OK. */
+int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec, int lik, int n_gh);
+
+/* Release the workspace.  The caller must make sure queued work has finished
+ * (or the stream is synchronised) first.  NULL is accepted. */
+void ifsvgp_destroy(ifsvgp_ctx *ctx);
+
+/* Bind the context to a HIP stream (hipStream_t passed as void*). */
+int ifsvgp_set_stream(ifsvgp_ctx *ctx, void *hip_stream);
+
+/* Synchronise the stream, then report and clear the sticky device flag:
+ * IFSVGP_OK, IFSVGP_EDOMAIN or IFSVGP_ENONFINITE. */
+int ifsvgp_status(ifsvgp_ctx *ctx);
+
+/* Physicists' Gauss-Hermite rule with n points (host only, no device use):
+ * nodes t_k and weights w_k with sum_k w_k g(t_k) ~ int exp(-t^2) g(t) dt.
+ * Computed by Newton iteration on the three-term Hermite recurrence.
+ * nodes/weights are HOST arrays of n doubles.  Returns IFSVGP_EINVAL unless
+ * 1 <= n <= 64. */
+int ifsvgp_gh_rule(int n, double *nodes, double *weights);
+
+/* Natural-gradient steps only (Prop. 1): builds K~ from (Z, ell, sf2, s_tilde)
+ * and runs n_ng >= 1 steps L <- L - gammas[t] * L [tril(W) - (I + diag W)/2],
+ * W = L^T K~ L, in place on L.  gammas: HOST array of n_ng floats.
+ * out_resid: device fp64[n_ng] (may be NULL) receiving ||W - I||_F/sqrt(M)
+ * measured before each step (eq. stopping_frobenius). */
+int ifsvgp_natgrad(ifsvgp_ctx *ctx, const float *Z, const float *ell, const float *sf2,
+                   const float *s_tilde, float *L, const float *gammas, int n_ng,
+                   double *out_resid);
+
+/* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
+ * the data-set size (the data term is scaled by N_total / B).  noise_var is
+ * read only for the Gaussian likelihood (may be NULL for probit).
+ * out_bound: device fp64[1] = F.  out_terms: device fp64[IFSVGP_N_TERMS] or
+ * NULL.  The intermediates of this call stay in the workspace for a following
+ * ifsvgp_bound_bwd with identical arguments. */
+int ifsvgp_bound(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
+                 const float *ell, const float *sf2, const float *noise_var,
+                 const float *Z, const float *m_tilde, const float *s_tilde,
+                 const float *L, double *out_bound, double *out_terms);
+
+/* Gradient of the bound evaluated by the immediately preceding
+ * ifsvgp_bound / ifsvgp_step on this context, which must have received the
+ * same arguments (IFSVGP_ESTATE if there was none or B differs).  K_uf tiles
+ * are recomputed, not stored.  grad_scale: device fp64[1] multiplying every
+ * gradient (e.g. the incoming adjoint), or NULL for 1.  Gradient outputs are
+ * device fp32 arrays shaped like their parameters; each may be NULL to skip
+ * it (g_s costs an extra M^3 product).  The gradient is of F (to be
+ * maximised) with respect to the constrained values. */
+int ifsvgp_bound_bwd(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
+                     const float *ell, const float *sf2, const float *noise_var,
+                     const float *Z, const float *m_tilde, const float *s_tilde,
+                     const float *L, const double *grad_scale,
+                     float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
+                     float *g_m, float *g_s);
+
+/* One full training iteration in the order of Section 3.1: n_ng >= 0 NG
+ * steps on L (in place, gammas on the host, out_resid as in
+ * ifsvgp_natgrad), then the bound and its gradient at the updated L.
+ * Arguments as in ifsvgp_natgrad / ifsvgp_bound / ifsvgp_bound_bwd. */
+int ifsvgp_step(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
+                const float *ell, const float *sf2, const float *noise_var,
+                const float *Z, const float *m_tilde, const float *s_tilde,
+                float *L, const float *gammas, int n_ng,
+                double *out_bound, double *out_terms, double *out_resid,
+                float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
+                float *g_m, float *g_s);
+
+/* Per-kernel timing for profiling.  When enabled, every kernel launch of the
+ * context is bracketed by HIP events on the context's stream.
+ * ifsvgp_timing_read synchronises, accumulates the elapsed times since the
+ * last read, and returns the number of kernel kinds; for kind k < cap it
+ * writes the total milliseconds, launch count and a static name. */
+int ifsvgp_timing_enable(ifsvgp_ctx *ctx, int on);
+int ifsvgp_timing_read(ifsvgp_ctx *ctx, int cap, double *total_ms, int *count,
+                       const char **names);
+
+/* Algorithmic flop count of one launch of each kernel kind for batch size B
+ * (the count used for roofline fractions; triangular operands at their
+ * nonzero density, symmetric outputs once).  Same indexing and names as
+ * ifsvgp_timing_read; names may be NULL.  Returns the number of kinds. */
+int ifsvgp_kernel_flops(ifsvgp_ctx *ctx, int B, int cap, double *flops, const char **names);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFSVGP_H */

@@ -1,0 +1,265 @@
+"""ctypes binding of libifsvgp.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module checks tensor
+shapes, dtypes and devices, passes raw device pointers and the current torch
+stream, and turns status codes into exceptions.  PyTorch is used only for
+device memory and streams.  There is no fallback: if the library or a GPU is
+missing, calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libifsvgp.so")
+
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+LIK = {"gaussian": 0, "probit": 1}
+N_TERMS = 8
+TERM_NAMES = ["data", "KL", "sum_var", "resid", "trW", "trPK", "quad", "logdet"]
+
+OK, EINVAL, EDOMAIN, EHIP, ENONFINITE, ENOMEM, ESTATE = 0, -1, -2, -3, -4, -5, -6
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_SIGS = {
+    "ifsvgp_version": (_I, []),
+    "ifsvgp_strerror": (ctypes.c_char_p, [_I]),
+    "ifsvgp_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _I]),
+    "ifsvgp_destroy": (None, [_P]),
+    "ifsvgp_set_stream": (_I, [_P, _P]),
+    "ifsvgp_status": (_I, [_P]),
+    "ifsvgp_gh_rule": (_I, [_I, _P, _P]),
+    "ifsvgp_natgrad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
+    "ifsvgp_bound": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_bound_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
+                              _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_step": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
+                         _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_timing_enable": (_I, [_P, _I]),
+    "ifsvgp_timing_read": (_I, [_P, _I, _P, _P, _P]),
+    "ifsvgp_kernel_flops": (_I, [_P, _I, _I, _P, _P]),
+}
+
+EXPORTED = sorted(_SIGS)
+
+
+class IFSVGPError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else strerror(code))
+
+
+def load(path=LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} not found: build it with `python -m paper_2604_00697_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code):
+    return load().ifsvgp_strerror(code).decode()
+
+
+def gh_rule(n):
+    """The library's Gauss-Hermite rule (host code, no GPU needed)."""
+    t = np.zeros(max(n, 1))
+    w = np.zeros(max(n, 1))
+    rc = load().ifsvgp_gh_rule(n, t.ctypes.data, w.ctypes.data)
+    if rc != OK:
+        raise IFSVGPError(rc, "ifsvgp_gh_rule")
+    return t, w
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise IFSVGPError(rc, what)
+
+
+def _ptr(t, shape, name, dtype=None, optional=False):
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    dtype = dtype or torch.float32
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """One library context: fixed M, B_max, D, precision and likelihood."""
+
+    def __init__(self, M, B_max, D, prec="fp32", lik="gaussian", n_gh=20, device=None):
+        import torch
+        lib = load()
+        self.M, self.B_max, self.D = int(M), int(B_max), int(D)
+        self.prec, self.lik, self.n_gh = prec, lik, int(n_gh)
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(lib.ifsvgp_create(ctypes.byref(h), self.M, self.B_max, self.D,
+                                     PREC[prec], LIK[lik], self.n_gh), "ifsvgp_create")
+        self._h = h
+        self._lib = lib
+        self.generation = 0   # incremented by every forward (bound / step)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            import torch
+            torch.cuda.synchronize(self.device)
+            self._lib.ifsvgp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- plumbing
+    def _stream(self):
+        import torch
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self._lib.ifsvgp_set_stream(self._h, s), "ifsvgp_set_stream")
+
+    def status(self):
+        """Synchronise and return (and clear) the device error flag code."""
+        return self._lib.ifsvgp_status(self._h)
+
+    def raise_status(self):
+        _check(self.status(), "device check")
+
+    def _inputs(self, X, y, ell, sf2, noise, Z, m, s, L):
+        B = X.shape[0]
+        M, D = self.M, self.D
+        return dict(
+            X=_ptr(X, (B, D), "X"), y=_ptr(y, (B,), "y"), B=B,
+            ell=_ptr(ell, (D,), "ell"), sf2=_ptr(sf2, (1,), "sf2"),
+            noise=_ptr(noise, (1,), "noise_var", optional=self.lik != "gaussian"),
+            Z=_ptr(Z, (M, D), "Z"), m=_ptr(m, (M,), "m_tilde"),
+            s=_ptr(s, (M,), "s_tilde"), L=_ptr(L, (M, M), "L"))
+
+    # ---------------------------------------------------------------- calls
+    def natgrad(self, Z, ell, sf2, s, L, gammas, resid=None):
+        """n NG steps on L in place; returns the fp64 residual tensor (n,)."""
+        import torch
+        g = np.ascontiguousarray(np.asarray(gammas, np.float32).reshape(-1))
+        n = g.shape[0]
+        if resid is None:
+            resid = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._stream()
+        _check(self._lib.ifsvgp_natgrad(
+            self._h, _ptr(Z, (self.M, self.D), "Z"), _ptr(ell, (self.D,), "ell"),
+            _ptr(sf2, (1,), "sf2"), _ptr(s, (self.M,), "s_tilde"),
+            _ptr(L, (self.M, self.M), "L"), g.ctypes.data, n,
+            _ptr(resid, (n,), "resid", torch.float64)), "ifsvgp_natgrad")
+        return resid
+
+    def bound(self, X, y, N, ell, sf2, noise, Z, m, s, L, out=None, terms=None):
+        """F (fp64 tensor (1,)) and terms (fp64 tensor (8,)) at the given L."""
+        import torch
+        a = self._inputs(X, y, ell, sf2, noise, Z, m, s, L)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        terms = torch.empty(N_TERMS, dtype=torch.float64, device=self.device) if terms is None else terms
+        self._stream()
+        _check(self._lib.ifsvgp_bound(
+            self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
+            a["m"], a["s"], a["L"], _ptr(out, (1,), "out", torch.float64),
+            _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound")
+        self.generation += 1
+        return out, terms
+
+    def bound_bwd(self, X, y, N, ell, sf2, noise, Z, m, s, L, grad_scale=None,
+                  want=("ell", "sf2", "noise_var", "Z", "m")):
+        """Gradients of the preceding forward's F; dict of fp32 tensors."""
+        import torch
+        a = self._inputs(X, y, ell, sf2, noise, Z, m, s, L)
+        g = self._grad_buffers(want)
+        self._stream()
+        gs = None if grad_scale is None else _ptr(grad_scale, (1,), "grad_scale", torch.float64)
+        _check(self._lib.ifsvgp_bound_bwd(
+            self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
+            a["m"], a["s"], a["L"], gs, *self._grad_ptrs(g)), "ifsvgp_bound_bwd")
+        return g
+
+    def step(self, X, y, N, ell, sf2, noise, Z, m, s, L, gammas, out=None, terms=None,
+             resid=None, want=("ell", "sf2", "noise_var", "Z", "m"), grads=None):
+        """One training iteration: NG steps on L (in place), bound and gradient."""
+        import torch
+        a = self._inputs(X, y, ell, sf2, noise, Z, m, s, L)
+        gm = np.ascontiguousarray(np.asarray(gammas, np.float32).reshape(-1))
+        n = gm.shape[0]
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        terms = torch.empty(N_TERMS, dtype=torch.float64, device=self.device) if terms is None else terms
+        if resid is None and n > 0:
+            resid = torch.empty(n, dtype=torch.float64, device=self.device)
+        g = grads if grads is not None else self._grad_buffers(want)
+        self._stream()
+        _check(self._lib.ifsvgp_step(
+            self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
+            a["m"], a["s"], a["L"], gm.ctypes.data if n else None, n,
+            _ptr(out, (1,), "out", torch.float64), _ptr(terms, (N_TERMS,), "terms", torch.float64),
+            _ptr(resid, (n,), "resid", torch.float64) if n else None,
+            *self._grad_ptrs(g)), "ifsvgp_step")
+        self.generation += 1
+        return out, terms, resid, g
+
+    def _grad_buffers(self, want):
+        import torch
+        shapes = {"ell": (self.D,), "sf2": (1,), "noise_var": (1,),
+                  "Z": (self.M, self.D), "m": (self.M,), "s": (self.M,)}
+        return {k: torch.empty(shapes[k], dtype=torch.float32, device=self.device)
+                for k in want if not (k == "noise_var" and self.lik != "gaussian")}
+
+    @staticmethod
+    def _grad_ptrs(g):
+        return [g[k].data_ptr() if k in g else None
+                for k in ("ell", "sf2", "noise_var", "Z", "m", "s")]
+
+    # ---------------------------------------------------------------- profiling
+    def timing(self, on):
+        _check(self._lib.ifsvgp_timing_enable(self._h, 1 if on else 0), "timing_enable")
+
+    def timing_read(self):
+        cap = 64
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int * cap)()
+        names = (ctypes.c_char_p * cap)()
+        n = self._lib.ifsvgp_timing_read(self._h, cap, ms, cnt, names)
+        if n < 0:
+            raise IFSVGPError(n, "timing_read")
+        return {names[k].decode(): (ms[k], cnt[k]) for k in range(n)}
+
+    def kernel_flops(self, B):
+        """Algorithmic flops of one launch of each kernel kind at batch size B."""
+        cap = 64
+        f = (ctypes.c_double * cap)()
+        names = (ctypes.c_char_p * cap)()
+        n = self._lib.ifsvgp_kernel_flops(self._h, int(B), cap, f, names)
+        if n < 0:
+            raise IFSVGPError(n, "kernel_flops")
+        return {names[k].decode(): f[k] for k in range(n)}
