@@ -106,19 +106,31 @@ def _as64(*xs):
     return [np.asarray(x, np.float64) for x in xs]
 
 
+def _perturbed(K, perturb, key):
+    """K * (1 + perturb[key]) when a relative perturbation is supplied.
+
+    Used only to measure how much rounding of the formed kernel matrices moves
+    the results (tests set their tolerances from it); None leaves K exact."""
+    if perturb is None or key not in perturb:
+        return K
+    return K * (1.0 + perturb[key])
+
+
 def rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
-                n_gh=20, return_parts=False):
+                n_gh=20, return_parts=False, perturb=None):
     """Evaluate F = (N/B) sum_n E_n - KL at T = L L^T, literally.
 
     Returns a dict with F, data (the scaled expected log likelihood), KL,
     sum_var (sum_n sigma_n^2), mu (B), var (B), and the per-datum E_n.
+    perturb: optional dict of relative perturbations of the formed K_uu
+    ('Kuu', M x M) and K_uf ('Kuf', M x B).
     """
     X, y, ell, Z, m, s, L = _as64(X, y, ell, Z, m, s, L)
     sf2 = float(sf2)
     B = X.shape[0]
     M = Z.shape[0]
-    Kuu = se_ard(Z, Z, ell, sf2)
-    Kuf = se_ard(Z, X, ell, sf2)
+    Kuu = _perturbed(se_ard(Z, Z, ell, sf2), perturb, "Kuu")
+    Kuf = _perturbed(se_ard(Z, X, ell, sf2), perturb, "Kuf")
     Kt = Kuu + np.diag(s)
     T = L @ L.T
     P = 2.0 * T - T @ Kt @ T
@@ -137,18 +149,19 @@ def rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
 
 
 def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
-                     n_gh=20):
+                     n_gh=20, perturb=None):
     """Gradient of rsvgp_bound w.r.t. xi at fixed T (adjoint of the literal form).
 
     Returns dict: ell (D), sf2, noise_var (Gaussian only, else 0), Z (MxD),
-    m (M), s (M), plus the bound dict under key 'bound'.
+    m (M), s (M), plus the bound dict under key 'bound'.  perturb: as in
+    rsvgp_bound.
     """
     X, y, ell, Z, m, s, L = _as64(X, y, ell, Z, m, s, L)
     sf2 = float(sf2)
     B, D = X.shape
     c = N / B
     bd = rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik, n_gh,
-                     return_parts=True)
+                     return_parts=True, perturb=perturb)
     Kuu, Kuf, T, P = bd["Kuu"], bd["Kuf"], bd["T"], bd["P"]
     mu, var = bd["mu"], bd["var"]
     _, dmu, dv, ds2 = expectation(lik, y, mu, var, noise_var, n_gh)
@@ -183,28 +196,39 @@ def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
     g_sf2 = (np.sum(Huu) + np.sum(Huf)) / sf2 + np.sum(beta)
     g_ell = np.zeros(D)
     g_Z = np.zeros_like(Z)
+    # the same sums over absolute values of their terms: the scale against
+    # which any floating-point evaluation of these sums must be judged
+    a_ell = np.zeros(D)
+    a_Z = np.zeros_like(Z)
     for d in range(D):
         dzz = Z[:, d][:, None] - Z[:, d][None, :]
         dzx = Z[:, d][:, None] - X[:, d][None, :]
         g_ell[d] = (np.sum(Huu * dzz**2) + np.sum(Huf * dzx**2)) / ell[d]**3
+        a_ell[d] = (np.sum(np.abs(Huu) * dzz**2) + np.sum(np.abs(Huf) * dzx**2)) / ell[d]**3
         # K_uu[i,j] depends on Z_i through row i and column i
         g_Z[:, d] = -(np.sum((Huu + Huu.T) * dzz, axis=1)
                       + np.sum(Huf * dzx, axis=1)) / ell[d]**2
+        a_Z[:, d] = (np.sum(np.abs(Huu + Huu.T) * np.abs(dzz), axis=1)
+                     + np.sum(np.abs(Huf * dzx), axis=1)) / ell[d]**2
+    a_sf2 = (np.sum(np.abs(Huu)) + np.sum(np.abs(Huf))) / sf2 + np.sum(np.abs(beta))
     g_noise = c * np.sum(ds2) if ds2 is not None else 0.0
     return dict(ell=g_ell, sf2=g_sf2, noise_var=g_noise, Z=g_Z, m=g_m, s=g_s,
-                bound=bd, alpha=alpha, beta=beta)
+                bound=bd, alpha=alpha, beta=beta,
+                abs_terms=dict(ell=a_ell, Z=a_Z, sf2=a_sf2))
 
 
 def training_iteration(X, y, N, ell, sf2, noise_var, Z, m, s, L, gammas,
-                       lik="gaussian", n_gh=20, with_grad=True):
+                       lik="gaussian", n_gh=20, with_grad=True, perturb=None):
     """One iteration in the order of Section 3.1: NG steps on L with K~(xi),
-    then bound (and gradient) at the updated L.  Returns (L_new, res, out)."""
-    Kt = ktilde(Z, ell, sf2, s)
+    then bound (and gradient) at the updated L.  Returns (L_new, res, out).
+    perturb: as in rsvgp_bound (applied to K_uu in the NG steps as well)."""
+    Kuu = _perturbed(se_ard(Z, Z, ell, sf2), perturb, "Kuu")
+    Kt = Kuu + np.diag(np.asarray(s, np.float64))
     L_new, res = ng_steps(L, Kt, gammas)
     if with_grad:
         out = rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L_new,
-                               lik, n_gh)
+                               lik, n_gh, perturb=perturb)
     else:
         out = dict(bound=rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s,
-                                     L_new, lik, n_gh))
+                                     L_new, lik, n_gh, perturb=perturb))
     return L_new, res, out

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ifsvgp.h"
@@ -45,7 +46,7 @@ struct ifsvgp_ctx {
   void *Kuf, *V, *U;
   float *Zs, *Xs, *inv_ell;
   float *va, *vb, *vLb, *vWub, *vVa, *vt1, *vt2, *vpart;
-  float *mu_part, *var_part, *mu, *var, *alpha, *beta;
+  float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
   float *hrow, *hcol, *hx, *hzrow, *hz;
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part;
   double *gh;
@@ -241,6 +242,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->var, (size_t)c->Bp);
   ALLOC(c->alpha, (size_t)c->Bp);
   ALLOC(c->beta, (size_t)c->Bp);
+  ALLOC(c->sqnb, (size_t)c->Bp);
   ALLOC(c->hrow, (size_t)c->nb128n * M);
   ALLOC(c->hcol, (size_t)c->nb128m * c->Bp);
   ALLOC(c->hx, (size_t)c->nb128n * M * D);
@@ -355,7 +357,11 @@ template <typename T>
 struct Ops {
   using CS = Cfg<64, 64, 2, 2, 2, T>;    // M x M products
   using CR = Cfg<128, 128, 2, 2, 2, T>;  // M x B products
-  using LdF = Ld<float, true, XfNone>;
+  // The two products with the backward matrix C (whose entries grow like
+  // B / noise_var) need fp32's exponent range: fp16 operands would overflow,
+  // so the fp16 form runs them on bf16 MFMA.
+  using TW = typename std::conditional<std::is_same<T, _Float16>::value, __bf16, T>::type;
+  using CSW = Cfg<64, 64, 2, 2, 2, TW>;
 
   // Y = K~ L (lower tiles), k >= n0
   static hipError_t ng_Y(ifsvgp_ctx *c, const float *L, float *Y) {
@@ -431,11 +437,14 @@ struct Ops {
     const int D4 = (D + 3) & ~3;
     return launch_gemm<CR>(c->st, la, lb, sc, e, (CR::BM + CR::BN) * D4 * 4);
   }
-  // Ys[s] = V_s diag(beta_s) V_s^T (lower tiles, split-K over the batch)
+  // Ys[s] = (V_s D)(V_s D)^T with D = diag(sqrt(-beta)), i.e. -V diag(beta) V^T
+  // (lower tiles, split-K over the batch).  beta <= 0 for log-concave
+  // likelihoods (Gaussian, probit), so the split keeps both operands at the
+  // scale sqrt(|beta|) |V| instead of |beta| |V|.
   static hipError_t syrk(ifsvgp_ctx *c, int B) {
     const int M = c->M;
-    Ld<T, true, XfNone> la{(const T *)c->V, c->Bp, M, B, 1, {}};
-    Ld<T, true, XfScaleCol> lb{(const T *)c->V, c->Bp, M, B, 1, {c->beta}};
+    Ld<T, true, XfScaleCol> la{(const T *)c->V, c->Bp, M, B, 1, {c->sqnb}};
+    Ld<T, true, XfScaleCol> lb{(const T *)c->V, c->Bp, M, B, 1, {c->sqnb}};
     const int ns = std::max(1, std::min(c->nsplit, cdiv(B, CS::BK)));
     Sched sc{c->nb64, c->nb64, 1, ns, B, 0};
     EpiStore<float> e{c->Ys, c->Mp, M, M, 0, (long)M * c->Mp};
@@ -448,7 +457,7 @@ struct Ops {
     Ld<float, false, XfNone> lb{c->Cm, c->Mp, M, M, 1, {}};
     Sched sc{c->nb64, c->nb64, 0, 1, M, K_HI_M1};
     EpiStore<float> e{c->Y2, c->Mp, M, M, 0, 0};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+    return launch_gemm<CSW>(c->st, la, lb, sc, e);
   }
   // G_uu = Y2 L^T (lower tiles), k < n0+BN -> H_uu reductions
   static hipError_t gemm_Guu(ifsvgp_ctx *c, const float *L, const float *s) {
@@ -458,7 +467,7 @@ struct Ops {
     Sched sc{c->nb64, c->nb64, 1, 1, M, K_HI_N1};
     EpiGradUu e{c->Kt, s, c->Zs, c->Mp, M, D, c->hz, c->hzrow, c->tp_uu};
     const int D4 = (D + 3) & ~3;
-    return launch_gemm<CS>(c->st, la, lb, sc, e, 2 * CS::BM * D4 * 4);
+    return launch_gemm<CSW>(c->st, la, lb, sc, e, 2 * CSW::BM * D4 * 4);
   }
 };
 
@@ -559,7 +568,7 @@ static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, dou
     Timed t(c, KK_LIK);
     LikArgs a{c->mu_part, cdiv(M, 64), c->var_part, cdiv(M, 128), (long)c->Bp,
               y, B, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
-              c->mu, c->var, c->alpha, c->beta, c->lik_part};
+              c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part};
     hipLaunchKernelGGL(k_lik, dim3(nlik), dim3(NTB), 0, c->st, a);
   }
   {

@@ -213,7 +213,7 @@ struct LikArgs {
   const float *mu_part; int n_mu; const float *var_part; int n_var; long ldp;
   const float *y; int B; const float *sf2; const float *noise; double c;
   int lik; const double *gh; int ngh;  // gh: nodes[ngh] then weights[ngh]
-  float *mu, *var, *alpha, *beta;
+  float *mu, *var, *alpha, *beta, *sqnb;  // sqnb = sqrt(max(0, -beta))
   double *part;  // [nblocks][4]
 };
 
@@ -272,6 +272,7 @@ __global__ void k_lik(LikArgs a) {
     a.var[n] = (float)var;
     a.alpha[n] = (float)(a.c * dmu);
     a.beta[n] = (float)(a.c * dv);
+    a.sqnb[n] = (float)sqrt(fmax(0.0, -a.c * dv));
     e = E;
     vs = var;
     bs = a.c * dv;
@@ -342,8 +343,9 @@ __global__ void k_finalize_bound(const double *gram_part, int n_gram, const doub
 }
 
 // ---------------------------------------------------------------- backward
-// C = -sym((V alpha) a^T) + sum_s Ys[s] - 1/2 (Wu + I - Wub a^T - a Wub^T)
-//     + 1/2 (Q - b b^T).   Ys holds lower tiles only; read (max, min).
+// C = -sym((V alpha) a^T) + V diag(beta) V^T - 1/2 (Wu + I - Wub a^T - a Wub^T)
+//     + 1/2 (Q - b b^T), with V diag(beta) V^T = -sum_s Ys[s] (split-K pieces of
+// (V D)(V D)^T, D = diag(sqrt(-beta))).  Ys holds lower tiles only; read (max, min).
 __global__ void k_assemble_C(const float *Ys, int nsplit, long split_stride, const float *Wu,
                              const float *Q, const float *a, const float *b, const float *Wub,
                              const float *Va, int M, long ld, float *Cm) {
@@ -354,7 +356,7 @@ __global__ void k_assemble_C(const float *Ys, int nsplit, long split_stride, con
     float ys = 0.f;
     for (int s = 0; s < nsplit; ++s) ys += Ys[s * split_stride + (long)hi * ld + lo];
     const long ij = (long)i * ld + j;
-    const float c = -0.5f * (Va[i] * a[j] + a[i] * Va[j]) + ys -
+    const float c = -0.5f * (Va[i] * a[j] + a[i] * Va[j]) - ys -
                     0.5f * (Wu[ij] + (i == j ? 1.f : 0.f) - Wub[i] * a[j] - a[i] * Wub[j]) +
                     0.5f * (Q[ij] - b[i] * b[j]);
     Cm[ij] = c;
