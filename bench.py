@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput of the inverse-free SVGP training iteration on one MI355X.
+
+One step = one pass of the whole hot path on one mini-batch resident in HBM:
+a natural-gradient step on L (gamma = 1), the preconditioned bound at the
+updated L, and its hand-written backward (gradients for the lengthscales,
+signal and noise variance, Z and m~), all in the HIP library.  The workload
+is the paper-shaped regression configuration with D = 16, N = 1e6,
+B = 4096, M = 1024 (synthetic data, seeded; see paper_2604_00697_amd.synth).
+
+Prints one JSON line.  `value` is iterations per second of the bf16 form
+(bf16 MFMA operands, fp32 accumulation, fp32 master L, fp64 final sums);
+the fp32 form is timed on the same inputs and reported under "fp32".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "train iters/sec (bound+backward+T natgrad) M=1024,B=4096, BF16 vs FP32; MFMA %"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
+N_BATCHES = 8
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(wname, dev):
+    import numpy as np
+    import torch
+    from paper_2604_00697_amd import synth
+    w = synth.workload(wname)
+    p = synth.params_s1(w)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(dev)
+    batches = []
+    for it in range(N_BATCHES):
+        X, y = w.batch(it)
+        batches.append((t(X), t(y)))
+    par = dict(ell=t(p.ell), sf2=t([p.sf2]), noise=t([p.noise_var]), Z=t(p.Z), m=t(p.m),
+               s=t(p.s), L=t(p.L))
+    return w, p, batches, par
+
+
+def schedule(n, g0=1e-5, g1=1.0, ramp=10):
+    """Log-linear NG step sizes g0 -> g1 over `ramp` steps, then constant."""
+    import math
+    out = []
+    for t in range(n):
+        f = min(t, ramp - 1) / (ramp - 1)
+        out.append(10.0 ** (math.log10(g0) + (math.log10(g1) - math.log10(g0)) * f))
+    return out
+
+
+def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev):
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    ctx = Context(w.M, w.B, w.D, prec, w.lik)
+    L = L0.clone()
+    F = torch.empty(1, dtype=torch.float64, device=dev)
+    terms = torch.empty(8, dtype=torch.float64, device=dev)
+    resid = torch.empty(1, dtype=torch.float64, device=dev)
+    grads = ctx._grad_buffers(("ell", "sf2", "noise_var", "Z", "m"))
+
+    def step(i):
+        X, y = batches[i % len(batches)]
+        ctx.step(X, y, w.N, par["ell"], par["sf2"], par["noise"], par["Z"], par["m"],
+                 par["s"], L, [1.0], out=F, terms=terms, resid=resid, grads=grads)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if ctx.status() != 0:
+        raise RuntimeError(f"{prec}: device status flag set during warmup")
+    ctx.timing([dominant])
+    ctx.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.timing(False)
+    kt = ctx.timing_read()
+    status = ctx.status()
+    flops = ctx.kernel_flops(w.B)
+    ms, cnt = kt[dominant]
+    res = dict(ms_per_step=1e3 * (t1 - t0) / steps, iters_per_s=steps / (t1 - t0),
+               dom_ms=ms / max(cnt, 1), dom_count=cnt, flops=flops, status=status,
+               F=F.item(), resid=terms[3].item())
+    ctx.close()
+    return res
+
+
+def kernel_breakdown(prec, w, batches, par, L0, steps, dev):
+    """Per-kernel mean durations (all kinds timed; a separate, untimed pass)."""
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    ctx = Context(w.M, w.B, w.D, prec, w.lik)
+    L = L0.clone()
+    for i in range(3):
+        X, y = batches[i % len(batches)]
+        ctx.step(X, y, w.N, par["ell"], par["sf2"], par["noise"], par["Z"], par["m"], par["s"],
+                 L, [1.0])
+    ctx.timing(True)
+    ctx.timing_read()
+    for i in range(steps):
+        X, y = batches[i % len(batches)]
+        ctx.step(X, y, w.N, par["ell"], par["sf2"], par["noise"], par["Z"], par["m"], par["s"],
+                 L, [1.0])
+    kt = ctx.timing_read()
+    ctx.close()
+    return {k: round(ms / steps * 1e3, 2) for k, (ms, c) in kt.items() if c}
+
+
+def cpu_baseline(w, p, budget_s=20.0):
+    """The float64 oracle (as it stands) on the host cores: iterations per second
+    on the same workload, timed over a bounded number of full iterations."""
+    import numpy as np
+    from oracle import svgp
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(i.get("num_threads", 1) for i in threadpool_info()) or 1
+    except Exception:
+        threads = os.cpu_count()
+    X, y = w.batch(0)
+    Kt = svgp.ktilde(p.Z, p.ell, p.sf2, p.s)
+    L, _ = svgp.ng_steps(np.eye(w.M), Kt, schedule(20))
+    n, t0 = 0, time.perf_counter()
+    while True:
+        X, y = w.batch(n % N_BATCHES)
+        L, _, _ = svgp.training_iteration(X, y, w.N, p.ell, p.sf2, p.noise_var, p.Z, p.m, p.s,
+                                          L, [1.0])
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 20:
+            break
+    return dict(value=round(n / el, 4), unit="iters/s", cores=int(threads), kind="oracle",
+                sample=f"{n} full iterations (NG step + bound + gradient) of the same "
+                       f"workload in float64 NumPy/OpenBLAS, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline")
+    ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the iteration's multi-GPU "
+              "sharding is a design, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: workload {args.workload}, building inputs")
+    w, p, batches, par = make_inputs(args.workload, dev)
+
+    # converge L towards chol(K~^{-1}) before timing (gamma = 1 from here on)
+    c32 = Context(w.M, w.B, w.D, "fp32", w.lik)
+    L0 = par["L"].clone()
+    r = c32.natgrad(par["Z"], par["ell"], par["sf2"], par["s"], L0, schedule(30))
+    torch.cuda.synchronize()
+    log(f"bench: NG schedule residuals first/last {r[0].item():.3e} / {r[-1].item():.3e}")
+    c32.close()
+
+    dominant = "gemm_U"
+    forms = [args.prec] + ([] if args.no_fp32 or args.prec == "fp32" else ["fp32"])
+    res = {}
+    for prec in forms:
+        log(f"bench: timing {prec}: {args.warmup} warmup + {args.steps} steps")
+        res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup, dominant, dev)
+        log(f"bench: {prec} {res[prec]['ms_per_step']:.3f} ms/step, {dominant} "
+            f"{res[prec]['dom_ms'] * 1e3:.1f} us, status {res[prec]['status']}")
+    main_r = res[args.prec]
+    flops = main_r["flops"]
+    f_iter = sum(v for k, v in flops.items() if k not in ("kuu", "kuf"))
+    peak = PEAK_TFLOPS[args.prec]
+    dom_tflops = flops[dominant] / (main_r["dom_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(main_r["iters_per_s"], 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: SE-ARD regression, D={w.D}, N={w.N}, "
+                               f"B={w.B}, M={w.M}, Gaussian likelihood; step = 1 NG step "
+                               f"(gamma=1) + bound + backward",
+                   "M": w.M, "B": w.B, "D": w.D, "N": w.N, "state": "S1"},
+        "mfma_pct": round(100.0 * f_iter / (main_r["ms_per_step"] * 1e-3) / (peak * 1e12), 3),
+        "flops_per_step": f_iter,
+        "roofline": {"bound": "mfma", "kernel": dominant, "achieved": round(dom_tflops, 3),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(dom_tflops / peak, 4),
+                     "traffic": None, "flops_per_launch": flops[dominant],
+                     "avg_launch_us": round(main_r["dom_ms"] * 1e3, 3)},
+    }
+    if "fp32" in res and args.prec != "fp32":
+        r32 = res["fp32"]
+        out["fp32"] = {"value": round(r32["iters_per_s"], 3),
+                       "ms_per_step": round(r32["ms_per_step"], 4),
+                       "mfma_pct": round(100.0 * f_iter / (r32["ms_per_step"] * 1e-3) /
+                                         (PEAK_TFLOPS["fp32"] * 1e12), 3),
+                       "F": r32["F"]}
+        out["F"] = main_r["F"]
+    if args.breakdown:
+        out["kernel_us"] = kernel_breakdown(args.prec, w, batches, par, L0, 20, dev)
+    if not args.no_cpu:
+        log("bench: cpu_baseline (oracle on host cores)")
+        out["cpu_baseline"] = cpu_baseline(w, p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -161,12 +161,14 @@ int ifsvgp_step(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N
                 float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
                 float *g_m, float *g_s);
 
-/* Per-kernel timing for profiling.  When enabled, every kernel launch of the
- * context is bracketed by HIP events on the context's stream.
- * ifsvgp_timing_read synchronises, accumulates the elapsed times since the
- * last read, and returns the number of kernel kinds; for kind k < cap it
- * writes the total milliseconds, launch count and a static name. */
-int ifsvgp_timing_enable(ifsvgp_ctx *ctx, int on);
+/* Per-kernel timing for profiling.  kind_mask selects kernel kinds (bit k
+ * for kind k, as indexed by ifsvgp_timing_read; -1 for all, 0 to stop);
+ * every launch of a selected kind is bracketed by HIP events on the
+ * context's stream.  ifsvgp_timing_read synchronises, accumulates the
+ * elapsed times since the last read, and returns the number of kernel kinds;
+ * for kind k < cap it writes the total milliseconds, launch count and a
+ * static name (each array may be NULL). */
+int ifsvgp_timing_enable(ifsvgp_ctx *ctx, long long kind_mask);
 int ifsvgp_timing_read(ifsvgp_ctx *ctx, int cap, double *total_ms, int *count,
                        const char **names);
 

@@ -55,7 +55,7 @@ struct ifsvgp_ctx {
   int fwd_valid, fwd_B;
   int cur_L;  // which Lw holds the bound's L
   // timing
-  int timing;
+  long long timing;  // bit mask of timed kernel kinds
   std::vector<TimingRec> recs;
   std::vector<hipEvent_t> pool;
   double t_ms[KK_N];
@@ -78,14 +78,14 @@ struct Timed {
   int kind;
   hipEvent_t b;
   Timed(ifsvgp_ctx *c_, int k) : c(c_), kind(k), b(nullptr) {
-    if (!c->timing) return;
+    if (!((c->timing >> kind) & 1)) return;
     hipEvent_t a = get();
     b = get();
     hipEventRecord(a, c->st);
     c->recs.push_back({kind, a, b});
   }
   ~Timed() {
-    if (c->timing && b) hipEventRecord(b, c->st);
+    if (b) hipEventRecord(b, c->st);
   }
   hipEvent_t get() {
     if (!c->pool.empty()) {
@@ -294,9 +294,9 @@ extern "C" int ifsvgp_status(ifsvgp_ctx *c) {
   return IFSVGP_OK;
 }
 
-extern "C" int ifsvgp_timing_enable(ifsvgp_ctx *c, int on) {
+extern "C" int ifsvgp_timing_enable(ifsvgp_ctx *c, long long kind_mask) {
   if (!c) return IFSVGP_EINVAL;
-  c->timing = on ? 1 : 0;
+  c->timing = kind_mask;
   return IFSVGP_OK;
 }
 

@@ -41,7 +41,7 @@ _SIGS = {
                               _P, _P, _P, _P, _P, _P]),
     "ifsvgp_step": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
                          _P, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "ifsvgp_timing_enable": (_I, [_P, _I]),
+    "ifsvgp_timing_enable": (_I, [_P, ctypes.c_longlong]),
     "ifsvgp_timing_read": (_I, [_P, _I, _P, _P, _P]),
     "ifsvgp_kernel_flops": (_I, [_P, _I, _I, _P, _P]),
 }
@@ -241,8 +241,19 @@ class Context:
                 for k in ("ell", "sf2", "noise_var", "Z", "m", "s")]
 
     # ---------------------------------------------------------------- profiling
-    def timing(self, on):
-        _check(self._lib.ifsvgp_timing_enable(self._h, 1 if on else 0), "timing_enable")
+    def timing(self, kinds):
+        """Time launches of the named kernel kinds (a list of names, True for
+        all, False/None to stop)."""
+        if kinds is True:
+            mask = -1
+        elif not kinds:
+            mask = 0
+        else:
+            names = list(self.kernel_flops(1))
+            mask = 0
+            for k in kinds:
+                mask |= 1 << names.index(k)
+        _check(self._lib.ifsvgp_timing_enable(self._h, mask), "timing_enable")
 
     def timing_read(self):
         cap = 64
