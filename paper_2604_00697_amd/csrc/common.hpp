@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define IFS_DEV __device__ __forceinline__
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));

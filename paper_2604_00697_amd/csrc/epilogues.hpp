@@ -1,6 +1,8 @@
 // GEMM epilogues of the inverse-free SVGP iteration.  Each runs with the whole
 // workgroup after the fp32 accumulator tile Cs[BM][LDC] has been staged in LDS;
-// scratch LDS past the tile is at Cs + BM * LDC.
+// 16*NT bytes of scratch LDS follow the tile, then any epilogue-specific LDS.
+// Outputs are written in the layout their consumer's NT product reads:
+// "T" suffixes below mark transposed stores (out[j][i] = C[i][j]).
 #pragma once
 #include "gemm.hpp"
 
@@ -14,6 +16,8 @@
   for (int _i = threadIdx.x; _i < C::BM * C::BN; _i += C::NT)                 \
     if (const int c = _i / C::BM, r = _i % C::BM; true)
 
+#define CS(r, c) Cs[(r) * C::LDC + (c)]
+
 // Sum of one double per thread over the workgroup, result in thread 0.
 template <class C>
 IFS_DEV double tile_sum(double v, const float *Cs) {
@@ -21,52 +25,74 @@ IFS_DEV double tile_sum(double v, const float *Cs) {
   return block_sum<C::NT>(v, sh);
 }
 
-// ---------------------------------------------------------------- plain store
-// out[gi][gj] = acc for valid rows < R and cols < N; optional transposed
-// mirror for off-diagonal tiles of a symmetric (lower-tile) schedule.
+// ---------------------------------------------------------------- plain stores
+// out[gi][gj] = acc for rows < R, cols < N; optional transposed mirror for
+// off-diagonal tiles of a symmetric lower-tile schedule; split-K piece s
+// writes to out + s * split_stride.
 template <typename TO>
 struct EpiStore {
   TO *out;
   long ld;
   int R, N, mirror;
-  long split_stride;  // split-K piece s writes to out + s * split_stride
+  long split_stride;
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
-    TO *out = this->out + (long)t.split * split_stride;
+    TO *o = out + (long)t.split * split_stride;
     TILE_LOOP(C, r, c) {
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < R && gj < N) out[(long)gi * ld + gj] = from_f32<TO>(Cs[r * C::LDC + c]);
+      if (gi < R && gj < N) o[(long)gi * ld + gj] = from_f32<TO>(CS(r, c));
     }
     if (mirror && t.m0 != t.n0) {
       TILE_LOOP_T(C, r, c) {
         const int gi = t.m0 + r, gj = t.n0 + c;
-        if (gi < R && gj < N) out[(long)gj * ld + gi] = from_f32<TO>(Cs[r * C::LDC + c]);
+        if (gi < R && gj < N) o[(long)gj * ld + gi] = from_f32<TO>(CS(r, c));
       }
     }
   }
 };
 
+// out[gj][gi] = acc (transposed store).
+template <typename TO>
+struct EpiStoreT {
+  TO *out;
+  long ld;
+  int R, N;
+  template <class C>
+  IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+    TILE_LOOP_T(C, r, c) {
+      const int gi = t.m0 + r, gj = t.n0 + c;
+      if (gi < R && gj < N) out[(long)gj * ld + gi] = from_f32<TO>(CS(r, c));
+    }
+  }
+};
+
 // ---------------------------------------------------------------- NG gram
-// W = L^T A L on lower tiles: store the tile and the partial of
-// ||W - I||_F^2 (off-diagonal elements count twice, the strict upper part of
-// diagonal tiles is skipped).
+// W = L^T K~ L on lower tiles.  Writes the natural-gradient middle factor
+// X = tril(W) - (I + diag W)/2 transposed (Xt[j][i] = X[i][j], the operand
+// layout of L X), and the partial of ||W - I||_F^2 (off-diagonal elements
+// count twice).
+template <typename T>
 struct EpiNgGram {
-  float *W;
+  T *Xt;
   long ld;
   int M;
   double *part;  // [ntiles]
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     double s = 0.0;
-    TILE_LOOP(C, r, c) {
+    TILE_LOOP_T(C, r, c) {
       const int gi = t.m0 + r, gj = t.n0 + c;
       if (gi < M && gj < M) {
-        const float v = Cs[r * C::LDC + c];
-        W[(long)gi * ld + gj] = v;
-        if (gi >= gj) {
-          const double e = (double)v - (gi == gj ? 1.0 : 0.0);
-          s += (gi == gj ? 1.0 : 2.0) * e * e;
+        const float w = CS(r, c);
+        float x = 0.f;
+        if (gi > gj) {
+          x = w;
+          s += 2.0 * (double)w * (double)w;
+        } else if (gi == gj) {
+          x = 0.5f * (w - 1.0f);
+          s += ((double)w - 1.0) * ((double)w - 1.0);
         }
+        Xt[(long)gj * ld + gi] = from_f32<T>(x);
       }
     }
     s = tile_sum<C>(s, Cs);
@@ -75,33 +101,67 @@ struct EpiNgGram {
 };
 
 // ---------------------------------------------------------------- NG update
-// Lnew = L - gamma * (L X), lower triangle only (strict upper written as 0
-// inside diagonal tiles; upper tiles are never touched and stay zero).
+// Lnew = L - gamma * (L X) on lower tiles (strict upper inside diagonal tiles
+// written as 0; upper tiles are never touched and stay zero).  Writes the fp32
+// master, the operand copy, the operand-type and fp32 transposes, and, on the
+// last step of a call, the caller's L (lower triangle only).  Tile 0 also
+// turns the gram partials of this step into the residual ||W - I||_F/sqrt(M).
+template <typename T>
 struct EpiNgUpdate {
   const float *L;
-  long ldl;
-  float *Ln;
+  float *Ln, *Lnt32;  // Lnt32 aliases LntT when T is float
+  T *LnT, *LntT;      // LnT aliases Ln when T is float
   long ld;
   int M;
   float gamma;
+  float *Lout;        // caller's L (leading dimension M) or null
+  const double *gram_part;
+  int n_gram;
+  double *resid_out, *scal;
   template <class C>
-  IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+  IFS_DEV void run(float *Cs, const TileInfo &t) const {
     TILE_LOOP(C, r, c) {
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < M)
-        Ln[(long)gi * ld + gj] =
-            gi >= gj ? L[(long)gi * ldl + gj] - gamma * Cs[r * C::LDC + c] : 0.f;
+      float v = 0.f;
+      if (gi < M && gj < M) {
+        v = gi >= gj ? L[(long)gi * ld + gj] - gamma * CS(r, c) : 0.f;
+        Ln[(long)gi * ld + gj] = v;
+        if constexpr (!std::is_same<T, float>::value) LnT[(long)gi * ld + gj] = from_f32<T>(v);
+        if (Lout && gi >= gj) Lout[(long)gi * M + gj] = v;
+      }
+      Cs[r * C::LDC + c] = v;
+    }
+    __syncthreads();
+    TILE_LOOP_T(C, r, c) {
+      const int gi = t.m0 + r, gj = t.n0 + c;
+      if (gi < M && gj < M) {
+        const float v = CS(r, c);
+        LntT[(long)gj * ld + gi] = from_f32<T>(v);
+        if constexpr (!std::is_same<T, float>::value) Lnt32[(long)gj * ld + gi] = v;
+      }
+    }
+    if (t.ti == 0) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < n_gram; i += C::NT) s += gram_part[i];
+      s = tile_sum<C>(s, Cs);
+      if (threadIdx.x == 0) {
+        const double r = sqrt(s / M);
+        scal[S_RESID] = r;
+        if (resid_out) *resid_out = r;
+      }
     }
   }
 };
 
 // ---------------------------------------------------------------- bound gram
 // Tile of E = L^T S~ L with W = L^T K~ L already stored (lower tiles) in W.
-// Writes Q = 2I - W and Wu = W - E (both symmetric, mirrored) and per-tile
-// partials [tr W, sum Q o Wu, ||W - I||_F^2].
+// Writes Q = 2I - W and Wu = W - E (fp32, symmetric, mirrored), Q in the
+// operand type (mirrored), and per-tile partials [tr W, sum Q o Wu, ||W - I||^2].
+template <typename T>
 struct EpiBoundGram {
   const float *W;
   float *Q, *Wu;
+  T *QT;
   long ld;
   int M;
   double *part;  // [ntiles][3]
@@ -112,10 +172,11 @@ struct EpiBoundGram {
       const int gi = t.m0 + r, gj = t.n0 + c;
       if (gi < M && gj < M && gi >= gj) {
         const float w = W[(long)gi * ld + gj];
-        const float e = Cs[r * C::LDC + c];
+        const float e = CS(r, c);
         const float q = (gi == gj ? 2.f : 0.f) - w;
         const float wu = w - e;
         Q[(long)gi * ld + gj] = q;
+        QT[(long)gi * ld + gj] = from_f32<T>(q);
         Wu[(long)gi * ld + gj] = wu;
         const double mult = gi == gj ? 1.0 : 2.0;
         if (gi == gj) trw += w;
@@ -124,14 +185,13 @@ struct EpiBoundGram {
         r2 += mult * d * d;
       }
     }
-    // mirror the strict lower part (transposed, coalesced along rows)
     TILE_LOOP_T(C, r, c) {
       const int gi = t.m0 + r, gj = t.n0 + c;
       if (gi < M && gj < M && gi > gj) {
         const float w = W[(long)gi * ld + gj];
-        const float e = Cs[r * C::LDC + c];
         Q[(long)gj * ld + gi] = -w;
-        Wu[(long)gj * ld + gi] = w - e;
+        QT[(long)gj * ld + gi] = from_f32<T>(-w);
+        Wu[(long)gj * ld + gi] = w - CS(r, c);
       }
     }
     trw = tile_sum<C>(trw, Cs);
@@ -145,33 +205,59 @@ struct EpiBoundGram {
   }
 };
 
-// ---------------------------------------------------------------- U = Q V
-// Store U and the partial of sum_i V_in U_in over the tile's rows.
-template <typename TO>
-struct EpiU {
-  TO *U;
-  const TO *V;
-  long ld;
+// ---------------------------------------------------------------- V = L^T K_uf
+// V[i][n] and its transpose Vt[n][i] in the operand type.  Columns n >= B of
+// the last tile are written as zeros, so padding read by the split-K batch
+// product never carries values of an earlier, larger batch.
+template <typename T>
+struct EpiV {
+  T *V, *Vt;
+  long ldv, ldt;
   int M, B;
-  float *var_part;  // [m-tiles][ldp]
-  long ldp;
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     TILE_LOOP(C, r, c) {
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < B) U[(long)gi * ld + gj] = from_f32<TO>(Cs[r * C::LDC + c]);
+      if (gi < M) V[(long)gi * ldv + gj] = from_f32<T>(gj < B ? CS(r, c) : 0.f);
     }
-    float *sh = (float *)(Cs + C::BM * C::LDC);
+    TILE_LOOP_T(C, r, c) {
+      const int gi = t.m0 + r, gj = t.n0 + c;
+      if (gi < M) Vt[(long)gj * ldt + gi] = from_f32<T>(gj < B ? CS(r, c) : 0.f);
+    }
+  }
+};
+
+// ---------------------------------------------------------------- U = Q V
+// Ut[n][i] = U[i][n] and the partial sum_i V_in U_in over the tile's rows.
+template <typename T>
+struct EpiU {
+  T *Ut;
+  const T *V;
+  long ldv, ldt;
+  int M, B;
+  float *var_part;  // [m-tiles][ldp]
+  long ldp;
+  template <class C>
+  IFS_DEV void run(float *Cs, const TileInfo &t) const {
+    TILE_LOOP_T(C, r, c) {
+      const int gi = t.m0 + r, gj = t.n0 + c;
+      if (gi < M && gj < B) Ut[(long)gj * ldt + gi] = from_f32<T>(CS(r, c));
+    }
+    __syncthreads();
+    // V o U in place (independent, coalesced loads of the V tile), then column sums in LDS
+    TILE_LOOP(C, r, c) {
+      const int gi = t.m0 + r, gj = t.n0 + c;
+      const float v = (gi < M && gj < B) ? to_f32(V[(long)gi * ldv + gj]) : 0.f;
+      Cs[r * C::LDC + c] = v * CS(r, c);
+    }
+    __syncthreads();
+    float *sh = Cs + C::BM * C::LDC;
     constexpr int RG = C::NT / C::BN;  // row groups per column
     static_assert(C::NT % C::BN == 0, "column partial layout");
     const int c = threadIdx.x % C::BN, g = threadIdx.x / C::BN;
     const int gj = t.n0 + c;
     float s = 0.f;
-    if (gj < B)
-      for (int r = g; r < C::BM; r += RG) {
-        const int gi = t.m0 + r;
-        if (gi < M) s += to_f32(V[(long)gi * ld + gj]) * Cs[r * C::LDC + c];
-      }
+    for (int r = g; r < C::BM; r += RG) s += CS(r, c);
     sh[threadIdx.x] = s;
     __syncthreads();
     if (g == 0 && gj < B) {
@@ -183,7 +269,7 @@ struct EpiU {
 
 // ---------------------------------------------------------------- backward K_uf side
 // Tile of R = L U.  Forms G_uf = (L b) alpha^T - 2 R diag(beta), recomputes the
-// K_uf tile from the scaled inputs, and reduces H = G_uf o K_uf to
+// K_uf tile from the scaled inputs staged in LDS, and reduces H = G_uf o K_uf to
 //   hrow[i]    = sum_n H_in                 (per n-tile partial)
 //   hcol[n]    = sum_i H_in                 (per m-tile partial)
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
@@ -202,7 +288,7 @@ struct EpiGradUf {
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     const int D4 = (D + 3) & ~3;
-    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][D4]  (after 16*NT bytes of scratch)
+    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][D4]
     float *xs = zs + BM * D4;               // [BN][D4]
     for (int i = threadIdx.x; i < BM * D4; i += NT) {
       const int r = i / D4, d = i % D4, gi = t.m0 + r;
@@ -225,7 +311,7 @@ struct EpiGradUf {
           d2 = fmaf(df, df, d2);
         }
         const float kuf = s2f * __expf(-0.5f * d2);
-        const float g = Lb[gi] * alpha[gj] - 2.f * Cs[r * C::LDC + c] * beta[gj];
+        const float g = Lb[gi] * alpha[gj] - 2.f * CS(r, c) * beta[gj];
         h = g * kuf;
         hs += h;
       }
@@ -235,21 +321,19 @@ struct EpiGradUf {
     hs = tile_sum<C>(hs, Cs);
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int nti = t.n0 / BN, mti = t.m0 / BM;
-    // column sums
     for (int c = threadIdx.x; c < BN; c += NT) {
       const int gj = t.n0 + c;
       if (gj < B) {
         float s = 0.f;
-        for (int r = 0; r < BM; ++r) s += Cs[r * C::LDC + c];
+        for (int r = 0; r < BM; ++r) s += CS(r, c);
         hcol[(long)mti * ldc + gj] = s;
       }
     }
-    // row sums
     for (int r = threadIdx.x; r < BM; r += NT) {
       const int gi = t.m0 + r;
       if (gi < M) {
         float s = 0.f;
-        for (int c = 0; c < BN; ++c) s += Cs[r * C::LDC + c];
+        for (int c = 0; c < BN; ++c) s += CS(r, c);
         hrow[(long)nti * M + gi] = s;
       }
     }
@@ -261,7 +345,7 @@ struct EpiGradUf {
       for (int c = 0; c < BN; ++c) {
         float hv[4], xv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = Cs[(r4 + i) * C::LDC + c];
+        for (int i = 0; i < 4; ++i) hv[i] = CS(r4 + i, c);
 #pragma unroll
         for (int j = 0; j < 4; ++j) xv[j] = xs[c * D4 + d4 + j];
 #pragma unroll
@@ -312,7 +396,7 @@ struct EpiGradUu {
       float h = 0.f;
       if (gi < M && gj < M) {
         const float k = Kt[(long)gi * ld + gj] - (gi == gj ? s[gi] : 0.f);
-        h = Cs[r * C::LDC + c] * k;
+        h = CS(r, c) * k;
         hs += (off ? 2.0 : 1.0) * h;
       }
       Cs[r * C::LDC + c] = h;
@@ -322,12 +406,11 @@ struct EpiGradUu {
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int I = t.m0 / BM, J = t.n0 / BN;
     const int nd4 = D4 / 4;
-    // rows of block I: H zj
     for (int r = threadIdx.x; r < BM; r += NT) {
       const int gi = t.m0 + r;
       if (gi < M) {
         float s_ = 0.f;
-        for (int c = 0; c < BN; ++c) s_ += Cs[r * C::LDC + c];
+        for (int c = 0; c < BN; ++c) s_ += CS(r, c);
         hzrow[(long)J * M + gi] = s_;
       }
     }
@@ -337,7 +420,7 @@ struct EpiGradUu {
       for (int c = 0; c < BN; ++c) {
         float hv[4], zv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = Cs[(r4 + i) * C::LDC + c];
+        for (int i = 0; i < 4; ++i) hv[i] = CS(r4 + i, c);
 #pragma unroll
         for (int j = 0; j < 4; ++j) zv[j] = zj[c * D4 + d4 + j];
 #pragma unroll
@@ -355,12 +438,11 @@ struct EpiGradUu {
       }
     }
     if (!off) return;
-    // rows of block J: H^T zi
     for (int c = threadIdx.x; c < BN; c += NT) {
       const int gj = t.n0 + c;
       if (gj < M) {
         float s_ = 0.f;
-        for (int r = 0; r < BM; ++r) s_ += Cs[r * C::LDC + c];
+        for (int r = 0; r < BM; ++r) s_ += CS(r, c);
         hzrow[(long)I * M + gj] = s_;
       }
     }
@@ -370,7 +452,7 @@ struct EpiGradUu {
       for (int r = 0; r < BM; ++r) {
         float hv[4], zv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = Cs[r * C::LDC + c4 + i];
+        for (int i = 0; i < 4; ++i) hv[i] = CS(r, c4 + i);
 #pragma unroll
         for (int j = 0; j < 4; ++j) zv[j] = zi[r * D4 + d4 + j];
 #pragma unroll

@@ -1,25 +1,34 @@
-// Tiled MFMA GEMM for gfx950 with pluggable operand loaders, tile schedules
-// and epilogues.  C[m][n] = sum_k A(m,k) B(k,n) over a k-range chosen per tile
-// (triangular operands skip their zero blocks).
+// Tiled MFMA GEMM for gfx950 in "NT" form:
+//     C[i][j] = sum_k A[i][k] * Bt[j][k]
+// with both operands stored k-contiguous in the MFMA operand type, in
+// zero-padded buffers (rows padded to the tile, k padded to the k-step), so
+// every global load is an unconditional 16-byte vector.  Producers write
+// their outputs in the layout the next product consumes (plain or
+// transposed), which removes all transposes from the inner loops.
 //
 // Data path per workgroup (NT = 64 * WGM * WGN threads):
-//   global --(loader: bounds, triangular mask, scaling, fp32 -> operand type)-->
-//   registers --> LDS (double buffered, k-contiguous rows, 16-byte padding) -->
-//   16x16 MFMA tiles (fp32: 16x16x4, bf16/fp16: 16x16x32) with fp32 accumulators
+//   global (16 B per lane, 8 lanes per 128-byte k-row) --> registers
+//   (optional per-k scaling) --> LDS, double buffered, rows padded by 16 B
+//   --> 16x16 MFMA (fp32: 4 x 16x16x4, bf16/fp16: 16x16x32), fp32 accumulators
 //   --> fp32 tile staged in LDS --> epilogue functor (stores, fused reductions).
+// Triangular operands skip their zero k-blocks through the tile schedule.
 #pragma once
 #include "common.hpp"
 
-template <int BM_, int BN_, int WGM_, int WGN_, int KCH_, typename T_>
+// P_: k-tiles whose global loads are in flight while one tile is computed
+// (register sets of prefetched operands).
+template <int BM_, int BN_, int WGM_, int WGN_, typename T_, int P_ = 2>
 struct Cfg {
   using T = T_;
-  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, KCH = KCH_;
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, P = P_;
   static constexpr int NT = 64 * WGM * WGN;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
   static constexpr int TM = WM / 16, TN = WN / 16;
   static constexpr int KPL = 16 / (int)sizeof(T);  // operand elements per 16 bytes
-  static constexpr int BK = 4 * KPL * KCH;         // k per LDS tile
-  static constexpr int LDK = BK + KPL;             // padded LDS row, elements
+  static constexpr int BK = 8 * KPL;               // k per stage: 128 bytes per row
+  static constexpr int LDK = BK + KPL;             // padded LDS row (elements): 144 bytes
+  static constexpr int RPP = NT / 8;               // rows covered by one load pass
+  static constexpr int PA = BM / RPP, PB = BN / RPP;
   static constexpr int LDC = BN + 1;               // epilogue staging row, floats
   static constexpr int SMEM_MAIN = 2 * (BM + BN) * LDK * (int)sizeof(T);
   // epilogue: staged tile + 16*NT bytes of reduction scratch (+ extra per epilogue)
@@ -28,93 +37,52 @@ struct Cfg {
     return SMEM_MAIN > SMEM_EPI + extra ? SMEM_MAIN : SMEM_EPI + extra;
   }
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
-  static_assert(BM % 4 == 0 && BN % 4 == 0 && BK % 4 == 0, "4x4 load chunks");
+  static_assert(BM % RPP == 0 && BN % RPP == 0, "tile rows per load pass");
 };
 
-// ------------------------------------------------------------------ transforms
-// Applied to element (a, b) of the stored source matrix after loading.
-struct XfNone {
-  IFS_DEV float operator()(float v, int, int) const { return v; }
-};
-struct XfLower {  // keep the lower triangle (a >= b)
-  IFS_DEV float operator()(float v, int a, int b) const { return a >= b ? v : 0.f; }
-};
-struct XfLowerScaleRow {  // diag(s) L : lower triangle times s[a]
-  const float *s;
-  IFS_DEV float operator()(float v, int a, int b) const { return a >= b ? v * s[a] : 0.f; }
-};
-struct XfScaleCol {  // A diag(s)
-  const float *s;
-  IFS_DEV float operator()(float v, int, int b) const { return v * s[b]; }
-};
-// Natural-gradient middle factor from the lower triangle of W = L^T A L:
-// tril(W) - (I + diag(W))/2, i.e. W_ab below the diagonal, (W_aa - 1)/2 on it.
-struct XfNatgrad {
-  IFS_DEV float operator()(float v, int a, int b) const {
-    return a > b ? v : (a == b ? 0.5f * (v - 1.0f) : 0.f);
-  }
-};
-
-// ------------------------------------------------------------------ loaders
-// Logical operand element (r, k): r is the row of A (m) or the column of B (n).
-// The stored matrix p (leading dimension ld) holds it at source coordinates
-// (a, b) = KC ? (r, k) : (k, r).  Rows a < AR and columns b < BC are valid;
-// everything else reads as zero.  load4 returns 4 consecutive elements along
-// the contiguous source dimension starting at (r, k).
-template <typename S, bool KC_, class Xf>
-struct Ld {
-  static constexpr bool KC = KC_;
-  const S *p;
+// One operand: k-contiguous rows of length >= the padded k extent.
+// scale (optional, when the kernel's SA/SB flag is set): multiply element k by scale[k].
+template <typename T>
+struct Opnd {
+  const T *p;
   long ld;
-  int AR, BC;
-  int vec;  // 1 if ld and p allow aligned 4-element vector loads
-  Xf xf;
-  IFS_DEV void load4(int r, int k, float v[4]) const {
-    const int a = KC ? r : k, b = KC ? k : r;
-    const bool rowok = a < AR;
-    const S *q = p + (long)a * ld + b;
-    if (rowok && vec && b + 3 < BC) {
-      if constexpr (sizeof(S) == 4) {
-        const f32x4 t = *(const f32x4 *)q;
-        v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
-      } else {
-        typedef S s4 __attribute__((ext_vector_type(4)));
-        const s4 t = *(const s4 *)q;
-        v[0] = to_f32(t[0]); v[1] = to_f32(t[1]); v[2] = to_f32(t[2]); v[3] = to_f32(t[3]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = xf(v[j], a, b + j);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        v[j] = (rowok && b + j < BC) ? xf(to_f32(q[j]), a, b + j) : 0.f;
-    }
-  }
+  const float *scale;
 };
 
 // ------------------------------------------------------------------ schedule
 enum : int { K_LO_M0 = 1, K_LO_N0 = 2, K_HI_M1 = 4, K_HI_N1 = 8 };
 
 // Maps blockIdx.x to an output tile and its k-range.
-//   sym = 0: rectangular grid mt x nt (row-major over tiles);
+//   sym = 0: rectangular grid of mt x nt tiles;
 //   sym = 1: lower-triangular tiles (I >= J) of an mt x mt grid.
-// rule: bitmask of K_* bounds (k >= m0, k >= n0, k < m0+BM, k < n0+BN) that
-// skip blocks of a triangular operand known to be zero.  nsplit > 1 splits
-// the k-range into BK-aligned pieces (split-K); blockIdx.y selects the piece.
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2), so block b is renumbered to run consecutive tiles on one XCD; for
+// rectangular grids consecutive tiles share a column block (I fastest), so an
+// XCD streams one slice of the B operand against the whole A operand.
+// rule: K_* bounds (k >= m0, k >= n0, k < m0+BM, k < n0+BN) skipping blocks of
+// a triangular operand known to be zero.  nsplit > 1 splits the k-range into
+// BK-aligned pieces (split-K) selected by blockIdx.y.
 struct Sched {
   int mt, nt, sym, nsplit, K, rule;
   template <class C>
-  IFS_DEV bool tile(int &m0, int &n0, int &kb, int &ke, int &ti) const {
+  IFS_DEV void tile(int &m0, int &n0, int &kb, int &ke, int &ti) const {
+    const int ntile = sym ? mt * (mt + 1) / 2 : mt * nt;
+    const int b = blockIdx.x;
+    // XCD-contiguous renumbering: blocks b, b+8, b+16, ... share XCD b % 8
+    const int per = (ntile + 7) / 8, rem = ntile % 8;
+    const int x = b % 8, q = b / 8;
+    int t;
+    if (rem == 0 || x < rem) t = x * per + q;
+    else t = rem * per + (x - rem) * (per - 1) + q;
     int I, J;
-    const int t = blockIdx.x;
     if (sym) {
       I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
       while (I * (I + 1) / 2 > t) --I;
       J = t - I * (I + 1) / 2;
     } else {
-      I = t / nt;
-      J = t - I * nt;
+      J = t / mt;
+      I = t - J * mt;
     }
     ti = t;
     m0 = I * C::BM;
@@ -127,15 +95,14 @@ struct Sched {
     lo = (lo / C::BK) * C::BK;
     if (nsplit > 1) {
       const int nkt = hi > lo ? (hi - lo + C::BK - 1) / C::BK : 0;
-      const int per = (nkt + nsplit - 1) / nsplit;
+      const int per_s = (nkt + nsplit - 1) / nsplit;
       const int s = blockIdx.y;
-      kb = lo + s * per * C::BK;
-      ke = min(hi, lo + (s + 1) * per * C::BK);
+      kb = lo + s * per_s * C::BK;
+      ke = min(hi, lo + (s + 1) * per_s * C::BK);
     } else {
       kb = lo;
       ke = hi;
     }
-    return true;
   }
 };
 
@@ -143,18 +110,39 @@ struct TileInfo {
   int m0, n0, ti, split;
 };
 
+// 16 bytes of operands, optionally scaled element-wise by s[k .. k+KPL).
+template <typename T, bool SCALE>
+IFS_DEV uint4 load_chunk(const T *p, const float *s) {
+  uint4 v = *(const uint4 *)p;
+  if constexpr (SCALE) {
+    if constexpr (sizeof(T) == 4) {
+      float *f = (float *)&v;
+      const f32x4 sc = *(const f32x4 *)s;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) f[j] *= sc[j];
+    } else {
+      T *h = (T *)&v;
+      const f32x4 s0 = *(const f32x4 *)s, s1 = *(const f32x4 *)(s + 4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = from_f32<T>(to_f32(h[j]) * s0[j]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[4 + j] = from_f32<T>(to_f32(h[4 + j]) * s1[j]);
+    }
+  }
+  return v;
+}
+
 // ------------------------------------------------------------------ kernel
-template <class C, class LA, class LB, class EPI>
-__global__ __launch_bounds__(C::NT) void gemm_kernel(LA la, LB lb, Sched sc, EPI epi) {
+template <class C, bool SA, bool SB, class EPI>
+__global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
+                                                     Opnd<typename C::T> Bt, Sched sc, EPI epi) {
   using T = typename C::T;
   using V = typename Vec16<T>::type;
-  constexpr int NT = C::NT, BM = C::BM, BN = C::BN, BK = C::BK, LDK = C::LDK;
-  constexpr int CA = (BM / 4) * (BK / 4), CB = (BN / 4) * (BK / 4);
-  constexpr int PA = (CA + NT - 1) / NT, PB = (CB + NT - 1) / NT;
+  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, LDK = C::LDK, KPL = C::KPL;
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  T *As = (T *)smem_raw;                 // [2][BM][LDK]
-  T *Bs = As + 2 * BM * LDK;             // [2][BN][LDK]
+  T *As = (T *)smem_raw;          // [2][BM][LDK]
+  T *Bs = As + 2 * BM * LDK;      // [2][BN][LDK]
 
   int m0, n0, kb, ke, ti;
   sc.tile<C>(m0, n0, kb, ke, ti);
@@ -164,6 +152,7 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(LA la, LB lb, Sched sc, EPI
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / C::WGN, wn = wave % C::WGN;
   const int lr = lane & 15, kq = lane >> 4;
+  const int lrow = tid >> 3, lch = (tid & 7) * KPL;  // load row within a pass, k offset
 
   f32x4 acc[C::TM][C::TN];
 #pragma unroll
@@ -171,117 +160,63 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(LA la, LB lb, Sched sc, EPI
 #pragma unroll
     for (int j = 0; j < C::TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  T ra[PA][4][4], rb[PB][4][4];
+  const T *pa = A.p + (long)(m0 + lrow) * A.ld + lch;
+  const T *pb = Bt.p + (long)(n0 + lrow) * Bt.ld + lch;
+  constexpr int P = C::P;
+  uint4 ra[P][C::PA], rb[P][C::PB];  // P register sets of prefetched k-tiles
 
-  auto chunk_rk = [](int c, bool kc, int R, int &cr, int &ck) {
-    if (kc) { cr = c / (BK / 4); ck = c % (BK / 4); }
-    else    { ck = c / (R / 4); cr = c % (R / 4); }
+  auto fetch = [&](int set, int k0) {
+#pragma unroll
+    for (int p = 0; p < C::PA; ++p)
+      ra[set][p] = load_chunk<T, SA>(pa + (long)p * C::RPP * A.ld + k0,
+                                     SA ? A.scale + k0 + lch : nullptr);
+#pragma unroll
+    for (int p = 0; p < C::PB; ++p)
+      rb[set][p] = load_chunk<T, SB>(pb + (long)p * C::RPP * Bt.ld + k0,
+                                     SB ? Bt.scale + k0 + lch : nullptr);
   };
-  auto fetch = [&](int k0) {
+  auto stash = [&](int set, int buf) {
+    T *a = As + buf * BM * LDK + lrow * LDK + lch;
+    T *b = Bs + buf * BN * LDK + lrow * LDK + lch;
 #pragma unroll
-    for (int i = 0; i < PA; ++i) {
-      const int c = tid + i * NT;
-      if (CA % NT == 0 || c < CA) {
-        int cr, ck;
-        chunk_rk(c, LA::KC, BM, cr, ck);
-        float v[4][4];
-        if (LA::KC) {
+    for (int p = 0; p < C::PA; ++p) *(uint4 *)(a + p * C::RPP * LDK) = ra[set][p];
 #pragma unroll
-          for (int rr = 0; rr < 4; ++rr) la.load4(m0 + 4 * cr + rr, k0 + 4 * ck, v[rr]);
-        } else {
-          float w[4][4];
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) la.load4(m0 + 4 * cr, k0 + 4 * ck + kk, w[kk]);
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) v[rr][kk] = w[kk][rr];
-        }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) ra[i][rr][kk] = from_f32<T>(v[rr][kk]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      const int c = tid + i * NT;
-      if (CB % NT == 0 || c < CB) {
-        int cr, ck;
-        chunk_rk(c, LB::KC, BN, cr, ck);
-        float v[4][4];
-        if (LB::KC) {
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) lb.load4(n0 + 4 * cr + rr, k0 + 4 * ck, v[rr]);
-        } else {
-          float w[4][4];
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) lb.load4(n0 + 4 * cr, k0 + 4 * ck + kk, w[kk]);
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) v[rr][kk] = w[kk][rr];
-        }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) rb[i][rr][kk] = from_f32<T>(v[rr][kk]);
-      }
-    }
+    for (int p = 0; p < C::PB; ++p) *(uint4 *)(b + p * C::RPP * LDK) = rb[set][p];
   };
-  auto stash = [&](int buf) {
-    T *A = As + buf * BM * LDK;
-    T *Bq = Bs + buf * BN * LDK;
+  auto compute = [&](int buf) {
+    const T *a = As + buf * BM * LDK + (wm * C::WM + lr) * LDK;
+    const T *b = Bs + buf * BN * LDK + (wn * C::WN + lr) * LDK;
 #pragma unroll
-    for (int i = 0; i < PA; ++i) {
-      const int c = tid + i * NT;
-      if (CA % NT == 0 || c < CA) {
-        int cr, ck;
-        chunk_rk(c, LA::KC, BM, cr, ck);
+    for (int kc = 0; kc < 2; ++kc) {
+      const int koff = kc * 4 * KPL + kq * KPL;
+      V av[C::TM], bv[C::TN];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          T *dst = A + (4 * cr + rr) * LDK + 4 * ck;
+      for (int i = 0; i < C::TM; ++i) av[i] = *(const V *)(a + i * 16 * LDK + koff);
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) dst[kk] = ra[i][rr][kk];
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < PB; ++i) {
-      const int c = tid + i * NT;
-      if (CB % NT == 0 || c < CB) {
-        int cr, ck;
-        chunk_rk(c, LB::KC, BN, cr, ck);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          T *dst = Bq + (4 * cr + rr) * LDK + 4 * ck;
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) dst[kk] = rb[i][rr][kk];
-        }
-      }
-    }
-  };
-
-  if (nk > 0) fetch(kb);
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    stash(buf);
-    __syncthreads();
-    if (it + 1 < nk) fetch(kb + (it + 1) * BK);
-    const T *A = As + buf * BM * LDK + (wm * C::WM + lr) * LDK;
-    const T *Bq = Bs + buf * BN * LDK + (wn * C::WN + lr) * LDK;
-#pragma unroll
-    for (int kc = 0; kc < C::KCH; ++kc) {
-      const int koff = kc * 4 * C::KPL + kq * C::KPL;
-      V a[C::TM], b[C::TN];
-#pragma unroll
-      for (int i = 0; i < C::TM; ++i) a[i] = *(const V *)(A + i * 16 * LDK + koff);
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) b[j] = *(const V *)(Bq + j * 16 * LDK + koff);
+      for (int j = 0; j < C::TN; ++j) bv[j] = *(const V *)(b + j * 16 * LDK + koff);
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-        for (int j = 0; j < C::TN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < C::TN; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
+    }
+  };
+
+#pragma unroll
+  for (int s = 0; s < P; ++s)
+    if (s < nk) fetch(s, kb + s * BK);
+  // k-tile `it` lives in register set it % P and LDS buffer it % 2; the loop is
+  // unrolled by P so register sets are indexed at compile time.
+  for (int it0 = 0; it0 < nk; it0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int it = it0 + u;
+      if (it < nk) {
+        const int buf = it & 1;
+        stash(u, buf);
+        __syncthreads();
+        if (it + P < nk) fetch(u, kb + (it + P) * BK);
+        compute(buf);
+      }
     }
   }
   __syncthreads();
@@ -299,15 +234,16 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(LA la, LB lb, Sched sc, EPI
   epi.template run<C>(Cs, t);
 }
 
-// Host-side launch helper.
-// extra: LDS bytes the epilogue needs beyond the staged tile and scratch.
-template <class C, class LA, class LB, class EPI>
-static inline hipError_t launch_gemm(hipStream_t st, const LA &la, const LB &lb,
-                                     const Sched &sc, const EPI &epi, int extra = 0) {
+// Host-side launch helper.  extra: LDS bytes the epilogue needs beyond the
+// staged tile and its scratch.
+template <class C, bool SA, bool SB, class EPI>
+static inline hipError_t launch_gemm(hipStream_t st, const Opnd<typename C::T> &A,
+                                     const Opnd<typename C::T> &Bt, const Sched &sc,
+                                     const EPI &epi, int extra = 0) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
   if (ntile <= 0) return hipSuccess;
   dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1);
-  auto kern = gemm_kernel<C, LA, LB, EPI>;
+  auto kern = gemm_kernel<C, SA, SB, EPI>;
   const int smem = C::smem(extra);
   static int attr_bytes = 0;
   if (smem > attr_bytes) {
@@ -316,6 +252,6 @@ static inline hipError_t launch_gemm(hipStream_t st, const LA &la, const LB &lb,
     if (e != hipSuccess) return e;
     attr_bytes = smem;
   }
-  hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, st, la, lb, sc, epi);
+  hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, st, A, Bt, sc, epi);
   return hipGetLastError();
 }

@@ -1,5 +1,10 @@
 // C ABI of the inverse-free SVGP training iteration (host orchestration).
 // Declarations and the contract of every entry point: include/ifsvgp.h.
+//
+// Every product of the iteration is an NT GEMM (gemm.hpp) over zero-padded
+// operands in the MFMA operand type; the context's workspace holds each
+// operand in the layout its consumer reads.  Padded extents: Mp and Bp are
+// M and B_max rounded up to 128.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,12 +16,13 @@
 #include <vector>
 
 #include "../../include/ifsvgp.h"
-#include "epilogues.hpp"
 #include "kernels.hpp"
+#include "epilogues.hpp"
 
-#define IFSVGP_VERSION 100
+#define IFSVGP_VERSION 200
 
 static constexpr int MAXD = 64;  // input dimension limit of the LDS-staged kernels
+static constexpr int PAD = 128;  // padding granule of every workspace extent
 
 // ------------------------------------------------------------------ kernel kinds
 enum KernelKind : int {
@@ -38,22 +44,24 @@ struct TimingRec {
 struct ifsvgp_ctx {
   int M, Bmax, D, prec, lik, ngh;
   int Mp, Bp;
-  int nb64, nb128m, nb128n;  // tile counts
   int nsplit;
   hipStream_t st;
-  // buffers
-  float *Kt, *Lw[2], *Y, *Wn, *Q, *Wu, *Cm, *Y2, *Ys;
-  void *Kuf, *V, *U;
-  float *Zs, *Xs, *inv_ell;
-  float *va, *vb, *vLb, *vWub, *vVa, *vt1, *vt2, *vpart;
+  // fp32 M x M ([Mp][Mp])
+  float *Kt, *L32[2], *Lt32[2], *W32, *Q32, *Wu32, *Ys;  // Ys: [nsplit][Mp][Mp]
+  // operand-type M x M ([Mp][Mp]); C and Y2 use the wide-range type of the form
+  void *KtT, *LT[2], *LtT[2], *Yt, *Xgt, *QT, *Cm, *Y2;
+  // operand-type M x B: Kft, Vt, Ut are [Bp][Mp]; V is [Mp][Bp]
+  void *Kft, *V, *Vt, *Ut;
+  float *Zs, *Xs, *inv_ell, *sP;  // sP: s~ zero-padded to Mp
+  float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
   float *hrow, *hcol, *hx, *hzrow, *hz;
-  double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part;
+  double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
   double *gh;
-  int *flag;
+  int *flag, *counters;
   // last forward state for the backward
   int fwd_valid, fwd_B;
-  int cur_L;  // which Lw holds the bound's L
+  int cur;  // which L32/LT/LtT slot holds the bound's L
   // timing
   long long timing;  // bit mask of timed kernel kinds
   std::vector<TimingRec> recs;
@@ -66,6 +74,9 @@ struct ifsvgp_ctx {
 // ------------------------------------------------------------------ helpers
 static inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 static inline int cdiv(long x, long m) { return (int)((x + m - 1) / m); }
+static int grid1(long n) {
+  return (int)std::min<long>(std::max<long>(1, (n + NTB - 1) / NTB), 65536);
+}
 
 #define HIPCK(x)                                      \
   do {                                                \
@@ -99,25 +110,35 @@ struct Timed {
   }
 };
 
+static hipError_t dmalloc_bytes(ifsvgp_ctx *c, void **p, size_t bytes) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) return e;
+  e = hipMemset(q, 0, std::max<size_t>(bytes, 16));
+  c->allocs.push_back(q);
+  *p = q;
+  return e;
+}
 template <typename T>
 static hipError_t dmalloc(ifsvgp_ctx *c, T **p, size_t n) {
   void *q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
-  if (e != hipSuccess) return e;
-  e = hipMemset(q, 0, std::max<size_t>(n, 1) * sizeof(T));
-  c->allocs.push_back(q);
+  hipError_t e = dmalloc_bytes(c, &q, n * sizeof(T));
   *p = (T *)q;
   return e;
 }
 
+// bytes of the MFMA operand type and of the wide-range type used for the two
+// products with the backward matrix C (fp16 would overflow there, so the
+// fp16 form runs them in fp32)
 static size_t op_size(int prec) { return prec == IFSVGP_PREC_FP32 ? 4 : 2; }
+static size_t wide_size(int prec) { return prec == IFSVGP_PREC_BF16 ? 2 : 4; }
 
 // ------------------------------------------------------------------ GH rule (host)
-// Physicists' Hermite polynomials by the three-term recurrence
-//   H_{k+1}(t) = 2 t H_k(t) - 2 k H_{k-1}(t),
-// roots by Newton's method from asymptotic initial guesses, weights
-// w_k = 2^{n-1} n! sqrt(pi) / (n^2 H_{n-1}(t_k)^2), evaluated with the
-// normalised recurrence to avoid overflow.
+// Physicists' Gauss-Hermite rule: nodes are the roots of H_n, found by Newton's
+// method on the orthonormal three-term recurrence
+//   p_k(t) = sqrt(2/k) t p_{k-1}(t) - sqrt((k-1)/k) p_{k-2}(t),  p_0 = pi^{-1/4},
+// from asymptotic starting values; weights w = 2 / p_n'(t)^2 with
+// p_n' = sqrt(2n) p_{n-1}.
 extern "C" int ifsvgp_gh_rule(int n, double *nodes, double *weights) {
   if (n < 1 || n > 64 || !nodes || !weights) return IFSVGP_EINVAL;
   const double pim4 = 0.7511255444649425;  // pi^{-1/4}
@@ -132,14 +153,13 @@ extern "C" int ifsvgp_gh_rule(int n, double *nodes, double *weights) {
     else z = 2.0 * z - nodes[i - 2];
     double pp = 0.0;
     for (int it = 0; it < 100; ++it) {
-      // orthonormal recurrence: p_{k} = sqrt(2/k) t p_{k-1} - sqrt((k-1)/k) p_{k-2}
       double p1 = pim4, p2 = 0.0;
       for (int k = 1; k <= n; ++k) {
         const double p3 = p2;
         p2 = p1;
         p1 = z * std::sqrt(2.0 / k) * p2 - std::sqrt((k - 1.0) / k) * p3;
       }
-      pp = std::sqrt(2.0 * n) * p2;  // derivative of the orthonormal p_n
+      pp = std::sqrt(2.0 * n) * p2;
       const double z1 = z;
       z = z1 - p1 / pp;
       if (std::fabs(z - z1) <= 1e-15 * std::max(1.0, std::fabs(z))) break;
@@ -150,8 +170,7 @@ extern "C" int ifsvgp_gh_rule(int n, double *nodes, double *weights) {
     weights[n - 1 - i] = weights[i];
   }
   if (n % 2 == 1) nodes[m - 1] = 0.0;  // exact middle root
-  // return ascending order
-  for (int i = 0; i < n / 2; ++i) {
+  for (int i = 0; i < n / 2; ++i) {    // ascending order
     std::swap(nodes[i], nodes[n - 1 - i]);
     std::swap(weights[i], weights[n - 1 - i]);
   }
@@ -190,74 +209,92 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   if (!out || M < 1 || B_max < 1 || D < 1 || D > MAXD) return IFSVGP_EINVAL;
   if (prec < 0 || prec > 2 || lik < 0 || lik > 1) return IFSVGP_EINVAL;
   if (lik == IFSVGP_LIK_PROBIT && (n_gh < 1 || n_gh > 64)) return IFSVGP_EINVAL;
-  if ((long)M * M > (1L << 30) || (long)M * B_max > (1L << 31)) return IFSVGP_EINVAL;
+  if ((long)M > 32768 || (long)B_max > (1L << 24) || (long)M * B_max > (1L << 31))
+    return IFSVGP_EINVAL;
   ifsvgp_ctx *c = new (std::nothrow) ifsvgp_ctx();
   if (!c) return IFSVGP_ENOMEM;
   c->M = M; c->Bmax = B_max; c->D = D; c->prec = prec; c->lik = lik;
   c->ngh = lik == IFSVGP_LIK_PROBIT ? n_gh : 0;
-  c->Mp = rup(M, 64);
-  c->Bp = rup(B_max, 64);
-  c->nb64 = cdiv(M, 64);
-  c->nb128m = cdiv(M, 128);
-  c->nb128n = cdiv(B_max, 128);
-  c->nsplit = std::max(1, std::min(16, cdiv(B_max, 512)));
+  c->Mp = rup(M, PAD);
+  c->Bp = rup(B_max, PAD);
+  c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
-  const size_t MM = (size_t)M * c->Mp, MB = (size_t)M * c->Bp;
-  const size_t os = op_size(prec);
-  const int nt_sym64 = c->nb64 * (c->nb64 + 1) / 2;
-  const int nt_rect = c->nb128m * c->nb128n;
+  const size_t Mp = c->Mp, Bp = c->Bp;
+  const size_t MM = Mp * Mp, MB = Mp * Bp;
+  const size_t os = op_size(prec), ws = wide_size(prec);
+  const bool f32 = prec == IFSVGP_PREC_FP32;
+  const int nb64 = cdiv(M, 64), nb128 = cdiv(M, 128), nbB = cdiv(B_max, 128);
+  const int nt_sym64 = nb64 * (nb64 + 1) / 2;
   hipError_t e = hipSuccess;
 #define ALLOC(p, n) if (e == hipSuccess) e = dmalloc(c, &(p), (n))
+#define ALLOCB(p, bytes) if (e == hipSuccess) e = dmalloc_bytes(c, &(p), (bytes))
   ALLOC(c->Kt, MM);
-  ALLOC(c->Lw[0], MM);
-  ALLOC(c->Lw[1], MM);
-  ALLOC(c->Y, MM);
-  ALLOC(c->Wn, MM);
-  ALLOC(c->Q, MM);
-  ALLOC(c->Wu, MM);
-  ALLOC(c->Cm, MM);
-  ALLOC(c->Y2, MM);
+  ALLOC(c->L32[0], MM);
+  ALLOC(c->L32[1], MM);
+  ALLOC(c->W32, MM);
+  ALLOC(c->Q32, MM);
+  ALLOC(c->Wu32, MM);
   ALLOC(c->Ys, MM * c->nsplit);
-  {
-    unsigned char *k = nullptr, *v = nullptr, *u = nullptr;
-    ALLOC(k, MB * os);
-    ALLOC(v, MB * os);
-    ALLOC(u, MB * os);
-    c->Kuf = k; c->V = v; c->U = u;
+  if (f32) {
+    c->KtT = c->Kt; c->LT[0] = c->L32[0]; c->LT[1] = c->L32[1]; c->QT = c->Q32;
+  } else {
+    ALLOCB(c->KtT, MM * os);
+    ALLOCB(c->LT[0], MM * os);
+    ALLOCB(c->LT[1], MM * os);
+    ALLOCB(c->QT, MM * os);
   }
+  ALLOCB(c->LtT[0], MM * os);
+  ALLOCB(c->LtT[1], MM * os);
+  if (f32) {
+    c->Lt32[0] = (float *)c->LtT[0];
+    c->Lt32[1] = (float *)c->LtT[1];
+  } else {
+    ALLOC(c->Lt32[0], MM);
+    ALLOC(c->Lt32[1], MM);
+  }
+  ALLOCB(c->Yt, MM * os);
+  ALLOCB(c->Xgt, MM * os);
+  ALLOCB(c->Cm, MM * ws);
+  ALLOCB(c->Y2, MM * ws);
+  ALLOCB(c->Kft, MB * os);
+  ALLOCB(c->V, MB * os);
+  ALLOCB(c->Vt, MB * os);
+  ALLOCB(c->Ut, MB * os);
   ALLOC(c->Zs, (size_t)M * D);
   ALLOC(c->Xs, (size_t)B_max * D);
   ALLOC(c->inv_ell, (size_t)D);
-  ALLOC(c->va, (size_t)c->Mp);
-  ALLOC(c->vb, (size_t)c->Mp);
-  ALLOC(c->vLb, (size_t)c->Mp);
-  ALLOC(c->vWub, (size_t)c->Mp);
-  ALLOC(c->vVa, (size_t)c->Mp);
-  ALLOC(c->vt1, (size_t)c->Mp);
-  ALLOC(c->vt2, (size_t)c->Mp);
-  ALLOC(c->vpart, (size_t)c->nb64 * c->Mp);
-  ALLOC(c->mu_part, (size_t)c->nb64 * c->Bp);
-  ALLOC(c->var_part, (size_t)c->nb128m * c->Bp);
-  ALLOC(c->mu, (size_t)c->Bp);
-  ALLOC(c->var, (size_t)c->Bp);
-  ALLOC(c->alpha, (size_t)c->Bp);
-  ALLOC(c->beta, (size_t)c->Bp);
-  ALLOC(c->sqnb, (size_t)c->Bp);
-  ALLOC(c->hrow, (size_t)c->nb128n * M);
-  ALLOC(c->hcol, (size_t)c->nb128m * c->Bp);
-  ALLOC(c->hx, (size_t)c->nb128n * M * D);
-  ALLOC(c->hzrow, (size_t)c->nb64 * M);
-  ALLOC(c->hz, (size_t)c->nb64 * M * D);
+  ALLOC(c->sP, Mp);
+  ALLOC(c->va, Mp);
+  ALLOC(c->vb, Mp);
+  ALLOC(c->vLb, Mp);
+  ALLOC(c->vWub, Mp);
+  ALLOC(c->vVa, Mp);
+  ALLOC(c->vt2, Mp);
+  ALLOC(c->mu_part, (size_t)nb64 * Bp);
+  ALLOC(c->var_part, (size_t)nb128 * Bp);
+  ALLOC(c->mu, Bp);
+  ALLOC(c->var, Bp);
+  ALLOC(c->alpha, Bp);
+  ALLOC(c->beta, Bp);
+  ALLOC(c->sqnb, Bp);
+  ALLOC(c->hrow, (size_t)nbB * M);
+  ALLOC(c->hcol, (size_t)nb128 * Bp);
+  ALLOC(c->hx, (size_t)nbB * M * D);
+  ALLOC(c->hzrow, (size_t)nb64 * M);
+  ALLOC(c->hz, (size_t)nb64 * M * D);
   ALLOC(c->scal, (size_t)S_NSLOT);
   ALLOC(c->tp_ng, (size_t)nt_sym64);
   ALLOC(c->tp_gram, (size_t)3 * nt_sym64);
-  ALLOC(c->tp_uf, (size_t)nt_rect);
+  ALLOC(c->tp_uf, (size_t)nb128 * nbB);
   ALLOC(c->tp_uu, (size_t)nt_sym64);
-  ALLOC(c->lik_part, (size_t)4 * cdiv(B_max, NTB));
-  ALLOC(c->ell_part, (size_t)(cdiv(M, 64) + cdiv(B_max, 64)) * D);
+  ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
+  ALLOC(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
+  ALLOC(c->ell_part, (size_t)(M + B_max + 64) * D);
   ALLOC(c->gh, (size_t)2 * std::max(1, c->ngh));
   ALLOC(c->flag, (size_t)1);
+  ALLOC(c->counters, (size_t)CNT_N);
 #undef ALLOC
+#undef ALLOCB
   if (e == hipSuccess && c->ngh > 0) {
     std::vector<double> g(2 * c->ngh);
     ifsvgp_gh_rule(c->ngh, g.data(), g.data() + c->ngh);
@@ -269,7 +306,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
     return code;
   }
   c->fwd_valid = 0;
-  c->cur_L = 0;
+  c->cur = 0;
   c->timing = 0;
   for (int k = 0; k < KK_N; ++k) { c->t_ms[k] = 0.0; c->t_cnt[k] = 0; }
   *out = c;
@@ -331,7 +368,7 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
   if (!c || !flops) return IFSVGP_EINVAL;
   const double M = c->M, Bd = B, D = c->D;
   double f[KK_N] = {0};
-  f[KK_NG_Y] = 2.0 * M * M * M / 3.0;   // lower part of K~ L, sum_{l>=j} over k>=j
+  f[KK_NG_Y] = 2.0 * M * M * M / 3.0;   // lower part of K~ L: sum_{l>=j} for k>=j
   f[KK_NG_W] = M * M * M / 3.0;         // lower part of L^T Y
   f[KK_NG_L] = M * M * M / 3.0;         // L X, both lower triangular
   f[KK_GR_Y] = 2.0 * M * M * M / 3.0;
@@ -340,7 +377,7 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
   f[KK_V] = M * M * Bd;                 // L^T K_uf, triangular
   f[KK_U] = 2.0 * M * M * Bd;           // Q V
   f[KK_R] = M * M * Bd + 2.0 * M * Bd * D;  // L U (+ H X)
-  f[KK_SYRK] = M * M * Bd;              // lower half of V diag(beta) V^T
+  f[KK_SYRK] = M * M * Bd;              // lower half of (V D)(V D)^T
   f[KK_Y2] = M * M * M;                 // L C
   f[KK_GUU] = M * M * M / 3.0 + 2.0 * M * M * D;  // lower half of Y2 L^T (+ H Z)
   f[KK_KUF] = 3.0 * M * Bd * D;
@@ -355,228 +392,194 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
 // ------------------------------------------------------------------ GEMM wrappers
 template <typename T>
 struct Ops {
-  using CS = Cfg<64, 64, 2, 2, 2, T>;    // M x M products
-  using CR = Cfg<128, 128, 2, 2, 2, T>;  // M x B products
-  // The two products with the backward matrix C (whose entries grow like
-  // B / noise_var) need fp32's exponent range: fp16 operands would overflow,
-  // so the fp16 form runs them on bf16 MFMA.
-  using TW = typename std::conditional<std::is_same<T, _Float16>::value, __bf16, T>::type;
-  using CSW = Cfg<64, 64, 2, 2, 2, TW>;
+  // TW: operand type of the two products with C (fp32 in the fp16 form)
+  using TW = typename std::conditional<std::is_same<T, _Float16>::value, float, T>::type;
+  using CS = Cfg<64, 64, 2, 2, T>;     // M x M products
+  using CSW = Cfg<64, 64, 2, 2, TW>;
+  using CR = Cfg<128, 128, 2, 2, T>;   // M x B products
 
-  // Y = K~ L (lower tiles), k >= n0
-  static hipError_t ng_Y(ifsvgp_ctx *c, const float *L, float *Y) {
-    const int M = c->M;
-    Ld<float, true, XfNone> la{c->Kt, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfLower> lb{L, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_LO_N0};
-    EpiStore<float> e{Y, c->Mp, M, M, 0, 0};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+  static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
+  static T *LtT(ifsvgp_ctx *c, int i) { return (T *)c->LtT[i]; }
+  static TW *LW(ifsvgp_ctx *c, int i) {
+    return std::is_same<TW, T>::value ? (TW *)c->LT[i] : (TW *)c->L32[i];
   }
-  // W = L^T Y (lower tiles), k >= m0, with residual partials
-  static hipError_t ng_W(ifsvgp_ctx *c, const float *L) {
-    const int M = c->M;
-    Ld<float, false, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfNone> lb{c->Y, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_LO_M0};
-    EpiNgGram e{c->Wn, c->Mp, M, c->tp_ng};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+  static int nb(ifsvgp_ctx *c) { return cdiv(c->M, 64); }
+
+  // Y = K~ L on lower tiles (k >= n0), stored transposed: Yt[j][i] = Y[i][j]
+  static hipError_t gram_Y(ifsvgp_ctx *c, int cur) {
+    Opnd<T> a{(const T *)c->KtT, c->Mp, nullptr}, b{LtT(c, cur), c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0};
+    EpiStoreT<T> e{(T *)c->Yt, c->Mp, c->M, c->M};
+    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
   }
-  // Lnew = L - gamma L X(W), lower tiles, n0 <= k < m0+BM
-  static hipError_t ng_L(ifsvgp_ctx *c, const float *L, float *Ln, float gamma) {
-    const int M = c->M;
-    Ld<float, true, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfNatgrad> lb{c->Wn, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_LO_N0 | K_HI_M1};
-    EpiNgUpdate e{L, c->Mp, Ln, c->Mp, M, gamma};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+  // W = L^T Y on lower tiles (k >= m0) -> natural-gradient factor + residual
+  static hipError_t ng_W(ifsvgp_ctx *c, int cur) {
+    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Yt, c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
+    EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
+    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
   }
-  // W' = L^T Y (lower tiles, plain store)
-  static hipError_t gr_W(ifsvgp_ctx *c, const float *L) {
-    const int M = c->M;
-    Ld<float, false, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfNone> lb{c->Y, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_LO_M0};
-    EpiStore<float> e{c->Wn, c->Mp, M, M, 0, 0};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+  // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM; also the residual of
+  // this step and (Lout non-null) the caller's L
+  static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, float gamma, float *Lout,
+                         double *resid_out) {
+    Opnd<T> a{LT(c, cur), c->Mp, nullptr}, b{(const T *)c->Xgt, c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0 | K_HI_M1};
+    EpiNgUpdate<T> e{c->L32[cur], c->L32[nxt], c->Lt32[nxt], LT(c, nxt), LtT(c, nxt),
+                     c->Mp, c->M, gamma, Lout, c->tp_ng, nb(c) * (nb(c) + 1) / 2,
+                     resid_out, c->scal};
+    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
+  }
+  // W' = L^T Y (lower tiles, fp32)
+  static hipError_t gr_W(ifsvgp_ctx *c, int cur) {
+    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Yt, c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
+    EpiStore<float> e{c->W32, c->Mp, c->M, c->M, 0, 0};
+    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
   }
   // E' = L^T diag(s) L (lower tiles) -> Q, Wu, gram partials
-  static hipError_t gr_E(ifsvgp_ctx *c, const float *L, const float *s) {
-    const int M = c->M;
-    Ld<float, false, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfLowerScaleRow> lb{L, c->Mp, M, M, 1, {s}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_LO_M0};
-    EpiBoundGram e{c->Wn, c->Q, c->Wu, c->Mp, M, c->tp_gram};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+  static hipError_t gr_E(ifsvgp_ctx *c, int cur) {
+    Opnd<T> a{LtT(c, cur), c->Mp, c->sP}, b{LtT(c, cur), c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
+    EpiBoundGram<T> e{c->W32, c->Q32, c->Wu32, (T *)c->QT, c->Mp, c->M, c->tp_gram};
+    return launch_gemm<CS, true, false>(c->st, a, b, sc, e);
   }
-  // V = L^T K_uf, k >= m0
-  static hipError_t gemm_V(ifsvgp_ctx *c, const float *L, int B) {
-    const int M = c->M;
-    Ld<float, false, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<T, false, XfNone> lb{(const T *)c->Kuf, c->Bp, M, B, 1, {}};
-    Sched sc{cdiv(M, 128), cdiv(B, 128), 0, 1, M, K_LO_M0};
-    EpiStore<T> e{(T *)c->V, c->Bp, M, B, 0, 0};
-    return launch_gemm<CR>(c->st, la, lb, sc, e);
+  // V = L^T K_uf (k >= m0) -> V, Vt
+  static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
+    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Kft, c->Mp, nullptr};
+    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_LO_M0};
+    EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
+    return launch_gemm<CR, false, false>(c->st, a, b, sc, e);
   }
-  // U = Q V, sigma^2 partials
+  // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
-    const int M = c->M;
-    Ld<float, true, XfNone> la{c->Q, c->Mp, M, M, 1, {}};
-    Ld<T, false, XfNone> lb{(const T *)c->V, c->Bp, M, B, 1, {}};
-    Sched sc{cdiv(M, 128), cdiv(B, 128), 0, 1, M, 0};
-    EpiU<T> e{(T *)c->U, (const T *)c->V, c->Bp, M, B, c->var_part, c->Bp};
-    return launch_gemm<CR>(c->st, la, lb, sc, e);
+    Opnd<T> a{(const T *)c->QT, c->Mp, nullptr}, b{(const T *)c->Vt, c->Mp, nullptr};
+    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, 0};
+    EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->Bp, c->Mp, c->M, B, c->var_part, c->Bp};
+    return launch_gemm<CR, false, false>(c->st, a, b, sc, e);
   }
-  // R = L U -> H_uf reductions
-  static hipError_t gemm_R(ifsvgp_ctx *c, const float *L, int B, const float *sf2) {
-    const int M = c->M, D = c->D;
-    Ld<float, true, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<T, false, XfNone> lb{(const T *)c->U, c->Bp, M, B, 1, {}};
-    Sched sc{cdiv(M, 128), cdiv(B, 128), 0, 1, M, K_HI_M1};
-    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, M, B, D,
+  // R = L U (k < m0+BM) -> H_uf reductions
+  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *sf2) {
+    const int D = c->D;
+    Opnd<T> a{LT(c, cur), c->Mp, nullptr}, b{(const T *)c->Ut, c->Mp, nullptr};
+    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
+    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
     const int D4 = (D + 3) & ~3;
-    return launch_gemm<CR>(c->st, la, lb, sc, e, (CR::BM + CR::BN) * D4 * 4);
+    return launch_gemm<CR, false, false>(c->st, a, b, sc, e, (CR::BM + CR::BN) * D4 * 4);
   }
-  // Ys[s] = (V_s D)(V_s D)^T with D = diag(sqrt(-beta)), i.e. -V diag(beta) V^T
-  // (lower tiles, split-K over the batch).  beta <= 0 for log-concave
-  // likelihoods (Gaussian, probit), so the split keeps both operands at the
-  // scale sqrt(|beta|) |V| instead of |beta| |V|.
+  // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
+  // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
+  // log-concave Gaussian and probit likelihoods.
+  static int syrk_splits(ifsvgp_ctx *c, int B) {
+    return std::max(1, std::min(c->nsplit, cdiv(B, 4 * CS::BK)));
+  }
   static hipError_t syrk(ifsvgp_ctx *c, int B) {
-    const int M = c->M;
-    Ld<T, true, XfScaleCol> la{(const T *)c->V, c->Bp, M, B, 1, {c->sqnb}};
-    Ld<T, true, XfScaleCol> lb{(const T *)c->V, c->Bp, M, B, 1, {c->sqnb}};
-    const int ns = std::max(1, std::min(c->nsplit, cdiv(B, CS::BK)));
-    Sched sc{c->nb64, c->nb64, 1, ns, B, 0};
-    EpiStore<float> e{c->Ys, c->Mp, M, M, 0, (long)M * c->Mp};
-    return launch_gemm<CS>(c->st, la, lb, sc, e);
+    Opnd<T> a{(const T *)c->V, c->Bp, c->sqnb}, b{(const T *)c->V, c->Bp, c->sqnb};
+    Sched sc{nb(c), nb(c), 1, syrk_splits(c, B), B, 0};
+    EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, 1, (long)c->Mp * c->Mp};
+    return launch_gemm<CS, true, true>(c->st, a, b, sc, e);
   }
-  // Y2 = L C, k < m0+BM
-  static hipError_t gemm_Y2(ifsvgp_ctx *c, const float *L) {
-    const int M = c->M;
-    Ld<float, true, XfLower> la{L, c->Mp, M, M, 1, {}};
-    Ld<float, false, XfNone> lb{c->Cm, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 0, 1, M, K_HI_M1};
-    EpiStore<float> e{c->Y2, c->Mp, M, M, 0, 0};
-    return launch_gemm<CSW>(c->st, la, lb, sc, e);
+  // Y2 = L C (k < m0+BM), C symmetric
+  static hipError_t gemm_Y2(ifsvgp_ctx *c, int cur) {
+    Opnd<TW> a{LW(c, cur), c->Mp, nullptr}, b{(const TW *)c->Cm, c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 0, 1, c->M, K_HI_M1};
+    EpiStore<TW> e{(TW *)c->Y2, c->Mp, c->M, c->M, 0, 0};
+    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e);
   }
-  // G_uu = Y2 L^T (lower tiles), k < n0+BN -> H_uu reductions
-  static hipError_t gemm_Guu(ifsvgp_ctx *c, const float *L, const float *s) {
-    const int M = c->M, D = c->D;
-    Ld<float, true, XfNone> la{c->Y2, c->Mp, M, M, 1, {}};
-    Ld<float, true, XfLower> lb{L, c->Mp, M, M, 1, {}};
-    Sched sc{c->nb64, c->nb64, 1, 1, M, K_HI_N1};
-    EpiGradUu e{c->Kt, s, c->Zs, c->Mp, M, D, c->hz, c->hzrow, c->tp_uu};
+  // G_uu = Y2 L^T (lower tiles, k < n0+BN) -> H_uu reductions
+  static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s) {
+    const int D = c->D;
+    Opnd<TW> a{(const TW *)c->Y2, c->Mp, nullptr}, b{LW(c, cur), c->Mp, nullptr};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
+    EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu};
     const int D4 = (D + 3) & ~3;
-    return launch_gemm<CSW>(c->st, la, lb, sc, e, 2 * CSW::BM * D4 * 4);
+    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e, 2 * CSW::BM * D4 * 4);
   }
 };
 
 // ------------------------------------------------------------------ stages
-static int grid1(long n) { return (int)std::min<long>(std::max<long>(1, (n + NTB - 1) / NTB), 65536); }
-
-static int stage_kernel_blocks(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
-                               const float *noise, const float *s, int need_noise) {
-  const int M = c->M, D = c->D;
-  {
-    Timed t(c, KK_PREP);
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(NTB), 0, c->st, ell, sf2, noise, s, M, D,
-                       need_noise, c->inv_ell, c->scal, c->flag);
-    hipLaunchKernelGGL(k_scale_rows, dim3(grid1((long)M * D)), dim3(NTB), 0, c->st, Z, M, D,
-                       (const float *)c->inv_ell, c->Zs);
-  }
-  {
-    Timed t(c, KK_KUU);
-    hipLaunchKernelGGL(k_kuu<MAXD>, dim3(cdiv(M, 16), cdiv(M, 16)), dim3(NTB), 0, c->st,
-                       (const float *)c->Zs, M, D, sf2, s, c->Kt, (long)c->Mp);
-  }
+template <typename T>
+static int stage_setup(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
+                       const float *noise, const float *s, int need_noise, const float *Lin) {
+  const int M = c->M;
+  Timed t(c, KK_PREP);
+  SetupArgs a;
+  a.Z = Z; a.ell = ell; a.sf2 = sf2; a.noise = noise; a.s = s;
+  a.M = M; a.D = c->D; a.need_noise = need_noise;
+  a.Zs = c->Zs; a.inv_ell = c->inv_ell; a.sP = c->sP; a.Kt = c->Kt; a.KtT = c->KtT;
+  a.ld = c->Mp;
+  a.Lin = Lin;
+  a.L32 = c->L32[0]; a.Lt32 = c->Lt32[0]; a.LT = c->LT[0]; a.LtT = c->LtT[0];
+  a.scal = c->scal; a.flag = c->flag;
+  a.nKx = cdiv(M, 16);
+  a.nK = a.nKx * a.nKx;
+  a.nLx = cdiv(M, 32);
+  const int nL = Lin ? a.nLx * a.nLx : 0;
+  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + nL), dim3(NTB), 0, c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
 
+// n_ng natural-gradient steps from slot 0; the last writes the caller's L.
 template <typename T>
-static int stage_natgrad(ifsvgp_ctx *c, const float *L_in, const float *gammas, int n_ng,
+static int stage_natgrad(ifsvgp_ctx *c, float *Lcaller, const float *gammas, int n_ng,
                          double *out_resid) {
-  const int M = c->M;
-  {
-    Timed t(c, KK_COPYL);
-    hipLaunchKernelGGL(k_copy_lower, dim3(grid1((long)M * M)), dim3(NTB), 0, c->st, L_in,
-                       (long)M, c->Lw[0], (long)c->Mp, M);
-  }
   int cur = 0;
-  const int nt = c->nb64 * (c->nb64 + 1) / 2;
   for (int s = 0; s < n_ng; ++s) {
-    { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::ng_Y(c, c->Lw[cur], c->Y)); }
-    { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, c->Lw[cur])); }
-    { Timed t(c, KK_NG_L); HIPCK(Ops<T>::ng_L(c, c->Lw[cur], c->Lw[1 - cur], gammas[s])); }
+    { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
+    { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, cur)); }
     {
-      Timed t(c, KK_RESID);
-      hipLaunchKernelGGL(k_resid, dim3(1), dim3(NTB), 0, c->st, (const double *)c->tp_ng, nt, M,
-                         out_resid ? out_resid + s : (double *)nullptr, c->scal);
+      Timed t(c, KK_NG_L);
+      HIPCK(Ops<T>::ng_L(c, cur, 1 - cur, gammas[s], s == n_ng - 1 ? Lcaller : nullptr,
+                         out_resid ? out_resid + s : nullptr));
     }
     cur = 1 - cur;
   }
-  c->cur_L = cur;
-  HIPCK(hipGetLastError());
+  c->cur = cur;
   return IFSVGP_OK;
 }
 
 template <typename T>
 static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
-                       const float *sf2, const float *noise, const float *m, const float *s,
+                       const float *sf2, const float *noise, const float *m,
                        double *out_bound, double *out_terms) {
-  const int M = c->M, D = c->D;
-  const float *L = c->Lw[c->cur_L];
+  const int M = c->M, D = c->D, cur = c->cur;
+  const float *L = c->L32[cur];
   const long Mp = c->Mp;
-  { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::ng_Y(c, L, c->Y)); }
-  { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, L)); }
-  { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, L, s)); }
+  { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
+  { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, cur)); }
+  { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, cur)); }
   {
     Timed t(c, KK_VEC);
-    const int nch = cdiv(M, 64);
-    // a = L^T m~
-    hipLaunchKernelGGL(k_gemv_cols_part, dim3(cdiv(M, NTB), nch), dim3(NTB), 0, c->st, L, Mp, M,
-                       M, m, 1, c->vpart, Mp);
-    hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(M, NTB)), dim3(NTB), 0, c->st,
-                       (const float *)c->vpart, Mp, nch, M, c->va);
-    // b = Q a
-    hipLaunchKernelGGL(k_gemv_rows<float>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
-                       (const float *)c->Q, Mp, M, M, (const float *)c->va, 0, 1.f,
-                       (const float *)nullptr, 0.f, c->vb);
-    // Lb = L b
-    hipLaunchKernelGGL(k_gemv_rows<float>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st, L, Mp, M,
-                       M, (const float *)c->vb, 1, 1.f, (const float *)nullptr, 0.f, c->vLb);
-    // Wub = Wu b
-    hipLaunchKernelGGL(k_gemv_rows<float>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
-                       (const float *)c->Wu, Mp, M, M, (const float *)c->vb, 0, 1.f,
-                       (const float *)nullptr, 0.f, c->vWub);
-    hipLaunchKernelGGL(k_kl_scalars, dim3(1), dim3(NTB), 0, c->st, (const float *)c->vb,
-                       (const float *)c->vWub, L, Mp, M, c->scal, c->flag);
+    const int rows = cdiv(M, NTB / 64);
+    // a = L^T m~ (rows of the fp32 transpose), b = Q a
+    hipLaunchKernelGGL(k_gemv_rows, dim3(rows), dim3(NTB), 0, c->st, (const float *)c->Lt32[cur],
+                       Mp, M, M, m, 0, (const double *)nullptr, c->va);
+    hipLaunchKernelGGL(k_gemv_rows, dim3(rows), dim3(NTB), 0, c->st, (const float *)c->Q32, Mp,
+                       M, M, (const float *)c->va, 0, (const double *)nullptr, c->vb);
+    // Lb = L b, Wub = Wu b, with partials of quad and log|T|
+    hipLaunchKernelGGL(k_vec_lb_wub, dim3(cdiv(2 * M, NTB / 64)), dim3(NTB), 0, c->st, L,
+                       (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
+                       c->vec_part, c->flag);
   }
   {
     Timed t(c, KK_KUF);
-    hipLaunchKernelGGL(k_scale_rows, dim3(grid1((long)B * D)), dim3(NTB), 0, c->st, X, B, D,
-                       (const float *)c->inv_ell, c->Xs);
     hipLaunchKernelGGL((k_kuf<MAXD, T>), dim3(cdiv(B, 64), cdiv(M, 64)), dim3(NTB), 0, c->st,
-                       (const float *)c->Zs, (const float *)c->Xs, M, B, D, sf2,
-                       (const float *)c->vLb, (T *)c->Kuf, (long)c->Bp, c->mu_part,
-                       (long)c->Bp);
+                       (const float *)c->Zs, X, (const float *)c->inv_ell, M, B, D, sf2,
+                       (const float *)c->vLb, c->Xs, (T *)c->Kft, Mp, c->mu_part, (long)c->Bp);
   }
-  { Timed t(c, KK_V); HIPCK(Ops<T>::gemm_V(c, L, B)); }
+  { Timed t(c, KK_V); HIPCK(Ops<T>::gemm_V(c, cur, B)); }
   { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
-  const int nlik = cdiv(B, NTB);
   {
     Timed t(c, KK_LIK);
+    const int nb = cdiv(M, 64);
     LikArgs a{c->mu_part, cdiv(M, 64), c->var_part, cdiv(M, 128), (long)c->Bp,
-              y, B, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
-              c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part};
-    hipLaunchKernelGGL(k_lik, dim3(nlik), dim3(NTB), 0, c->st, a);
-  }
-  {
-    Timed t(c, KK_FIN);
-    const int nt = c->nb64 * (c->nb64 + 1) / 2;
-    hipLaunchKernelGGL(k_finalize_bound, dim3(1), dim3(NTB), 0, c->st,
-                       (const double *)c->tp_gram, nt, (const double *)c->lik_part, nlik,
-                       (const double *)c->scal, M, N / (double)B, out_bound, out_terms, c->flag);
+              y, B, c->Bp, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
+              c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
+              c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
+              c->scal, M, out_bound, out_terms, c->flag, c->counters + CNT_LIK};
+    hipLaunchKernelGGL(k_lik, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
   }
   HIPCK(hipGetLastError());
   c->fwd_valid = 1;
@@ -588,10 +591,10 @@ template <typename T>
 static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, const float *s,
                           const double *grad_scale, float *g_ell, float *g_sf2, float *g_noise,
                           float *g_Z, float *g_m) {
-  const int M = c->M, D = c->D;
-  const float *L = c->Lw[c->cur_L];
+  using TW = typename Ops<T>::TW;
+  const int M = c->M, D = c->D, cur = c->cur;
   const long Mp = c->Mp;
-  { Timed t(c, KK_R); HIPCK(Ops<T>::gemm_R(c, L, B, sf2)); }
+  { Timed t(c, KK_R); HIPCK(Ops<T>::gemm_R(c, cur, B, sf2)); }
   {
     Timed t(c, KK_VALPHA);
     hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
@@ -600,39 +603,30 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
   { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B)); }
   {
     Timed t(c, KK_ASM);
-    const int ns = std::max(1, std::min(c->nsplit, cdiv(B, Ops<T>::CS::BK)));
-    hipLaunchKernelGGL(k_assemble_C, dim3(grid1((long)M * M)), dim3(NTB), 0, c->st,
-                       (const float *)c->Ys, ns, (long)M * Mp, (const float *)c->Wu,
-                       (const float *)c->Q, (const float *)c->va, (const float *)c->vb,
-                       (const float *)c->vWub, (const float *)c->vVa, M, Mp, c->Cm);
+    hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * M)), dim3(NTB), 0, c->st,
+                       (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
+                       (const float *)c->Wu32, (const float *)c->Q32, (const float *)c->va,
+                       (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M,
+                       Mp, (TW *)c->Cm);
   }
-  { Timed t(c, KK_Y2); HIPCK(Ops<T>::gemm_Y2(c, L)); }
-  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, L, s)); }
+  { Timed t(c, KK_Y2); HIPCK(Ops<T>::gemm_Y2(c, cur)); }
+  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, s)); }
   {
     Timed t(c, KK_GRAD);
-    const int rb = cdiv(M, 64), cb = cdiv(B, 64);
+    const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
+    const int R = NTB / D;
+    const int rb = cdiv(M, R), cb = cdiv(B, R), rq = cdiv(M, NTB / 64);
     GradArgs g{M, B, D, c->Zs, c->Xs, c->inv_ell, sf2,
-               c->hrow, cdiv(B, 128), c->hx, c->hcol, cdiv(M, 128), (long)c->Bp,
-               c->hzrow, c->hz, c->nb64,
-               c->tp_uf, cdiv(M, 128) * cdiv(B, 128), c->tp_uu, c->nb64 * (c->nb64 + 1) / 2,
-               c->lik_part, cdiv(B, NTB), N / (double)B, grad_scale,
-               g_Z, g_ell, g_sf2, g_noise, c->ell_part};
-    hipLaunchKernelGGL(k_grad_rows, dim3(rb), dim3(NTB), 0, c->st, g);
-    hipLaunchKernelGGL(k_grad_cols, dim3(cb), dim3(NTB), 0, c->st, g, rb);
-    hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(NTB), 0, c->st, g, rb + cb);
-    if (g_m) {
-      // dF/dm~ = L Q (V alpha - Wu b)
-      hipLaunchKernelGGL(k_sub_vec, dim3(cdiv(M, NTB)), dim3(NTB), 0, c->st,
-                         (const float *)c->vVa, (const float *)c->vWub, M, c->vt1);
-      hipLaunchKernelGGL(k_gemv_rows<float>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
-                         (const float *)c->Q, Mp, M, M, (const float *)c->vt1, 0, 1.f,
-                         (const float *)nullptr, 0.f, c->vt2);
-      hipLaunchKernelGGL(k_gemv_rows<float>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st, L,
-                         Mp, M, M, (const float *)c->vt2, 1, 1.f, (const float *)nullptr, 0.f,
-                         c->vt1);
-      hipLaunchKernelGGL(k_scale_vec, dim3(cdiv(M, NTB)), dim3(NTB), 0, c->st,
-                         (const float *)c->vt1, M, grad_scale, g_m);
-    }
+               c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
+               c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
+               c->lik_part, cdiv(c->Bp, NTB),
+               c->Q32, c->vVa, c->vWub, Mp, c->vt2,
+               N / (double)B, grad_scale, g_Z, g_ell, g_sf2, g_noise, c->ell_part, rb, cb};
+    hipLaunchKernelGGL(k_grad, dim3(rb + cb + rq), dim3(NTB), 0, c->st, g);
+    // dF/dm~ = L t2, t2 = Q (V alpha - Wu b), and the scalar gradients
+    const int mrows = g_m ? cdiv(M, NTB / 64) : 0;
+    hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
+                       (const float *)c->L32[cur], g_m, mrows);
   }
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
@@ -647,16 +641,10 @@ static bool bad_common(ifsvgp_ctx *c, const float *ell, const float *sf2, const 
 template <typename T>
 static int do_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
                       const float *s, float *L, const float *gammas, int n_ng, double *out_resid) {
-  int r = stage_kernel_blocks(c, Z, ell, sf2, nullptr, s, 0);
+  int r = stage_setup<T>(c, Z, ell, sf2, nullptr, s, 0, L);
   if (r) return r;
-  r = stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
-  if (r) return r;
-  Timed t(c, KK_STOREL);
-  hipLaunchKernelGGL(k_store_lower, dim3(grid1((long)c->M * c->M)), dim3(NTB), 0, c->st,
-                     (const float *)c->Lw[c->cur_L], (long)c->Mp, L, (long)c->M, c->M);
-  HIPCK(hipGetLastError());
   c->fwd_valid = 0;
-  return IFSVGP_OK;
+  return stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
 }
 
 extern "C" int ifsvgp_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
@@ -689,11 +677,11 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
   const int need_noise = c->lik == IFSVGP_LIK_GAUSSIAN;
   int r;
   if (fwd) {
-    r = stage_kernel_blocks(c, Z, ell, sf2, noise, s, need_noise);
+    r = stage_setup<T>(c, Z, ell, sf2, noise, s, need_noise, L);
     if (r) return r;
     r = stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
     if (r) return r;
-    r = stage_bound<T>(c, X, y, B, N, sf2, noise, m, s, out_bound, out_terms);
+    r = stage_bound<T>(c, X, y, B, N, sf2, noise, m, out_bound, out_terms);
     if (r) return r;
   }
   if (bwd) {
@@ -701,24 +689,15 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
     r = stage_backward<T>(c, B, N, sf2, s, grad_scale, g_ell, g_sf2, g_noise, g_Z, g_m);
     if (r) return r;
   }
-  if (fwd && n_ng > 0) {
-    Timed t(c, KK_STOREL);
-    hipLaunchKernelGGL(k_store_lower, dim3(grid1((long)c->M * c->M)), dim3(NTB), 0, c->st,
-                       (const float *)c->Lw[c->cur_L], (long)c->Mp, L, (long)c->M, c->M);
-    HIPCK(hipGetLastError());
-  }
   return IFSVGP_OK;
 }
 
-template <typename T>
-static int bound_impl(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
-                      const float *ell, const float *sf2, const float *noise, const float *Z,
-                      const float *m, const float *s, const float *L, double *out_bound,
-                      double *out_terms) {
-  return do_step<T>(c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0, out_bound,
-                    out_terms, nullptr, true, false, nullptr, nullptr, nullptr, nullptr, nullptr,
-                    nullptr);
-}
+#define PREC_DISPATCH(fn, ...)                                     \
+  switch (c->prec) {                                               \
+    case IFSVGP_PREC_FP32: return fn<float>(__VA_ARGS__);          \
+    case IFSVGP_PREC_BF16: return fn<__bf16>(__VA_ARGS__);         \
+    default: return fn<_Float16>(__VA_ARGS__);                     \
+  }
 
 extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
                             const float *ell, const float *sf2, const float *noise,
@@ -727,11 +706,9 @@ extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
   if (!out_bound) return IFSVGP_EINVAL;
-  switch (c->prec) {
-    case IFSVGP_PREC_FP32: return bound_impl<float>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, out_bound, out_terms);
-    case IFSVGP_PREC_BF16: return bound_impl<__bf16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, out_bound, out_terms);
-    default: return bound_impl<_Float16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, out_bound, out_terms);
-  }
+  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
+                out_bound, out_terms, nullptr, true, false, nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr)
 }
 
 extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -741,21 +718,10 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
                                 float *g_noise, float *g_Z, float *g_m, float *g_s) {
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
-  if (g_s) return IFSVGP_EINVAL;  // gradient w.r.t. s~ not provided by this build
-  switch (c->prec) {
-    case IFSVGP_PREC_FP32:
-      return do_step<float>(c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
-                            nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2,
-                            g_noise, g_Z, g_m);
-    case IFSVGP_PREC_BF16:
-      return do_step<__bf16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
-                             nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2,
-                             g_noise, g_Z, g_m);
-    default:
-      return do_step<_Float16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
-                               nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2,
-                               g_noise, g_Z, g_m);
-  }
+  if (g_s) return IFSVGP_EINVAL;  // gradient w.r.t. s~ is not provided by this library
+  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
+                nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2, g_noise, g_Z,
+                g_m)
 }
 
 extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -768,18 +734,6 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   if (r) return r;
   if (n_ng < 0 || (n_ng > 0 && !gammas) || !out_bound) return IFSVGP_EINVAL;
   if (g_s) return IFSVGP_EINVAL;
-  switch (c->prec) {
-    case IFSVGP_PREC_FP32:
-      return do_step<float>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng, out_bound,
-                            out_terms, out_resid, true, true, nullptr, g_ell, g_sf2, g_noise,
-                            g_Z, g_m);
-    case IFSVGP_PREC_BF16:
-      return do_step<__bf16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng,
-                             out_bound, out_terms, out_resid, true, true, nullptr, g_ell, g_sf2,
-                             g_noise, g_Z, g_m);
-    default:
-      return do_step<_Float16>(c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng,
-                               out_bound, out_terms, out_resid, true, true, nullptr, g_ell,
-                               g_sf2, g_noise, g_Z, g_m);
-  }
+  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng, out_bound,
+                out_terms, out_resid, true, true, nullptr, g_ell, g_sf2, g_noise, g_Z, g_m)
 }

@@ -1,5 +1,8 @@
-// Non-GEMM kernels of the iteration: input scaling, kernel-matrix generation,
-// matrix-vector products, likelihood expectations, fp64 finalisation.
+// Non-GEMM kernels of the iteration: set-up (validation, kernel matrix, layout
+// copies), K_uf generation, matrix-vector products, likelihood expectations
+// with the fp64 finalisation of the bound, and the gradient reductions.
+// Small reductions finish in the last workgroup of the producing kernel
+// (device-scope fence + atomic arrival counter; no workgroup ever waits).
 #pragma once
 #include "common.hpp"
 
@@ -14,96 +17,169 @@ enum : int {
   S_NSLOT = 8
 };
 
-// ---------------------------------------------------------------- validation
-// Domain checks, 1/ell and sum log s~ (one block).
-__global__ void k_prep(const float *ell, const float *sf2, const float *noise, const float *s,
-                       int M, int D, int need_noise, float *inv_ell, double *scal, int *flag) {
-  __shared__ double sh[NTB / 64];
-  int bad = 0;
-  for (int d = threadIdx.x; d < D; d += NTB) {
-    const float l = ell[d];
-    if (!(l > 0.f) || !isfinite(l)) bad = 1;
-    inv_ell[d] = 1.0f / l;
-  }
+// Arrival counters (one int each, reset to 0 by the last arriving workgroup).
+enum : int { CNT_VEC = 0, CNT_LIK = 1, CNT_GRAD = 2, CNT_N = 4 };
+
+// True in exactly one workgroup of the grid: the last to arrive.  Every
+// workgroup's global writes before the call are visible to it.
+IFS_DEV bool arrive_last(int *counter, int *s_flag) {
+  __threadfence();
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const float v = *sf2;
-    if (!(v > 0.f) || !isfinite(v)) bad = 1;
-    if (need_noise) {
-      const float n = *noise;
-      if (!(n > 0.f) || !isfinite(n)) bad = 1;
-    }
-  }
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < M; i += NTB) {
-    const float v = s[i];
-    if (!(v > 0.f) || !isfinite(v)) bad = 1;
-    acc += log((double)v);
-  }
-  acc = block_sum<NTB>(acc, sh);
-  if (threadIdx.x == 0) scal[S_SUMLOGS] = acc;
-  if (bad) atomicOr(flag, FLAG_DOMAIN);
-}
-
-// out[i][d] = A[i][d] / ell_d
-__global__ void k_scale_rows(const float *A, int R, int D, const float *inv_ell, float *out) {
-  const long n = (long)R * D;
-  for (long i = blockIdx.x * (long)NTB + threadIdx.x; i < n; i += (long)gridDim.x * NTB)
-    out[i] = A[i] * inv_ell[i % D];
-}
-
-// ---------------------------------------------------------------- kernel matrices
-// K~[i][j] = sf2 exp(-1/2 |zs_i - zs_j|^2) + delta_ij s~_i, full square matrix.
-// 16 x 16 threads per block, each block a 16 x 16 tile; scaled rows in LDS.
-template <int MAXD>
-__global__ void k_kuu(const float *Zs, int M, int D, const float *sf2, const float *s,
-                      float *Kt, long ld) {
-  __shared__ float zi[16][MAXD + 1], zj[16][MAXD + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
-  for (int e = threadIdx.x; e < 16 * D; e += NTB) {
-    const int r = e / D, d = e % D;
-    zi[r][d] = (i0 + r < M) ? Zs[(long)(i0 + r) * D + d] : 0.f;
-    zj[r][d] = (j0 + r < M) ? Zs[(long)(j0 + r) * D + d] : 0.f;
+    const int prev = atomicAdd(counter, 1);
+    *s_flag = prev == (int)(gridDim.x * gridDim.y * gridDim.z) - 1;
   }
   __syncthreads();
-  const int i = i0 + ty, j = j0 + tx;
-  if (i < M && j < M) {
-    float d2 = 0.f;
-    for (int d = 0; d < D; ++d) {
-      const float df = zi[ty][d] - zj[tx][d];
-      d2 = fmaf(df, df, d2);
+  const bool last = *s_flag != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(counter, 0);
+  }
+  return last;
+}
+
+// ---------------------------------------------------------------- set-up
+// One launch per iteration before any product:
+//  * blocks [0, nK): 16 x 16 tiles of K~ = sf2 exp(-1/2 |zs_i - zs_j|^2) + diag(s~)
+//    (fp32, plus the operand type), zs = Z / ell; the first tile column also
+//    writes Zs and the zero-padded copy of s~; block 0 validates ell, sf2,
+//    noise_var, s~ and forms 1/ell and sum log s~;
+//  * blocks [nK, nK + nL): 32 x 32 tiles of the caller's L: fp32 master (lower
+//    triangle, strict upper 0), operand copy, and both transposes.
+struct SetupArgs {
+  const float *Z, *ell, *sf2, *noise, *s;
+  int M, D, need_noise;
+  float *Zs, *inv_ell, *sP, *Kt;
+  void *KtT;
+  long ld;
+  const float *Lin;  // caller's L (leading dimension M), or null
+  float *L32, *Lt32;
+  void *LT, *LtT;
+  double *scal;
+  int *flag;
+  int nKx, nK, nLx;
+};
+
+template <int MAXD, typename T>
+__global__ void k_setup(SetupArgs a) {
+  __shared__ float zi[16][MAXD + 1], zj[16][MAXD + 1];
+  __shared__ float tile[32][33];
+  __shared__ double sh[NTB / 64];
+  const int b = blockIdx.x;
+  const int M = a.M, D = a.D;
+  if (b < a.nK) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int bi = b / a.nKx, bj = b % a.nKx;
+    const int i0 = bi * 16, j0 = bj * 16;
+    for (int e = threadIdx.x; e < 16 * D; e += NTB) {
+      const int r = e / D, d = e % D;
+      const float il = 1.0f / a.ell[d];
+      zi[r][d] = (i0 + r < M) ? a.Z[(long)(i0 + r) * D + d] * il : 0.f;
+      zj[r][d] = (j0 + r < M) ? a.Z[(long)(j0 + r) * D + d] * il : 0.f;
     }
-    float v = (*sf2) * __expf(-0.5f * d2);
-    if (i == j) v += s[i];
-    Kt[(long)i * ld + j] = v;
+    __syncthreads();
+    if (bj == 0) {
+      for (int e = threadIdx.x; e < 16 * D; e += NTB) {
+        const int r = e / D, d = e % D;
+        if (i0 + r < M) a.Zs[(long)(i0 + r) * D + d] = zi[r][d];
+      }
+      if (threadIdx.x < 16 && i0 + threadIdx.x < M) a.sP[i0 + threadIdx.x] = a.s[i0 + threadIdx.x];
+    }
+    const int i = i0 + ty, j = j0 + tx;
+    if (i < M && j < M) {
+      float d2 = 0.f;
+      for (int d = 0; d < D; ++d) {
+        const float df = zi[ty][d] - zj[tx][d];
+        d2 = fmaf(df, df, d2);
+      }
+      float v = (*a.sf2) * __expf(-0.5f * d2);
+      if (i == j) v += a.s[i];
+      a.Kt[(long)i * a.ld + j] = v;
+      if constexpr (!std::is_same<T, float>::value) ((T *)a.KtT)[(long)i * a.ld + j] = from_f32<T>(v);
+    }
+    if (b == 0) {
+      int bad = 0;
+      for (int d = threadIdx.x; d < D; d += NTB) {
+        const float l = a.ell[d];
+        if (!(l > 0.f) || !isfinite(l)) bad = 1;
+        a.inv_ell[d] = 1.0f / l;
+      }
+      if (threadIdx.x == 0) {
+        const float v = *a.sf2;
+        if (!(v > 0.f) || !isfinite(v)) bad = 1;
+        if (a.need_noise) {
+          const float n = *a.noise;
+          if (!(n > 0.f) || !isfinite(n)) bad = 1;
+        }
+      }
+      double acc = 0.0;
+      for (int q = threadIdx.x; q < M; q += NTB) {
+        const float v = a.s[q];
+        if (!(v > 0.f) || !isfinite(v)) bad = 1;
+        acc += log((double)v);
+      }
+      acc = block_sum<NTB>(acc, sh);
+      if (threadIdx.x == 0) a.scal[S_SUMLOGS] = acc;
+      if (bad) atomicOr(a.flag, FLAG_DOMAIN);
+    }
+    return;
+  }
+  // caller's L -> L32, LT, LtT, Lt32
+  const int bl = b - a.nK;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int i0 = (bl / a.nLx) * 32, j0 = (bl % a.nLx) * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    float v = 0.f;
+    if (i < M && j < M && i >= j) v = a.Lin[(long)i * M + j];
+    tile[r][tx] = v;
+    if (i < M && j < M) {
+      a.L32[(long)i * a.ld + j] = v;
+      if constexpr (!std::is_same<T, float>::value) ((T *)a.LT)[(long)i * a.ld + j] = from_f32<T>(v);
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + tx;  // transposes: [j][i] = L[i][j]
+    if (i < M && j < M) {
+      const float v = tile[tx][r];
+      ((T *)a.LtT)[(long)j * a.ld + i] = from_f32<T>(v);
+      if constexpr (!std::is_same<T, float>::value) a.Lt32[(long)j * a.ld + i] = v;
+    }
   }
 }
 
-// K_uf[k][n] = sf2 exp(-1/2 |zs_k - xs_n|^2) in the operand type, plus the
-// partial mean mu_part[k-tile][n] = sum_{k in tile} K_uf[k][n] Lb[k] (fp32 values).
-// Block: 64 (k) x 64 (n) tile, thread (ty, tx) owns rows ty+16i, cols tx+16j.
+// ---------------------------------------------------------------- K_uf
+// K_uf[k][n] = sf2 exp(-1/2 |zs_k - xs_n|^2), written transposed in the operand
+// type (Kft[n][k], the B operand layout of V = L^T K_uf), plus the partial mean
+// mu_part[k-tile][n] = sum_{k in tile} K_uf[k][n] Lb[k] from the fp32 values.
+// xs = X / ell is formed here; the first tile row writes it for later kernels.
+// Block: 64 (k) x 64 (n) tile; thread (tx, ty) owns k = tx+16i, n = ty+16j.
 template <int MAXD, typename T>
-__global__ void k_kuf(const float *Zs, const float *Xs, int M, int B, int D, const float *sf2,
-                      const float *Lb, T *out, long ld, float *mu_part, long ldp) {
+__global__ void k_kuf(const float *Zs, const float *X, const float *inv_ell, int M, int B, int D,
+                      const float *sf2, const float *Lb, float *Xs, T *Kft, long ld,
+                      float *mu_part, long ldp) {
   __shared__ float zk[64][MAXD + 1], xn[64][MAXD + 1];
-  __shared__ float red[16][65];
+  __shared__ float red[64][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   for (int e = threadIdx.x; e < 64 * D; e += NTB) {
     const int r = e / D, d = e % D;
     zk[r][d] = (k0 + r < M) ? Zs[(long)(k0 + r) * D + d] : 0.f;
-    xn[r][d] = (n0 + r < B) ? Xs[(long)(n0 + r) * D + d] : 0.f;
+    const float x = (n0 + r < B) ? X[(long)(n0 + r) * D + d] * inv_ell[d] : 0.f;
+    xn[r][d] = x;
+    if (blockIdx.y == 0 && n0 + r < B) Xs[(long)(n0 + r) * D + d] = x;
   }
   __syncthreads();
   const float s2 = *sf2;
   float mu[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = ty + 16 * i, k = k0 + r;
+    const int r = tx + 16 * i, k = k0 + r;
     const float lb = k < M ? Lb[k] : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = tx + 16 * j, n = n0 + c;
+      const int c = ty + 16 * j, n = n0 + c;
       float d2 = 0.f;
       for (int d = 0; d < D; ++d) {
         const float df = zk[r][d] - xn[c][d];
@@ -111,110 +187,121 @@ __global__ void k_kuf(const float *Zs, const float *Xs, int M, int B, int D, con
       }
       const float v = s2 * __expf(-0.5f * d2);
       if (k < M && n < B) {
-        out[(long)k * ld + n] = from_f32<T>(v);
+        Kft[(long)n * ld + k] = from_f32<T>(v);
         mu[j] = fmaf(v, lb, mu[j]);
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) red[ty][tx + 16 * j] = mu[j];
+  for (int j = 0; j < 4; ++j) red[ty + 16 * j][tx] = mu[j];
   __syncthreads();
   if (threadIdx.x < 64) {
     const int n = n0 + threadIdx.x;
     float s = 0.f;
-    for (int r = 0; r < 16; ++r) s += red[r][threadIdx.x];
+    for (int r = 0; r < 16; ++r) s += red[threadIdx.x][r];
     if (n < B) mu_part[(long)blockIdx.y * ldp + n] = s;
   }
 }
 
-// ---------------------------------------------------------------- copies
-// dst = lower triangle of src (strict upper of dst set to 0).
-__global__ void k_copy_lower(const float *src, long lds, float *dst, long ldd, int M) {
-  const long n = (long)M * M;
-  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
-    const int i = (int)(e / M), j = (int)(e % M);
-    dst[(long)i * ldd + j] = i >= j ? src[(long)i * lds + j] : 0.f;
+// sum_{k < np} p[k * stride] with eight independent loads in flight.
+template <typename F>
+IFS_DEV F slot_sum(const F *p, int np, long stride) {
+  F a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int k = 0;
+  for (; k + 8 <= np; k += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[(long)(k + u) * stride];
   }
-}
-// dst lower triangle = src lower triangle; dst strict upper untouched.
-__global__ void k_store_lower(const float *src, long lds, float *dst, long ldd, int M) {
-  const long n = (long)M * M;
-  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
-    const int i = (int)(e / M), j = (int)(e % M);
-    if (i >= j) dst[(long)i * ldd + j] = src[(long)i * lds + j];
-  }
+  for (; k < np; ++k) a[0] += p[(long)k * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // ---------------------------------------------------------------- matrix-vector
-// y[i] = alpha * sum_j A[i][j] x[j] + beta * z[i]; one wave per row; lower:
-// restrict to j <= i.  A is fp32 or the operand type.
-template <typename S>
-__global__ void k_gemv_rows(const S *A, long ld, int R, int Cn, const float *x, int lower,
-                            float alpha, const float *z, float beta, float *y) {
+// Row dot product of one wave: sum_{j < cend} a[j] (x[j] - xs[j]) (xs optional),
+// 4 floats per lane per load.
+IFS_DEV float row_dot(const float *a, const float *x, const float *xs, int cend) {
   const int lane = threadIdx.x & 63;
+  float s = 0.f;
+  int j = lane * 4;
+  for (; j + 3 < cend; j += 256) {
+    const f32x4 v = *(const f32x4 *)(a + j);
+    f32x4 u = *(const f32x4 *)(x + j);
+    if (xs) u -= *(const f32x4 *)(xs + j);
+    s = fmaf(v[0], u[0], s); s = fmaf(v[1], u[1], s);
+    s = fmaf(v[2], u[2], s); s = fmaf(v[3], u[3], s);
+  }
+  for (; j < cend; ++j) s = fmaf(a[j], x[j] - (xs ? xs[j] : 0.f), s);  // tail
+  return wave_sum(s);
+}
+
+// y[i] = scale * sum_j A[i][j] x[j] over j < Cn (lower: j <= i); one wave per row.
+__global__ void k_gemv_rows(const float *A, long ld, int R, int Cn, const float *x, int lower,
+                            const double *scale, float *y) {
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= R) return;
-  const int cend = lower ? min(Cn, row + 1) : Cn;
-  const S *a = A + (long)row * ld;
-  float s = 0.f;
-  for (int j = lane; j < cend; j += 64) s = fmaf(to_f32(a[j]), x[j], s);
-  s = wave_sum(s);
-  if (lane == 0) y[row] = alpha * s + (z ? beta * z[row] : 0.f);
+  const float s = row_dot(A + (long)row * ld, x, nullptr, lower ? min(Cn, row + 1) : Cn);
+  if ((threadIdx.x & 63) == 0) y[row] = scale ? (float)(*scale * s) : s;
 }
 
-// Partial column products: part[chunk][j] = sum_{i in chunk} A[i][j] x[i]
-// (lower: i >= j only).  Grid: (ceil(Cn/NTB), nchunk); chunk = 64 rows.
-__global__ void k_gemv_cols_part(const float *A, long ld, int R, int Cn, const float *x,
-                                 int lower, float *part, long ldp) {
-  const int j = blockIdx.x * NTB + threadIdx.x;
-  const int i0 = blockIdx.y * 64;
-  if (j >= Cn) return;
-  float s = 0.f;
-  const int iend = min(R, i0 + 64);
-  for (int i = lower ? max(i0, j) : i0; i < iend; ++i) s = fmaf(A[(long)i * ld + j], x[i], s);
-  part[(long)blockIdx.y * ldp + j] = s;
-}
-// y[j] = sum_c part[c][j]
-__global__ void k_sum_parts(const float *part, long ldp, int nchunk, int n, float *y) {
-  const int j = blockIdx.x * NTB + threadIdx.x;
-  if (j >= n) return;
-  float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += part[(long)c * ldp + j];
-  y[j] = s;
-}
-
-// ---------------------------------------------------------------- scalars of the KL
-// quad = b^T Wub, logdet = 2 sum log|L_ii| (one block).
-__global__ void k_kl_scalars(const float *b, const float *Wub, const float *L, long ld, int M,
-                             double *scal, int *flag) {
-  __shared__ double sh[NTB / 64];
+// Lb = L b (lower) for rows [0, M) and Wub = Wu b for rows [M, 2M), one wave
+// per row, with workgroup partials part[blk] = {sum b_i Wub_i, sum log|L_ii|}
+// (fp64) over the workgroup's rows; the bound's finalisation sums them.
+__global__ void k_vec_lb_wub(const float *L, const float *Wu, long ld, int M, const float *b,
+                             float *Lb, float *Wub, double *part, int *flag) {
+  __shared__ double sq[NTB / 64], sl[NTB / 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (NTB / 64) + w;
   double q = 0.0, ldt = 0.0;
-  int bad = 0;
-  for (int i = threadIdx.x; i < M; i += NTB) {
-    q += (double)b[i] * (double)Wub[i];
-    const float d = L[(long)i * ld + i];
-    if (d == 0.f || !isfinite(d)) bad = 1;
-    ldt += log(fabs((double)d));
+  if (row < M) {
+    const float s = row_dot(L + (long)row * ld, b, nullptr, row + 1);
+    if (lane == 0) {
+      Lb[row] = s;
+      const float d = L[(long)row * ld + row];
+      if (d == 0.f || !isfinite(d)) atomicOr(flag, FLAG_DOMAIN);
+      ldt = log(fabs((double)d));
+    }
+  } else if (row < 2 * M) {
+    const int r = row - M;
+    const float s = row_dot(Wu + (long)r * ld, b, nullptr, M);
+    if (lane == 0) {
+      Wub[r] = s;
+      q = (double)b[r] * (double)s;
+    }
   }
-  q = block_sum<NTB>(q, sh);
-  ldt = block_sum<NTB>(ldt, sh);
+  if (lane == 0) {
+    sq[w] = q;
+    sl[w] = ldt;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    scal[S_QUAD] = q;
-    scal[S_LOGDET] = 2.0 * ldt;
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < NTB / 64; ++k) {
+      a += sq[k];
+      c += sl[k];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = c;
   }
-  if (bad) atomicOr(flag, FLAG_DOMAIN);
 }
 
-// ---------------------------------------------------------------- likelihood
+// ---------------------------------------------------------------- likelihood + bound
 // Per datum: mu = sum of mean partials, var = sf2 - sum of variance partials,
-// E_n and alpha_n = c dE/dmu, beta_n = c dE/dvar (c = N/B); block partials of
-// [sum E, sum var, sum dE/dnoise, sum beta] in fp64.
+// E_n and alpha_n = c dE/dmu, beta_n = c dE/dvar (c = N/B), sqrt(-beta_n);
+// workgroup partials of [sum E, sum var, sum dE/dnoise, sum beta] in fp64.
+// The grid covers the padded batch: padded entries get alpha = beta = 0.
+// The last workgroup forms F = c sum E - KL with
+//   KL = 1/2 (-tr(Q Wu) + tr W - M + quad - log|T| - sum log s~).
 struct LikArgs {
   const float *mu_part; int n_mu; const float *var_part; int n_var; long ldp;
-  const float *y; int B; const float *sf2; const float *noise; double c;
+  const float *y; int B; int Bp; const float *sf2; const float *noise; double c;
   int lik; const double *gh; int ngh;  // gh: nodes[ngh] then weights[ngh]
   float *mu, *var, *alpha, *beta, *sqnb;  // sqnb = sqrt(max(0, -beta))
   double *part;  // [nblocks][4]
+  const double *gram_part; int n_gram;  // [n_gram][3]: tr W, sum Q o Wu, ||W - I||^2
+  const double *vec_part; int n_vec;    // [n_vec][2]: b^T Wu b, sum log|L_ii|
+  double *scal; int M;
+  double *out_bound, *out_terms;
+  int *flag, *counter;
 };
 
 __device__ __forceinline__ void probit_terms(double y, double mu, double v, const double *gh,
@@ -236,9 +323,8 @@ __device__ __forceinline__ void probit_terms(double y, double mu, double v, cons
       logPhi = log(0.5 * ex) - u * u;
       lam = sq2_over_pi / ex;
     } else {
-      const double ec = erfc(u);
       logPhi = log1p(-0.5 * erfc(-u));
-      lam = sq2_over_pi * exp(-u * u) / ec;
+      lam = sq2_over_pi * exp(-u * u) / erfc(u);
     }
     E += w * logPhi;
     dmu += w * lam * y;
@@ -249,12 +335,12 @@ __device__ __forceinline__ void probit_terms(double y, double mu, double v, cons
 
 __global__ void k_lik(LikArgs a) {
   __shared__ double sh[NTB / 64];
+  __shared__ int s_last;
   const int n = blockIdx.x * NTB + threadIdx.x;
   double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
   if (n < a.B) {
-    float m = 0.f, vp = 0.f;
-    for (int k = 0; k < a.n_mu; ++k) m += a.mu_part[(long)k * a.ldp + n];
-    for (int k = 0; k < a.n_var; ++k) vp += a.var_part[(long)k * a.ldp + n];
+    const float m = slot_sum(a.mu_part + n, a.n_mu, a.ldp);
+    const float vp = slot_sum(a.var_part + n, a.n_var, a.ldp);
     const double mu = m, var = (double)(*a.sf2) - (double)vp;
     const double y = a.y[n];
     double E, dmu, dv;
@@ -276,6 +362,10 @@ __global__ void k_lik(LikArgs a) {
     e = E;
     vs = var;
     bs = a.c * dv;
+  } else if (n < a.Bp) {
+    a.alpha[n] = 0.f;
+    a.beta[n] = 0.f;
+    a.sqnb[n] = 0.f;
   }
   e = block_sum<NTB>(e, sh);
   vs = block_sum<NTB>(vs, sh);
@@ -285,59 +375,43 @@ __global__ void k_lik(LikArgs a) {
     double *p = a.part + 4 * blockIdx.x;
     p[0] = e; p[1] = vs; p[2] = dn; p[3] = bs;
   }
-}
-
-// ---------------------------------------------------------------- finalisation
-// Residual of one NG step from the gram partials: sqrt(sum / M).
-__global__ void k_resid(const double *part, int n, int M, double *out, double *scal) {
-  __shared__ double sh[NTB / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NTB) s += part[i];
-  s = block_sum<NTB>(s, sh);
-  if (threadIdx.x == 0) {
-    const double r = sqrt(s / M);
-    scal[S_RESID] = r;
-    if (out) *out = r;
+  if (!arrive_last(a.counter, &s_last)) return;
+  double trw = 0.0, qwu = 0.0, r2 = 0.0, qd = 0.0, ldt = 0.0;
+  e = 0.0;
+  vs = 0.0;
+  for (int i = threadIdx.x; i < a.n_gram; i += NTB) {
+    trw += a.gram_part[3 * i];
+    qwu += a.gram_part[3 * i + 1];
+    r2 += a.gram_part[3 * i + 2];
   }
-}
-
-// F = c sum E - KL with
-// KL = 1/2 (-tr(Q Wu) + tr W - M + quad - log|T| - sum log s~).
-__global__ void k_finalize_bound(const double *gram_part, int n_gram, const double *lik_part,
-                                 int n_lik, const double *scal, int M, double c,
-                                 double *out_bound, double *out_terms, int *flag) {
-  __shared__ double sh[NTB / 64];
-  double trw = 0.0, qwu = 0.0, r2 = 0.0, e = 0.0, vs = 0.0;
-  for (int i = threadIdx.x; i < n_gram; i += NTB) {
-    trw += gram_part[3 * i];
-    qwu += gram_part[3 * i + 1];
-    r2 += gram_part[3 * i + 2];
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTB) {
+    e += a.part[4 * i];
+    vs += a.part[4 * i + 1];
   }
-  for (int i = threadIdx.x; i < n_lik; i += NTB) {
-    e += lik_part[4 * i];
-    vs += lik_part[4 * i + 1];
+  for (int i = threadIdx.x; i < a.n_vec; i += NTB) {
+    qd += a.vec_part[2 * i];
+    ldt += a.vec_part[2 * i + 1];
   }
   trw = block_sum<NTB>(trw, sh);
   qwu = block_sum<NTB>(qwu, sh);
   r2 = block_sum<NTB>(r2, sh);
   e = block_sum<NTB>(e, sh);
   vs = block_sum<NTB>(vs, sh);
+  qd = block_sum<NTB>(qd, sh);
+  ldt = block_sum<NTB>(ldt, sh);
   if (threadIdx.x == 0) {
-    const double quad = scal[S_QUAD], logdet = scal[S_LOGDET], sls = scal[S_SUMLOGS];
-    const double KL = 0.5 * (-qwu + trw - (double)M + quad - logdet - sls);
-    const double data = c * e;
+    a.scal[S_QUAD] = qd;
+    a.scal[S_LOGDET] = 2.0 * ldt;
+    const double quad = qd, logdet = 2.0 * ldt, sls = a.scal[S_SUMLOGS];
+    const double KL = 0.5 * (-qwu + trw - (double)a.M + quad - logdet - sls);
+    const double data = a.c * e;
     const double F = data - KL;
-    if (!isfinite(F)) atomicOr(flag, FLAG_NONFINITE);
-    if (out_bound) *out_bound = F;
-    if (out_terms) {
-      out_terms[0] = data;
-      out_terms[1] = KL;
-      out_terms[2] = vs;
-      out_terms[3] = sqrt(r2 / M);
-      out_terms[4] = trw;
-      out_terms[5] = qwu;
-      out_terms[6] = quad;
-      out_terms[7] = logdet;
+    if (!isfinite(F)) atomicOr(a.flag, FLAG_NONFINITE);
+    if (a.out_bound) *a.out_bound = F;
+    if (a.out_terms) {
+      double *o = a.out_terms;
+      o[0] = data; o[1] = KL; o[2] = vs; o[3] = sqrt(r2 / a.M);
+      o[4] = trw; o[5] = qwu; o[6] = quad; o[7] = logdet;
     }
   }
 }
@@ -345,135 +419,153 @@ __global__ void k_finalize_bound(const double *gram_part, int n_gram, const doub
 // ---------------------------------------------------------------- backward
 // C = -sym((V alpha) a^T) + V diag(beta) V^T - 1/2 (Wu + I - Wub a^T - a Wub^T)
 //     + 1/2 (Q - b b^T), with V diag(beta) V^T = -sum_s Ys[s] (split-K pieces of
-// (V D)(V D)^T, D = diag(sqrt(-beta))).  Ys holds lower tiles only; read (max, min).
+// (V D)(V D)^T, D = diag(sqrt(-beta)), stored symmetric), written in the
+// operand type TC over the M x M block.
+template <typename TC>
 __global__ void k_assemble_C(const float *Ys, int nsplit, long split_stride, const float *Wu,
                              const float *Q, const float *a, const float *b, const float *Wub,
-                             const float *Va, int M, long ld, float *Cm) {
+                             const float *Va, int M, long ld, TC *Cm) {
   const long n = (long)M * M;
   for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
     const int i = (int)(e / M), j = (int)(e % M);
-    const int hi = max(i, j), lo = min(i, j);
-    float ys = 0.f;
-    for (int s = 0; s < nsplit; ++s) ys += Ys[s * split_stride + (long)hi * ld + lo];
     const long ij = (long)i * ld + j;
+    float ys = 0.f;
+    for (int s = 0; s < nsplit; ++s) ys += Ys[s * split_stride + ij];
     const float c = -0.5f * (Va[i] * a[j] + a[i] * Va[j]) - ys -
                     0.5f * (Wu[ij] + (i == j ? 1.f : 0.f) - Wub[i] * a[j] - a[i] * Wub[j]) +
                     0.5f * (Q[ij] - b[i] * b[j]);
-    Cm[ij] = c;
+    Cm[ij] = from_f32<TC>(c);
   }
 }
 
-// V alpha over the operand-type V (one wave per row).
+// V alpha over the operand-type V (one wave per row, 16 bytes per lane per load).
 template <typename T>
 __global__ void k_valpha(const T *V, long ld, int M, int B, const float *alpha, float *out) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= M) return;
+  constexpr int KPL = 16 / (int)sizeof(T);
   const T *v = V + (long)row * ld;
   float s = 0.f;
-  for (int n = lane; n < B; n += 64) s = fmaf(to_f32(v[n]), alpha[n], s);
+  for (int n = lane * KPL; n < B; n += 64 * KPL) {
+    if (n + KPL <= B) {
+      const uint4 raw = *(const uint4 *)(v + n);
+      const T *e = (const T *)&raw;
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) s = fmaf(to_f32(e[q]), alpha[n + q], s);
+    } else {
+      for (int q = 0; n + q < B; ++q) s = fmaf(to_f32(v[n + q]), alpha[n + q], s);
+    }
+  }
   s = wave_sum(s);
   if (lane == 0) out[row] = s;
 }
 
+// All gradient reductions in one launch, with blocks of three roles:
+//  * [0, rb): rows of Z.  For thread (i, d): r_uf = sum of H_uf row sums,
+//    hx = sum_n H_uf,in xs_nd, r_uu, hz likewise for H_uu over their per-tile
+//    slots; dF/dZ_id = -(1/ell_d) [(zs r_uf - hx) + 2 (zs r_uu - hz)] and the
+//    block partial of the lengthscale sums in scaled coordinates
+//      sum_i r_uf zs^2 - 2 zs hx + 2 (r_uu zs^2 - zs hz);
+//  * [rb, rb + cb): data columns: c_n = sum_i H_uf,in, partial sum_n c_n xs_nd^2;
+//  * [rb + cb, rb + cb + rq): t2 = Q (V alpha - Wu b), one wave per row (the
+//    inducing-mean gradient is L t2, formed by the next launch).
+// The last workgroup forms dF/dell_d = (1/ell_d) sum of partials,
+// dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and dF/dnoise = c sum dE/dnoise.
 struct GradArgs {
   int M, B, D;
   const float *Zs, *Xs, *inv_ell, *sf2;
-  const float *hrow; int n_uf_nt;       // [n_uf_nt][M]
-  const float *hx;                      // [n_uf_nt][M][D]
-  const float *hcol; int n_uf_mt; long ldc;  // [n_uf_mt][ldc]
-  const float *hzrow; const float *hz; int nb;  // [nb][M], [nb][M][D]
+  const float *hrow, *hx; int n_uf_nt;          // [n_uf_nt][M], [n_uf_nt][M][D]
+  const float *hzrow, *hz; int nb;              // [nb][M], [nb][M][D]
+  const float *hcol; int n_uf_mt; long ldc;     // [n_uf_mt][ldc]
   const double *uf_part; int n_uf_tiles;
   const double *uu_part; int n_uu_tiles;
   const double *lik_part; int n_lik;
+  const float *Q, *Va, *Wub; long ld; float *t2;
   double c;
   const double *grad_scale;
   float *g_Z, *g_ell, *g_sf2, *g_noise;
-  double *ell_part;  // [nblk_rows + nblk_cols][D]
+  double *ell_part;  // [rb + cb][D]
+  int rb, cb;
 };
 
-// Per inducing row i: reduce the partials, write dF/dZ_i, and accumulate the
-// row part of dF/dell_d (scaled coordinates, divided by ell_d at the end):
-//   sum_i r_uf_i zs_id^2 - 2 zs_id hx_id + 2 (r_uu_i zs_id^2 - zs_id hz_id)
-__global__ void k_grad_rows(GradArgs g) {
-  __shared__ double sh[64][65];
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int dgrp = threadIdx.x >> 6;  // 4 groups of d
-  const double scale = g.grad_scale ? *g.grad_scale : 1.0;
-  float ruf = 0.f, ruu = 0.f;
-  if (i < g.M) {
-    for (int k = 0; k < g.n_uf_nt; ++k) ruf += g.hrow[(long)k * g.M + i];
-    for (int k = 0; k < g.nb; ++k) ruu += g.hzrow[(long)k * g.M + i];
-  }
-  for (int d0 = 0; d0 < g.D; d0 += 64) {
-    for (int dd = dgrp; dd < 64; dd += 4) {
-      const int d = d0 + dd;
-      double contrib = 0.0;
-      if (i < g.M && d < g.D) {
-        float hx = 0.f, hz = 0.f;
-        for (int k = 0; k < g.n_uf_nt; ++k) hx += g.hx[((long)k * g.M + i) * g.D + d];
-        for (int k = 0; k < g.nb; ++k) hz += g.hz[((long)k * g.M + i) * g.D + d];
-        const double zs = g.Zs[(long)i * g.D + d];
-        const double il = g.inv_ell[d];
-        // dF/dZ_id = -(1/ell_d) [ (zs r_uf - hx) + 2 (zs r_uu - hz) ]
-        const double gz = -il * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
-        if (g.g_Z) g.g_Z[(long)i * g.D + d] = (float)(scale * gz);
-        contrib = ruf * zs * zs - 2.0 * zs * hx + 2.0 * (ruu * zs * zs - zs * hz);
-      }
-      sh[dd][threadIdx.x & 63] = contrib;
+__global__ void k_grad(GradArgs g) {
+  __shared__ double sh[NTB];
+  const int blk = blockIdx.x, t = threadIdx.x;
+  const int R = NTB / g.D;
+  if (blk < g.rb) {
+    const int r = t / g.D, d = t % g.D;
+    const int i = blk * R + r;
+    const double scale = g.grad_scale ? *g.grad_scale : 1.0;
+    double contrib = 0.0;
+    if (r < R && i < g.M) {
+      const long e = (long)i * g.D + d, MD = (long)g.M * g.D;
+      const float ruf = slot_sum(g.hrow + i, g.n_uf_nt, (long)g.M);
+      const float hx = slot_sum(g.hx + e, g.n_uf_nt, MD);
+      const float ruu = slot_sum(g.hzrow + i, g.nb, (long)g.M);
+      const float hz = slot_sum(g.hz + e, g.nb, MD);
+      const double zs = g.Zs[e];
+      const double gz = -(double)g.inv_ell[d] * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
+      if (g.g_Z) g.g_Z[e] = (float)(scale * gz);
+      contrib = ruf * zs * zs - 2.0 * zs * hx + 2.0 * (ruu * zs * zs - zs * hz);
     }
+    sh[t] = contrib;
     __syncthreads();
-    for (int dd = threadIdx.x; dd < 64; dd += NTB) {
+    if (t < g.D) {
       double s = 0.0;
-      for (int r = 0; r < 64; ++r) s += sh[dd][r];
-      if (d0 + dd < g.D) g.ell_part[(long)blockIdx.x * g.D + d0 + dd] = s;
+      for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
+      g.ell_part[(long)blk * g.D + t] = s;
     }
+  } else if (blk < g.rb + g.cb) {
+    const int r = t / g.D, d = t % g.D;
+    const int n = (blk - g.rb) * R + r;
+    double contrib = 0.0;
+    if (r < R && n < g.B) {
+      const float cn = slot_sum(g.hcol + n, g.n_uf_mt, g.ldc);
+      const double xs = g.Xs[(long)n * g.D + d];
+      contrib = (double)cn * xs * xs;
+    }
+    sh[t] = contrib;
     __syncthreads();
+    if (t < g.D) {
+      double s = 0.0;
+      for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
+      g.ell_part[(long)blk * g.D + t] = s;
+    }
+  } else {
+    const int row = (blk - g.rb - g.cb) * (NTB / 64) + (t >> 6);
+    if (row < g.M) {
+      const float s = row_dot(g.Q + (long)row * g.ld, g.Va, g.Wub, g.M);
+      if ((t & 63) == 0) g.t2[row] = s;
+    }
   }
 }
 
-// Per datum n: c_n = sum_i H_in; accumulate sum_n c_n xs_nd^2 into ell_part.
-__global__ void k_grad_cols(GradArgs g, int row_blocks) {
-  __shared__ double sh[64][65];
-  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int dgrp = threadIdx.x >> 6;
-  float cn = 0.f;
-  if (n < g.B)
-    for (int k = 0; k < g.n_uf_mt; ++k) cn += g.hcol[(long)k * g.ldc + n];
-  for (int d0 = 0; d0 < g.D; d0 += 64) {
-    for (int dd = dgrp; dd < 64; dd += 4) {
-      const int d = d0 + dd;
-      double contrib = 0.0;
-      if (n < g.B && d < g.D) {
-        const double xs = g.Xs[(long)n * g.D + d];
-        contrib = cn * xs * xs;
-      }
-      sh[dd][threadIdx.x & 63] = contrib;
-    }
-    __syncthreads();
-    for (int dd = threadIdx.x; dd < 64; dd += NTB) {
-      double s = 0.0;
-      for (int r = 0; r < 64; ++r) s += sh[dd][r];
-      if (d0 + dd < g.D) g.ell_part[(long)(row_blocks + blockIdx.x) * g.D + d0 + dd] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// dF/dell_d = (1/ell_d) sum of partials; dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta;
-// dF/dnoise = c sum dE/dnoise.  One block.
-__global__ void k_grad_final(GradArgs g, int nparts) {
+// Tail of the gradient: blocks [0, rows) form dF/dm~ = scale * L t2 (one wave
+// per row, when g_m is requested); the last block forms
+// dF/dell_d = (1/ell_d) sum of partials, dF/dsf2 = (sum H_uu + sum H_uf)/sf2 +
+// sum beta and dF/dnoise = c sum dE/dnoise.
+__global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
   __shared__ double sh[NTB / 64];
+  const int t = threadIdx.x;
   const double scale = g.grad_scale ? *g.grad_scale : 1.0;
-  for (int d = threadIdx.x; d < g.D; d += NTB) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += g.ell_part[(long)p * g.D + d];
+  if ((int)blockIdx.x < rows) {
+    const int row = blockIdx.x * (NTB / 64) + (t >> 6);
+    if (row < g.M) {
+      const float s = row_dot(L + (long)row * g.ld, g.t2, nullptr, row + 1);
+      if ((t & 63) == 0) g_m[row] = (float)(scale * s);
+    }
+    return;
+  }
+  const int nparts = g.rb + g.cb;
+  for (int d = t; d < g.D; d += NTB) {
+    const double s = slot_sum(g.ell_part + d, nparts, (long)g.D);
     if (g.g_ell) g.g_ell[d] = (float)(scale * s * g.inv_ell[d]);
   }
   double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
-  for (int i = threadIdx.x; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
-  for (int i = threadIdx.x; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
-  for (int i = threadIdx.x; i < g.n_lik; i += NTB) {
+  for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
+  for (int i = t; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
+  for (int i = t; i < g.n_lik; i += NTB) {
     dn += g.lik_part[4 * i + 2];
     bs += g.lik_part[4 * i + 3];
   }
@@ -481,19 +573,8 @@ __global__ void k_grad_final(GradArgs g, int nparts) {
   huu = block_sum<NTB>(huu, sh);
   dn = block_sum<NTB>(dn, sh);
   bs = block_sum<NTB>(bs, sh);
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     if (g.g_sf2) *g.g_sf2 = (float)(scale * ((huf + huu) / (double)(*g.sf2) + bs));
     if (g.g_noise) *g.g_noise = (float)(scale * g.c * dn);
   }
-}
-
-// out = scale * x (optional scale pointer).
-__global__ void k_scale_vec(const float *x, int n, const double *scale, float *out) {
-  const int i = blockIdx.x * NTB + threadIdx.x;
-  if (i < n) out[i] = (float)((scale ? *scale : 1.0) * x[i]);
-}
-// out = x - y
-__global__ void k_sub_vec(const float *x, const float *y, int n, float *out) {
-  const int i = blockIdx.x * NTB + threadIdx.x;
-  if (i < n) out[i] = x[i] - y[i];
 }
