@@ -21,6 +21,8 @@ FLAGS = [
     "-shared",
     # packed fp32 VALU forms are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: no AGPR copies around the GEMM main loop
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-variable",
     "-Wno-unused-command-line-argument",
 ]

@@ -6,15 +6,52 @@
 #pragma once
 #include "gemm.hpp"
 
-// Row-major element loop over the tile (coalesced along columns).
-#define TILE_LOOP(C, r, c)                                                    \
-  for (int _i = threadIdx.x; _i < C::BM * C::BN; _i += C::NT)                 \
-    if (const int r = _i / C::BN, c = _i % C::BN; true)
+// Each thread owns chunks of VEC consecutive elements of the tile:
+//   row chunk    (r, c .. c+VEC)   -- one 16/32-byte access of a row-major array
+//   column chunk (r .. r+VEC, c)   -- one access of a transposed array
+// Workspace buffers are padded to whole tiles, so every chunk access is in
+// bounds and unconditional; elements outside the logical extent are written
+// as zeros, which keeps the padding of every operand zero.
+constexpr int VEC = 8;
 
-// Column-major element loop (coalesced along rows, for transposed stores).
-#define TILE_LOOP_T(C, r, c)                                                  \
-  for (int _i = threadIdx.x; _i < C::BM * C::BN; _i += C::NT)                 \
-    if (const int c = _i / C::BM, r = _i % C::BM; true)
+template <typename T>
+struct alignas(VEC * sizeof(T)) Pack {
+  T v[VEC];
+};
+
+template <typename T>
+IFS_DEV void ld_pack(const T *p, float (&x)[VEC]) {
+  const Pack<T> v = *(const Pack<T> *)p;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) x[q] = to_f32(v.v[q]);
+}
+template <typename T>
+IFS_DEV void st_pack(T *p, const float (&x)[VEC]) {
+  Pack<T> v;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) v.v[q] = from_f32<T>(x[q]);
+  *(Pack<T> *)p = v;
+}
+
+template <class C>
+struct Chunks {
+  static constexpr int RPR = C::BN / VEC;                  // row chunks per tile row
+  static constexpr int CPC = C::BM / VEC;                  // column chunks per tile column
+  static constexpr int N = C::BM * C::BN / (VEC * C::NT);  // chunks per thread
+  static_assert((C::BM * C::BN) % (VEC * C::NT) == 0, "tile / chunk mismatch");
+  static_assert(C::NT % RPR == 0, "a thread's row chunks share their columns");
+  // row chunk k of this thread; c is the same for every k
+  static IFS_DEV void row(int k, int &r, int &c) {
+    const int ch = threadIdx.x + k * C::NT;
+    r = ch / RPR;
+    c = (ch % RPR) * VEC;
+  }
+  static IFS_DEV void col(int k, int &r, int &c) {
+    const int ch = threadIdx.x + k * C::NT;
+    c = ch / CPC;
+    r = (ch % CPC) * VEC;
+  }
+};
 
 #define CS(r, c) Cs[(r) * C::LDC + (c)]
 
@@ -25,10 +62,85 @@ IFS_DEV double tile_sum(double v, const float *Cs) {
   return block_sum<C::NT>(v, sh);
 }
 
+// Column sums of the staged tile over its BM rows (NT / BN threads per column,
+// partials combined in the scratch LDS).  Valid for threads with g == 0, where
+// c = threadIdx.x % BN.
+template <class C>
+IFS_DEV float tile_colsum(const float *Cs) {
+  constexpr int RG = C::NT / C::BN;
+  static_assert(C::NT % C::BN == 0, "column partial layout");
+  float *sh = (float *)(Cs + C::BM * C::LDC);
+  const int c = threadIdx.x % C::BN, g = threadIdx.x / C::BN;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll 4
+  for (int r = g; r < C::BM; r += 4 * RG) {
+    s0 += CS(r, c);
+    s1 += CS(r + RG, c);
+    s2 += CS(r + 2 * RG, c);
+    s3 += CS(r + 3 * RG, c);
+  }
+  float s = (s0 + s1) + (s2 + s3);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0)
+    for (int k = 1; k < RG; ++k) s += sh[k * C::BN + c];
+  __syncthreads();
+  return s;
+}
+
+// Small fp32 MFMA product of LDS operands, used for the D-wide reductions of
+// the gradient epilogues:  Out[i][d] = sum_k A[i][k] Z[k][d],  i < R, d < DP,
+// with A = H (row-major, stride ldh) or, TRANS, A = H^T.  Z is row-major
+// [K][ldz].  R, K and DP are multiples of 16, 4 and 16.  Each 16 x 16 output
+// tile goes to sink(i, d, value) from the lane that holds it.
+template <int NW, bool TRANS, class F>
+IFS_DEV void lds_mfma_f32(const float *H, int ldh, int R, int K, const float *Z, int ldz,
+                          int DP, F &&sink) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int ndt = DP / 16, nt = (R / 16) * ndt;
+  for (int tix = wave; tix < nt; tix += NW) {
+    const int i0 = (tix / ndt) * 16, d0 = (tix % ndt) * 16;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const float a = TRANS ? H[(k0 + l4) * ldh + i0 + l16] : H[(i0 + l16) * ldh + k0 + l4];
+      const float b = Z[(k0 + l4) * ldz + d0 + l16];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sink(i0 + 4 * l4 + q, d0 + l16, acc[q]);
+  }
+}
+
+// Stages rows [g0, g0 + R) of a row-major [n][D] array into LDS as [R][ld],
+// zero-padded past D and past n; column onecol (if >= D) holds 1 for real rows,
+// turning a row sum into one more output column of lds_mfma_f32.
+template <int NT>
+IFS_DEV void stage_rows(float *dst, int ld, const float *src, int g0, int R, int n, int D,
+                        int onecol) {
+  const int tot = R * ld;
+  for (int i0 = 0; i0 < tot; i0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + (int)threadIdx.x;
+      const int r = i / ld, d = i % ld, g = g0 + r;
+      v[u] = (i < tot && g < n && d < D) ? src[(long)g * D + d] : 0.f;
+      if (i < tot && g < n && d == onecol) v[u] = 1.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + (int)threadIdx.x;
+      if (i < tot) dst[i] = v[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- plain stores
-// out[gi][gj] = acc for rows < R, cols < N; optional transposed mirror for
-// off-diagonal tiles of a symmetric lower-tile schedule; split-K piece s
-// writes to out + s * split_stride.
+// out[gi][gj] = acc for rows < R, cols < N (zeros elsewhere in the tile);
+// optional transposed mirror for off-diagonal tiles of a symmetric lower-tile
+// schedule; split-K piece s writes to out + s * split_stride.
 template <typename TO>
 struct EpiStore {
   TO *out;
@@ -37,15 +149,28 @@ struct EpiStore {
   long split_stride;
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
     TO *o = out + (long)t.split * split_stride;
-    TILE_LOOP(C, r, c) {
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < R && gj < N) o[(long)gi * ld + gj] = from_f32<TO>(CS(r, c));
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = (gi < R && gj + q < N) ? CS(r, c + q) : 0.f;
+      st_pack(o + (long)gi * ld + gj, x);
     }
     if (mirror && t.m0 != t.n0) {
-      TILE_LOOP_T(C, r, c) {
+#pragma unroll
+      for (int k = 0; k < K::N; ++k) {
+        int r, c;
+        K::col(k, r, c);
         const int gi = t.m0 + r, gj = t.n0 + c;
-        if (gi < R && gj < N) o[(long)gj * ld + gi] = from_f32<TO>(CS(r, c));
+        float x[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) x[q] = (gi + q < R && gj < N) ? CS(r + q, c) : 0.f;
+        st_pack(o + (long)gj * ld + gi, x);
       }
     }
   }
@@ -59,9 +184,16 @@ struct EpiStoreT {
   int R, N;
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
-    TILE_LOOP_T(C, r, c) {
+    using K = Chunks<C>;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < R && gj < N) out[(long)gj * ld + gi] = from_f32<TO>(CS(r, c));
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < R && gj < N) ? CS(r + q, c) : 0.f;
+      st_pack(out + (long)gj * ld + gi, x);
     }
   }
 };
@@ -79,21 +211,30 @@ struct EpiNgGram {
   double *part;  // [ntiles]
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
     double s = 0.0;
-    TILE_LOOP_T(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < M) {
-        const float w = CS(r, c);
-        float x = 0.f;
-        if (gi > gj) {
-          x = w;
-          s += 2.0 * (double)w * (double)w;
-        } else if (gi == gj) {
-          x = 0.5f * (w - 1.0f);
-          s += ((double)w - 1.0) * ((double)w - 1.0);
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
+      const int gi0 = t.m0 + r, gj = t.n0 + c;
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const int gi = gi0 + q;
+        const float w = CS(r + q, c);
+        x[q] = 0.f;
+        if (gi < M && gj < M) {
+          if (gi > gj) {
+            x[q] = w;
+            s += 2.0 * (double)w * (double)w;
+          } else if (gi == gj) {
+            x[q] = 0.5f * (w - 1.0f);
+            s += ((double)w - 1.0) * ((double)w - 1.0);
+          }
         }
-        Xt[(long)gj * ld + gi] = from_f32<T>(x);
       }
+      st_pack(Xt + (long)gj * ld + gi0, x);
     }
     s = tile_sum<C>(s, Cs);
     if (threadIdx.x == 0) part[t.ti] = s;
@@ -120,25 +261,46 @@ struct EpiNgUpdate {
   double *resid_out, *scal;
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
-    TILE_LOOP(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      float v = 0.f;
-      if (gi < M && gj < M) {
-        v = gi >= gj ? L[(long)gi * ld + gj] - gamma * CS(r, c) : 0.f;
-        Ln[(long)gi * ld + gj] = v;
-        if constexpr (!std::is_same<T, float>::value) LnT[(long)gi * ld + gj] = from_f32<T>(v);
-        if (Lout && gi >= gj) Lout[(long)gi * M + gj] = v;
+    using K = Chunks<C>;
+    float lv[K::N][VEC];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      ld_pack(L + (long)(t.m0 + r) * ld + t.n0 + c, lv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      const int gi = t.m0 + r, gj0 = t.n0 + c;
+      float v[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const int gj = gj0 + q;
+        v[q] = (gi < M && gj < M && gi >= gj) ? lv[k][q] - gamma * CS(r, c + q) : 0.f;
       }
-      Cs[r * C::LDC + c] = v;
+      st_pack(Ln + (long)gi * ld + gj0, v);
+      if constexpr (!std::is_same<T, float>::value) st_pack(LnT + (long)gi * ld + gj0, v);
+      if (Lout && gi < M) {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+          if (gj0 + q <= gi) Lout[(long)gi * M + gj0 + q] = v[q];
+      }
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + c + q] = v[q];
     }
     __syncthreads();
-    TILE_LOOP_T(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < M) {
-        const float v = CS(r, c);
-        LntT[(long)gj * ld + gi] = from_f32<T>(v);
-        if constexpr (!std::is_same<T, float>::value) Lnt32[(long)gj * ld + gi] = v;
-      }
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
+      const int gi0 = t.m0 + r, gj = t.n0 + c;
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = CS(r + q, c);
+      st_pack(LntT + (long)gj * ld + gi0, x);
+      if constexpr (!std::is_same<T, float>::value) st_pack(Lnt32 + (long)gj * ld + gi0, x);
     }
     if (t.ti == 0) {
       double s = 0.0;
@@ -157,6 +319,8 @@ struct EpiNgUpdate {
 // Tile of E = L^T S~ L with W = L^T K~ L already stored (lower tiles) in W.
 // Writes Q = 2I - W and Wu = W - E (fp32, symmetric, mirrored), Q in the
 // operand type (mirrored), and per-tile partials [tr W, sum Q o Wu, ||W - I||^2].
+// Only lower-triangle elements are used; the upper triangle is their mirror.
+// Needs one extra staged tile of LDS (BM * LDC floats).
 template <typename T>
 struct EpiBoundGram {
   const float *W;
@@ -166,32 +330,74 @@ struct EpiBoundGram {
   int M;
   double *part;  // [ntiles][3]
   template <class C>
-  IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+  IFS_DEV void run(float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
+    float *S2 = Cs + C::BM * C::LDC + 4 * C::NT;  // staged Wu tile
+    float wv[K::N][VEC];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      ld_pack(W + (long)(t.m0 + r) * ld + t.n0 + c, wv[k]);
+    }
     double trw = 0.0, qwu = 0.0, r2 = 0.0;
-    TILE_LOOP(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < M && gi >= gj) {
-        const float w = W[(long)gi * ld + gj];
-        const float e = CS(r, c);
-        const float q = (gi == gj ? 2.f : 0.f) - w;
-        const float wu = w - e;
-        Q[(long)gi * ld + gj] = q;
-        QT[(long)gi * ld + gj] = from_f32<T>(q);
-        Wu[(long)gi * ld + gj] = wu;
-        const double mult = gi == gj ? 1.0 : 2.0;
-        if (gi == gj) trw += w;
-        qwu += mult * (double)q * (double)wu;
-        const double d = (double)w - (gi == gj ? 1.0 : 0.0);
-        r2 += mult * d * d;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      const int gi = t.m0 + r;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const int gj = t.n0 + c + q;
+        const bool in = gi < M && gj < M;
+        const float w = wv[k][q];
+        const float qv = in ? (gi == gj ? 2.f : 0.f) - w : 0.f;
+        const float wu = in ? w - CS(r, c + q) : 0.f;
+        if (in && gi >= gj) {
+          const double mult = gi == gj ? 1.0 : 2.0;
+          if (gi == gj) trw += w;
+          qwu += mult * (double)qv * (double)wu;
+          const double d = (double)w - (gi == gj ? 1.0 : 0.0);
+          r2 += mult * d * d;
+        }
+        Cs[r * C::LDC + c + q] = qv;
+        S2[r * C::LDC + c + q] = wu;
       }
     }
-    TILE_LOOP_T(C, r, c) {
+    __syncthreads();
+    const bool diag = t.m0 == t.n0;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < M && gi > gj) {
-        const float w = W[(long)gi * ld + gj];
-        Q[(long)gj * ld + gi] = -w;
-        QT[(long)gj * ld + gi] = from_f32<T>(-w);
-        Wu[(long)gj * ld + gi] = w - CS(r, c);
+      float xq[VEC], xw[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const bool up = diag && r < c + q;  // upper triangle of a diagonal tile: mirror
+        const int rr = up ? c + q : r, cc = up ? r : c + q;
+        xq[q] = Cs[rr * C::LDC + cc];
+        xw[q] = S2[rr * C::LDC + cc];
+      }
+      st_pack(Q + (long)gi * ld + gj, xq);
+      st_pack(QT + (long)gi * ld + gj, xq);
+      st_pack(Wu + (long)gi * ld + gj, xw);
+    }
+    if (!diag) {
+#pragma unroll
+      for (int k = 0; k < K::N; ++k) {
+        int r, c;
+        K::col(k, r, c);
+        const int gi0 = t.m0 + r, gj = t.n0 + c;
+        float xq[VEC], xw[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          xq[q] = Cs[(r + q) * C::LDC + c];
+          xw[q] = S2[(r + q) * C::LDC + c];
+        }
+        st_pack(Q + (long)gj * ld + gi0, xq);
+        st_pack(QT + (long)gj * ld + gi0, xq);
+        st_pack(Wu + (long)gj * ld + gi0, xw);
       }
     }
     trw = tile_sum<C>(trw, Cs);
@@ -216,13 +422,26 @@ struct EpiV {
   int M, B;
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
-    TILE_LOOP(C, r, c) {
+    using K = Chunks<C>;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M) V[(long)gi * ldv + gj] = from_f32<T>(gj < B ? CS(r, c) : 0.f);
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = (gi < M && gj + q < B) ? CS(r, c + q) : 0.f;
+      st_pack(V + (long)gi * ldv + gj, x);
     }
-    TILE_LOOP_T(C, r, c) {
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M) Vt[(long)gj * ldt + gi] = from_f32<T>(gj < B ? CS(r, c) : 0.f);
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < M && gj < B) ? CS(r + q, c) : 0.f;
+      st_pack(Vt + (long)gj * ldt + gi, x);
     }
   }
 };
@@ -239,33 +458,44 @@ struct EpiU {
   long ldp;
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
-    TILE_LOOP_T(C, r, c) {
+    using K = Chunks<C>;
+    float vv[K::N][VEC];  // the V tile, loaded before anything waits on it
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      ld_pack(V + (long)(t.m0 + r) * ldv + t.n0 + c, vv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
-      if (gi < M && gj < B) Ut[(long)gj * ldt + gi] = from_f32<T>(CS(r, c));
+      float x[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < M && gj < B) ? CS(r + q, c) : 0.f;
+      st_pack(Ut + (long)gj * ldt + gi, x);
     }
     __syncthreads();
-    // V o U in place (independent, coalesced loads of the V tile), then column sums in LDS
-    TILE_LOOP(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      const float v = (gi < M && gj < B) ? to_f32(V[(long)gi * ldv + gj]) : 0.f;
-      Cs[r * C::LDC + c] = v * CS(r, c);
+    // V o U in place (V padding is zero), then column sums
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + c + q] = vv[k][q] * CS(r, c + q);
     }
     __syncthreads();
-    float *sh = Cs + C::BM * C::LDC;
-    constexpr int RG = C::NT / C::BN;  // row groups per column
-    static_assert(C::NT % C::BN == 0, "column partial layout");
-    const int c = threadIdx.x % C::BN, g = threadIdx.x / C::BN;
-    const int gj = t.n0 + c;
-    float s = 0.f;
-    for (int r = g; r < C::BM; r += RG) s += CS(r, c);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (g == 0 && gj < B) {
-      for (int k = 1; k < RG; ++k) s += sh[k * C::BN + c];
-      var_part[(long)(t.m0 / C::BM) * ldp + gj] = s;
-    }
+    const float s = tile_colsum<C>(Cs);
+    const int c = threadIdx.x % C::BN, gj = t.n0 + c;
+    if (threadIdx.x < C::BN && gj < B) var_part[(long)(t.m0 / C::BM) * ldp + gj] = s;
   }
 };
+
+// Staged inputs for the D-wide MFMA reductions: D4 = D rounded up to 4 columns
+// of data, a ones column at D4, width DP rounded up to 16.
+__host__ __device__ inline int d4of(int D) { return (D + 3) & ~3; }
+__host__ __device__ inline int dpof(int D) { return ((d4of(D) + 1 + 15) / 16) * 16; }
 
 // ---------------------------------------------------------------- backward K_uf side
 // Tile of R = L U.  Forms G_uf = (L b) alpha^T - 2 R diag(beta), recomputes the
@@ -274,6 +504,8 @@ struct EpiU {
 //   hcol[n]    = sum_i H_in                 (per m-tile partial)
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
 //   sum H                                   (per tile partial)
+// hrow and hx come from one fp32 MFMA product H [Xs | 1].
+// Extra LDS: (BM * D4 + BN * DP) floats (D4, DP: d4of, dpof).
 struct EpiGradUf {
   const float *Lb, *alpha, *beta;
   const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
@@ -286,89 +518,105 @@ struct EpiGradUf {
   double *part; // [ntiles]
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
-    const int D4 = (D + 3) & ~3;
+    const int D4 = d4of(D), DP = dpof(D);
     float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][D4]
-    float *xs = zs + BM * D4;               // [BN][D4]
-    for (int i = threadIdx.x; i < BM * D4; i += NT) {
-      const int r = i / D4, d = i % D4, gi = t.m0 + r;
-      zs[i] = (gi < M && d < D) ? Zs[(long)gi * D + d] : 0.f;
+    float *xs = zs + BM * D4;               // [BN][DP], ones column at D4
+    // per-thread operands, issued before the staging waits
+    int r0, c;
+    K::row(0, r0, c);
+    const int gj0 = t.n0 + c;
+    float al[VEC], be[VEC], lb[K::N];
+    {
+      const Pack<float> a = *(const Pack<float> *)(alpha + gj0);
+      const Pack<float> b = *(const Pack<float> *)(beta + gj0);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        al[q] = a.v[q];
+        be[q] = b.v[q];
+      }
     }
-    for (int i = threadIdx.x; i < BN * D4; i += NT) {
-      const int c = i / D4, d = i % D4, gj = t.n0 + c;
-      xs[i] = (gj < B && d < D) ? Xs[(long)gj * D + d] : 0.f;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, cc;
+      K::row(k, r, cc);
+      lb[k] = Lb[t.m0 + r];
     }
+    stage_rows<NT>(zs, D4, Zs, t.m0, BM, M, D, -1);
+    stage_rows<NT>(xs, DP, Xs, t.n0, BN, B, D, D4);
     __syncthreads();
+    // squared scaled distances for the thread's chunks: its 8 columns' inputs
+    // are read once per 4 dimensions and reused over its rows
+    float d2[K::N][VEC];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) d2[k][q] = 0.f;
+    for (int d0 = 0; d0 < D4; d0 += 4) {
+      f32x4 xv[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) xv[q] = *(const f32x4 *)(xs + (c + q) * DP + d0);
+#pragma unroll
+      for (int k = 0; k < K::N; ++k) {
+        int r, cc;
+        K::row(k, r, cc);
+        const f32x4 zv = *(const f32x4 *)(zs + r * D4 + d0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float df = zv[j] - xv[q][j];
+            d2[k][q] = fmaf(df, df, d2[k][q]);
+          }
+      }
+    }
     const float s2f = *sf2;
     double hs = 0.0;
-    TILE_LOOP(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      float h = 0.f;
-      if (gi < M && gj < B) {
-        float d2 = 0.f;
-        for (int d = 0; d < D; ++d) {
-          const float df = zs[r * D4 + d] - xs[c * D4 + d];
-          d2 = fmaf(df, df, d2);
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, cc;
+      K::row(k, r, cc);
+      const int gi = t.m0 + r;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        float h = 0.f;
+        if (gi < M && gj0 + q < B) {
+          const float kuf = s2f * __expf(-0.5f * d2[k][q]);
+          const float g = lb[k] * al[q] - 2.f * CS(r, c + q) * be[q];
+          h = g * kuf;
+          hs += h;
         }
-        const float kuf = s2f * __expf(-0.5f * d2);
-        const float g = Lb[gi] * alpha[gj] - 2.f * CS(r, c) * beta[gj];
-        h = g * kuf;
-        hs += h;
+        Cs[r * C::LDC + c + q] = h;
       }
-      Cs[r * C::LDC + c] = h;
     }
     __syncthreads();
     hs = tile_sum<C>(hs, Cs);
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int nti = t.n0 / BN, mti = t.m0 / BM;
-    for (int c = threadIdx.x; c < BN; c += NT) {
-      const int gj = t.n0 + c;
-      if (gj < B) {
-        float s = 0.f;
-        for (int r = 0; r < BM; ++r) s += CS(r, c);
-        hcol[(long)mti * ldc + gj] = s;
-      }
+    {
+      const float s = tile_colsum<C>(Cs);
+      const int cl = threadIdx.x % BN, gj = t.n0 + cl;
+      if (threadIdx.x < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
     }
-    for (int r = threadIdx.x; r < BM; r += NT) {
-      const int gi = t.m0 + r;
-      if (gi < M) {
-        float s = 0.f;
-        for (int c = 0; c < BN; ++c) s += CS(r, c);
-        hrow[(long)nti * M + gi] = s;
+    const int D_ = D, M_ = M;
+    float *hrow_ = hrow + (long)nti * M, *hx_ = hx + (long)nti * M * D;
+    lds_mfma_f32<NT / 64, false>(Cs, C::LDC, BM, BN, xs, DP, DP, [&](int i, int d, float v) {
+      const int gi = t.m0 + i;
+      if (gi < M_) {
+        if (d < D_) hx_[(long)gi * D_ + d] = v;
+        else if (d == D4) hrow_[gi] = v;
       }
-    }
-    // hx = H Xs over the tile's columns, 4 x 4 register blocks of (r, d)
-    const int nd4 = D4 / 4;
-    for (int b = threadIdx.x; b < (BM / 4) * nd4; b += NT) {
-      const int r4 = (b / nd4) * 4, d4 = (b % nd4) * 4;
-      float a[4][4] = {};
-      for (int c = 0; c < BN; ++c) {
-        float hv[4], xv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = CS(r4 + i, c);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = xs[c * D4 + d4 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[i][j] = fmaf(hv[i], xv[j], a[i][j]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gi = t.m0 + r4 + i;
-        if (gi < M)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (d4 + j < D) hx[((long)nti * M + gi) * D + d4 + j] = a[i][j];
-      }
-    }
+    });
   }
 };
 
 // ---------------------------------------------------------------- backward K_uu side
 // Tile (I >= J) of G_uu = Y2 L^T.  H = G_uu o K_uu with K_uu = K~ - diag(s~).
 // For rows of block I (slot J): hz[i][d] = sum_j H_ij Zs_jd and hzrow[i] = sum_j H_ij;
-// for an off-diagonal tile also rows of block J (slot I) through H^T.
+// for an off-diagonal tile also rows of block J (slot I) through H^T.  Both come
+// from fp32 MFMA products with [Zs | 1].
+// Extra LDS: 2 * BM * DP floats (DP: dpof).
 struct EpiGradUu {
   const float *Kt, *s, *Zs;
   long ld;
@@ -378,96 +626,73 @@ struct EpiGradUu {
   double *part;  // [ntiles]
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     static_assert(BM == BN, "symmetric tiles");
-    const int D4 = (D + 3) & ~3;
-    float *zi = Cs + BM * C::LDC + 4 * NT;  // rows of block I  [BM][D4]
-    float *zj = zi + BM * D4;               // rows of block J  [BN][D4]
-    for (int i = threadIdx.x; i < BM * D4; i += NT) {
-      const int r = i / D4, d = i % D4;
-      const int gi = t.m0 + r, gj = t.n0 + r;
-      zi[i] = (gi < M && d < D) ? Zs[(long)gi * D + d] : 0.f;
-      zj[i] = (gj < M && d < D) ? Zs[(long)gj * D + d] : 0.f;
+    const int D4 = d4of(D), DP = dpof(D);
+    float *zi = Cs + BM * C::LDC + 4 * NT;  // rows of block I  [BM][DP]
+    float *zj = zi + BM * DP;               // rows of block J  [BN][DP]
+    float kv[K::N][VEC];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      ld_pack(Kt + (long)(t.m0 + r) * ld + t.n0 + c, kv[k]);
     }
+    float sv[K::N];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      sv[k] = t.m0 + r < M ? s[t.m0 + r] : 0.f;
+    }
+    stage_rows<NT>(zi, DP, Zs, t.m0, BM, M, D, D4);
+    stage_rows<NT>(zj, DP, Zs, t.n0, BN, M, D, D4);
     double hs = 0.0;
     const bool off = t.m0 != t.n0;
-    TILE_LOOP(C, r, c) {
-      const int gi = t.m0 + r, gj = t.n0 + c;
-      float h = 0.f;
-      if (gi < M && gj < M) {
-        const float k = Kt[(long)gi * ld + gj] - (gi == gj ? s[gi] : 0.f);
-        h = CS(r, c) * k;
-        hs += (off ? 2.0 : 1.0) * h;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      const int gi = t.m0 + r;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const int gj = t.n0 + c + q;
+        float h = 0.f;
+        if (gi < M && gj < M) {
+          const float kk = kv[k][q] - (gi == gj ? sv[k] : 0.f);
+          h = CS(r, c + q) * kk;
+          hs += (off ? 2.0 : 1.0) * h;
+        }
+        Cs[r * C::LDC + c + q] = h;
       }
-      Cs[r * C::LDC + c] = h;
     }
     __syncthreads();
     hs = tile_sum<C>(hs, Cs);
     if (threadIdx.x == 0) part[t.ti] = hs;
-    const int I = t.m0 / BM, J = t.n0 / BN;
-    const int nd4 = D4 / 4;
-    for (int r = threadIdx.x; r < BM; r += NT) {
-      const int gi = t.m0 + r;
-      if (gi < M) {
-        float s_ = 0.f;
-        for (int c = 0; c < BN; ++c) s_ += CS(r, c);
-        hzrow[(long)J * M + gi] = s_;
-      }
-    }
-    for (int b = threadIdx.x; b < (BM / 4) * nd4; b += NT) {
-      const int r4 = (b / nd4) * 4, d4 = (b % nd4) * 4;
-      float a[4][4] = {};
-      for (int c = 0; c < BN; ++c) {
-        float hv[4], zv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = CS(r4 + i, c);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) zv[j] = zj[c * D4 + d4 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[i][j] = fmaf(hv[i], zv[j], a[i][j]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gi = t.m0 + r4 + i;
-        if (gi < M)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (d4 + j < D) hz[((long)J * M + gi) * D + d4 + j] = a[i][j];
-      }
+    const int I = t.m0 / BM, J = t.n0 / BN, D_ = D, M_ = M;
+    {
+      float *hz_ = hz + (long)J * M * D, *hr_ = hzrow + (long)J * M;
+      const int base = t.m0;
+      lds_mfma_f32<NT / 64, false>(Cs, C::LDC, BM, BN, zj, DP, DP, [&](int i, int d, float v) {
+        const int gi = base + i;
+        if (gi < M_) {
+          if (d < D_) hz_[(long)gi * D_ + d] = v;
+          else if (d == D4) hr_[gi] = v;
+        }
+      });
     }
     if (!off) return;
-    for (int c = threadIdx.x; c < BN; c += NT) {
-      const int gj = t.n0 + c;
-      if (gj < M) {
-        float s_ = 0.f;
-        for (int r = 0; r < BM; ++r) s_ += CS(r, c);
-        hzrow[(long)I * M + gj] = s_;
-      }
-    }
-    for (int b = threadIdx.x; b < (BN / 4) * nd4; b += NT) {
-      const int c4 = (b / nd4) * 4, d4 = (b % nd4) * 4;
-      float a[4][4] = {};
-      for (int r = 0; r < BM; ++r) {
-        float hv[4], zv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = CS(r, c4 + i);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) zv[j] = zi[r * D4 + d4 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[i][j] = fmaf(hv[i], zv[j], a[i][j]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gj = t.n0 + c4 + i;
-        if (gj < M)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (d4 + j < D) hz[((long)I * M + gj) * D + d4 + j] = a[i][j];
-      }
+    {
+      float *hz_ = hz + (long)I * M * D, *hr_ = hzrow + (long)I * M;
+      const int base = t.n0;
+      lds_mfma_f32<NT / 64, true>(Cs, C::LDC, BN, BM, zi, DP, DP, [&](int i, int d, float v) {
+        const int gj = base + i;
+        if (gj < M_) {
+          if (d < D_) hz_[(long)gj * D_ + d] = v;
+          else if (d == D4) hr_[gj] = v;
+        }
+      });
     }
   }
 };

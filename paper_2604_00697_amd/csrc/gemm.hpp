@@ -186,37 +186,53 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
   auto compute = [&](int buf) {
     const T *a = As + buf * BM * LDK + (wm * C::WM + lr) * LDK;
     const T *b = Bs + buf * BN * LDK + (wn * C::WN + lr) * LDK;
+    // all fragments of the k-tile are read before the first MFMA
+    V av[2][C::TM], bv[2][C::TN];
 #pragma unroll
     for (int kc = 0; kc < 2; ++kc) {
       const int koff = kc * 4 * KPL + kq * KPL;
-      V av[C::TM], bv[C::TN];
 #pragma unroll
-      for (int i = 0; i < C::TM; ++i) av[i] = *(const V *)(a + i * 16 * LDK + koff);
+      for (int i = 0; i < C::TM; ++i) av[kc][i] = *(const V *)(a + i * 16 * LDK + koff);
 #pragma unroll
-      for (int j = 0; j < C::TN; ++j) bv[j] = *(const V *)(b + j * 16 * LDK + koff);
+      for (int j = 0; j < C::TN; ++j) bv[kc][j] = *(const V *)(b + j * 16 * LDK + koff);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-        for (int j = 0; j < C::TN; ++j) acc[i][j] = mfma16(av[i], bv[j], acc[i][j]);
-    }
+        for (int j = 0; j < C::TN; ++j) acc[i][j] = mfma16(av[kc][i], bv[kc][j], acc[i][j]);
   };
 
-#pragma unroll
-  for (int s = 0; s < P; ++s)
-    if (s < nk) fetch(s, kb + s * BK);
-  // k-tile `it` lives in register set it % P and LDS buffer it % 2; the loop is
-  // unrolled by P so register sets are indexed at compile time.
-  for (int it0 = 0; it0 < nk; it0 += P) {
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      const int it = it0 + u;
-      if (it < nk) {
-        const int buf = it & 1;
-        stash(u, buf);
-        __syncthreads();
-        if (it + P < nk) fetch(u, kb + (it + P) * BK);
-        compute(buf);
-      }
+  // k-tile `it` lives in register set it % P and LDS buffer it % 2.  Fetch
+  // addresses are clamped to the last k-tile (a harmless re-read), so the
+  // steady-state loop has no branches and the accumulators stay in place.
+  static_assert(P == 2, "the main loop is unrolled for two register sets");
+  auto kclamp = [&](int it) { return kb + min(it, nk - 1) * BK; };
+  if (nk > 0) {
+    fetch(0, kclamp(0));
+    fetch(1, kclamp(1));
+    int it = 0;
+    // scheduling fences keep each fetch ahead of the compute that hides it
+    for (; it + 2 <= nk; it += 2) {
+      stash(0, 0);
+      __syncthreads();
+      fetch(0, kclamp(it + 2));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      stash(1, 1);
+      __syncthreads();
+      fetch(1, kclamp(it + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (it < nk) {
+      stash(0, 0);
+      __syncthreads();
+      compute(0);
     }
   }
   __syncthreads();

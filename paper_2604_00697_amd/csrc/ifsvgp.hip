@@ -442,7 +442,7 @@ struct Ops {
     Opnd<T> a{LtT(c, cur), c->Mp, c->sP}, b{LtT(c, cur), c->Mp, nullptr};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiBoundGram<T> e{c->W32, c->Q32, c->Wu32, (T *)c->QT, c->Mp, c->M, c->tp_gram};
-    return launch_gemm<CS, true, false>(c->st, a, b, sc, e);
+    return launch_gemm<CS, true, false>(c->st, a, b, sc, e, CS::BM * CS::LDC * 4);
   }
   // V = L^T K_uf (k >= m0) -> V, Vt
   static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
@@ -465,8 +465,8 @@ struct Ops {
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
     EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    const int D4 = (D + 3) & ~3;
-    return launch_gemm<CR, false, false>(c->st, a, b, sc, e, (CR::BM + CR::BN) * D4 * 4);
+    return launch_gemm<CR, false, false>(c->st, a, b, sc, e,
+                                         (CR::BM * d4of(D) + CR::BN * dpof(D)) * 4);
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
@@ -493,8 +493,7 @@ struct Ops {
     Opnd<TW> a{(const TW *)c->Y2, c->Mp, nullptr}, b{LW(c, cur), c->Mp, nullptr};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
     EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu};
-    const int D4 = (D + 3) & ~3;
-    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e, 2 * CSW::BM * D4 * 4);
+    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e, 2 * CSW::BM * dpof(D) * 4);
   }
 };
 
