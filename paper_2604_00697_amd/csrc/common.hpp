@@ -52,6 +52,16 @@ IFS_DEV f32x4 mfma16(const f16x8 &a, const f16x8 &b, f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
 }
 
+// ---------------------------------------------------------------- guarded loads
+// p[i] if ok, else 0, without a branch around the load: the address falls back
+// to p[0] (every array passed here is non-empty), so loads issued back to back
+// stay in flight together instead of each waiting behind its own branch.
+template <typename F>
+IFS_DEV F ld_or0(const F *p, long i, bool ok) {
+  const F v = p[ok ? i : 0];
+  return ok ? v : F(0);
+}
+
 // ---------------------------------------------------------------- reductions
 IFS_DEV float wave_sum(float v) {
 #pragma unroll
@@ -78,6 +88,90 @@ IFS_DEV double block_sum(double v, double *sh /* >= NT/64 */) {
   }
   __syncthreads();
   return r;
+}
+
+// Stages rows [g0, g0 + R) of a row-major [n][D] array into LDS as [R][ld]
+// (ld > D).  The real rows are one contiguous run of floats in global memory,
+// read as 16-byte vectors, up to 8 in flight per thread; every other element
+// (columns >= D, rows >= n) is written as 0, except column onecol (if >= D),
+// which holds 1 on real rows and turns a row sum into one more output column
+// of a reduction product.  Rows whose start is not 16-byte aligned are read
+// with scalar loads.
+template <int NT>
+IFS_DEV void stage_rows(float *dst, int ld, const float *src, int g0, int R, int n, int D,
+                        int onecol) {
+  const int tid = threadIdx.x;
+  const int rows = max(0, min(R, n - g0));
+  const int nreal = rows * D;
+  const float *sp = src + (long)g0 * D;
+  const int n4 = ((uintptr_t)sp & 15) ? 0 : nreal / 4;
+  for (int b0 = 0; b0 < n4; b0 += 8 * NT) {
+    f32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = b0 + u * NT + tid;
+      v[u] = *(const f32x4 *)(sp + 4 * (q < n4 ? q : 0));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = b0 + u * NT + tid;
+      if (q < n4)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = 4 * q + j;
+          dst[(e / D) * ld + e % D] = v[u][j];
+        }
+    }
+  }
+  for (int e0 = 4 * n4; e0 < nreal; e0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld_or0(sp, e0 + u * NT + tid, e0 + u * NT + tid < nreal);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT + tid;
+      if (e < nreal) dst[(e / D) * ld + e % D] = v[u];
+    }
+  }
+  const int padc = ld - D;
+  for (int i = tid; i < R * padc; i += NT) {
+    const int r = i / padc, d = D + i % padc;
+    dst[r * ld + d] = (r < rows && d == onecol) ? 1.f : 0.f;
+  }
+  for (int i = tid; i < (R - rows) * D; i += NT) dst[(rows + i / D) * ld + i % D] = 0.f;
+}
+
+// ---------------------------------------------------------------- SE kernel tiles
+// Squared scaled distance from norms and cross term (the cross term comes from
+// fp32 MFMA); clamped at 0 against rounding.
+IFS_DEV float kern_se(float sf2, float zn, float xn, float cross) {
+  return sf2 * __expf(-0.5f * fmaxf(zn + xn - 2.f * cross, 0.f));
+}
+
+// Cross terms C[i][j] = sum_d A[i][d] B[j][d] of a (16 TI) x (16 TJ) block
+// from LDS rows A (stride lda) and B (stride ldb), d < D4 (a multiple of 4,
+// zero-padded), with 16x16x4 fp32 MFMA on TI x TJ independent accumulators:
+// acc[i][j][q] = C[16 i + 4 (lane/16) + q][16 j + lane % 16].
+template <int TI, int TJ>
+IFS_DEV void cross_block(const float *A, int lda, const float *B, int ldb, int D4,
+                         f32x4 (&acc)[TI][TJ]) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, l4 = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int d0 = 0; d0 < D4; d0 += 4) {
+    float a[TI], b[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) a[i] = A[(i * 16 + l16) * lda + d0 + l4];
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) b[j] = B[(j * 16 + l16) * ldb + d0 + l4];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
 }
 
 // Device-side error flags (sticky until read by the host).

@@ -91,49 +91,36 @@ IFS_DEV float tile_colsum(const float *Cs) {
 // Small fp32 MFMA product of LDS operands, used for the D-wide reductions of
 // the gradient epilogues:  Out[i][d] = sum_k A[i][k] Z[k][d],  i < R, d < DP,
 // with A = H (row-major, stride ldh) or, TRANS, A = H^T.  Z is row-major
-// [K][ldz].  R, K and DP are multiples of 16, 4 and 16.  Each 16 x 16 output
-// tile goes to sink(i, d, value) from the lane that holds it.
-template <int NW, bool TRANS, class F>
-IFS_DEV void lds_mfma_f32(const float *H, int ldh, int R, int K, const float *Z, int ldz,
-                          int DP, F &&sink) {
+// [K][ldz].  R = 16 * TI * NW (each wave owns TI row tiles), K a multiple of 4,
+// DP a multiple of 32 (d tiles in pairs).  Each output element goes to
+// sink(i, d, value) from the lane that holds it.
+template <int NW, int TI, bool TRANS, class F>
+IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ldz, int DP,
+                          F &&sink) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int ndt = DP / 16, nt = (R / 16) * ndt;
-  for (int tix = wave; tix < nt; tix += NW) {
-    const int i0 = (tix / ndt) * 16, d0 = (tix % ndt) * 16;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
+  const int ib = wave * TI * 16;
+  for (int d0 = 0; d0 < DP; d0 += 32) {
+    f32x4 acc[TI][2];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
     for (int k0 = 0; k0 < K; k0 += 4) {
-      const float a = TRANS ? H[(k0 + l4) * ldh + i0 + l16] : H[(i0 + l16) * ldh + k0 + l4];
-      const float b = Z[(k0 + l4) * ldz + d0 + l16];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      const float b0 = Z[(k0 + l4) * ldz + d0 + l16], b1 = Z[(k0 + l4) * ldz + d0 + 16 + l16];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const int r = ib + 16 * i + l16;
+        const float a = TRANS ? H[(k0 + l4) * ldh + r] : H[r * ldh + k0 + l4];
+        acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[i][0], 0, 0, 0);
+        acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[i][1], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sink(i0 + 4 * l4 + q, d0 + l16, acc[q]);
-  }
-}
-
-// Stages rows [g0, g0 + R) of a row-major [n][D] array into LDS as [R][ld],
-// zero-padded past D and past n; column onecol (if >= D) holds 1 for real rows,
-// turning a row sum into one more output column of lds_mfma_f32.
-template <int NT>
-IFS_DEV void stage_rows(float *dst, int ld, const float *src, int g0, int R, int n, int D,
-                        int onecol) {
-  const int tot = R * ld;
-  for (int i0 = 0; i0 < tot; i0 += 8 * NT) {
-    float v[8];
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * NT + (int)threadIdx.x;
-      const int r = i / ld, d = i % ld, g = g0 + r;
-      v[u] = (i < tot && g < n && d < D) ? src[(long)g * D + d] : 0.f;
-      if (i < tot && g < n && d == onecol) v[u] = 1.f;
-    }
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * NT + (int)threadIdx.x;
-      if (i < tot) dst[i] = v[u];
-    }
+        for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, d0 + 16 * h + l16, acc[i][h][q]);
   }
 }
 
@@ -244,14 +231,17 @@ struct EpiNgGram {
 // ---------------------------------------------------------------- NG update
 // Lnew = L - gamma * (L X) on lower tiles (strict upper inside diagonal tiles
 // written as 0; upper tiles are never touched and stay zero).  Writes the fp32
-// master, the operand copy, the operand-type and fp32 transposes, and, on the
-// last step of a call, the caller's L (lower triangle only).  Tile 0 also
+// master, the operand copy, the operand-type and fp32 transposes, the
+// transpose scaled by s~ along k, and, on the last step of a call, the
+// caller's L (lower triangle only).  Tile 0 also
 // turns the gram partials of this step into the residual ||W - I||_F/sqrt(M).
 template <typename T>
 struct EpiNgUpdate {
   const float *L;
   float *Ln, *Lnt32;  // Lnt32 aliases LntT when T is float
   T *LnT, *LntT;      // LnT aliases Ln when T is float
+  const float *sP;    // s~, zero-padded
+  T *LnsT;            // LnsT[j][i] = Lnew[i][j] s~_i
   long ld;
   int M;
   float gamma;
@@ -301,6 +291,11 @@ struct EpiNgUpdate {
       for (int q = 0; q < VEC; ++q) x[q] = CS(r + q, c);
       st_pack(LntT + (long)gj * ld + gi0, x);
       if constexpr (!std::is_same<T, float>::value) st_pack(Lnt32 + (long)gj * ld + gi0, x);
+      float sv[VEC];
+      ld_pack(sP + gi0, sv);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[q] *= sv[q];
+      st_pack(LnsT + (long)gj * ld + gi0, x);
     }
     if (t.ti == 0) {
       double s = 0.0;
@@ -493,19 +488,25 @@ struct EpiU {
 };
 
 // Staged inputs for the D-wide MFMA reductions: D4 = D rounded up to 4 columns
-// of data, a ones column at D4, width DP rounded up to 16.
+// of data, a ones column at D4, width DP rounded up to 32.
 __host__ __device__ inline int d4of(int D) { return (D + 3) & ~3; }
-__host__ __device__ inline int dpof(int D) { return ((d4of(D) + 1 + 15) / 16) * 16; }
+__host__ __device__ inline int dpof(int D) { return ((d4of(D) + 1 + 31) / 32) * 32; }
 
 // ---------------------------------------------------------------- backward K_uf side
-// Tile of R = L U.  Forms G_uf = (L b) alpha^T - 2 R diag(beta), recomputes the
-// K_uf tile from the scaled inputs staged in LDS, and reduces H = G_uf o K_uf to
+// Tile of R = L U, taken straight from the accumulators.  Forms
+// G_uf = (L b) alpha^T - 2 R diag(beta), recomputes the K_uf tile (norms plus
+// an fp32 MFMA cross term, as in the forward), and reduces
+// H = G_uf o K_uf to
 //   hrow[i]    = sum_n H_in                 (per n-tile partial)
 //   hcol[n]    = sum_i H_in                 (per m-tile partial)
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
 //   sum H                                   (per tile partial)
 // hrow and hx come from one fp32 MFMA product H [Xs | 1].
-// Extra LDS: (BM * D4 + BN * DP) floats (D4, DP: d4of, dpof).
+// Extra LDS: graduf_extra(BM, BN, D) bytes.
+__host__ __device__ inline int graduf_extra(int BM, int BN, int D) {
+  const int D4 = d4of(D), LDX = dpof(D) + 1;
+  return (BM * (D4 + 1) + BN * LDX + 2 * BM + 3 * BN) * 4;
+}
 struct EpiGradUf {
   const float *Lb, *alpha, *beta;
   const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
@@ -516,92 +517,76 @@ struct EpiGradUf {
   long ldc;
   float *hx;    // [n-tiles][M][D]
   double *part; // [ntiles]
+  static constexpr bool kRegs = true;  // takes the accumulators in registers
   template <class C>
-  IFS_DEV void run(float *Cs, const TileInfo &t) const {
-    using K = Chunks<C>;
+  IFS_DEV void run_regs(const f32x4 (&acc)[C::TM][C::TN], float *Cs, const TileInfo &t) const {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
-    const int D4 = d4of(D), DP = dpof(D);
-    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][D4]
-    float *xs = zs + BM * D4;               // [BN][DP], ones column at D4
-    // per-thread operands, issued before the staging waits
-    int r0, c;
-    K::row(0, r0, c);
-    const int gj0 = t.n0 + c;
-    float al[VEC], be[VEC], lb[K::N];
-    {
-      const Pack<float> a = *(const Pack<float> *)(alpha + gj0);
-      const Pack<float> b = *(const Pack<float> *)(beta + gj0);
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        al[q] = a.v[q];
-        be[q] = b.v[q];
-      }
+    const int D4 = d4of(D), DP = dpof(D), LDZ = D4 + 1, LDX = DP + 1;
+    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][LDZ]
+    float *xs = zs + BM * LDZ;              // [BN][LDX], ones column at D4
+    float *zn = xs + BN * LDX;              // [BM]
+    float *lb = zn + BM;                    // [BM]
+    float *xn = lb + BM;                    // [BN]
+    float *al = xn + BN;                    // [BN]
+    float *be = al + BN;                    // [BN]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < BM; i += NT) lb[i] = Lb[t.m0 + i];    // padded to Mp
+    for (int i = tid; i < BN; i += NT) {
+      al[i] = alpha[t.n0 + i];                                   // padded to Bp
+      be[i] = beta[t.n0 + i];
     }
-#pragma unroll
-    for (int k = 0; k < K::N; ++k) {
-      int r, cc;
-      K::row(k, r, cc);
-      lb[k] = Lb[t.m0 + r];
-    }
-    stage_rows<NT>(zs, D4, Zs, t.m0, BM, M, D, -1);
-    stage_rows<NT>(xs, DP, Xs, t.n0, BN, B, D, D4);
+    stage_rows<NT>(zs, LDZ, Zs, t.m0, BM, M, D, -1);
+    stage_rows<NT>(xs, LDX, Xs, t.n0, BN, B, D, D4);
     __syncthreads();
-    // squared scaled distances for the thread's chunks: its 8 columns' inputs
-    // are read once per 4 dimensions and reused over its rows
-    float d2[K::N][VEC];
-#pragma unroll
-    for (int k = 0; k < K::N; ++k)
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) d2[k][q] = 0.f;
-    for (int d0 = 0; d0 < D4; d0 += 4) {
-      f32x4 xv[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) xv[q] = *(const f32x4 *)(xs + (c + q) * DP + d0);
-#pragma unroll
-      for (int k = 0; k < K::N; ++k) {
-        int r, cc;
-        K::row(k, r, cc);
-        const f32x4 zv = *(const f32x4 *)(zs + r * D4 + d0);
-#pragma unroll
-        for (int q = 0; q < VEC; ++q)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float df = zv[j] - xv[q][j];
-            d2[k][q] = fmaf(df, df, d2[k][q]);
-          }
-      }
+    for (int i = tid; i < BM + BN; i += NT) {
+      const float *row = i < BM ? zs + i * LDZ : xs + (i - BM) * LDX;
+      float s = 0.f;
+      for (int d = 0; d < D4; ++d) s = fmaf(row[d], row[d], s);
+      (i < BM ? zn : xn)[i < BM ? i : i - BM] = s;
     }
+    __syncthreads();
     const float s2f = *sf2;
     double hs = 0.0;
+    {
+      // wave (wm, wn) owns the WM x WN sub-block it accumulated in the product;
+      // the cross term lands in the accumulators' lane layout
+      const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+      const int ib = (wave / C::WGN) * C::WM, jb = (wave % C::WGN) * C::WN;
+      f32x4 c[C::TM][C::TN];
+      cross_block<C::TM, C::TN>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
 #pragma unroll
-    for (int k = 0; k < K::N; ++k) {
-      int r, cc;
-      K::row(k, r, cc);
-      const int gi = t.m0 + r;
+      for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) {
-        float h = 0.f;
-        if (gi < M && gj0 + q < B) {
-          const float kuf = s2f * __expf(-0.5f * d2[k][q]);
-          const float g = lb[k] * al[q] - 2.f * CS(r, c + q) * be[q];
-          h = g * kuf;
-          hs += h;
+        for (int jj = 0; jj < C::TN; ++jj) {
+          const int n = jb + 16 * jj + l16;
+          const bool nok = t.n0 + n < B;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = ib + 16 * ii + 4 * l4 + q;
+            float h = 0.f;
+            if (nok && t.m0 + i < M) {
+              const float kuf = kern_se(s2f, zn[i], xn[n], c[ii][jj][q]);
+              const float g = lb[i] * al[n] - 2.f * acc[ii][jj][q] * be[n];
+              h = g * kuf;
+              hs += h;
+            }
+            Cs[i * C::LDC + n] = h;
+          }
         }
-        Cs[r * C::LDC + c + q] = h;
-      }
     }
     __syncthreads();
     hs = tile_sum<C>(hs, Cs);
-    if (threadIdx.x == 0) part[t.ti] = hs;
+    if (tid == 0) part[t.ti] = hs;
     const int nti = t.n0 / BN, mti = t.m0 / BM;
     {
       const float s = tile_colsum<C>(Cs);
-      const int cl = threadIdx.x % BN, gj = t.n0 + cl;
-      if (threadIdx.x < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
+      const int cl = tid % BN, gj = t.n0 + cl;
+      if (tid < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
     }
     const int D_ = D, M_ = M;
     float *hrow_ = hrow + (long)nti * M, *hx_ = hx + (long)nti * M * D;
-    lds_mfma_f32<NT / 64, false>(Cs, C::LDC, BM, BN, xs, DP, DP, [&](int i, int d, float v) {
+    lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, C::LDC, BN, xs, LDX, DP,
+                                                [&](int i, int d, float v) {
       const int gi = t.m0 + i;
       if (gi < M_) {
         if (d < D_) hx_[(long)gi * D_ + d] = v;
@@ -616,7 +601,7 @@ struct EpiGradUf {
 // For rows of block I (slot J): hz[i][d] = sum_j H_ij Zs_jd and hzrow[i] = sum_j H_ij;
 // for an off-diagonal tile also rows of block J (slot I) through H^T.  Both come
 // from fp32 MFMA products with [Zs | 1].
-// Extra LDS: 2 * BM * DP floats (DP: dpof).
+// Extra LDS: 2 * BM * (DP + 1) floats (DP: dpof).
 struct EpiGradUu {
   const float *Kt, *s, *Zs;
   long ld;
@@ -629,9 +614,9 @@ struct EpiGradUu {
     using K = Chunks<C>;
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     static_assert(BM == BN, "symmetric tiles");
-    const int D4 = d4of(D), DP = dpof(D);
-    float *zi = Cs + BM * C::LDC + 4 * NT;  // rows of block I  [BM][DP]
-    float *zj = zi + BM * DP;               // rows of block J  [BN][DP]
+    const int D4 = d4of(D), DP = dpof(D), LDZ = DP + 1, LDC_ = C::LDC;
+    float *zi = Cs + BM * C::LDC + 4 * NT;  // rows of block I  [BM][LDZ]
+    float *zj = zi + BM * LDZ;              // rows of block J  [BN][LDZ]
     float kv[K::N][VEC];
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
@@ -644,10 +629,10 @@ struct EpiGradUu {
     for (int k = 0; k < K::N; ++k) {
       int r, c;
       K::row(k, r, c);
-      sv[k] = t.m0 + r < M ? s[t.m0 + r] : 0.f;
+      sv[k] = ld_or0(s, t.m0 + r, t.m0 + r < M);
     }
-    stage_rows<NT>(zi, DP, Zs, t.m0, BM, M, D, D4);
-    stage_rows<NT>(zj, DP, Zs, t.n0, BN, M, D, D4);
+    stage_rows<NT>(zi, LDZ, Zs, t.m0, BM, M, D, D4);
+    stage_rows<NT>(zj, LDZ, Zs, t.n0, BN, M, D, D4);
     double hs = 0.0;
     const bool off = t.m0 != t.n0;
 #pragma unroll
@@ -674,7 +659,8 @@ struct EpiGradUu {
     {
       float *hz_ = hz + (long)J * M * D, *hr_ = hzrow + (long)J * M;
       const int base = t.m0;
-      lds_mfma_f32<NT / 64, false>(Cs, C::LDC, BM, BN, zj, DP, DP, [&](int i, int d, float v) {
+      lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, LDC_, BN, zj, LDZ, DP,
+                                                  [&](int i, int d, float v) {
         const int gi = base + i;
         if (gi < M_) {
           if (d < D_) hz_[(long)gi * D_ + d] = v;
@@ -686,7 +672,8 @@ struct EpiGradUu {
     {
       float *hz_ = hz + (long)I * M * D, *hr_ = hzrow + (long)I * M;
       const int base = t.n0;
-      lds_mfma_f32<NT / 64, true>(Cs, C::LDC, BN, BM, zi, DP, DP, [&](int i, int d, float v) {
+      lds_mfma_f32<NT / 64, BN / (NT / 4), true>(Cs, LDC_, BM, zi, LDZ, DP,
+                                                 [&](int i, int d, float v) {
         const int gj = base + i;
         if (gj < M_) {
           if (d < D_) hz_[(long)gj * D_ + d] = v;

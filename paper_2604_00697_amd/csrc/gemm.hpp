@@ -1,52 +1,57 @@
 // Tiled MFMA GEMM for gfx950 in "NT" form:
 //     C[i][j] = sum_k A[i][k] * Bt[j][k]
 // with both operands stored k-contiguous in the MFMA operand type, in
-// zero-padded buffers (rows padded to the tile, k padded to the k-step), so
-// every global load is an unconditional 16-byte vector.  Producers write
-// their outputs in the layout the next product consumes (plain or
-// transposed), which removes all transposes from the inner loops.
+// zero-padded buffers (rows padded to the tile, k padded to the k-step).
+// Producers write their outputs in the layout the next product consumes
+// (plain or transposed), which removes all transposes from the inner loops.
 //
 // Data path per workgroup (NT = 64 * WGM * WGN threads):
-//   global (16 B per lane, 8 lanes per 128-byte k-row) --> registers
-//   (optional per-k scaling) --> LDS, double buffered, rows padded by 16 B
-//   --> 16x16 MFMA (fp32: 4 x 16x16x4, bf16/fp16: 16x16x32), fp32 accumulators
-//   --> fp32 tile staged in LDS --> epilogue functor (stores, fused reductions).
+//   global --(global_load_lds_dwordx4: 16 bytes per lane straight into LDS)-->
+//   S-stage LDS ring, each staged row 128 bytes with its 16-byte chunks
+//   XOR-swizzled by (row % 8) so the fragment reads of 16 rows spread over the
+//   banks --> 16x16 MFMA fragments, double-buffered in registers (the next
+//   k-tile is read while the second half of this one's MFMAs issue)
+//   --> fp32 accumulators --> fp32 tile staged in LDS --> epilogue functor.
+// Up to S-1 k-tiles are in flight per workgroup; each wave waits only for its
+// own loads of the next k-tile (vmcnt) before the workgroup barrier.
 // Triangular operands skip their zero k-blocks through the tile schedule.
 #pragma once
 #include "common.hpp"
 
-// P_: k-tiles whose global loads are in flight while one tile is computed
-// (register sets of prefetched operands).
-template <int BM_, int BN_, int WGM_, int WGN_, typename T_, int P_ = 2>
+#define LDS_AS __attribute__((address_space(3)))
+
+template <int BM_, int BN_, int WGM_, int WGN_, typename T_, int S_>
 struct Cfg {
   using T = T_;
-  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, P = P_;
-  static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, S = S_;
+  static constexpr int NW = WGM * WGN, NT = 64 * NW;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
   static constexpr int TM = WM / 16, TN = WN / 16;
-  static constexpr int KPL = 16 / (int)sizeof(T);  // operand elements per 16 bytes
-  static constexpr int BK = 8 * KPL;               // k per stage: 128 bytes per row
-  static constexpr int LDK = BK + KPL;             // padded LDS row (elements): 144 bytes
-  static constexpr int RPP = NT / 8;               // rows covered by one load pass
-  static constexpr int PA = BM / RPP, PB = BN / RPP;
-  static constexpr int LDC = BN + 1;               // epilogue staging row, floats
-  static constexpr int SMEM_MAIN = 2 * (BM + BN) * LDK * (int)sizeof(T);
+  static constexpr int KPL = 16 / (int)sizeof(T);   // operand elements per 16-byte chunk
+  static constexpr int BK = 8 * KPL;                // k per stage: 8 chunks = 128 bytes per row
+  static constexpr int ROWB = 128;                  // LDS bytes of one staged row
+  static constexpr int STAGE = (BM + BN) * ROWB;    // LDS bytes of one stage
+  static constexpr int IPW = (BM + BN) / (8 * NW);  // 1 KB load instructions per wave per stage
+  static constexpr int LDC = BN + 1;                // epilogue staging row, floats
+  static constexpr int SMEM_MAIN = S * STAGE;
   // epilogue: staged tile + 16*NT bytes of reduction scratch (+ extra per epilogue)
   static constexpr int SMEM_EPI = (BM * LDC + 4 * NT) * (int)sizeof(float);
   static constexpr int smem(int extra) {
     return SMEM_MAIN > SMEM_EPI + extra ? SMEM_MAIN : SMEM_EPI + extra;
   }
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
-  static_assert(BM % RPP == 0 && BN % RPP == 0, "tile rows per load pass");
+  static_assert((BM + BN) % (8 * NW) == 0 && BM % (8 * IPW) == 0,
+                "each wave loads whole 8-row groups of one operand");
+  static_assert((S & (S - 1)) == 0 && S >= 2, "power-of-two stage count");
+  static_assert(IPW * (S - 1) <= 63, "outstanding loads must fit the vmcnt counter");
+  static_assert(SMEM_MAIN <= 160 * 1024, "LDS capacity");
 };
 
 // One operand: k-contiguous rows of length >= the padded k extent.
-// scale (optional, when the kernel's SA/SB flag is set): multiply element k by scale[k].
 template <typename T>
 struct Opnd {
   const T *p;
   long ld;
-  const float *scale;
 };
 
 // ------------------------------------------------------------------ schedule
@@ -110,156 +115,168 @@ struct TileInfo {
   int m0, n0, ti, split;
 };
 
-// 16 bytes of operands, optionally scaled element-wise by s[k .. k+KPL).
-template <typename T, bool SCALE>
-IFS_DEV uint4 load_chunk(const T *p, const float *s) {
-  uint4 v = *(const uint4 *)p;
-  if constexpr (SCALE) {
-    if constexpr (sizeof(T) == 4) {
-      float *f = (float *)&v;
-      const f32x4 sc = *(const f32x4 *)s;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) f[j] *= sc[j];
-    } else {
-      T *h = (T *)&v;
-      const f32x4 s0 = *(const f32x4 *)s, s1 = *(const f32x4 *)(s + 4);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) h[j] = from_f32<T>(to_f32(h[j]) * s0[j]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) h[4 + j] = from_f32<T>(to_f32(h[4 + j]) * s1[j]);
+// s_waitcnt with vmcnt = v and lgkmcnt = 0 (gfx9 encoding; expcnt left open).
+template <int v>
+IFS_DEV void wait_vm_lgkm0() {
+  static_assert(v >= 0 && v <= 63, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((v & 15) | (7 << 4) | (0 << 8) | ((v >> 4) << 14));
+}
+// Wait until at most n stages (of IPW loads each) of this wave are in flight.
+template <int IPW, int NMAX>
+IFS_DEV void wait_stages(int n) {
+  if constexpr (NMAX > 0) {
+    if (n >= NMAX) {
+      wait_vm_lgkm0<NMAX * IPW>();
+      return;
     }
+    wait_stages<IPW, NMAX - 1>(n);
+  } else {
+    wait_vm_lgkm0<0>();
   }
-  return v;
 }
 
+// Epilogues declaring kRegs = true take the accumulators in registers
+// (run_regs: acc[i][j][q] = C[WM wm + 16 i + 4 (lane/16) + q][WN wn + 16 j + lane % 16],
+// LDS free for their own use); the others get the tile staged in LDS (run).
+template <class E, class = void>
+struct EpiTakesRegs : std::false_type {};
+template <class E>
+struct EpiTakesRegs<E, std::void_t<decltype(E::kRegs)>> : std::bool_constant<E::kRegs> {};
+
+template <int v>
+struct IC {
+  static constexpr int value = v;
+};
+
 // ------------------------------------------------------------------ kernel
-template <class C, bool SA, bool SB, class EPI>
+template <class C, class EPI>
 __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
                                                      Opnd<typename C::T> Bt, Sched sc, EPI epi) {
   using T = typename C::T;
   using V = typename Vec16<T>::type;
-  constexpr int BM = C::BM, BN = C::BN, BK = C::BK, LDK = C::LDK, KPL = C::KPL;
+  constexpr int BM = C::BM, BK = C::BK, S = C::S, ROWB = C::ROWB, IPW = C::IPW;
+  constexpr int TM = C::TM, TN = C::TN;
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  T *As = (T *)smem_raw;          // [2][BM][LDK]
-  T *Bs = As + 2 * BM * LDK;      // [2][BN][LDK]
 
   int m0, n0, kb, ke, ti;
   sc.tile<C>(m0, n0, kb, ke, ti);
   const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / C::WGN, wn = wave % C::WGN;
   const int lr = lane & 15, kq = lane >> 4;
-  const int lrow = tid >> 3, lch = (tid & 7) * KPL;  // load row within a pass, k offset
 
-  f32x4 acc[C::TM][C::TN];
+  // ---- loads: wave w fills combined rows [w*IPW*8, (w+1)*IPW*8) of [A rows; B rows]
+  const int drow0 = wave * IPW * 8;
+  const bool dA = drow0 < BM;
+  const T *dbase = dA ? A.p : Bt.p;
+  const long dld = dA ? A.ld : Bt.ld;
+  const int dorg = dA ? m0 + drow0 : n0 + drow0 - BM;
+  // lane -> (row lane/8, LDS slot lane%8) holding k-chunk slot ^ row%8
+  const int dchunk = (lane & 7) ^ (lane >> 3);
+  const T *dsrc = dbase + (long)(dorg + (lane >> 3)) * dld + dchunk * C::KPL + kb;
+  auto issue = [&](int j) {
+    unsigned char *dst = smem_raw + (j & (S - 1)) * C::STAGE + drow0 * ROWB;
+    const T *g = dsrc + (long)j * BK;
 #pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const T *pa = A.p + (long)(m0 + lrow) * A.ld + lch;
-  const T *pb = Bt.p + (long)(n0 + lrow) * Bt.ld + lch;
-  constexpr int P = C::P;
-  uint4 ra[P][C::PA], rb[P][C::PB];  // P register sets of prefetched k-tiles
-
-  auto fetch = [&](int set, int k0) {
-#pragma unroll
-    for (int p = 0; p < C::PA; ++p)
-      ra[set][p] = load_chunk<T, SA>(pa + (long)p * C::RPP * A.ld + k0,
-                                     SA ? A.scale + k0 + lch : nullptr);
-#pragma unroll
-    for (int p = 0; p < C::PB; ++p)
-      rb[set][p] = load_chunk<T, SB>(pb + (long)p * C::RPP * Bt.ld + k0,
-                                     SB ? Bt.scale + k0 + lch : nullptr);
+    for (int i = 0; i < IPW; ++i)
+      __builtin_amdgcn_global_load_lds((const void *)(g + (long)i * 8 * dld),
+                                       (LDS_AS void *)(dst + i * 8 * ROWB), 16, 0, 0);
   };
-  auto stash = [&](int set, int buf) {
-    T *a = As + buf * BM * LDK + lrow * LDK + lch;
-    T *b = Bs + buf * BN * LDK + lrow * LDK + lch;
+
+  // ---- fragments: lane reads row lr of a 16-row block, k-chunk 4*sub + kq
+  const int sw0 = ((0 + kq) ^ (lr & 7)) * 16, sw1 = ((4 + kq) ^ (lr & 7)) * 16;
+  const int aoff = (wm * C::WM + lr) * ROWB, boff = (BM + wn * C::WN + lr) * ROWB;
+  V fa[2][2][TM], fb[2][2][TN];  // [register set][k half][tile]
+  auto read = [&](auto set_c, int j) {
+    constexpr int SET = decltype(set_c)::value;
+    const unsigned char *st = smem_raw + (j & (S - 1)) * C::STAGE;
 #pragma unroll
-    for (int p = 0; p < C::PA; ++p) *(uint4 *)(a + p * C::RPP * LDK) = ra[set][p];
+    for (int h = 0; h < 2; ++h) {
+      const int sw = h ? sw1 : sw0;
 #pragma unroll
-    for (int p = 0; p < C::PB; ++p) *(uint4 *)(b + p * C::RPP * LDK) = rb[set][p];
-  };
-  auto compute = [&](int buf) {
-    const T *a = As + buf * BM * LDK + (wm * C::WM + lr) * LDK;
-    const T *b = Bs + buf * BN * LDK + (wn * C::WN + lr) * LDK;
-    // all fragments of the k-tile are read before the first MFMA
-    V av[2][C::TM], bv[2][C::TN];
+      for (int i = 0; i < TM; ++i) fa[SET][h][i] = *(const V *)(st + aoff + i * 16 * ROWB + sw);
 #pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const int koff = kc * 4 * KPL + kq * KPL;
-#pragma unroll
-      for (int i = 0; i < C::TM; ++i) av[kc][i] = *(const V *)(a + i * 16 * LDK + koff);
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) bv[kc][j] = *(const V *)(b + j * 16 * LDK + koff);
+      for (int j2 = 0; j2 < TN; ++j2) fb[SET][h][j2] = *(const V *)(st + boff + j2 * 16 * ROWB + sw);
     }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-      for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j) acc[i][j] = mfma16(av[kc][i], bv[kc][j], acc[i][j]);
   };
 
-  // k-tile `it` lives in register set it % P and LDS buffer it % 2.  Fetch
-  // addresses are clamped to the last k-tile (a harmless re-read), so the
-  // steady-state loop has no branches and the accumulators stay in place.
-  static_assert(P == 2, "the main loop is unrolled for two register sets");
-  auto kclamp = [&](int it) { return kb + min(it, nk - 1) * BK; };
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto mma = [&](auto set_c, int h) {
+    constexpr int SET = decltype(set_c)::value;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = mfma16(fa[SET][h][i], fb[SET][h][j], acc[i][j]);
+  };
+  // one k-tile: first half of its MFMAs, then (if there is a next k-tile) wait
+  // for it, refill the stage this k-tile vacated, read the next fragments, and
+  // issue the second half while those reads are in flight
+  auto step = [&](auto cur_c, int it) {
+    constexpr int CUR = decltype(cur_c)::value;
+    mma(cur_c, 0);
+    if (it + 1 < nk) {
+      __builtin_amdgcn_sched_barrier(0);
+      wait_stages<IPW, S - 2>(min(nk - it - 2, S - 2));
+      __builtin_amdgcn_s_barrier();
+      if (it + S < nk) issue(it + S);
+      read(IC<1 - CUR>{}, it + 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    mma(cur_c, 1);
+  };
+
   if (nk > 0) {
-    fetch(0, kclamp(0));
-    fetch(1, kclamp(1));
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      if (j < nk) issue(j);
+    wait_stages<IPW, S - 1>(min(nk, S) - 1);
+    __builtin_amdgcn_s_barrier();
+    read(IC<0>{}, 0);
     int it = 0;
-    // scheduling fences keep each fetch ahead of the compute that hides it
-    for (; it + 2 <= nk; it += 2) {
-      stash(0, 0);
-      __syncthreads();
-      fetch(0, kclamp(it + 2));
-      __builtin_amdgcn_sched_barrier(0);
-      compute(0);
-      __builtin_amdgcn_sched_barrier(0);
-      stash(1, 1);
-      __syncthreads();
-      fetch(1, kclamp(it + 3));
-      __builtin_amdgcn_sched_barrier(0);
-      compute(1);
-      __builtin_amdgcn_sched_barrier(0);
+    for (; it + 1 < nk; it += 2) {
+      step(IC<0>{}, it);
+      step(IC<1>{}, it + 1);
     }
-    if (it < nk) {
-      stash(0, 0);
-      __syncthreads();
-      compute(0);
-    }
+    if (it < nk) step(IC<0>{}, it);
   }
   __syncthreads();
-  // stage the fp32 accumulator tile in LDS: Cs[r][c], r < BM, c < BN
-  float *Cs = (float *)smem_raw;
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        Cs[(wm * C::WM + i * 16 + 4 * kq + q) * C::LDC + wn * C::WN + j * 16 + lr] = acc[i][j][q];
-  __syncthreads();
   TileInfo t{m0, n0, ti, (int)blockIdx.y};
-  epi.template run<C>(Cs, t);
+  if constexpr (EpiTakesRegs<EPI>::value) {
+    epi.template run_regs<C>(acc, (float *)smem_raw, t);
+  } else {
+    // stage the fp32 accumulator tile in LDS: Cs[r][c], r < BM, c < BN
+    float *Cs = (float *)smem_raw;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          Cs[(wm * C::WM + i * 16 + 4 * kq + q) * C::LDC + wn * C::WN + j * 16 + lr] =
+              acc[i][j][q];
+    __syncthreads();
+    epi.template run<C>(Cs, t);
+  }
 }
 
 // Host-side launch helper.  extra: LDS bytes the epilogue needs beyond the
 // staged tile and its scratch.
-template <class C, bool SA, bool SB, class EPI>
+template <class C, class EPI>
 static inline hipError_t launch_gemm(hipStream_t st, const Opnd<typename C::T> &A,
                                      const Opnd<typename C::T> &Bt, const Sched &sc,
                                      const EPI &epi, int extra = 0) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
   if (ntile <= 0) return hipSuccess;
   dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1);
-  auto kern = gemm_kernel<C, SA, SB, EPI>;
+  auto kern = gemm_kernel<C, EPI>;
   const int smem = C::smem(extra);
   static int attr_bytes = 0;
   if (smem > attr_bytes) {

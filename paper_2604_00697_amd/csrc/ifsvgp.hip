@@ -50,8 +50,9 @@ struct ifsvgp_ctx {
   float *Kt, *L32[2], *Lt32[2], *W32, *Q32, *Wu32, *Ys;  // Ys: [nsplit][Mp][Mp]
   // operand-type M x M ([Mp][Mp]); C and Y2 use the wide-range type of the form
   void *KtT, *LT[2], *LtT[2], *Yt, *Xgt, *QT, *Cm, *Y2;
-  // operand-type M x B: Kft, Vt, Ut are [Bp][Mp]; V is [Mp][Bp]
-  void *Kft, *V, *Vt, *Ut;
+  void *LstT[2];  // LstT[m][k] = L[k][m] s~_k: the scaled operand of L^T S~ L
+  // operand-type M x B: Kft, Vt, Ut are [Bp][Mp]; V and Vs = V diag(sqrt(-beta)) are [Mp][Bp]
+  void *Kft, *V, *Vt, *Ut, *Vs;
   float *Zs, *Xs, *inv_ell, *sP;  // sP: s~ zero-padded to Mp
   float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
@@ -245,6 +246,8 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   }
   ALLOCB(c->LtT[0], MM * os);
   ALLOCB(c->LtT[1], MM * os);
+  ALLOCB(c->LstT[0], MM * os);
+  ALLOCB(c->LstT[1], MM * os);
   if (f32) {
     c->Lt32[0] = (float *)c->LtT[0];
     c->Lt32[1] = (float *)c->LtT[1];
@@ -260,6 +263,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOCB(c->V, MB * os);
   ALLOCB(c->Vt, MB * os);
   ALLOCB(c->Ut, MB * os);
+  ALLOCB(c->Vs, MB * os);
   ALLOC(c->Zs, (size_t)M * D);
   ALLOC(c->Xs, (size_t)B_max * D);
   ALLOC(c->inv_ell, (size_t)D);
@@ -394,9 +398,11 @@ template <typename T>
 struct Ops {
   // TW: operand type of the two products with C (fp32 in the fp16 form)
   using TW = typename std::conditional<std::is_same<T, _Float16>::value, float, T>::type;
-  using CS = Cfg<64, 64, 2, 2, T>;     // M x M products
-  using CSW = Cfg<64, 64, 2, 2, TW>;
-  using CR = Cfg<128, 128, 2, 2, T>;   // M x B products
+  // M x M products: two stages keep the LDS small enough for several
+  // workgroups per CU, which hides more latency than deeper staging
+  using CS = Cfg<64, 64, 2, 2, T, 2>;
+  using CSW = Cfg<64, 64, 2, 2, TW, 2>;
+  using CR = Cfg<128, 128, 2, 2, T, 4>;   // M x B products
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
   static T *LtT(ifsvgp_ctx *c, int i) { return (T *)c->LtT[i]; }
@@ -407,93 +413,95 @@ struct Ops {
 
   // Y = K~ L on lower tiles (k >= n0), stored transposed: Yt[j][i] = Y[i][j]
   static hipError_t gram_Y(ifsvgp_ctx *c, int cur) {
-    Opnd<T> a{(const T *)c->KtT, c->Mp, nullptr}, b{LtT(c, cur), c->Mp, nullptr};
+    Opnd<T> a{(const T *)c->KtT, c->Mp}, b{LtT(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0};
     EpiStoreT<T> e{(T *)c->Yt, c->Mp, c->M, c->M};
-    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
   // W = L^T Y on lower tiles (k >= m0) -> natural-gradient factor + residual
   static hipError_t ng_W(ifsvgp_ctx *c, int cur) {
-    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Yt, c->Mp, nullptr};
+    Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
-    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
   // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM; also the residual of
   // this step and (Lout non-null) the caller's L
   static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, float gamma, float *Lout,
                          double *resid_out) {
-    Opnd<T> a{LT(c, cur), c->Mp, nullptr}, b{(const T *)c->Xgt, c->Mp, nullptr};
+    Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Xgt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0 | K_HI_M1};
     EpiNgUpdate<T> e{c->L32[cur], c->L32[nxt], c->Lt32[nxt], LT(c, nxt), LtT(c, nxt),
-                     c->Mp, c->M, gamma, Lout, c->tp_ng, nb(c) * (nb(c) + 1) / 2,
+                     c->sP, (T *)c->LstT[nxt], c->Mp, c->M, gamma, Lout, c->tp_ng, nb(c) * (nb(c) + 1) / 2,
                      resid_out, c->scal};
-    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
   // W' = L^T Y (lower tiles, fp32)
   static hipError_t gr_W(ifsvgp_ctx *c, int cur) {
-    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Yt, c->Mp, nullptr};
+    Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiStore<float> e{c->W32, c->Mp, c->M, c->M, 0, 0};
-    return launch_gemm<CS, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
   // E' = L^T diag(s) L (lower tiles) -> Q, Wu, gram partials
   static hipError_t gr_E(ifsvgp_ctx *c, int cur) {
-    Opnd<T> a{LtT(c, cur), c->Mp, c->sP}, b{LtT(c, cur), c->Mp, nullptr};
+    Opnd<T> a{(const T *)c->LstT[cur], c->Mp}, b{LtT(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiBoundGram<T> e{c->W32, c->Q32, c->Wu32, (T *)c->QT, c->Mp, c->M, c->tp_gram};
-    return launch_gemm<CS, true, false>(c->st, a, b, sc, e, CS::BM * CS::LDC * 4);
+    return launch_gemm<CS>(c->st, a, b, sc, e, CS::BM * CS::LDC * 4);
   }
   // V = L^T K_uf (k >= m0) -> V, Vt
   static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
-    Opnd<T> a{LtT(c, cur), c->Mp, nullptr}, b{(const T *)c->Kft, c->Mp, nullptr};
+    Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Kft, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
-    return launch_gemm<CR, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CR>(c->st, a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
-    Opnd<T> a{(const T *)c->QT, c->Mp, nullptr}, b{(const T *)c->Vt, c->Mp, nullptr};
+    Opnd<T> a{(const T *)c->QT, c->Mp}, b{(const T *)c->Vt, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, 0};
     EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->Bp, c->Mp, c->M, B, c->var_part, c->Bp};
-    return launch_gemm<CR, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CR>(c->st, a, b, sc, e);
   }
   // R = L U (k < m0+BM) -> H_uf reductions
   static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *sf2) {
     const int D = c->D;
-    Opnd<T> a{LT(c, cur), c->Mp, nullptr}, b{(const T *)c->Ut, c->Mp, nullptr};
+    Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Ut, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
     EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    return launch_gemm<CR, false, false>(c->st, a, b, sc, e,
-                                         (CR::BM * d4of(D) + CR::BN * dpof(D)) * 4);
+    return launch_gemm<CR>(c->st, a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
   // log-concave Gaussian and probit likelihoods.
+  // split-K pieces: enough workgroups for about four per CU, each piece at
+  // least 4 k-steps long; every piece costs an fp32 M x M partial
   static int syrk_splits(ifsvgp_ctx *c, int B) {
-    return std::max(1, std::min(c->nsplit, cdiv(B, 4 * CS::BK)));
+    const int nt = nb(c) * (nb(c) + 1) / 2;
+    return std::max(1, std::min({c->nsplit, cdiv(B, 4 * CS::BK), cdiv(1024, nt)}));
   }
   static hipError_t syrk(ifsvgp_ctx *c, int B) {
-    Opnd<T> a{(const T *)c->V, c->Bp, c->sqnb}, b{(const T *)c->V, c->Bp, c->sqnb};
+    Opnd<T> a{(const T *)c->Vs, c->Bp}, b{(const T *)c->Vs, c->Bp};
     Sched sc{nb(c), nb(c), 1, syrk_splits(c, B), B, 0};
     EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, 1, (long)c->Mp * c->Mp};
-    return launch_gemm<CS, true, true>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
   // Y2 = L C (k < m0+BM), C symmetric
   static hipError_t gemm_Y2(ifsvgp_ctx *c, int cur) {
-    Opnd<TW> a{LW(c, cur), c->Mp, nullptr}, b{(const TW *)c->Cm, c->Mp, nullptr};
+    Opnd<TW> a{LW(c, cur), c->Mp}, b{(const TW *)c->Cm, c->Mp};
     Sched sc{nb(c), nb(c), 0, 1, c->M, K_HI_M1};
     EpiStore<TW> e{(TW *)c->Y2, c->Mp, c->M, c->M, 0, 0};
-    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e);
+    return launch_gemm<CSW>(c->st, a, b, sc, e);
   }
   // G_uu = Y2 L^T (lower tiles, k < n0+BN) -> H_uu reductions
   static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s) {
     const int D = c->D;
-    Opnd<TW> a{(const TW *)c->Y2, c->Mp, nullptr}, b{LW(c, cur), c->Mp, nullptr};
+    Opnd<TW> a{(const TW *)c->Y2, c->Mp}, b{LW(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
     EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu};
-    return launch_gemm<CSW, false, false>(c->st, a, b, sc, e, 2 * CSW::BM * dpof(D) * 4);
+    return launch_gemm<CSW>(c->st, a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
 };
 
@@ -510,8 +518,9 @@ static int stage_setup(ifsvgp_ctx *c, const float *Z, const float *ell, const fl
   a.ld = c->Mp;
   a.Lin = Lin;
   a.L32 = c->L32[0]; a.Lt32 = c->Lt32[0]; a.LT = c->LT[0]; a.LtT = c->LtT[0];
+  a.LstT = c->LstT[0];
   a.scal = c->scal; a.flag = c->flag;
-  a.nKx = cdiv(M, 16);
+  a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);
   const int nL = Lin ? a.nLx * a.nLx : 0;
@@ -564,7 +573,14 @@ static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, dou
   }
   {
     Timed t(c, KK_KUF);
-    hipLaunchKernelGGL((k_kuf<MAXD, T>), dim3(cdiv(B, 64), cdiv(M, 64)), dim3(NTB), 0, c->st,
+    static int kuf_attr = 0;
+    const int kb = kuf_smem(c->D);
+    if (kb > kuf_attr) {
+      HIPCK(hipFuncSetAttribute((const void *)k_kuf<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kb));
+      kuf_attr = kb;
+    }
+    hipLaunchKernelGGL((k_kuf<T>), dim3(cdiv(B, KUF_T), cdiv(M, KUF_T)), dim3(NTB), kb, c->st,
                        (const float *)c->Zs, X, (const float *)c->inv_ell, M, B, D, sf2,
                        (const float *)c->vLb, c->Xs, (T *)c->Kft, Mp, c->mu_part, (long)c->Bp);
   }
@@ -573,7 +589,7 @@ static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, dou
   {
     Timed t(c, KK_LIK);
     const int nb = cdiv(M, 64);
-    LikArgs a{c->mu_part, cdiv(M, 64), c->var_part, cdiv(M, 128), (long)c->Bp,
+    LikArgs a{c->mu_part, cdiv(M, KUF_T), c->var_part, cdiv(M, 128), (long)c->Bp,
               y, B, c->Bp, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
               c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
               c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
@@ -597,12 +613,13 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
   {
     Timed t(c, KK_VALPHA);
     hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
-                       (const T *)c->V, (long)c->Bp, M, B, (const float *)c->alpha, c->vVa);
+                       (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
+                       (const float *)c->sqnb, (T *)c->Vs, c->vVa);
   }
   { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B)); }
   {
     Timed t(c, KK_ASM);
-    hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * M)), dim3(NTB), 0, c->st,
+    hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0, c->st,
                        (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
                        (const float *)c->Wu32, (const float *)c->Q32, (const float *)c->va,
                        (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M,

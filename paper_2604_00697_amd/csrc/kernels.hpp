@@ -40,12 +40,13 @@ IFS_DEV bool arrive_last(int *counter, int *s_flag) {
 
 // ---------------------------------------------------------------- set-up
 // One launch per iteration before any product:
-//  * blocks [0, nK): 16 x 16 tiles of K~ = sf2 exp(-1/2 |zs_i - zs_j|^2) + diag(s~)
+//  * blocks [0, nK): 64 x 64 tiles of K~ = sf2 exp(-1/2 |zs_i - zs_j|^2) + diag(s~)
 //    (fp32, plus the operand type), zs = Z / ell; the first tile column also
 //    writes Zs and the zero-padded copy of s~; block 0 validates ell, sf2,
 //    noise_var, s~ and forms 1/ell and sum log s~;
 //  * blocks [nK, nK + nL): 32 x 32 tiles of the caller's L: fp32 master (lower
-//    triangle, strict upper 0), operand copy, and both transposes.
+//    triangle, strict upper 0), operand copy, both transposes, and the
+//    transpose scaled by s~ along k (operand of L^T S~ L).
 struct SetupArgs {
   const float *Z, *ell, *sf2, *noise, *s;
   int M, D, need_noise;
@@ -54,48 +55,82 @@ struct SetupArgs {
   long ld;
   const float *Lin;  // caller's L (leading dimension M), or null
   float *L32, *Lt32;
-  void *LT, *LtT;
+  void *LT, *LtT, *LstT;
   double *scal;
   int *flag;
   int nKx, nK, nLx;
 };
 
 template <int MAXD, typename T>
-__global__ void k_setup(SetupArgs a) {
-  __shared__ float zi[16][MAXD + 1], zj[16][MAXD + 1];
+__global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
+  __shared__ float zi[64][MAXD + 1], zj[64][MAXD + 1];
   __shared__ float tile[32][33];
   __shared__ double sh[NTB / 64];
   const int b = blockIdx.x;
   const int M = a.M, D = a.D;
   if (b < a.nK) {
+    // 64 x 64 tile; thread (tx, ty) owns rows ty + 16 p and columns tx + 16 q
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int bi = b / a.nKx, bj = b % a.nKx;
-    const int i0 = bi * 16, j0 = bj * 16;
-    for (int e = threadIdx.x; e < 16 * D; e += NTB) {
-      const int r = e / D, d = e % D;
-      const float il = 1.0f / a.ell[d];
-      zi[r][d] = (i0 + r < M) ? a.Z[(long)(i0 + r) * D + d] * il : 0.f;
-      zj[r][d] = (j0 + r < M) ? a.Z[(long)(j0 + r) * D + d] * il : 0.f;
+    const int i0 = bi * 64, j0 = bj * 64;
+    for (int e0 = 0; e0 < 64 * D; e0 += 4 * NTB) {
+      float vi[4], vj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * NTB + (int)threadIdx.x, r = e / D, d = e % D;
+        const bool in = e < 64 * D;
+        const float il = 1.0f / ld_or0(a.ell, d, in);
+        vi[u] = ld_or0(a.Z, (long)(i0 + r) * D + d, in && i0 + r < M) * il;
+        vj[u] = ld_or0(a.Z, (long)(j0 + r) * D + d, in && j0 + r < M) * il;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * NTB + (int)threadIdx.x, r = e / D, d = e % D;
+        if (e < 64 * D) {
+          zi[r][d] = vi[u];
+          zj[r][d] = vj[u];
+          if (bj == 0 && i0 + r < M) a.Zs[(long)(i0 + r) * D + d] = vi[u];
+        }
+      }
     }
+    if (bj == 0 && threadIdx.x < 64 && i0 + threadIdx.x < M)
+      a.sP[i0 + threadIdx.x] = a.s[i0 + threadIdx.x];
     __syncthreads();
-    if (bj == 0) {
-      for (int e = threadIdx.x; e < 16 * D; e += NTB) {
-        const int r = e / D, d = e % D;
-        if (i0 + r < M) a.Zs[(long)(i0 + r) * D + d] = zi[r][d];
-      }
-      if (threadIdx.x < 16 && i0 + threadIdx.x < M) a.sP[i0 + threadIdx.x] = a.s[i0 + threadIdx.x];
+    float d2[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d2[p][q] = 0.f;
+    for (int d = 0; d < D; ++d) {
+      float zr[4], zc[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) zr[p] = zi[ty + 16 * p][d];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zc[q] = zj[tx + 16 * q][d];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float df = zr[p] - zc[q];
+          d2[p][q] = fmaf(df, df, d2[p][q]);
+        }
     }
-    const int i = i0 + ty, j = j0 + tx;
-    if (i < M && j < M) {
-      float d2 = 0.f;
-      for (int d = 0; d < D; ++d) {
-        const float df = zi[ty][d] - zj[tx][d];
-        d2 = fmaf(df, df, d2);
+    const float sf2 = *a.sf2;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = i0 + ty + 16 * p;
+      const float si = ld_or0(a.s, i, i < M);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + tx + 16 * q;
+        if (i < M && j < M) {
+          float v = sf2 * __expf(-0.5f * d2[p][q]);
+          if (i == j) v += si;
+          a.Kt[(long)i * a.ld + j] = v;
+          if constexpr (!std::is_same<T, float>::value)
+            ((T *)a.KtT)[(long)i * a.ld + j] = from_f32<T>(v);
+        }
       }
-      float v = (*a.sf2) * __expf(-0.5f * d2);
-      if (i == j) v += a.s[i];
-      a.Kt[(long)i * a.ld + j] = v;
-      if constexpr (!std::is_same<T, float>::value) ((T *)a.KtT)[(long)i * a.ld + j] = from_f32<T>(v);
     }
     if (b == 0) {
       int bad = 0;
@@ -128,10 +163,17 @@ __global__ void k_setup(SetupArgs a) {
   const int bl = b - a.nK;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   const int i0 = (bl / a.nLx) * 32, j0 = (bl % a.nLx) * 32;
-  for (int r = ty; r < 32; r += 8) {
+  float lv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + ty + 8 * u, j = j0 + tx;
+    lv[u] = ld_or0(a.Lin, (long)i * M + j, i < M && j < M && i >= j);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = ty + 8 * u;
     const int i = i0 + r, j = j0 + tx;
-    float v = 0.f;
-    if (i < M && j < M && i >= j) v = a.Lin[(long)i * M + j];
+    const float v = lv[u];
     tile[r][tx] = v;
     if (i < M && j < M) {
       a.L32[(long)i * a.ld + j] = v;
@@ -139,68 +181,121 @@ __global__ void k_setup(SetupArgs a) {
     }
   }
   __syncthreads();
+  const float si = ld_or0(a.s, i0 + tx, i0 + tx < M);
   for (int r = ty; r < 32; r += 8) {
     const int j = j0 + r, i = i0 + tx;  // transposes: [j][i] = L[i][j]
     if (i < M && j < M) {
       const float v = tile[tx][r];
       ((T *)a.LtT)[(long)j * a.ld + i] = from_f32<T>(v);
+      ((T *)a.LstT)[(long)j * a.ld + i] = from_f32<T>(v * si);
       if constexpr (!std::is_same<T, float>::value) a.Lt32[(long)j * a.ld + i] = v;
     }
   }
 }
 
 // ---------------------------------------------------------------- K_uf
-// K_uf[k][n] = sf2 exp(-1/2 |zs_k - xs_n|^2), written transposed in the operand
-// type (Kft[n][k], the B operand layout of V = L^T K_uf), plus the partial mean
-// mu_part[k-tile][n] = sum_{k in tile} K_uf[k][n] Lb[k] from the fp32 values.
-// xs = X / ell is formed here; the first tile row writes it for later kernels.
-// Block: 64 (k) x 64 (n) tile; thread (tx, ty) owns k = tx+16i, n = ty+16j.
-template <int MAXD, typename T>
-__global__ void k_kuf(const float *Zs, const float *X, const float *inv_ell, int M, int B, int D,
-                      const float *sf2, const float *Lb, float *Xs, T *Kft, long ld,
-                      float *mu_part, long ldp) {
-  __shared__ float zk[64][MAXD + 1], xn[64][MAXD + 1];
-  __shared__ float red[64][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int k0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < 64 * D; e += NTB) {
-    const int r = e / D, d = e % D;
-    zk[r][d] = (k0 + r < M) ? Zs[(long)(k0 + r) * D + d] : 0.f;
-    const float x = (n0 + r < B) ? X[(long)(n0 + r) * D + d] * inv_ell[d] : 0.f;
-    xn[r][d] = x;
-    if (blockIdx.y == 0 && n0 + r < B) Xs[(long)(n0 + r) * D + d] = x;
+// K_uf[k][n] = sf2 exp(-1/2 |zs_k - xs_n|^2) for a block of 128 inducing
+// points x 128 data points, written transposed in the operand type (Kft[n][k],
+// the B operand layout of V = L^T K_uf; zero outside k < M, n < B), plus the
+// partial mean mu_part[k-block][n] = sum_{k in block} K_uf[k][n] Lb[k] from the
+// fp32 values.  xs = X / ell is formed here; the first block row writes it.
+// Each wave owns a 64 (k) x 64 (n) sub-block; the MFMA lane layout gives every
+// lane 4 consecutive k of one n, stored straight from registers, so the
+// workgroup needs only the staged inputs in LDS (kuf_smem(D) bytes) and
+// several workgroups share a CU.
+constexpr int KUF_T = 128;
+__host__ __device__ inline int kuf_ldz(int D) { return ((D + 3) & ~3) + 1; }
+__host__ __device__ inline int kuf_smem(int D) {
+  return (2 * KUF_T * kuf_ldz(D) + 3 * KUF_T + 2 * KUF_T + D) * 4;
+}
+template <typename T>
+__global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
+                                             const float *inv_ell, int M, int B, int D,
+                                             const float *sf2, const float *Lb, float *Xs, T *Kft,
+                                             long ld, float *mu_part, long ldp) {
+  extern __shared__ __attribute__((aligned(16))) float ksm[];
+  const int D4 = (D + 3) & ~3, LDZ = kuf_ldz(D);
+  float *zs = ksm;                    // [128][LDZ]
+  float *xs = zs + KUF_T * LDZ;       // [128][LDZ]
+  float *zn = xs + KUF_T * LDZ;       // [128]
+  float *xn = zn + KUF_T;             // [128]
+  float *lb = xn + KUF_T;             // [128]
+  float *mred = lb + KUF_T;           // [2][128]: mean partials of the two k halves
+  float *il = mred + 2 * KUF_T;       // [D]: 1 / ell
+  const int t = threadIdx.x;
+  const int k0 = blockIdx.y * KUF_T, n0 = blockIdx.x * KUF_T;
+  if (t < D) il[t] = inv_ell[t];
+  if (t < KUF_T) lb[t] = ld_or0(Lb, k0 + t, k0 + t < M);
+  // stage Zs rows and raw X rows, then scale X by 1/ell in LDS
+  stage_rows<NTB>(zs, LDZ, Zs, k0, KUF_T, M, D, -1);
+  stage_rows<NTB>(xs, LDZ, X, n0, KUF_T, B, D, -1);
+  __syncthreads();
+  for (int i = t; i < KUF_T * D; i += NTB) {
+    const int r = i / D, d = i % D;
+    const float v = xs[r * LDZ + d] * il[d];
+    xs[r * LDZ + d] = v;
+    if (blockIdx.y == 0 && n0 + r < B) Xs[(long)(n0 + r) * D + d] = v;
+  }
+  __syncthreads();
+  {
+    const float *row = t < KUF_T ? zs + t * LDZ : xs + (t - KUF_T) * LDZ;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    for (int d = 0; d < D4; d += 4) {
+      s0 = fmaf(row[d], row[d], s0);
+      s1 = fmaf(row[d + 1], row[d + 1], s1);
+      s2 = fmaf(row[d + 2], row[d + 2], s2);
+      s3 = fmaf(row[d + 3], row[d + 3], s3);
+    }
+    (t < KUF_T ? zn : xn)[t % KUF_T] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   const float s2 = *sf2;
-  float mu[4] = {0.f, 0.f, 0.f, 0.f};
+  const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
+  const int kb0 = (wave >> 1) * 64, nb0 = (wave & 1) * 64;
+  f32x4 c[4][4];
+  cross_block<4, 4>(zs + kb0 * LDZ, LDZ, xs + nb0 * LDZ, LDZ, D4, c);
+  float zr[4][4], lr_[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = tx + 16 * i, k = k0 + r;
-    const float lb = k < M ? Lb[k] : 0.f;
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = ty + 16 * j, n = n0 + c;
-      float d2 = 0.f;
-      for (int d = 0; d < D; ++d) {
-        const float df = zk[r][d] - xn[c][d];
-        d2 = fmaf(df, df, d2);
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb0 + 16 * i + 4 * l4 + q;
+      zr[i][q] = zn[k];
+      lr_[i][q] = lb[k];
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = nb0 + 16 * j + l16;
+    const bool nok = n0 + n < B;
+    const float xv = xn[n];
+    float mu = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kq = kb0 + 16 * i + 4 * l4;  // first of this lane's 4 consecutive k
+      T e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float v = (nok && k0 + kq + q < M) ? kern_se(s2, zr[i][q], xv, c[i][j][q]) : 0.f;
+        mu = fmaf(v, lr_[i][q], mu);
+        e[q] = from_f32<T>(v);
       }
-      const float v = s2 * __expf(-0.5f * d2);
-      if (k < M && n < B) {
-        Kft[(long)n * ld + k] = from_f32<T>(v);
-        mu[j] = fmaf(v, lb, mu[j]);
+      T *dst = Kft + (long)(n0 + n) * ld + k0 + kq;
+      if constexpr (sizeof(T) == 4) {
+        *(f32x4 *)dst = f32x4{(float)e[0], (float)e[1], (float)e[2], (float)e[3]};
+      } else {
+        uint2 raw;
+        __builtin_memcpy(&raw, e, 8);
+        *(uint2 *)dst = raw;
       }
     }
+    // sum over the four lanes (l4) that share n, then over the two k halves
+    mu += __shfl_xor(mu, 16, 64);
+    mu += __shfl_xor(mu, 32, 64);
+    if (l4 == 0) mred[(wave >> 1) * KUF_T + n] = mu;
   }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) red[ty + 16 * j][tx] = mu[j];
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int n = n0 + threadIdx.x;
-    float s = 0.f;
-    for (int r = 0; r < 16; ++r) s += red[threadIdx.x][r];
-    if (n < B) mu_part[(long)blockIdx.y * ldp + n] = s;
-  }
+  if (t < KUF_T && n0 + t < B)
+    mu_part[(long)blockIdx.y * ldp + n0 + t] = mred[t] + mred[KUF_T + t];
 }
 
 // sum_{k < np} p[k * stride] with eight independent loads in flight.
@@ -422,40 +517,79 @@ __global__ void k_lik(LikArgs a) {
 // (V D)(V D)^T, D = diag(sqrt(-beta)), stored symmetric), written in the
 // operand type TC over the M x M block.
 template <typename TC>
-__global__ void k_assemble_C(const float *Ys, int nsplit, long split_stride, const float *Wu,
-                             const float *Q, const float *a, const float *b, const float *Wub,
-                             const float *Va, int M, long ld, TC *Cm) {
-  const long n = (long)M * M;
+__global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
+                                                    long split_stride, const float *Wu,
+                                                    const float *Q, const float *a, const float *b,
+                                                    const float *Wub, const float *Va, int M,
+                                                    long ld, TC *Cm) {
+  // one thread per 4 consecutive columns of a row; the padded columns
+  // (j >= M, inputs zero there) come out as zeros
+  const int cpr = (M + 3) / 4;
+  const long n = (long)M * cpr;
   for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
-    const int i = (int)(e / M), j = (int)(e % M);
-    const long ij = (long)i * ld + j;
-    float ys = 0.f;
-    for (int s = 0; s < nsplit; ++s) ys += Ys[s * split_stride + ij];
-    const float c = -0.5f * (Va[i] * a[j] + a[i] * Va[j]) - ys -
-                    0.5f * (Wu[ij] + (i == j ? 1.f : 0.f) - Wub[i] * a[j] - a[i] * Wub[j]) +
-                    0.5f * (Q[ij] - b[i] * b[j]);
-    Cm[ij] = from_f32<TC>(c);
+    const int i = (int)(e / cpr), j0 = (int)(e % cpr) * 4;
+    const long ij = (long)i * ld + j0;
+    f32x4 ys = *(const f32x4 *)(Ys + ij);
+#pragma unroll 4
+    for (int s = 1; s < nsplit; ++s) ys += *(const f32x4 *)(Ys + s * split_stride + ij);
+    const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
+    const f32x4 aj = *(const f32x4 *)(a + j0), bj = *(const f32x4 *)(b + j0);
+    const f32x4 wj = *(const f32x4 *)(Wub + j0), vj = *(const f32x4 *)(Va + j0);
+    const float ai = a[i], bi = b[i], wi = Wub[i], vi = Va[i];
+    TC out[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] -
+                      0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f) - wi * aj[u] - ai * wj[u]) +
+                      0.5f * (q[u] - bi * bj[u]);
+      out[u] = from_f32<TC>(c);
+    }
+    if constexpr (sizeof(TC) == 4) {
+      *(f32x4 *)(Cm + ij) = f32x4{(float)out[0], (float)out[1], (float)out[2], (float)out[3]};
+    } else {
+      uint2 raw;
+      __builtin_memcpy(&raw, out, 8);
+      *(uint2 *)(Cm + ij) = raw;
+    }
   }
 }
 
-// V alpha over the operand-type V (one wave per row, 16 bytes per lane per load).
+// One wave per row of the operand-type V: (V alpha)_i and the scaled copy
+// Vs[i][n] = V[i][n] sqnb[n] over the whole padded row, the operand of the
+// batch product (V D)(V D)^T.  alpha and sqnb are zero for n >= B (set by the
+// likelihood kernel), so padded entries contribute nothing and Vs is zero there.
 template <typename T>
-__global__ void k_valpha(const T *V, long ld, int M, int B, const float *alpha, float *out) {
+__global__ void k_valpha(const T *V, long ld, int M, int Bp, const float *alpha,
+                         const float *sqnb, T *Vs, float *out) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= M) return;
   constexpr int KPL = 16 / (int)sizeof(T);
   const T *v = V + (long)row * ld;
+  T *vs = Vs + (long)row * ld;
   float s = 0.f;
-  for (int n = lane * KPL; n < B; n += 64 * KPL) {
-    if (n + KPL <= B) {
-      const uint4 raw = *(const uint4 *)(v + n);
-      const T *e = (const T *)&raw;
+  for (int n = lane * KPL; n < Bp; n += 64 * KPL) {  // Bp is a multiple of KPL
+    const uint4 raw = *(const uint4 *)(v + n);
+    const T *e = (const T *)&raw;
+    float al[KPL], sq[KPL];
 #pragma unroll
-      for (int q = 0; q < KPL; ++q) s = fmaf(to_f32(e[q]), alpha[n + q], s);
-    } else {
-      for (int q = 0; n + q < B; ++q) s = fmaf(to_f32(v[n + q]), alpha[n + q], s);
+    for (int q = 0; q < KPL; q += 4) {
+      const f32x4 a4 = *(const f32x4 *)(alpha + n + q), s4 = *(const f32x4 *)(sqnb + n + q);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        al[q + u] = a4[u];
+        sq[q + u] = s4[u];
+      }
     }
+    uint4 sraw;
+    T *se = (T *)&sraw;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const float x = to_f32(e[q]);
+      s = fmaf(x, al[q], s);
+      se[q] = from_f32<T>(x * sq[q]);
+    }
+    *(uint4 *)(vs + n) = sraw;
   }
   s = wave_sum(s);
   if (lane == 0) out[row] = s;
@@ -557,10 +691,29 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
     }
     return;
   }
-  const int nparts = g.rb + g.cb;
-  for (int d = t; d < g.D; d += NTB) {
-    const double s = slot_sum(g.ell_part + d, nparts, (long)g.D);
-    if (g.g_ell) g.g_ell[d] = (float)(scale * s * g.inv_ell[d]);
+  // lengthscale partials: thread (slice, d) sums every R-th block partial of d
+  const int nparts = g.rb + g.cb, R = NTB / g.D;
+  __shared__ double sd[NTB];
+  {
+    const int slice = t / g.D, d = t % g.D;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (slice < R) {
+      int p = slice;
+      for (; p + 3 * R < nparts; p += 4 * R) {
+        s0 += g.ell_part[(long)p * g.D + d];
+        s1 += g.ell_part[(long)(p + R) * g.D + d];
+        s2 += g.ell_part[(long)(p + 2 * R) * g.D + d];
+        s3 += g.ell_part[(long)(p + 3 * R) * g.D + d];
+      }
+      for (; p < nparts; p += R) s0 += g.ell_part[(long)p * g.D + d];
+    }
+    sd[t] = (s0 + s1) + (s2 + s3);
+  }
+  __syncthreads();
+  if (t < g.D) {
+    double s = 0.0;
+    for (int q = 0; q < R; ++q) s += sd[q * g.D + t];
+    if (g.g_ell) g.g_ell[t] = (float)(scale * s * g.inv_ell[t]);
   }
   double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
   for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
