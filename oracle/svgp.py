@@ -211,10 +211,12 @@ def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
         a_Z[:, d] = (np.sum(np.abs(Huu + Huu.T) * np.abs(dzz), axis=1)
                      + np.sum(np.abs(Huf * dzx), axis=1)) / ell[d]**2
     a_sf2 = (np.sum(np.abs(Huu)) + np.sum(np.abs(Huf))) / sf2 + np.sum(np.abs(beta))
+    # s~: diag(G_Kt) = diag(G_Kuu) - diag(P)/2 + (P m~)^2/2, each term's size
+    a_s = np.abs(np.diag(G_Kuu)) + 0.5 * np.abs(np.diag(P)) + 0.5 * Pm**2 + 0.5 / s
     g_noise = c * np.sum(ds2) if ds2 is not None else 0.0
     return dict(ell=g_ell, sf2=g_sf2, noise_var=g_noise, Z=g_Z, m=g_m, s=g_s,
                 bound=bd, alpha=alpha, beta=beta,
-                abs_terms=dict(ell=a_ell, Z=a_Z, sf2=a_sf2))
+                abs_terms=dict(ell=a_ell, Z=a_Z, sf2=a_sf2, s=a_s))
 
 
 def training_iteration(X, y, N, ell, sf2, noise_var, Z, m, s, L, gammas,

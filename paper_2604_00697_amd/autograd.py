@@ -3,21 +3,25 @@
 The forward evaluates F (eq. rsvgp_precond) at the given factor L; the
 backward calls the library's backward kernels (K_uf tiles recomputed, T held
 fixed as in Section 3.1), scaled in-kernel by the incoming adjoint.  Gradients
-flow to the lengthscales, signal variance, noise variance, Z and m~.
+flow to the lengthscales, signal variance, noise variance, Z, m~ and s~; only
+those whose inputs require grad are computed (s~ costs one more M^3 product).
 """
 import torch
 
 from .lib import Context
 
 
+_GRAD_NAMES = ("ell", "sf2", "noise_var", "Z", "m", "s")
+
+
 class _Bound(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, ell, sf2, noise, Z, m, X, y, s, L, N, lib):
+    def forward(ctx, ell, sf2, noise, Z, m, s, X, y, L, N, lib):
         F, terms = lib.bound(X, y, N, ell, sf2, noise, Z, m, s, L)
         ctx.lib = lib
         ctx.gen = lib.generation
         ctx.N = N
-        ctx.save_for_backward(ell, sf2, noise if noise is not None else sf2, Z, m, X, y, s, L)
+        ctx.save_for_backward(ell, sf2, noise if noise is not None else sf2, Z, m, s, X, y, L)
         ctx.has_noise = noise is not None
         ctx.mark_non_differentiable(terms)
         return F.reshape(()), terms
@@ -28,14 +32,15 @@ class _Bound(torch.autograd.Function):
         if lib.generation != ctx.gen:
             raise RuntimeError("another forward ran on this library context since this "
                                "bound was evaluated; use one context per graph in flight")
-        ell, sf2, noise, Z, m, X, y, s, L = ctx.saved_tensors
+        ell, sf2, noise, Z, m, s, X, y, L = ctx.saved_tensors
         noise = noise if ctx.has_noise else None
+        want = tuple(n for n, need in zip(_GRAD_NAMES, ctx.needs_input_grad[:6])
+                     if need and (n != "noise_var" or ctx.has_noise))
         scale = gF.detach().to(torch.float64).reshape(1).contiguous()
-        g = lib.bound_bwd(X, y, ctx.N, ell, sf2, noise, Z, m, s, L, grad_scale=scale)
-        return (g["ell"], g["sf2"], g.get("noise_var") if ctx.has_noise else None,
-                g["Z"], g["m"], None, None, None, None, None, None)
+        g = lib.bound_bwd(X, y, ctx.N, ell, sf2, noise, Z, m, s, L, grad_scale=scale, want=want)
+        return tuple(g.get(n) for n in _GRAD_NAMES) + (None,) * 5
 
 
 def ifsvgp_bound(lib: Context, X, y, N, ell, sf2, noise, Z, m, s, L):
-    """F (0-dim fp64 tensor, differentiable w.r.t. ell, sf2, noise, Z, m) and terms."""
-    return _Bound.apply(ell, sf2, noise, Z, m, X, y, s, L, float(N), lib)
+    """F (0-dim fp64 tensor, differentiable w.r.t. ell, sf2, noise, Z, m, s) and terms."""
+    return _Bound.apply(ell, sf2, noise, Z, m, s, X, y, L, float(N), lib)

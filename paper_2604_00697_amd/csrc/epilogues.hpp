@@ -609,6 +609,7 @@ struct EpiGradUu {
   float *hz;     // [nb][M][D]
   float *hzrow;  // [nb][M]
   double *part;  // [ntiles]
+  float *gdiag;  // [M]: diagonal of G_uu from the diagonal tiles, or null
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -646,6 +647,7 @@ struct EpiGradUu {
         float h = 0.f;
         if (gi < M && gj < M) {
           const float kk = kv[k][q] - (gi == gj ? sv[k] : 0.f);
+          if (gdiag && gi == gj) gdiag[gi] = CS(r, c + q);
           h = CS(r, c + q) * kk;
           hs += (off ? 2.0 : 1.0) * h;
         }
@@ -680,6 +682,48 @@ struct EpiGradUu {
           else if (d == D4) hr_[gj] = v;
         }
       });
+    }
+  }
+};
+
+// ---------------------------------------------------------------- diag(L Q L^T)
+// Tile (I >= J) of L Q.  part[J][i] = sum_{j in tile} (L Q)_ij L_ij, the
+// tile's share of diag(L Q L^T) = diag(P); tiles with J > I would only meet
+// L_ij = 0.  Used by the gradient with respect to s~.
+struct EpiRowDotL {
+  const float *L;  // fp32 master [Mp][Mp]
+  long ld;
+  int M;
+  float *part;     // [nb][ldp]
+  long ldp;
+  template <class C>
+  IFS_DEV void run(float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
+    float lv[K::N][VEC];
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+      ld_pack(L + (long)(t.m0 + r) * ld + t.n0 + c, lv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::row(k, r, c);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + c + q] = CS(r, c + q) * lv[k][q];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < C::BM; r += C::NT) {
+      const int gi = t.m0 + r;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+      for (int c = 0; c < C::BN; c += 4) {
+        a0 += CS(r, c);
+        a1 += CS(r, c + 1);
+        a2 += CS(r, c + 2);
+        a3 += CS(r, c + 3);
+      }
+      if (gi < M) part[(long)(t.n0 / C::BN) * ldp + gi] = (a0 + a1) + (a2 + a3);
     }
   }
 };

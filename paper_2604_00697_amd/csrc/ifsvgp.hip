@@ -26,15 +26,15 @@ static constexpr int PAD = 128;  // padding granule of every workspace extent
 
 // ------------------------------------------------------------------ kernel kinds
 enum KernelKind : int {
-  KK_PREP = 0, KK_KUU, KK_COPYL, KK_NG_Y, KK_NG_W, KK_NG_L, KK_RESID,
-  KK_GR_Y, KK_GR_W, KK_GR_E, KK_VEC, KK_KUF, KK_V, KK_U, KK_LIK, KK_FIN,
-  KK_R, KK_VALPHA, KK_SYRK, KK_ASM, KK_Y2, KK_GUU, KK_GRAD, KK_STOREL, KK_N
+  KK_PREP = 0, KK_NG_Y, KK_NG_W, KK_NG_L,
+  KK_GR_Y, KK_GR_W, KK_GR_E, KK_VEC, KK_KUF, KK_V, KK_U, KK_LIK,
+  KK_R, KK_VALPHA, KK_SYRK, KK_ASM, KK_Y2, KK_GUU, KK_LQ, KK_GRAD, KK_N
 };
 static const char *KK_NAMES[KK_N] = {
-    "prep", "kuu", "copy_L", "ng_KL", "ng_gram", "ng_update", "ng_resid",
+    "prep", "ng_KL", "ng_gram", "ng_update",
     "bound_KL", "bound_gram", "bound_gram_E", "matvec", "kuf", "gemm_V", "gemm_U", "likelihood",
-    "finalize", "gemm_R_grad_uf", "valpha", "syrk", "assemble_C", "gemm_LC", "gemm_G_grad_uu",
-    "grad_final", "store_L"};
+    "gemm_R_grad_uf", "valpha", "syrk", "assemble_C", "gemm_LC", "gemm_G_grad_uu",
+    "gemm_LQ_diag", "grad_final"};
 
 struct TimingRec {
   int kind;
@@ -57,6 +57,7 @@ struct ifsvgp_ctx {
   float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
   float *hrow, *hcol, *hx, *hzrow, *hz;
+  float *gdiag, *pdiag;  // diag(G_uu) [Mp]; partials of diag(L Q L^T) [nb64][Mp]
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
   double *gh;
   int *flag, *counters;
@@ -286,6 +287,8 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->hx, (size_t)nbB * M * D);
   ALLOC(c->hzrow, (size_t)nb64 * M);
   ALLOC(c->hz, (size_t)nb64 * M * D);
+  ALLOC(c->gdiag, Mp);
+  ALLOC(c->pdiag, (size_t)nb64 * Mp);
   ALLOC(c->scal, (size_t)S_NSLOT);
   ALLOC(c->tp_ng, (size_t)nt_sym64);
   ALLOC(c->tp_gram, (size_t)3 * nt_sym64);
@@ -380,12 +383,13 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
   f[KK_GR_E] = M * M * M / 3.0;
   f[KK_V] = M * M * Bd;                 // L^T K_uf, triangular
   f[KK_U] = 2.0 * M * M * Bd;           // Q V
-  f[KK_R] = M * M * Bd + 2.0 * M * Bd * D;  // L U (+ H X)
+  f[KK_R] = M * M * Bd + 4.0 * M * Bd * D;  // L U, + K_uf cross term and H [Xs | 1]
   f[KK_SYRK] = M * M * Bd;              // lower half of (V D)(V D)^T
   f[KK_Y2] = M * M * M;                 // L C
   f[KK_GUU] = M * M * M / 3.0 + 2.0 * M * M * D;  // lower half of Y2 L^T (+ H Z)
-  f[KK_KUF] = 3.0 * M * Bd * D;
-  f[KK_KUU] = 3.0 * M * M * D;
+  f[KK_LQ] = M * M * M / 3.0;           // lower tiles of L Q (only with the s~ gradient)
+  f[KK_KUF] = 2.0 * M * Bd * D;         // cross term Zs Xs^T (MFMA)
+  f[KK_PREP] = 3.0 * M * M * D;         // K~ from differences (VALU)
   for (int k = 0; k < KK_N && k < cap; ++k) {
     flops[k] = f[k];
     if (names) names[k] = KK_NAMES[k];
@@ -496,12 +500,19 @@ struct Ops {
     return launch_gemm<CSW>(c->st, a, b, sc, e);
   }
   // G_uu = Y2 L^T (lower tiles, k < n0+BN) -> H_uu reductions
-  static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s) {
+  static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s, float *gdiag) {
     const int D = c->D;
     Opnd<TW> a{(const TW *)c->Y2, c->Mp}, b{LW(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
-    EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu};
+    EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, gdiag};
     return launch_gemm<CSW>(c->st, a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
+  }
+  // L Q on lower tiles (k < m0+BM) -> partials of diag(L Q L^T) = diag(P)
+  static hipError_t gemm_LQ(ifsvgp_ctx *c, int cur) {
+    Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->QT, c->Mp};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_M1};
+    EpiRowDotL e{c->L32[cur], c->Mp, c->M, c->pdiag, c->Mp};
+    return launch_gemm<CS>(c->st, a, b, sc, e);
   }
 };
 
@@ -605,7 +616,7 @@ static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, dou
 template <typename T>
 static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, const float *s,
                           const double *grad_scale, float *g_ell, float *g_sf2, float *g_noise,
-                          float *g_Z, float *g_m) {
+                          float *g_Z, float *g_m, float *g_s) {
   using TW = typename Ops<T>::TW;
   const int M = c->M, D = c->D, cur = c->cur;
   const long Mp = c->Mp;
@@ -626,7 +637,11 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
                        Mp, (TW *)c->Cm);
   }
   { Timed t(c, KK_Y2); HIPCK(Ops<T>::gemm_Y2(c, cur)); }
-  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, s)); }
+  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, s, g_s ? c->gdiag : nullptr)); }
+  if (g_s) {
+    Timed t(c, KK_LQ);
+    HIPCK(Ops<T>::gemm_LQ(c, cur));
+  }
   {
     Timed t(c, KK_GRAD);
     const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
@@ -637,10 +652,11 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
                c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
                c->lik_part, cdiv(c->Bp, NTB),
                c->Q32, c->vVa, c->vWub, Mp, c->vt2,
-               N / (double)B, grad_scale, g_Z, g_ell, g_sf2, g_noise, c->ell_part, rb, cb};
+               N / (double)B, grad_scale, g_Z, g_ell, g_sf2, g_noise, c->ell_part, rb, cb,
+               c->gdiag, c->pdiag, (long)Mp, c->vLb, s, g_s};
     hipLaunchKernelGGL(k_grad, dim3(rb + cb + rq), dim3(NTB), 0, c->st, g);
-    // dF/dm~ = L t2, t2 = Q (V alpha - Wu b), and the scalar gradients
-    const int mrows = g_m ? cdiv(M, NTB / 64) : 0;
+    // dF/dm~ = L t2, t2 = Q (V alpha - Wu b), dF/ds~, and the scalar gradients
+    const int mrows = (g_m || g_s) ? cdiv(M, NTB / 64) : 0;
     hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
                        (const float *)c->L32[cur], g_m, mrows);
   }
@@ -689,7 +705,7 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
                    const float *m, const float *s, float *L, const float *gammas, int n_ng,
                    double *out_bound, double *out_terms, double *out_resid, bool fwd, bool bwd,
                    const double *grad_scale, float *g_ell, float *g_sf2, float *g_noise,
-                   float *g_Z, float *g_m) {
+                   float *g_Z, float *g_m, float *g_s) {
   const int need_noise = c->lik == IFSVGP_LIK_GAUSSIAN;
   int r;
   if (fwd) {
@@ -702,7 +718,7 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
   }
   if (bwd) {
     if (!c->fwd_valid || c->fwd_B != B) return IFSVGP_ESTATE;
-    r = stage_backward<T>(c, B, N, sf2, s, grad_scale, g_ell, g_sf2, g_noise, g_Z, g_m);
+    r = stage_backward<T>(c, B, N, sf2, s, grad_scale, g_ell, g_sf2, g_noise, g_Z, g_m, g_s);
     if (r) return r;
   }
   return IFSVGP_OK;
@@ -724,7 +740,7 @@ extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B
   if (!out_bound) return IFSVGP_EINVAL;
   PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
                 out_bound, out_terms, nullptr, true, false, nullptr, nullptr, nullptr, nullptr,
-                nullptr, nullptr)
+                nullptr, nullptr, nullptr)
 }
 
 extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -734,10 +750,9 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
                                 float *g_noise, float *g_Z, float *g_m, float *g_s) {
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
-  if (g_s) return IFSVGP_EINVAL;  // gradient w.r.t. s~ is not provided by this library
   PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
                 nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2, g_noise, g_Z,
-                g_m)
+                g_m, g_s)
 }
 
 extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -749,7 +764,6 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
   if (n_ng < 0 || (n_ng > 0 && !gammas) || !out_bound) return IFSVGP_EINVAL;
-  if (g_s) return IFSVGP_EINVAL;
   PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng, out_bound,
-                out_terms, out_resid, true, true, nullptr, g_ell, g_sf2, g_noise, g_Z, g_m)
+                out_terms, out_resid, true, true, nullptr, g_ell, g_sf2, g_noise, g_Z, g_m, g_s)
 }

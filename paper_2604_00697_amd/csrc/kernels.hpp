@@ -621,6 +621,10 @@ struct GradArgs {
   float *g_Z, *g_ell, *g_sf2, *g_noise;
   double *ell_part;  // [rb + cb][D]
   int rb, cb;
+  // gradient with respect to s~ (g_s null: skipped)
+  const float *gdiag, *pdiag; long ldpd;  // diag(G_uu); [nb][ldpd] partials of diag(P)
+  const float *Lb, *s_in;
+  float *g_s;
 };
 
 __global__ void k_grad(GradArgs g) {
@@ -675,8 +679,8 @@ __global__ void k_grad(GradArgs g) {
   }
 }
 
-// Tail of the gradient: blocks [0, rows) form dF/dm~ = scale * L t2 (one wave
-// per row, when g_m is requested); the last block forms
+// Tail of the gradient: blocks [0, rows) form dF/dm~ = scale * L t2 and
+// dF/ds~ (one wave per row, when requested); the last block forms
 // dF/dell_d = (1/ell_d) sum of partials, dF/dsf2 = (sum H_uu + sum H_uf)/sf2 +
 // sum beta and dF/dnoise = c sum dE/dnoise.
 __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
@@ -684,10 +688,25 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
   const int t = threadIdx.x;
   const double scale = g.grad_scale ? *g.grad_scale : 1.0;
   if ((int)blockIdx.x < rows) {
-    const int row = blockIdx.x * (NTB / 64) + (t >> 6);
+    const int row = blockIdx.x * (NTB / 64) + (t >> 6), lane = t & 63;
     if (row < g.M) {
-      const float s = row_dot(L + (long)row * g.ld, g.t2, nullptr, row + 1);
-      if ((t & 63) == 0) g_m[row] = (float)(scale * s);
+      if (g_m) {
+        const float s = row_dot(L + (long)row * g.ld, g.t2, nullptr, row + 1);
+        if (lane == 0) g_m[row] = (float)(scale * s);
+      }
+      if (g.g_s) {
+        // dF/ds~_i = diag(G_Kt)_i + 1/(2 s~_i), diag(G_Kt) = diag(G_uu) - diag(P)/2 + (P m~)_i^2/2
+        // with P m~ = L b; diag(P) from the per-tile partials of L Q with J <= i/64
+        float pd = 0.f;
+        for (int J = lane; J <= row / 64; J += 64) pd += g.pdiag[(long)J * g.ldpd + row];
+        pd = wave_sum(pd);
+        if (lane == 0) {
+          const double lb = g.Lb[row];
+          const double gs = (double)g.gdiag[row] - 0.5 * (double)pd + 0.5 * lb * lb +
+                            0.5 / (double)g.s_in[row];
+          g.g_s[row] = (float)(scale * gs);
+        }
+      }
     }
     return;
   }
