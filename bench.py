@@ -26,8 +26,43 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
 N_BATCHES = 8
 
 
+# MFMA products of one step (the flop count of the MFMA percentage); the s~
+# gradient's extra product is not requested by the step timed here.
+STEP_GEMMS = ("ng_KL", "ng_gram", "ng_update", "bound_KL", "bound_gram", "bound_gram_E",
+              "gemm_V", "gemm_U", "gemm_R_grad_uf", "syrk", "gemm_LC", "gemm_G_grad_uu")
+# Sources whose change invalidates a stored HBM traffic measurement.
+KERNEL_SOURCES = ("paper_2604_00697_amd/csrc/gemm.hpp", "paper_2604_00697_amd/csrc/epilogues.hpp",
+                  "paper_2604_00697_amd/csrc/common.hpp", "paper_2604_00697_amd/csrc/ifsvgp.hip")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def dominant_traffic(workload, prec):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    counter's reading for a plain copy of known size), or None when there is
+    none for this workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"gemm_U_{workload}_{prec}_hbm_traffic.md")
+    try:
+        with open(path) as fh:
+            kv = dict(line.strip()[2:].split(": ", 1) for line in fh
+                      if line.startswith("- ") and ": " in line)
+        if kv.get("sources_digest") != kernel_sources_digest():
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def make_inputs(wname, dev):
@@ -154,6 +189,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run one plain device-to-device copy of BYTES bytes (the "
+                         "reference dispatch for scaling HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -186,7 +224,7 @@ def main():
             f"{res[prec]['dom_ms'] * 1e3:.1f} us, status {res[prec]['status']}")
     main_r = res[args.prec]
     flops = main_r["flops"]
-    f_iter = sum(v for k, v in flops.items() if k not in ("kuu", "kuf"))
+    f_iter = sum(flops[k] for k in STEP_GEMMS)
     peak = PEAK_TFLOPS[args.prec]
     dom_tflops = flops[dominant] / (main_r["dom_ms"] * 1e-3) / 1e12
     out = {
@@ -202,15 +240,17 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: SE-ARD regression, D={w.D}, N={w.N}, "
-                               f"B={w.B}, M={w.M}, Gaussian likelihood; step = 1 NG step "
-                               f"(gamma=1) + bound + backward",
+        "config": {"workload": f"{args.workload}: SE-ARD "
+                               f"{'regression' if w.lik == 'gaussian' else 'classification'}, "
+                               f"D={w.D}, N={w.N}, B={w.B}, M={w.M}, {w.lik} likelihood; step = "
+                               f"1 NG step (gamma=1) + bound + backward",
                    "M": w.M, "B": w.B, "D": w.D, "N": w.N, "state": "S1"},
         "mfma_pct": round(100.0 * f_iter / (main_r["ms_per_step"] * 1e-3) / (peak * 1e12), 3),
         "flops_per_step": f_iter,
         "roofline": {"bound": "mfma", "kernel": dominant, "achieved": round(dom_tflops, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(dom_tflops / peak, 4),
-                     "traffic": None, "flops_per_launch": flops[dominant],
+                     "traffic": dominant_traffic(args.workload, args.prec),
+                     "flops_per_launch": flops[dominant],
                      "avg_launch_us": round(main_r["dom_ms"] * 1e3, 3)},
     }
     if "fp32" in res and args.prec != "fp32":
@@ -226,6 +266,14 @@ def main():
     if not args.no_cpu:
         log("bench: cpu_baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(w, p)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration {4 * n} bytes")
     print(json.dumps(out), flush=True)
 
 

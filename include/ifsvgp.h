@@ -53,8 +53,10 @@ typedef struct ifsvgp_ctx ifsvgp_ctx;
 
 /* GEMM operand precision.  FP32: every product in fp32 on fp32 MFMA.
  * BF16 / FP16: the cubic and B*M^2 products take bf16 / fp16 operands with
- * fp32 accumulation; L, the kernel-matrix exponentials, the likelihood terms
- * and all reductions stay fp32 and the final scalar sums are fp64. */
+ * fp32 accumulation (FP16 keeps the two products with the backward's M x M
+ * matrix C in fp32, whose entries can exceed the fp16 range); the master L,
+ * the kernel-matrix exponentials, the likelihood terms and all reductions
+ * stay fp32 and the final scalar sums are fp64. */
 enum ifsvgp_prec { IFSVGP_PREC_FP32 = 0, IFSVGP_PREC_BF16 = 1, IFSVGP_PREC_FP16 = 2 };
 
 enum ifsvgp_lik { IFSVGP_LIK_GAUSSIAN = 0, IFSVGP_LIK_PROBIT = 1 };
@@ -140,8 +142,9 @@ int ifsvgp_bound(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double 
  * are recomputed, not stored.  grad_scale: device fp64[1] multiplying every
  * gradient (e.g. the incoming adjoint), or NULL for 1.  Gradient outputs are
  * device fp32 arrays shaped like their parameters; each may be NULL to skip
- * it (g_s costs an extra M^3 product).  The gradient is of F (to be
- * maximised) with respect to the constrained values. */
+ * it.  g_s (dF/ds~) adds one triangular M^3 product, diag(L Q L^T) with
+ * Q = 2I - L^T K~ L, and runs only when requested.  The gradient is of F (to
+ * be maximised) with respect to the constrained values. */
 int ifsvgp_bound_bwd(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
                      const float *ell, const float *sf2, const float *noise_var,
                      const float *Z, const float *m_tilde, const float *s_tilde,

@@ -16,6 +16,8 @@
 // own loads of the next k-tile (vmcnt) before the workgroup barrier.
 // Triangular operands skip their zero k-blocks through the tile schedule.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 #define LDS_AS __attribute__((address_space(3)))
@@ -267,10 +269,18 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
   }
 }
 
+// Where and how to launch: the stream, and optionally two events that the
+// dispatch itself stamps at kernel start and end (per-kernel timing without
+// the cost of separately recorded events).
+struct Launch {
+  hipStream_t st;
+  hipEvent_t t0, t1;
+};
+
 // Host-side launch helper.  extra: LDS bytes the epilogue needs beyond the
 // staged tile and its scratch.
 template <class C, class EPI>
-static inline hipError_t launch_gemm(hipStream_t st, const Opnd<typename C::T> &A,
+static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T> &A,
                                      const Opnd<typename C::T> &Bt, const Sched &sc,
                                      const EPI &epi, int extra = 0) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
@@ -285,6 +295,9 @@ static inline hipError_t launch_gemm(hipStream_t st, const Opnd<typename C::T> &
     if (e != hipSuccess) return e;
     attr_bytes = smem;
   }
-  hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, st, A, Bt, sc, epi);
+  if (lc.t0)
+    hipExtLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, lc.t0, lc.t1, 0, A, Bt, sc, epi);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, A, Bt, sc, epi);
   return hipGetLastError();
 }

@@ -66,6 +66,7 @@ struct ifsvgp_ctx {
   int cur;  // which L32/LT/LtT slot holds the bound's L
   // timing
   long long timing;  // bit mask of timed kernel kinds
+  hipEvent_t lev0, lev1;  // dispatch-stamped events of the next GEMM launch (timing)
   std::vector<TimingRec> recs;
   std::vector<hipEvent_t> pool;
   double t_ms[KK_N];
@@ -86,19 +87,41 @@ static int grid1(long n) {
     if (_e != hipSuccess) return IFSVGP_EHIP;         \
   } while (0)
 
+// Kinds that are exactly one GEMM launch: timed by events the dispatch
+// stamps itself (kernel start to kernel end); other kinds are bracketed by
+// recorded events.
+static bool single_gemm_kind(int k) {
+  switch (k) {
+    case KK_NG_Y: case KK_NG_W: case KK_NG_L: case KK_GR_Y: case KK_GR_W: case KK_GR_E:
+    case KK_V: case KK_U: case KK_R: case KK_SYRK: case KK_Y2: case KK_GUU: case KK_LQ:
+      return true;
+    default:
+      return false;
+  }
+}
+
 struct Timed {
   ifsvgp_ctx *c;
   int kind;
   hipEvent_t b;
-  Timed(ifsvgp_ctx *c_, int k) : c(c_), kind(k), b(nullptr) {
+  bool stamped;
+  Timed(ifsvgp_ctx *c_, int k) : c(c_), kind(k), b(nullptr), stamped(false) {
     if (!((c->timing >> kind) & 1)) return;
     hipEvent_t a = get();
     b = get();
-    hipEventRecord(a, c->st);
+    stamped = single_gemm_kind(kind);
+    if (stamped) {
+      c->lev0 = a;
+      c->lev1 = b;
+    } else {
+      hipEventRecord(a, c->st);
+    }
     c->recs.push_back({kind, a, b});
   }
   ~Timed() {
-    if (b) hipEventRecord(b, c->st);
+    if (!b) return;
+    if (stamped) c->lev0 = c->lev1 = nullptr;
+    else hipEventRecord(b, c->st);
   }
   hipEvent_t get() {
     if (!c->pool.empty()) {
@@ -398,6 +421,8 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
 }
 
 // ------------------------------------------------------------------ GEMM wrappers
+static Launch lnc(ifsvgp_ctx *c) { return Launch{c->st, c->lev0, c->lev1}; }
+
 template <typename T>
 struct Ops {
   // TW: operand type of the two products with C (fp32 in the fp16 form)
@@ -420,14 +445,14 @@ struct Ops {
     Opnd<T> a{(const T *)c->KtT, c->Mp}, b{LtT(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0};
     EpiStoreT<T> e{(T *)c->Yt, c->Mp, c->M, c->M};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // W = L^T Y on lower tiles (k >= m0) -> natural-gradient factor + residual
   static hipError_t ng_W(ifsvgp_ctx *c, int cur) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM; also the residual of
   // this step and (Lout non-null) the caller's L
@@ -438,35 +463,35 @@ struct Ops {
     EpiNgUpdate<T> e{c->L32[cur], c->L32[nxt], c->Lt32[nxt], LT(c, nxt), LtT(c, nxt),
                      c->sP, (T *)c->LstT[nxt], c->Mp, c->M, gamma, Lout, c->tp_ng, nb(c) * (nb(c) + 1) / 2,
                      resid_out, c->scal};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // W' = L^T Y (lower tiles, fp32)
   static hipError_t gr_W(ifsvgp_ctx *c, int cur) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiStore<float> e{c->W32, c->Mp, c->M, c->M, 0, 0};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // E' = L^T diag(s) L (lower tiles) -> Q, Wu, gram partials
   static hipError_t gr_E(ifsvgp_ctx *c, int cur) {
     Opnd<T> a{(const T *)c->LstT[cur], c->Mp}, b{LtT(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiBoundGram<T> e{c->W32, c->Q32, c->Wu32, (T *)c->QT, c->Mp, c->M, c->tp_gram};
-    return launch_gemm<CS>(c->st, a, b, sc, e, CS::BM * CS::LDC * 4);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e, CS::BM * CS::LDC * 4);
   }
   // V = L^T K_uf (k >= m0) -> V, Vt
   static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Kft, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
-    return launch_gemm<CR>(c->st, a, b, sc, e);
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
     Opnd<T> a{(const T *)c->QT, c->Mp}, b{(const T *)c->Vt, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, 0};
     EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->Bp, c->Mp, c->M, B, c->var_part, c->Bp};
-    return launch_gemm<CR>(c->st, a, b, sc, e);
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // R = L U (k < m0+BM) -> H_uf reductions
   static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *sf2) {
@@ -475,7 +500,7 @@ struct Ops {
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
     EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    return launch_gemm<CR>(c->st, a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
+    return launch_gemm<CR>(lnc(c), a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
@@ -490,14 +515,14 @@ struct Ops {
     Opnd<T> a{(const T *)c->Vs, c->Bp}, b{(const T *)c->Vs, c->Bp};
     Sched sc{nb(c), nb(c), 1, syrk_splits(c, B), B, 0};
     EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, 1, (long)c->Mp * c->Mp};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // Y2 = L C (k < m0+BM), C symmetric
   static hipError_t gemm_Y2(ifsvgp_ctx *c, int cur) {
     Opnd<TW> a{LW(c, cur), c->Mp}, b{(const TW *)c->Cm, c->Mp};
     Sched sc{nb(c), nb(c), 0, 1, c->M, K_HI_M1};
     EpiStore<TW> e{(TW *)c->Y2, c->Mp, c->M, c->M, 0, 0};
-    return launch_gemm<CSW>(c->st, a, b, sc, e);
+    return launch_gemm<CSW>(lnc(c), a, b, sc, e);
   }
   // G_uu = Y2 L^T (lower tiles, k < n0+BN) -> H_uu reductions
   static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s, float *gdiag) {
@@ -505,14 +530,14 @@ struct Ops {
     Opnd<TW> a{(const TW *)c->Y2, c->Mp}, b{LW(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
     EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, gdiag};
-    return launch_gemm<CSW>(c->st, a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
+    return launch_gemm<CSW>(lnc(c), a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
   // L Q on lower tiles (k < m0+BM) -> partials of diag(L Q L^T) = diag(P)
   static hipError_t gemm_LQ(ifsvgp_ctx *c, int cur) {
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->QT, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_M1};
     EpiRowDotL e{c->L32[cur], c->Mp, c->M, c->pdiag, c->Mp};
-    return launch_gemm<CS>(c->st, a, b, sc, e);
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
 };
 
