@@ -92,15 +92,17 @@ IFS_DEV float tile_colsum(const float *Cs) {
 // the gradient epilogues:  Out[i][d] = sum_k A[i][k] Z[k][d],  i < R, d < DP,
 // with A = H (row-major, stride ldh) or, TRANS, A = H^T.  Z is row-major
 // [K][ldz].  R = 16 * TI * NW (each wave owns TI row tiles), K a multiple of 4,
-// DP a multiple of 32 (d tiles in pairs).  Each output element goes to
-// sink(i, d, value) from the lane that holds it.
+// DP a multiple of 16 (d tiles two at a time, then a last single one).  Each
+// output element goes to sink(i, d, value) from the lane that holds it.
 template <int NW, int TI, bool TRANS, class F>
 IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ldz, int DP,
                           F &&sink) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int ib = wave * TI * 16;
-  for (int d0 = 0; d0 < DP; d0 += 32) {
+  auto a_at = [&](int r, int k) { return TRANS ? H[k * ldh + r] : H[r * ldh + k]; };
+  int d0 = 0;
+  for (; d0 + 32 <= DP; d0 += 32) {
     f32x4 acc[TI][2];
 #pragma unroll
     for (int i = 0; i < TI; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -109,8 +111,7 @@ IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ld
       const float b0 = Z[(k0 + l4) * ldz + d0 + l16], b1 = Z[(k0 + l4) * ldz + d0 + 16 + l16];
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
-        const int r = ib + 16 * i + l16;
-        const float a = TRANS ? H[(k0 + l4) * ldh + r] : H[r * ldh + k0 + l4];
+        const float a = a_at(ib + 16 * i + l16, k0 + l4);
         acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[i][0], 0, 0, 0);
         acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[i][1], 0, 0, 0);
       }
@@ -122,6 +123,50 @@ IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ld
 #pragma unroll
         for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, d0 + 16 * h + l16, acc[i][h][q]);
   }
+  if (d0 < DP) {
+    f32x4 acc[TI];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const float b0 = Z[(k0 + l4) * ldz + d0 + l16];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_at(ib + 16 * i + l16, k0 + l4), b0,
+                                                      acc[i], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, d0 + l16, acc[i][q]);
+  }
+}
+
+// Row sums of the staged tile over its BN columns (NT / BM threads per row,
+// partials combined in the scratch LDS).  Valid for threads with
+// threadIdx.x < BM, where the row is threadIdx.x.
+template <class C>
+IFS_DEV float tile_rowsum(const float *Cs) {
+  constexpr int CG = C::NT / C::BM;  // column groups per row
+  static_assert(C::NT % C::BM == 0 && C::BN % (4 * CG) == 0, "row partial layout");
+  float *sh = (float *)(Cs + C::BM * C::LDC);
+  const int r = threadIdx.x % C::BM, g = threadIdx.x / C::BM;
+  constexpr int W = C::BN / CG;  // columns per group
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll 4
+  for (int c = g * W; c < (g + 1) * W; c += 4) {
+    s0 += CS(r, c);
+    s1 += CS(r, c + 1);
+    s2 += CS(r, c + 2);
+    s3 += CS(r, c + 3);
+  }
+  float s = (s0 + s1) + (s2 + s3);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0)
+    for (int k = 1; k < CG; ++k) s += sh[k * C::BM + r];
+  __syncthreads();
+  return s;
 }
 
 // ---------------------------------------------------------------- plain stores
@@ -487,10 +532,11 @@ struct EpiU {
   }
 };
 
-// Staged inputs for the D-wide MFMA reductions: D4 = D rounded up to 4 columns
-// of data, a ones column at D4, width DP rounded up to 32.
+// Staged inputs for the D-wide MFMA reductions: D4 = D rounded up to 4
+// columns (the cross term's contraction length), DP = D rounded up to 16 (the
+// reduction product's output width), rows of stride DP + 1.
 __host__ __device__ inline int d4of(int D) { return (D + 3) & ~3; }
-__host__ __device__ inline int dpof(int D) { return ((d4of(D) + 1 + 31) / 32) * 32; }
+__host__ __device__ inline int dpof(int D) { return (D + 15) / 16 * 16; }
 
 // ---------------------------------------------------------------- backward K_uf side
 // Tile of R = L U, taken straight from the accumulators.  Forms
@@ -501,7 +547,7 @@ __host__ __device__ inline int dpof(int D) { return ((d4of(D) + 1 + 31) / 32) * 
 //   hcol[n]    = sum_i H_in                 (per m-tile partial)
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
 //   sum H                                   (per tile partial)
-// hrow and hx come from one fp32 MFMA product H [Xs | 1].
+// hx comes from an fp32 MFMA product H Xs, the row and column sums from LDS.
 // Extra LDS: graduf_extra(BM, BN, D) bytes.
 __host__ __device__ inline int graduf_extra(int BM, int BN, int D) {
   const int D4 = d4of(D), LDX = dpof(D) + 1;
@@ -523,7 +569,7 @@ struct EpiGradUf {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     const int D4 = d4of(D), DP = dpof(D), LDZ = D4 + 1, LDX = DP + 1;
     float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][LDZ]
-    float *xs = zs + BM * LDZ;              // [BN][LDX], ones column at D4
+    float *xs = zs + BM * LDZ;              // [BN][LDX]
     float *zn = xs + BN * LDX;              // [BM]
     float *lb = zn + BM;                    // [BM]
     float *xn = lb + BM;                    // [BN]
@@ -536,7 +582,7 @@ struct EpiGradUf {
       be[i] = beta[t.n0 + i];
     }
     stage_rows<NT>(zs, LDZ, Zs, t.m0, BM, M, D, -1);
-    stage_rows<NT>(xs, LDX, Xs, t.n0, BN, B, D, D4);
+    stage_rows<NT>(xs, LDX, Xs, t.n0, BN, B, D, -1);
     __syncthreads();
     for (int i = tid; i < BM + BN; i += NT) {
       const float *row = i < BM ? zs + i * LDZ : xs + (i - BM) * LDX;
@@ -583,15 +629,17 @@ struct EpiGradUf {
       const int cl = tid % BN, gj = t.n0 + cl;
       if (tid < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
     }
+    {
+      const float s = tile_rowsum<C>(Cs);
+      const int gi = t.m0 + tid % BM;
+      if (tid < BM && gi < M) hrow[(long)nti * M + gi] = s;
+    }
     const int D_ = D, M_ = M;
-    float *hrow_ = hrow + (long)nti * M, *hx_ = hx + (long)nti * M * D;
+    float *hx_ = hx + (long)nti * M * D;
     lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, C::LDC, BN, xs, LDX, DP,
                                                 [&](int i, int d, float v) {
       const int gi = t.m0 + i;
-      if (gi < M_) {
-        if (d < D_) hx_[(long)gi * D_ + d] = v;
-        else if (d == D4) hrow_[gi] = v;
-      }
+      if (gi < M_ && d < D_) hx_[(long)gi * D_ + d] = v;
     });
   }
 };
@@ -599,8 +647,8 @@ struct EpiGradUf {
 // ---------------------------------------------------------------- backward K_uu side
 // Tile (I >= J) of G_uu = Y2 L^T.  H = G_uu o K_uu with K_uu = K~ - diag(s~).
 // For rows of block I (slot J): hz[i][d] = sum_j H_ij Zs_jd and hzrow[i] = sum_j H_ij;
-// for an off-diagonal tile also rows of block J (slot I) through H^T.  Both come
-// from fp32 MFMA products with [Zs | 1].
+// for an off-diagonal tile also rows of block J (slot I) through H^T.  The
+// products with Zs run on fp32 MFMA; the row / column sums come from LDS.
 // Extra LDS: 2 * BM * (DP + 1) floats (DP: dpof).
 struct EpiGradUu {
   const float *Kt, *s, *Zs;
@@ -615,7 +663,7 @@ struct EpiGradUu {
     using K = Chunks<C>;
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     static_assert(BM == BN, "symmetric tiles");
-    const int D4 = d4of(D), DP = dpof(D), LDZ = DP + 1, LDC_ = C::LDC;
+    const int DP = dpof(D), LDZ = DP + 1, LDC_ = C::LDC;
     float *zi = Cs + BM * C::LDC + 4 * NT;  // rows of block I  [BM][LDZ]
     float *zj = zi + BM * LDZ;              // rows of block J  [BN][LDZ]
     float kv[K::N][VEC];
@@ -632,8 +680,8 @@ struct EpiGradUu {
       K::row(k, r, c);
       sv[k] = ld_or0(s, t.m0 + r, t.m0 + r < M);
     }
-    stage_rows<NT>(zi, LDZ, Zs, t.m0, BM, M, D, D4);
-    stage_rows<NT>(zj, LDZ, Zs, t.n0, BN, M, D, D4);
+    stage_rows<NT>(zi, LDZ, Zs, t.m0, BM, M, D, -1);
+    stage_rows<NT>(zj, LDZ, Zs, t.n0, BN, M, D, -1);
     double hs = 0.0;
     const bool off = t.m0 != t.n0;
 #pragma unroll
@@ -659,28 +707,30 @@ struct EpiGradUu {
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int I = t.m0 / BM, J = t.n0 / BN, D_ = D, M_ = M;
     {
-      float *hz_ = hz + (long)J * M * D, *hr_ = hzrow + (long)J * M;
+      // rows of block I (slot J): row sums and H Zs_J
+      const float rs = tile_rowsum<C>(Cs);
+      const int gi = t.m0 + threadIdx.x % BM;
+      if (threadIdx.x < BM && gi < M) hzrow[(long)J * M + gi] = rs;
+      float *hz_ = hz + (long)J * M * D;
       const int base = t.m0;
       lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, LDC_, BN, zj, LDZ, DP,
                                                   [&](int i, int d, float v) {
-        const int gi = base + i;
-        if (gi < M_) {
-          if (d < D_) hz_[(long)gi * D_ + d] = v;
-          else if (d == D4) hr_[gi] = v;
-        }
+        const int g = base + i;
+        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
       });
     }
     if (!off) return;
     {
-      float *hz_ = hz + (long)I * M * D, *hr_ = hzrow + (long)I * M;
+      // rows of block J (slot I) through H^T: column sums and H^T Zs_I
+      const float cs = tile_colsum<C>(Cs);
+      const int gj = t.n0 + threadIdx.x % BN;
+      if (threadIdx.x < BN && gj < M) hzrow[(long)I * M + gj] = cs;
+      float *hz_ = hz + (long)I * M * D;
       const int base = t.n0;
       lds_mfma_f32<NT / 64, BN / (NT / 4), true>(Cs, LDC_, BM, zi, LDZ, DP,
                                                  [&](int i, int d, float v) {
-        const int gj = base + i;
-        if (gj < M_) {
-          if (d < D_) hz_[(long)gj * D_ + d] = v;
-          else if (d == D4) hr_[gj] = v;
-        }
+        const int g = base + i;
+        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
       });
     }
   }

@@ -42,8 +42,8 @@ struct Cfg {
     return SMEM_MAIN > SMEM_EPI + extra ? SMEM_MAIN : SMEM_EPI + extra;
   }
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
-  static_assert((BM + BN) % (8 * NW) == 0 && BM % (8 * IPW) == 0,
-                "each wave loads whole 8-row groups of one operand");
+  static_assert((BM + BN) % (8 * NW) == 0 && BM % 8 == 0,
+                "each wave loads whole 8-row groups");
   static_assert((S & (S - 1)) == 0 && S >= 2, "power-of-two stage count");
   static_assert(IPW * (S - 1) <= 63, "outstanding loads must fit the vmcnt counter");
   static_assert(SMEM_MAIN <= 160 * 1024, "LDS capacity");
@@ -173,20 +173,31 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
 
   // ---- loads: wave w fills combined rows [w*IPW*8, (w+1)*IPW*8) of [A rows; B rows]
   const int drow0 = wave * IPW * 8;
-  const bool dA = drow0 < BM;
-  const T *dbase = dA ? A.p : Bt.p;
-  const long dld = dA ? A.ld : Bt.ld;
-  const int dorg = dA ? m0 + drow0 : n0 + drow0 - BM;
   // lane -> (row lane/8, LDS slot lane%8) holding k-chunk slot ^ row%8
   const int dchunk = (lane & 7) ^ (lane >> 3);
-  const T *dsrc = dbase + (long)(dorg + (lane >> 3)) * dld + dchunk * C::KPL + kb;
+  const T *srcA = A.p + (long)(m0 + (lane >> 3)) * A.ld + dchunk * C::KPL + kb;
+  const T *srcB = Bt.p + (long)(n0 - BM + (lane >> 3)) * Bt.ld + dchunk * C::KPL + kb;
   auto issue = [&](int j) {
     unsigned char *dst = smem_raw + (j & (S - 1)) * C::STAGE + drow0 * ROWB;
-    const T *g = dsrc + (long)j * BK;
+    if constexpr (BM % (8 * IPW) == 0) {
+      // every wave's rows lie in one operand: one base pointer and stride
+      const bool dA = drow0 < BM;
+      const long dld = dA ? A.ld : Bt.ld;
+      const T *g = (dA ? srcA : srcB) + (long)drow0 * dld + (long)j * BK;
 #pragma unroll
-    for (int i = 0; i < IPW; ++i)
-      __builtin_amdgcn_global_load_lds((const void *)(g + (long)i * 8 * dld),
-                                       (LDS_AS void *)(dst + i * 8 * ROWB), 16, 0, 0);
+      for (int i = 0; i < IPW; ++i)
+        __builtin_amdgcn_global_load_lds((const void *)(g + (long)i * 8 * dld),
+                                         (LDS_AS void *)(dst + i * 8 * ROWB), 16, 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < IPW; ++i) {
+        const int R0 = drow0 + 8 * i;
+        const T *g = (R0 < BM ? srcA + (long)R0 * A.ld : srcB + (long)R0 * Bt.ld) +
+                     (long)j * BK;
+        __builtin_amdgcn_global_load_lds((const void *)g, (LDS_AS void *)(dst + i * 8 * ROWB),
+                                         16, 0, 0);
+      }
+    }
   };
 
   // ---- fragments: lane reads row lr of a 16-row block, k-chunk 4*sub + kq

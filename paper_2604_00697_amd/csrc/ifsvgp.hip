@@ -431,7 +431,11 @@ struct Ops {
   // workgroups per CU, which hides more latency than deeper staging
   using CS = Cfg<64, 64, 2, 2, T, 2>;
   using CSW = Cfg<64, 64, 2, 2, TW, 2>;
-  using CR = Cfg<128, 128, 2, 2, T, 4>;   // M x B products
+  // M x B products.  V and U: two stages (64 KB + a 70 KB epilogue) so two
+  // workgroups share a CU and one's epilogue overlaps the other's main loop;
+  // R, whose epilogue needs more LDS than that, keeps four stages.
+  using CR = Cfg<128, 128, 2, 2, T, 2>;
+  using CRR = Cfg<128, 128, 2, 2, T, 4>;
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
   static T *LtT(ifsvgp_ctx *c, int i) { return (T *)c->LtT[i]; }
@@ -500,7 +504,7 @@ struct Ops {
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
     EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
+    return launch_gemm<CRR>(lnc(c), a, b, sc, e, graduf_extra(CRR::BM, CRR::BN, D));
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the

@@ -298,17 +298,58 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
     mu_part[(long)blockIdx.y * ldp + n0 + t] = mred[t] + mred[KUF_T + t];
 }
 
-// sum_{k < np} p[k * stride] with eight independent loads in flight.
-template <typename F>
+// sum_{k < np} p[k * stride]: each round issues W loads (clamped to an
+// in-bounds slot, masked afterwards) before the first add uses them.
+template <int W = 16, typename F>
 IFS_DEV F slot_sum(const F *p, int np, long stride) {
-  F a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int k = 0;
-  for (; k + 8 <= np; k += 8) {
+  F a[W];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] += p[(long)(k + u) * stride];
+  for (int u = 0; u < W; ++u) a[u] = 0;
+  for (int k = 0; k < np; k += W) {
+    F v[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) v[u] = p[(long)min(k + u, np - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < W; ++u) a[u] += k + u < np ? v[u] : F(0);
   }
-  for (; k < np; ++k) a[0] += p[(long)k * stride];
-  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+  for (int w = W / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) a[u] += a[u + w];
+  return a[0];
+}
+
+// Two slot sums at once (uf side: nu slots, uu side: nz slots), all loads of
+// a round in flight together.
+IFS_DEV void slot_sum2(const float *pu, int nu, long su, const float *pz, int nz, long sz,
+                       float &ru, float &rz) {
+  constexpr int W = 16;
+  float a[W], b[W];
+#pragma unroll
+  for (int u = 0; u < W; ++u) a[u] = b[u] = 0.f;
+  const int n = nu > nz ? nu : nz;
+  for (int k = 0; k < n; k += W) {
+    float va[W], vb[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      va[u] = pu[(long)max(0, min(k + u, nu - 1)) * su];
+      vb[u] = pz[(long)max(0, min(k + u, nz - 1)) * sz];
+    }
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      a[u] += k + u < nu ? va[u] : 0.f;
+      b[u] += k + u < nz ? vb[u] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int w = W / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int u = 0; u < w; ++u) {
+      a[u] += a[u + w];
+      b[u] += b[u + w];
+    }
+  ru = a[0];
+  rz = b[0];
 }
 
 // ---------------------------------------------------------------- matrix-vector
@@ -434,8 +475,8 @@ __global__ void k_lik(LikArgs a) {
   const int n = blockIdx.x * NTB + threadIdx.x;
   double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
   if (n < a.B) {
-    const float m = slot_sum(a.mu_part + n, a.n_mu, a.ldp);
-    const float vp = slot_sum(a.var_part + n, a.n_var, a.ldp);
+    float m, vp;
+    slot_sum2(a.mu_part + n, a.n_mu, a.ldp, a.var_part + n, a.n_var, a.ldp, m, vp);
     const double mu = m, var = (double)(*a.sf2) - (double)vp;
     const double y = a.y[n];
     double E, dmu, dv;
@@ -638,10 +679,9 @@ __global__ void k_grad(GradArgs g) {
     double contrib = 0.0;
     if (r < R && i < g.M) {
       const long e = (long)i * g.D + d, MD = (long)g.M * g.D;
-      const float ruf = slot_sum(g.hrow + i, g.n_uf_nt, (long)g.M);
-      const float hx = slot_sum(g.hx + e, g.n_uf_nt, MD);
-      const float ruu = slot_sum(g.hzrow + i, g.nb, (long)g.M);
-      const float hz = slot_sum(g.hz + e, g.nb, MD);
+      float ruf, ruu, hx, hz;
+      slot_sum2(g.hrow + i, g.n_uf_nt, (long)g.M, g.hzrow + i, g.nb, (long)g.M, ruf, ruu);
+      slot_sum2(g.hx + e, g.n_uf_nt, MD, g.hz + e, g.nb, MD, hx, hz);
       const double zs = g.Zs[e];
       const double gz = -(double)g.inv_ell[d] * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
       if (g.g_Z) g.g_Z[e] = (float)(scale * gz);
