@@ -487,24 +487,29 @@ struct EpiV {
 };
 
 // ---------------------------------------------------------------- U = Q V
-// Ut[n][i] = U[i][n] and the partial sum_i V_in U_in over the tile's rows.
+// Ut[n][i] = U[i][n], and over the tile's rows the partials of
+// sigma^2: sum_i V_in U_in and of the mean mu_n = (K_fu L b)_n = sum_i V_in b_i.
 template <typename T>
 struct EpiU {
   T *Ut;
   const T *V;
+  const float *b;   // Q L^T m~, zero-padded to Mp
   long ldv, ldt;
   int M, B;
   float *var_part;  // [m-tiles][ldp]
+  float *mu_part;   // [m-tiles][ldp]
   long ldp;
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
     float vv[K::N][VEC];  // the V tile, loaded before anything waits on it
+    float bv[K::N];
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
       int r, c;
       K::row(k, r, c);
       ld_pack(V + (long)(t.m0 + r) * ldv + t.n0 + c, vv[k]);
+      bv[k] = b[t.m0 + r];
     }
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
@@ -517,7 +522,7 @@ struct EpiU {
       st_pack(Ut + (long)gj * ldt + gi, x);
     }
     __syncthreads();
-    // V o U in place (V padding is zero), then column sums
+    // V o U in place (V padding is zero), column sums; then V b the same way
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
       int r, c;
@@ -526,9 +531,24 @@ struct EpiU {
       for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + c + q] = vv[k][q] * CS(r, c + q);
     }
     __syncthreads();
-    const float s = tile_colsum<C>(Cs);
     const int c = threadIdx.x % C::BN, gj = t.n0 + c;
-    if (threadIdx.x < C::BN && gj < B) var_part[(long)(t.m0 / C::BM) * ldp + gj] = s;
+    const long slot = (long)(t.m0 / C::BM) * ldp + gj;
+    {
+      const float s = tile_colsum<C>(Cs);
+      if (threadIdx.x < C::BN && gj < B) var_part[slot] = s;
+    }
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, cc;
+      K::row(k, r, cc);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + cc + q] = vv[k][q] * bv[k];
+    }
+    __syncthreads();
+    {
+      const float s = tile_colsum<C>(Cs);
+      if (threadIdx.x < C::BN && gj < B) mu_part[slot] = s;
+    }
   }
 };
 

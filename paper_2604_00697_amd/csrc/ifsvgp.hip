@@ -46,6 +46,11 @@ struct ifsvgp_ctx {
   int Mp, Bp;
   int nsplit;
   hipStream_t st;
+  // side stream for branches of the iteration that are independent of the
+  // main chain (K_uf tiles and V during the Gram products; R = L U during the
+  // backward's C chain); forked from and joined back into st with events
+  hipStream_t st2;
+  hipEvent_t ev_fork, ev_join;
   // fp32 M x M ([Mp][Mp])
   float *Kt, *L32[2], *Lt32[2], *W32, *Q32, *Wu32, *Ys;  // Ys: [nsplit][Mp][Mp]
   // operand-type M x M ([Mp][Mp]); C and Y2 use the wide-range type of the form
@@ -135,6 +140,24 @@ struct Timed {
   }
 };
 
+// Side-stream branches: fork makes st2 wait for all work enqueued on st so
+// far, join makes st wait for all work enqueued on st2 so far; OnSide
+// redirects the enqueues of its scope (kernels and timing events) to st2.
+static hipError_t fork_side(ifsvgp_ctx *c) {
+  hipError_t e = hipEventRecord(c->ev_fork, c->st);
+  return e != hipSuccess ? e : hipStreamWaitEvent(c->st2, c->ev_fork, 0);
+}
+static hipError_t join_side(ifsvgp_ctx *c) {
+  hipError_t e = hipEventRecord(c->ev_join, c->st2);
+  return e != hipSuccess ? e : hipStreamWaitEvent(c->st, c->ev_join, 0);
+}
+struct OnSide {
+  ifsvgp_ctx *c;
+  hipStream_t saved;
+  explicit OnSide(ifsvgp_ctx *c_) : c(c_), saved(c_->st) { c->st = c->st2; }
+  ~OnSide() { c->st = saved; }
+};
+
 static hipError_t dmalloc_bytes(ifsvgp_ctx *c, void **p, size_t bytes) {
   void *q = nullptr;
   hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
@@ -220,6 +243,9 @@ extern "C" const char *ifsvgp_strerror(int code) {
 
 extern "C" void ifsvgp_destroy(ifsvgp_ctx *c) {
   if (!c) return;
+  if (c->st2) hipStreamDestroy(c->st2);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   for (void *p : c->allocs) hipFree(p);
   for (auto &r : c->recs) {
     hipEventDestroy(r.a);
@@ -244,6 +270,12 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   c->Bp = rup(B_max, PAD);
   c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
+  if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    ifsvgp_destroy(c);
+    return IFSVGP_EHIP;
+  }
   const size_t Mp = c->Mp, Bp = c->Bp;
   const size_t MM = Mp * Mp, MB = Mp * Bp;
   const size_t os = op_size(prec), ws = wide_size(prec);
@@ -431,11 +463,9 @@ struct Ops {
   // workgroups per CU, which hides more latency than deeper staging
   using CS = Cfg<64, 64, 2, 2, T, 2>;
   using CSW = Cfg<64, 64, 2, 2, TW, 2>;
-  // M x B products.  V and U: two stages (64 KB + a 70 KB epilogue) so two
-  // workgroups share a CU and one's epilogue overlaps the other's main loop;
-  // R, whose epilogue needs more LDS than that, keeps four stages.
+  // M x B products: two stages (64 KB), so workgroups of the products that
+  // run concurrently on the side stream can share a CU
   using CR = Cfg<128, 128, 2, 2, T, 2>;
-  using CRR = Cfg<128, 128, 2, 2, T, 4>;
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
   static T *LtT(ifsvgp_ctx *c, int i) { return (T *)c->LtT[i]; }
@@ -494,7 +524,8 @@ struct Ops {
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
     Opnd<T> a{(const T *)c->QT, c->Mp}, b{(const T *)c->Vt, c->Mp};
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, 0};
-    EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->Bp, c->Mp, c->M, B, c->var_part, c->Bp};
+    EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->vb, c->Bp, c->Mp, c->M, B, c->var_part,
+              c->mu_part, c->Bp};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // R = L U (k < m0+BM) -> H_uf reductions
@@ -504,7 +535,7 @@ struct Ops {
     Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
     EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    return launch_gemm<CRR>(lnc(c), a, b, sc, e, graduf_extra(CRR::BM, CRR::BN, D));
+    return launch_gemm<CR>(lnc(c), a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
@@ -588,6 +619,25 @@ static int stage_natgrad(ifsvgp_ctx *c, float *Lcaller, const float *gammas, int
   return IFSVGP_OK;
 }
 
+// K_uf tiles on the side stream.
+template <typename T>
+static int launch_kuf(ifsvgp_ctx *c, const float *X, int B, const float *sf2) {
+  OnSide side(c);
+  Timed t(c, KK_KUF);
+  static int kuf_attr = 0;
+  const int kb = kuf_smem(c->D);
+  if (kb > kuf_attr) {
+    HIPCK(hipFuncSetAttribute((const void *)k_kuf<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kb));
+    kuf_attr = kb;
+  }
+  hipLaunchKernelGGL((k_kuf<T>), dim3(cdiv(B, KUF_T), cdiv(c->M, KUF_T)), dim3(NTB), kb, c->st,
+                     (const float *)c->Zs, X, (const float *)c->inv_ell, c->M, B, c->D, sf2,
+                     c->Xs, (T *)c->Kft, (long)c->Mp);
+  HIPCK(hipGetLastError());
+  return IFSVGP_OK;
+}
+
 template <typename T>
 static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
                        const float *sf2, const float *noise, const float *m,
@@ -611,25 +661,13 @@ static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, dou
                        (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
                        c->vec_part, c->flag);
   }
-  {
-    Timed t(c, KK_KUF);
-    static int kuf_attr = 0;
-    const int kb = kuf_smem(c->D);
-    if (kb > kuf_attr) {
-      HIPCK(hipFuncSetAttribute((const void *)k_kuf<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kb));
-      kuf_attr = kb;
-    }
-    hipLaunchKernelGGL((k_kuf<T>), dim3(cdiv(B, KUF_T), cdiv(M, KUF_T)), dim3(NTB), kb, c->st,
-                       (const float *)c->Zs, X, (const float *)c->inv_ell, M, B, D, sf2,
-                       (const float *)c->vLb, c->Xs, (T *)c->Kft, Mp, c->mu_part, (long)c->Bp);
-  }
-  { Timed t(c, KK_V); HIPCK(Ops<T>::gemm_V(c, cur, B)); }
+  // V = L^T K_uf was produced on the side stream
+  HIPCK(join_side(c));
   { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_LIK);
     const int nb = cdiv(M, 64);
-    LikArgs a{c->mu_part, cdiv(M, KUF_T), c->var_part, cdiv(M, 128), (long)c->Bp,
+    LikArgs a{c->mu_part, cdiv(M, 128), c->var_part, cdiv(M, 128), (long)c->Bp,
               y, B, c->Bp, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
               c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
               c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
@@ -649,7 +687,13 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
   using TW = typename Ops<T>::TW;
   const int M = c->M, D = c->D, cur = c->cur;
   const long Mp = c->Mp;
-  { Timed t(c, KK_R); HIPCK(Ops<T>::gemm_R(c, cur, B, sf2)); }
+  // R = L U and its gradient epilogue run on the side stream beside the C chain
+  HIPCK(fork_side(c));
+  {
+    OnSide side(c);
+    Timed t(c, KK_R);
+    HIPCK(Ops<T>::gemm_R(c, cur, B, sf2));
+  }
   {
     Timed t(c, KK_VALPHA);
     hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
@@ -671,6 +715,7 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
     Timed t(c, KK_LQ);
     HIPCK(Ops<T>::gemm_LQ(c, cur));
   }
+  HIPCK(join_side(c));
   {
     Timed t(c, KK_GRAD);
     const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
@@ -740,8 +785,19 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
   if (fwd) {
     r = stage_setup<T>(c, Z, ell, sf2, noise, s, need_noise, L);
     if (r) return r;
+    // side stream: K_uf tiles need only Z / ell and the batch ...
+    HIPCK(fork_side(c));
+    r = launch_kuf<T>(c, X, B, sf2);
+    if (r) return r;
     r = stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
     if (r) return r;
+    // ... and V = L^T K_uf the updated L, so both run beside the Gram products
+    HIPCK(fork_side(c));
+    {
+      OnSide side(c);
+      Timed t(c, KK_V);
+      HIPCK(Ops<T>::gemm_V(c, c->cur, B));
+    }
     r = stage_bound<T>(c, X, y, B, N, sf2, noise, m, out_bound, out_terms);
     if (r) return r;
   }

@@ -196,36 +196,30 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
 // ---------------------------------------------------------------- K_uf
 // K_uf[k][n] = sf2 exp(-1/2 |zs_k - xs_n|^2) for a block of 128 inducing
 // points x 128 data points, written transposed in the operand type (Kft[n][k],
-// the B operand layout of V = L^T K_uf; zero outside k < M, n < B), plus the
-// partial mean mu_part[k-block][n] = sum_{k in block} K_uf[k][n] Lb[k] from the
-// fp32 values.  xs = X / ell is formed here; the first block row writes it.
-// Each wave owns a 64 (k) x 64 (n) sub-block; the MFMA lane layout gives every
-// lane 4 consecutive k of one n, stored straight from registers, so the
-// workgroup needs only the staged inputs in LDS (kuf_smem(D) bytes) and
-// several workgroups share a CU.
+// the B operand layout of V = L^T K_uf; zero outside k < M, n < B).
+// xs = X / ell is formed here; the first block row writes it.  Each wave owns
+// a 64 (k) x 64 (n) sub-block; the MFMA lane layout gives every lane 4
+// consecutive k of one n, stored straight from registers, so the workgroup
+// needs only the staged inputs in LDS (kuf_smem(D) bytes) and several
+// workgroups share a CU.  It depends on nothing but Z / ell and the batch, so
+// it runs alongside the natural-gradient and Gram products.
 constexpr int KUF_T = 128;
 __host__ __device__ inline int kuf_ldz(int D) { return ((D + 3) & ~3) + 1; }
-__host__ __device__ inline int kuf_smem(int D) {
-  return (2 * KUF_T * kuf_ldz(D) + 3 * KUF_T + 2 * KUF_T + D) * 4;
-}
+__host__ __device__ inline int kuf_smem(int D) { return (2 * KUF_T * kuf_ldz(D) + 2 * KUF_T + D) * 4; }
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
                                              const float *inv_ell, int M, int B, int D,
-                                             const float *sf2, const float *Lb, float *Xs, T *Kft,
-                                             long ld, float *mu_part, long ldp) {
+                                             const float *sf2, float *Xs, T *Kft, long ld) {
   extern __shared__ __attribute__((aligned(16))) float ksm[];
   const int D4 = (D + 3) & ~3, LDZ = kuf_ldz(D);
   float *zs = ksm;                    // [128][LDZ]
   float *xs = zs + KUF_T * LDZ;       // [128][LDZ]
   float *zn = xs + KUF_T * LDZ;       // [128]
   float *xn = zn + KUF_T;             // [128]
-  float *lb = xn + KUF_T;             // [128]
-  float *mred = lb + KUF_T;           // [2][128]: mean partials of the two k halves
-  float *il = mred + 2 * KUF_T;       // [D]: 1 / ell
+  float *il = xn + KUF_T;             // [D]: 1 / ell
   const int t = threadIdx.x;
   const int k0 = blockIdx.y * KUF_T, n0 = blockIdx.x * KUF_T;
   if (t < D) il[t] = inv_ell[t];
-  if (t < KUF_T) lb[t] = ld_or0(Lb, k0 + t, k0 + t < M);
   // stage Zs rows and raw X rows, then scale X by 1/ell in LDS
   stage_rows<NTB>(zs, LDZ, Zs, k0, KUF_T, M, D, -1);
   stage_rows<NTB>(xs, LDZ, X, n0, KUF_T, B, D, -1);
@@ -254,31 +248,23 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
   const int kb0 = (wave >> 1) * 64, nb0 = (wave & 1) * 64;
   f32x4 c[4][4];
   cross_block<4, 4>(zs + kb0 * LDZ, LDZ, xs + nb0 * LDZ, LDZ, D4, c);
-  float zr[4][4], lr_[4][4];
+  float zr[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = kb0 + 16 * i + 4 * l4 + q;
-      zr[i][q] = zn[k];
-      lr_[i][q] = lb[k];
-    }
+    for (int q = 0; q < 4; ++q) zr[i][q] = zn[kb0 + 16 * i + 4 * l4 + q];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int n = nb0 + 16 * j + l16;
     const bool nok = n0 + n < B;
     const float xv = xn[n];
-    float mu = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int kq = kb0 + 16 * i + 4 * l4;  // first of this lane's 4 consecutive k
       T e[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float v = (nok && k0 + kq + q < M) ? kern_se(s2, zr[i][q], xv, c[i][j][q]) : 0.f;
-        mu = fmaf(v, lr_[i][q], mu);
-        e[q] = from_f32<T>(v);
-      }
+      for (int q = 0; q < 4; ++q)
+        e[q] = from_f32<T>((nok && k0 + kq + q < M) ? kern_se(s2, zr[i][q], xv, c[i][j][q]) : 0.f);
       T *dst = Kft + (long)(n0 + n) * ld + k0 + kq;
       if constexpr (sizeof(T) == 4) {
         *(f32x4 *)dst = f32x4{(float)e[0], (float)e[1], (float)e[2], (float)e[3]};
@@ -288,14 +274,7 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
         *(uint2 *)dst = raw;
       }
     }
-    // sum over the four lanes (l4) that share n, then over the two k halves
-    mu += __shfl_xor(mu, 16, 64);
-    mu += __shfl_xor(mu, 32, 64);
-    if (l4 == 0) mred[(wave >> 1) * KUF_T + n] = mu;
   }
-  __syncthreads();
-  if (t < KUF_T && n0 + t < B)
-    mu_part[(long)blockIdx.y * ldp + n0 + t] = mred[t] + mred[KUF_T + t];
 }
 
 // sum_{k < np} p[k * stride]: each round issues W loads (clamped to an
