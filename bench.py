@@ -91,10 +91,11 @@ def schedule(n, g0=1e-5, g1=1.0, ramp=10):
     return out
 
 
-def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev):
+def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=True):
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
+    ctx.set_graphs(graphs)
     L = L0.clone()
     F = torch.empty(1, dtype=torch.float64, device=dev)
     terms = torch.empty(8, dtype=torch.float64, device=dev)
@@ -189,6 +190,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="run every call directly instead of replaying recorded HIP graphs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (the "
                          "reference dispatch for scaling HBM byte counters)")
@@ -219,7 +222,8 @@ def main():
     res = {}
     for prec in forms:
         log(f"bench: timing {prec}: {args.warmup} warmup + {args.steps} steps")
-        res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup, dominant, dev)
+        res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup, dominant, dev,
+                              graphs=not args.no_graphs)
         log(f"bench: {prec} {res[prec]['ms_per_step']:.3f} ms/step, {dominant} "
             f"{res[prec]['dom_ms'] * 1e3:.1f} us, status {res[prec]['status']}")
     main_r = res[args.prec]

@@ -176,3 +176,22 @@ IFS_DEV void cross_block(const float *A, int lda, const float *B, int ldb, int D
 
 // Device-side error flags (sticky until read by the host).
 enum : int { FLAG_DOMAIN = 1, FLAG_NONFINITE = 2 };
+
+// Caller arguments of one library call, copied into device memory by k_latch
+// at the start of the call.  Kernels take the caller's buffers and scalars
+// from here, so their launch arguments name only the context's workspace and
+// a recorded launch sequence (a HIP graph) replays for any caller buffers.
+constexpr int MAX_NG_LATCH = 64;  // natural-gradient step sizes per latch
+struct CallArgs {
+  const float *X, *y, *ell, *sf2, *noise, *Z, *m, *s;
+  float *L;                     // caller's L (read by the set-up, written by the last NG step)
+  const double *grad_scale;     // or null
+  double *out_bound, *out_terms, *out_resid;
+  float *g_ell, *g_sf2, *g_noise, *g_Z, *g_m, *g_s;
+  double c;                     // N / B, the data term's scale
+  float gammas[MAX_NG_LATCH];   // NG step sizes, from the latch's first step on
+};
+
+__global__ void k_latch(CallArgs a, CallArgs *dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}

@@ -55,6 +55,35 @@ struct Chunks {
 
 #define CS(r, c) Cs[(r) * C::LDC + (c)]
 
+// A chunk of VEC staged values along a row (cs_row: columns c..c+VEC-1 of row
+// r) or down a column (cs_col: rows r..r+VEC-1 of column c).  The staged tile
+// always spans the whole BM x BN block, so the reads are unconditional (and
+// stay in flight together); values outside the valid region (ok false, or
+// index q >= nq along the chunk) are replaced by zero afterwards.
+// lds_get: a read of the staged tile that the compiler may not move into the
+// branch of a later select (volatile), so that guarded uses of staged values
+// compile to selects after reads that are all in flight, not to one
+// branch-and-wait per value.
+IFS_DEV float lds_get(const float *p) { return *(const volatile float *)p; }
+#define CSV(r, c) lds_get(Cs + (r) * C::LDC + (c))
+
+template <class C>
+IFS_DEV void cs_row(const float *Cs, int r, int c, bool ok, int nq, float (&x)[VEC]) {
+  float v[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) v[q] = CSV(r, c + q);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) x[q] = (ok && q < nq) ? v[q] : 0.f;
+}
+template <class C>
+IFS_DEV void cs_col(const float *Cs, int r, int c, bool ok, int nq, float (&x)[VEC]) {
+  float v[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) v[q] = CSV(r + q, c);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) x[q] = (ok && q < nq) ? v[q] : 0.f;
+}
+
 // Sum of one double per thread over the workgroup, result in thread 0.
 template <class C>
 IFS_DEV double tile_sum(double v, const float *Cs) {
@@ -189,8 +218,7 @@ struct EpiStore {
       K::row(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
       float x[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) x[q] = (gi < R && gj + q < N) ? CS(r, c + q) : 0.f;
+      cs_row<C>(Cs, r, c, gi < R, N - gj, x);
       st_pack(o + (long)gi * ld + gj, x);
     }
     if (mirror && t.m0 != t.n0) {
@@ -200,8 +228,7 @@ struct EpiStore {
         K::col(k, r, c);
         const int gi = t.m0 + r, gj = t.n0 + c;
         float x[VEC];
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) x[q] = (gi + q < R && gj < N) ? CS(r + q, c) : 0.f;
+        cs_col<C>(Cs, r, c, gj < N, R - gi, x);
         st_pack(o + (long)gj * ld + gi, x);
       }
     }
@@ -223,8 +250,7 @@ struct EpiStoreT {
       K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
       float x[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < R && gj < N) ? CS(r + q, c) : 0.f;
+      cs_col<C>(Cs, r, c, gj < N, R - gi, x);
       st_pack(out + (long)gj * ld + gi, x);
     }
   }
@@ -289,14 +315,17 @@ struct EpiNgUpdate {
   T *LnsT;            // LnsT[j][i] = Lnew[i][j] s~_i
   long ld;
   int M;
-  float gamma;
-  float *Lout;        // caller's L (leading dimension M) or null
+  const CallArgs *ca;  // step size gammas[gidx]; the caller's L (leading
+                       // dimension M) when write_out; out_resid[step] if given
+  int gidx, step, write_out;
   const double *gram_part;
   int n_gram;
-  double *resid_out, *scal;
+  double *scal;
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
+    const float gamma = ca->gammas[gidx];
+    float *Lout = write_out ? ca->L : nullptr;
     float lv[K::N][VEC];
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
@@ -313,7 +342,8 @@ struct EpiNgUpdate {
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
         const int gj = gj0 + q;
-        v[q] = (gi < M && gj < M && gi >= gj) ? lv[k][q] - gamma * CS(r, c + q) : 0.f;
+        const float x = CSV(r, c + q);
+        v[q] = (gi < M && gj < M && gi >= gj) ? lv[k][q] - gamma * x : 0.f;
       }
       st_pack(Ln + (long)gi * ld + gj0, v);
       if constexpr (!std::is_same<T, float>::value) st_pack(LnT + (long)gi * ld + gj0, v);
@@ -349,7 +379,7 @@ struct EpiNgUpdate {
       if (threadIdx.x == 0) {
         const double r = sqrt(s / M);
         scal[S_RESID] = r;
-        if (resid_out) *resid_out = r;
+        if (ca->out_resid) ca->out_resid[step] = r;
       }
     }
   }
@@ -392,7 +422,8 @@ struct EpiBoundGram {
         const bool in = gi < M && gj < M;
         const float w = wv[k][q];
         const float qv = in ? (gi == gj ? 2.f : 0.f) - w : 0.f;
-        const float wu = in ? w - CS(r, c + q) : 0.f;
+        const float e = CSV(r, c + q);
+        const float wu = in ? w - e : 0.f;
         if (in && gi >= gj) {
           const double mult = gi == gj ? 1.0 : 2.0;
           if (gi == gj) trw += w;
@@ -469,8 +500,7 @@ struct EpiV {
       K::row(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
       float x[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) x[q] = (gi < M && gj + q < B) ? CS(r, c + q) : 0.f;
+      cs_row<C>(Cs, r, c, gi < M, B - gj, x);
       st_pack(V + (long)gi * ldv + gj, x);
     }
 #pragma unroll
@@ -479,8 +509,7 @@ struct EpiV {
       K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
       float x[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < M && gj < B) ? CS(r + q, c) : 0.f;
+      cs_col<C>(Cs, r, c, gj < B, M - gi, x);
       st_pack(Vt + (long)gj * ldt + gi, x);
     }
   }
@@ -517,8 +546,7 @@ struct EpiU {
       K::col(k, r, c);
       const int gi = t.m0 + r, gj = t.n0 + c;
       float x[VEC];
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) x[q] = (gi + q < M && gj < B) ? CS(r + q, c) : 0.f;
+      cs_col<C>(Cs, r, c, gj < B, M - gi, x);
       st_pack(Ut + (long)gj * ldt + gi, x);
     }
     __syncthreads();

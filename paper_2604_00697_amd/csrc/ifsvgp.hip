@@ -41,16 +41,44 @@ struct TimingRec {
   hipEvent_t a, b;
 };
 
+// Launch structure of a call (what a recorded graph depends on).
+struct GraphKey {
+  bool setup, fwd, bwd;
+  int B, n_ng;
+  bool need_noise, want_gm, want_gs;
+  int cur0;  // L slot a backward-only call starts from (0 otherwise)
+};
+struct GraphEnt {
+  GraphKey key;
+  hipGraphExec_t exec;  // null until the structure is seen a second time
+  int failed;           // recording failed: always run directly
+  int cur;              // c->cur after the call
+  long long tick;       // last use (least recently used entry is replaced)
+};
+static constexpr size_t kMaxGraphs = 16;
+
 struct ifsvgp_ctx {
   int M, Bmax, D, prec, lik, ngh;
   int Mp, Bp;
   int nsplit;
   hipStream_t st;
   // side stream for branches of the iteration that are independent of the
-  // main chain (K_uf tiles and V during the Gram products; R = L U during the
-  // backward's C chain); forked from and joined back into st with events
-  hipStream_t st2;
-  hipEvent_t ev_fork, ev_join;
+  // main chain (K_uf tiles, then V and L^T m~, during the NG and Gram
+  // products; R = L U during the backward's C chain); forked from and joined
+  // back into st with events
+  hipStream_t side;
+  static constexpr int kEvents = 16;
+  hipEvent_t evs[kEvents];  // fork / join points of one call, in order
+  int ev_next;
+  bool side_open;           // the side stream has work not yet joined into st
+  // device argument block of the current call, written by its k_latch
+  CallArgs *dca;
+  float *sfn;  // {sf2, noise_var} copied by the set-up
+  // recorded calls (HIP graphs) and the stream they are recorded on
+  hipStream_t cst;
+  int use_graphs;
+  std::vector<GraphEnt> graphs;
+  long long graph_tick;
   // fp32 M x M ([Mp][Mp])
   float *Kt, *L32[2], *Lt32[2], *W32, *Q32, *Wu32, *Ys;  // Ys: [nsplit][Mp][Mp]
   // operand-type M x M ([Mp][Mp]); C and Y2 use the wide-range type of the form
@@ -140,21 +168,40 @@ struct Timed {
   }
 };
 
-// Side-stream branches: fork makes st2 wait for all work enqueued on st so
-// far, join makes st wait for all work enqueued on st2 so far; OnSide
-// redirects the enqueues of its scope (kernels and timing events) to st2.
-static hipError_t fork_side(ifsvgp_ctx *c) {
-  hipError_t e = hipEventRecord(c->ev_fork, c->st);
-  return e != hipSuccess ? e : hipStreamWaitEvent(c->st2, c->ev_fork, 0);
+// Side-stream branches.  fork_side makes the side stream wait for all work
+// enqueued on st so far; join_side makes st wait for all work enqueued on the
+// side stream so far; OnSide redirects the enqueues of its scope (kernels and
+// timing events) to the side stream.  The side stream is forked only when it
+// has no work that st has not joined, so each branch's dependencies are
+// exactly its fork point, both in direct execution and when the launches are
+// recorded into a graph.  Every fork and join point of a call uses its own
+// event.
+static hipEvent_t next_event(ifsvgp_ctx *c) {
+  hipEvent_t e = c->evs[c->ev_next % ifsvgp_ctx::kEvents];
+  ++c->ev_next;
+  return e;
 }
 static hipError_t join_side(ifsvgp_ctx *c) {
-  hipError_t e = hipEventRecord(c->ev_join, c->st2);
-  return e != hipSuccess ? e : hipStreamWaitEvent(c->st, c->ev_join, 0);
+  if (!c->side_open) return hipSuccess;
+  hipEvent_t ev = next_event(c);
+  hipError_t e = hipEventRecord(ev, c->side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->st, ev, 0);
+  c->side_open = false;
+  return e;
+}
+static hipError_t fork_side(ifsvgp_ctx *c) {
+  hipError_t e = join_side(c);
+  if (e != hipSuccess) return e;
+  hipEvent_t ev = next_event(c);
+  e = hipEventRecord(ev, c->st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->side, ev, 0);
+  c->side_open = true;
+  return e;
 }
 struct OnSide {
   ifsvgp_ctx *c;
   hipStream_t saved;
-  explicit OnSide(ifsvgp_ctx *c_) : c(c_), saved(c_->st) { c->st = c->st2; }
+  explicit OnSide(ifsvgp_ctx *c_) : c(c_), saved(c_->st) { c->st = c->side; }
   ~OnSide() { c->st = saved; }
 };
 
@@ -241,11 +288,15 @@ extern "C" const char *ifsvgp_strerror(int code) {
   }
 }
 
+static void graphs_clear(ifsvgp_ctx *c);
+
 extern "C" void ifsvgp_destroy(ifsvgp_ctx *c) {
   if (!c) return;
-  if (c->st2) hipStreamDestroy(c->st2);
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_join) hipEventDestroy(c->ev_join);
+  graphs_clear(c);
+  if (c->cst) hipStreamDestroy(c->cst);
+  if (c->side) hipStreamDestroy(c->side);
+  for (auto ev : c->evs)
+    if (ev) hipEventDestroy(ev);
   for (void *p : c->allocs) hipFree(p);
   for (auto &r : c->recs) {
     hipEventDestroy(r.a);
@@ -270,9 +321,13 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   c->Bp = rup(B_max, PAD);
   c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
-  if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+  c->use_graphs = 1;
+  c->graph_tick = 0;
+  bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->cst, hipStreamNonBlocking) == hipSuccess;
+  for (int k = 0; ok && k < ifsvgp_ctx::kEvents; ++k)
+    ok = hipEventCreateWithFlags(&c->evs[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     ifsvgp_destroy(c);
     return IFSVGP_EHIP;
   }
@@ -355,6 +410,8 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->gh, (size_t)2 * std::max(1, c->ngh));
   ALLOC(c->flag, (size_t)1);
   ALLOC(c->counters, (size_t)CNT_N);
+  ALLOC(c->dca, (size_t)1);
+  ALLOC(c->sfn, (size_t)2);
 #undef ALLOC
 #undef ALLOCB
   if (e == hipSuccess && c->ngh > 0) {
@@ -463,9 +520,13 @@ struct Ops {
   // workgroups per CU, which hides more latency than deeper staging
   using CS = Cfg<64, 64, 2, 2, T, 2>;
   using CSW = Cfg<64, 64, 2, 2, TW, 2>;
-  // M x B products: two stages (64 KB), so workgroups of the products that
-  // run concurrently on the side stream can share a CU
-  using CR = Cfg<128, 128, 2, 2, T, 2>;
+  // M x B products, two stages.  CR: V and U on 128 x 64 tiles (twice the
+  // workgroups of 128 x 128, so several share a CU and one's epilogue overlaps
+  // another's main loop; their partial sums are per 128-row block).  CRG: R on
+  // 128 x 128 tiles, whose gradient partials are per 128-column block.
+  using CR = Cfg<128, 64, 2, 2, T, 2>;
+  using CRG = Cfg<128, 128, 2, 2, T, 2>;
+  static_assert(CR::BM == 128 && CRG::BM == 128 && CRG::BN == 128, "partial-sum layout");
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
   static T *LtT(ifsvgp_ctx *c, int i) { return (T *)c->LtT[i]; }
@@ -488,15 +549,15 @@ struct Ops {
     EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
     return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
-  // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM; also the residual of
-  // this step and (Lout non-null) the caller's L
-  static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, float gamma, float *Lout,
-                         double *resid_out) {
+  // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM, gamma the call's
+  // step size gidx; also the residual of NG step `step` and (write_out) the
+  // caller's L
+  static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, int gidx, int step, int write_out) {
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Xgt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0 | K_HI_M1};
     EpiNgUpdate<T> e{c->L32[cur], c->L32[nxt], c->Lt32[nxt], LT(c, nxt), LtT(c, nxt),
-                     c->sP, (T *)c->LstT[nxt], c->Mp, c->M, gamma, Lout, c->tp_ng, nb(c) * (nb(c) + 1) / 2,
-                     resid_out, c->scal};
+                     c->sP, (T *)c->LstT[nxt], c->Mp, c->M, c->dca, gidx, step, write_out,
+                     c->tp_ng, nb(c) * (nb(c) + 1) / 2, c->scal};
     return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // W' = L^T Y (lower tiles, fp32)
@@ -516,26 +577,26 @@ struct Ops {
   // V = L^T K_uf (k >= m0) -> V, Vt
   static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Kft, c->Mp};
-    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_LO_M0};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
     Opnd<T> a{(const T *)c->QT, c->Mp}, b{(const T *)c->Vt, c->Mp};
-    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, 0};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, 0};
     EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->vb, c->Bp, c->Mp, c->M, B, c->var_part,
               c->mu_part, c->Bp};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // R = L U (k < m0+BM) -> H_uf reductions
-  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *sf2) {
+  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B) {
     const int D = c->D;
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Ut, c->Mp};
-    Sched sc{cdiv(c->M, 128), cdiv(B, 128), 0, 1, c->M, K_HI_M1};
-    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, sf2, c->M, B, D,
+    Sched sc{cdiv(c->M, CRG::BM), cdiv(B, CRG::BN), 0, 1, c->M, K_HI_M1};
+    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, c->sfn, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e, graduf_extra(CR::BM, CR::BN, D));
+    return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D));
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
@@ -560,11 +621,11 @@ struct Ops {
     return launch_gemm<CSW>(lnc(c), a, b, sc, e);
   }
   // G_uu = Y2 L^T (lower tiles, k < n0+BN) -> H_uu reductions
-  static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, const float *s, float *gdiag) {
+  static hipError_t gemm_Guu(ifsvgp_ctx *c, int cur, float *gdiag) {
     const int D = c->D;
     Opnd<TW> a{(const TW *)c->Y2, c->Mp}, b{LW(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
-    EpiGradUu e{c->Kt, s, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, gdiag};
+    EpiGradUu e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, gdiag};
     return launch_gemm<CSW>(lnc(c), a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
   // L Q on lower tiles (k < m0+BM) -> partials of diag(L Q L^T) = diag(P)
@@ -577,41 +638,67 @@ struct Ops {
 };
 
 // ------------------------------------------------------------------ stages
+// One library call: the stages it runs and the host-side values that shape
+// its launches.  Everything else the kernels read about the call (the
+// caller's buffers, N / B, grad_scale, the NG step sizes) is in the device
+// argument block c->dca written by the call's k_latch.
+struct Call {
+  bool setup, fwd, bwd;  // set-up + NG steps; bound; backward
+  int B, n_ng;
+  const float *gammas;   // host, n_ng values
+  bool need_noise, want_gm, want_gs;
+};
+
+// Copies NG step sizes [s0, s0 + n) into the device block (stream ordered
+// after the steps that read the previous window).
+__global__ void k_latch_gammas(CallArgs g, int n, CallArgs *dst) {
+  const int t = threadIdx.x;
+  if (t < n) dst->gammas[t] = g.gammas[t];
+}
+
+// cav non-null: the set-up also writes the call's argument block (direct
+// execution); null: a k_latch has written it (recorded calls).
 template <typename T>
-static int stage_setup(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
-                       const float *noise, const float *s, int need_noise, const float *Lin) {
+static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
   const int M = c->M;
   Timed t(c, KK_PREP);
   SetupArgs a;
-  a.Z = Z; a.ell = ell; a.sf2 = sf2; a.noise = noise; a.s = s;
+  a.latch = cav != nullptr;
+  if (cav) a.cav = *cav;
+  a.ca = c->dca;
   a.M = M; a.D = c->D; a.need_noise = need_noise;
-  a.Zs = c->Zs; a.inv_ell = c->inv_ell; a.sP = c->sP; a.Kt = c->Kt; a.KtT = c->KtT;
+  a.Zs = c->Zs; a.inv_ell = c->inv_ell; a.sP = c->sP; a.Kt = c->Kt; a.sfn = c->sfn;
+  a.KtT = c->KtT;
   a.ld = c->Mp;
-  a.Lin = Lin;
   a.L32 = c->L32[0]; a.Lt32 = c->Lt32[0]; a.LT = c->LT[0]; a.LtT = c->LtT[0];
   a.LstT = c->LstT[0];
   a.scal = c->scal; a.flag = c->flag;
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);
-  const int nL = Lin ? a.nLx * a.nLx : 0;
-  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + nL), dim3(NTB), 0, c->st, a);
+  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + a.nLx * a.nLx), dim3(NTB), 0, c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
 
 // n_ng natural-gradient steps from slot 0; the last writes the caller's L.
+// Step sizes beyond the first MAX_NG_LATCH are latched window by window.
 template <typename T>
-static int stage_natgrad(ifsvgp_ctx *c, float *Lcaller, const float *gammas, int n_ng,
-                         double *out_resid) {
+static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng) {
   int cur = 0;
   for (int s = 0; s < n_ng; ++s) {
+    if (s > 0 && s % MAX_NG_LATCH == 0) {
+      CallArgs g{};
+      const int n = std::min(MAX_NG_LATCH, n_ng - s);
+      for (int k = 0; k < n; ++k) g.gammas[k] = gammas[s + k];
+      hipLaunchKernelGGL(k_latch_gammas, dim3(1), dim3(MAX_NG_LATCH), 0, c->st, g, n, c->dca);
+      HIPCK(hipGetLastError());
+    }
     { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
     { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, cur)); }
     {
       Timed t(c, KK_NG_L);
-      HIPCK(Ops<T>::ng_L(c, cur, 1 - cur, gammas[s], s == n_ng - 1 ? Lcaller : nullptr,
-                         out_resid ? out_resid + s : nullptr));
+      HIPCK(Ops<T>::ng_L(c, cur, 1 - cur, s % MAX_NG_LATCH, s, s == n_ng - 1));
     }
     cur = 1 - cur;
   }
@@ -621,7 +708,7 @@ static int stage_natgrad(ifsvgp_ctx *c, float *Lcaller, const float *gammas, int
 
 // K_uf tiles on the side stream.
 template <typename T>
-static int launch_kuf(ifsvgp_ctx *c, const float *X, int B, const float *sf2) {
+static int launch_kuf(ifsvgp_ctx *c, int B) {
   OnSide side(c);
   Timed t(c, KK_KUF);
   static int kuf_attr = 0;
@@ -632,67 +719,64 @@ static int launch_kuf(ifsvgp_ctx *c, const float *X, int B, const float *sf2) {
     kuf_attr = kb;
   }
   hipLaunchKernelGGL((k_kuf<T>), dim3(cdiv(B, KUF_T), cdiv(c->M, KUF_T)), dim3(NTB), kb, c->st,
-                     (const float *)c->Zs, X, (const float *)c->inv_ell, c->M, B, c->D, sf2,
-                     c->Xs, (T *)c->Kft, (long)c->Mp);
+                     (const float *)c->Zs, (const CallArgs *)c->dca, (const float *)c->inv_ell,
+                     c->M, B, c->D, (const float *)c->sfn, c->Xs, (T *)c->Kft, (long)c->Mp);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
 
+// Bound at c->cur.  V = L^T K_uf and a = L^T m~ have been enqueued on the
+// side stream (forked after the last update of L).
 template <typename T>
-static int stage_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
-                       const float *sf2, const float *noise, const float *m,
-                       double *out_bound, double *out_terms) {
-  const int M = c->M, D = c->D, cur = c->cur;
+static int stage_bound(ifsvgp_ctx *c, int B) {
+  const int M = c->M, cur = c->cur;
   const float *L = c->L32[cur];
   const long Mp = c->Mp;
   { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
   { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, cur)); }
   { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, cur)); }
+  HIPCK(join_side(c));
+  const int rows = cdiv(M, NTB / 64);
   {
+    // b = Q a
     Timed t(c, KK_VEC);
-    const int rows = cdiv(M, NTB / 64);
-    // a = L^T m~ (rows of the fp32 transpose), b = Q a
-    hipLaunchKernelGGL(k_gemv_rows, dim3(rows), dim3(NTB), 0, c->st, (const float *)c->Lt32[cur],
-                       Mp, M, M, m, 0, (const double *)nullptr, c->va);
     hipLaunchKernelGGL(k_gemv_rows, dim3(rows), dim3(NTB), 0, c->st, (const float *)c->Q32, Mp,
-                       M, M, (const float *)c->va, 0, (const double *)nullptr, c->vb);
+                       M, M, (const float *)c->va, (const float *)nullptr, 0,
+                       (const double *)nullptr, c->vb);
+  }
+  {
     // Lb = L b, Wub = Wu b, with partials of quad and log|T|
+    Timed t(c, KK_VEC);
     hipLaunchKernelGGL(k_vec_lb_wub, dim3(cdiv(2 * M, NTB / 64)), dim3(NTB), 0, c->st, L,
                        (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
                        c->vec_part, c->flag);
   }
-  // V = L^T K_uf was produced on the side stream
-  HIPCK(join_side(c));
   { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_LIK);
     const int nb = cdiv(M, 64);
     LikArgs a{c->mu_part, cdiv(M, 128), c->var_part, cdiv(M, 128), (long)c->Bp,
-              y, B, c->Bp, sf2, noise, N / (double)B, c->lik, c->gh, c->ngh,
+              c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
               c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
               c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
-              c->scal, M, out_bound, out_terms, c->flag, c->counters + CNT_LIK};
+              c->scal, M, c->flag, c->counters + CNT_LIK};
     hipLaunchKernelGGL(k_lik, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
   }
   HIPCK(hipGetLastError());
-  c->fwd_valid = 1;
-  c->fwd_B = B;
   return IFSVGP_OK;
 }
 
 template <typename T>
-static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, const float *s,
-                          const double *grad_scale, float *g_ell, float *g_sf2, float *g_noise,
-                          float *g_Z, float *g_m, float *g_s) {
+static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
   using TW = typename Ops<T>::TW;
   const int M = c->M, D = c->D, cur = c->cur;
   const long Mp = c->Mp;
-  // R = L U and its gradient epilogue run on the side stream beside the C chain
+  // R = L U and its gradient epilogue run on side stream 0 beside the C chain
   HIPCK(fork_side(c));
   {
     OnSide side(c);
     Timed t(c, KK_R);
-    HIPCK(Ops<T>::gemm_R(c, cur, B, sf2));
+    HIPCK(Ops<T>::gemm_R(c, cur, B));
   }
   {
     Timed t(c, KK_VALPHA);
@@ -710,8 +794,8 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
                        Mp, (TW *)c->Cm);
   }
   { Timed t(c, KK_Y2); HIPCK(Ops<T>::gemm_Y2(c, cur)); }
-  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, s, g_s ? c->gdiag : nullptr)); }
-  if (g_s) {
+  { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, want_gs ? c->gdiag : nullptr)); }
+  if (want_gs) {
     Timed t(c, KK_LQ);
     HIPCK(Ops<T>::gemm_LQ(c, cur));
   }
@@ -721,89 +805,62 @@ static int stage_backward(ifsvgp_ctx *c, int B, double N, const float *sf2, cons
     const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
     const int R = NTB / D;
     const int rb = cdiv(M, R), cb = cdiv(B, R), rq = cdiv(M, NTB / 64);
-    GradArgs g{M, B, D, c->Zs, c->Xs, c->inv_ell, sf2,
+    GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
                c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
                c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
                c->lik_part, cdiv(c->Bp, NTB),
-               c->Q32, c->vVa, c->vWub, Mp, c->vt2,
-               N / (double)B, grad_scale, g_Z, g_ell, g_sf2, g_noise, c->ell_part, rb, cb,
-               c->gdiag, c->pdiag, (long)Mp, c->vLb, s, g_s};
+               c->Q32, c->vVa, c->vWub, Mp, c->vt2, c->ell_part, rb, cb,
+               c->gdiag, c->pdiag, (long)Mp, c->vLb, c->sP};
     hipLaunchKernelGGL(k_grad, dim3(rb + cb + rq), dim3(NTB), 0, c->st, g);
-    // dF/dm~ = L t2, t2 = Q (V alpha - Wu b), dF/ds~, and the scalar gradients
-    const int mrows = (g_m || g_s) ? cdiv(M, NTB / 64) : 0;
+    // dF/dm~ = L t2 and dF/ds~ rows (when requested), then the scalar gradients
+    const int mrows = (want_gm || want_gs) ? rq : 0;
     hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
-                       (const float *)c->L32[cur], g_m, mrows);
+                       (const float *)c->L32[cur], mrows);
   }
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
 
-// ------------------------------------------------------------------ API: compute
-static bool bad_common(ifsvgp_ctx *c, const float *ell, const float *sf2, const float *Z,
-                       const float *s, const float *L) {
-  return !c || !ell || !sf2 || !Z || !s || !L;
-}
-
+// All launches of one call on c->st (and the side stream), in order.
 template <typename T>
-static int do_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
-                      const float *s, float *L, const float *gammas, int n_ng, double *out_resid) {
-  int r = stage_setup<T>(c, Z, ell, sf2, nullptr, s, 0, L);
-  if (r) return r;
-  c->fwd_valid = 0;
-  return stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
-}
-
-extern "C" int ifsvgp_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
-                              const float *s_tilde, float *L, const float *gammas, int n_ng,
-                              double *out_resid) {
-  if (bad_common(c, ell, sf2, Z, s_tilde, L) || !gammas || n_ng < 1) return IFSVGP_EINVAL;
-  switch (c->prec) {
-    case IFSVGP_PREC_FP32: return do_natgrad<float>(c, Z, ell, sf2, s_tilde, L, gammas, n_ng, out_resid);
-    case IFSVGP_PREC_BF16: return do_natgrad<__bf16>(c, Z, ell, sf2, s_tilde, L, gammas, n_ng, out_resid);
-    default: return do_natgrad<_Float16>(c, Z, ell, sf2, s_tilde, L, gammas, n_ng, out_resid);
-  }
-}
-
-static int check_bound_args(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
-                            const float *ell, const float *sf2, const float *noise,
-                            const float *Z, const float *m, const float *s, const float *L) {
-  if (bad_common(c, ell, sf2, Z, s, L) || !X || !y || !m) return IFSVGP_EINVAL;
-  if (B < 1 || B > c->Bmax || !(N > 0.0)) return IFSVGP_EINVAL;
-  if (c->lik == IFSVGP_LIK_GAUSSIAN && !noise) return IFSVGP_EINVAL;
-  return IFSVGP_OK;
-}
-
-template <typename T>
-static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
-                   const float *ell, const float *sf2, const float *noise, const float *Z,
-                   const float *m, const float *s, float *L, const float *gammas, int n_ng,
-                   double *out_bound, double *out_terms, double *out_resid, bool fwd, bool bwd,
-                   const double *grad_scale, float *g_ell, float *g_sf2, float *g_noise,
-                   float *g_Z, float *g_m, float *g_s) {
-  const int need_noise = c->lik == IFSVGP_LIK_GAUSSIAN;
+static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
   int r;
-  if (fwd) {
-    r = stage_setup<T>(c, Z, ell, sf2, noise, s, need_noise, L);
+  c->ev_next = 0;
+  c->side_open = false;
+  if (k.setup) {
+    r = stage_setup<T>(c, k.need_noise, cav);
     if (r) return r;
+    if (!k.fwd) {
+      c->fwd_valid = 0;
+      return stage_natgrad<T>(c, k.gammas, k.n_ng);
+    }
     // side stream: K_uf tiles need only Z / ell and the batch ...
     HIPCK(fork_side(c));
-    r = launch_kuf<T>(c, X, B, sf2);
+    r = launch_kuf<T>(c, k.B);
     if (r) return r;
-    r = stage_natgrad<T>(c, L, gammas, n_ng, out_resid);
+    r = stage_natgrad<T>(c, k.gammas, k.n_ng);
     if (r) return r;
-    // ... and V = L^T K_uf the updated L, so both run beside the Gram products
+    // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
+    // K_uf tiles first), so all of them run beside the Gram products
     HIPCK(fork_side(c));
     {
       OnSide side(c);
-      Timed t(c, KK_V);
-      HIPCK(Ops<T>::gemm_V(c, c->cur, B));
+      {
+        Timed t(c, KK_V);
+        HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
+      }
+      Timed t(c, KK_VEC);
+      hipLaunchKernelGGL(k_lt_m, dim3(cdiv(c->M, NTB / 64)), dim3(NTB), 0, c->st,
+                         (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
+                         (const CallArgs *)c->dca, c->va);
     }
-    r = stage_bound<T>(c, X, y, B, N, sf2, noise, m, out_bound, out_terms);
+    r = stage_bound<T>(c, k.B);
     if (r) return r;
+    c->fwd_valid = 1;
+    c->fwd_B = k.B;
   }
-  if (bwd) {
-    if (!c->fwd_valid || c->fwd_B != B) return IFSVGP_ESTATE;
-    r = stage_backward<T>(c, B, N, sf2, s, grad_scale, g_ell, g_sf2, g_noise, g_Z, g_m, g_s);
+  if (k.bwd) {
+    r = stage_backward<T>(c, k.B, k.want_gm, k.want_gs);
     if (r) return r;
   }
   return IFSVGP_OK;
@@ -816,6 +873,146 @@ static int do_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double 
     default: return fn<_Float16>(__VA_ARGS__);                     \
   }
 
+// cav: the call's arguments, latched by the set-up (direct execution of a
+// call with a set-up), or null when a k_latch has already written them.
+static int enqueue_any(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
+  PREC_DISPATCH(enqueue, c, k, cav)
+}
+static int latch(ifsvgp_ctx *c, const CallArgs &ca) {
+  hipLaunchKernelGGL(k_latch, dim3(1), dim3(64), 0, c->st, ca, c->dca);
+  HIPCK(hipGetLastError());
+  return IFSVGP_OK;
+}
+// direct execution: the set-up latches the arguments when there is one
+static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
+  if (k.setup) return enqueue_any(c, k, &ca);
+  int r = latch(c, ca);
+  return r ? r : enqueue_any(c, k, nullptr);
+}
+
+// ------------------------------------------------------------------ graphs
+// A call whose launch structure (stages, B, NG step count, requested
+// outputs) has been seen before is recorded once into a HIP graph on the
+// private capture stream, then replayed on c->st with one launch; the
+// caller's buffers reach the kernels through the argument block, so replays
+// serve any buffers.  Structures seen once run directly, so changing shapes
+// cost no recording.
+static bool same_key(const GraphKey &a, const GraphKey &b) {
+  return a.setup == b.setup && a.fwd == b.fwd && a.bwd == b.bwd && a.B == b.B &&
+         a.n_ng == b.n_ng && a.need_noise == b.need_noise && a.want_gm == b.want_gm &&
+         a.want_gs == b.want_gs && a.cur0 == b.cur0;
+}
+
+static void graphs_clear(ifsvgp_ctx *c) {
+  for (auto &g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+static int run_call(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
+  const GraphKey key{k.setup, k.fwd,     k.bwd,     k.B,
+                     k.n_ng,  k.need_noise, k.want_gm, k.want_gs,
+                     k.setup ? 0 : c->cur};
+  if (!c->use_graphs || c->timing || k.n_ng > MAX_NG_LATCH) return run_direct(c, k, ca);
+  GraphEnt *ent = nullptr;
+  for (auto &g : c->graphs)
+    if (same_key(g.key, key)) ent = &g;
+  if (ent && ent->exec) {
+    int r = latch(c, ca);
+    if (r) return r;
+    HIPCK(hipGraphLaunch(ent->exec, c->st));
+    ent->tick = ++c->graph_tick;
+    c->cur = ent->cur;
+    if (k.setup) c->fwd_valid = k.fwd ? 1 : 0;
+    if (k.fwd) c->fwd_B = k.B;
+    return IFSVGP_OK;
+  }
+  if (!ent || ent->failed) {
+    if (!ent) {
+      // first sighting: remember the structure, run directly
+      if (c->graphs.size() >= kMaxGraphs) {
+        auto old = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                    [](const GraphEnt &a, const GraphEnt &b) { return a.tick < b.tick; });
+        if (old->exec) (void)hipGraphExecDestroy(old->exec);
+        c->graphs.erase(old);
+      }
+      GraphEnt g{};
+      g.key = key;
+      g.tick = ++c->graph_tick;
+      c->graphs.push_back(g);
+    }
+    return run_direct(c, k, ca);
+  }
+  // second sighting: record on the capture stream, instantiate, replay
+  int r = latch(c, ca);
+  if (r) return r;
+  const hipStream_t user = c->st;
+  const int cur0 = c->cur, valid0 = c->fwd_valid, B0 = c->fwd_B;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cst, hipStreamCaptureModeRelaxed);
+  r = IFSVGP_EHIP;
+  if (e == hipSuccess) {
+    c->st = c->cst;
+    r = enqueue_any(c, k, nullptr);
+    c->st = user;
+    e = hipStreamEndCapture(c->cst, &graph);
+  }
+  hipGraphExec_t exec = nullptr;
+  if (r == IFSVGP_OK && e == hipSuccess && graph)
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (r != IFSVGP_OK || e != hipSuccess || !exec) {
+    // not recordable: this structure always runs directly (the arguments
+    // are latched already)
+    (void)hipGetLastError();
+    ent->failed = 1;
+    c->cur = cur0; c->fwd_valid = valid0; c->fwd_B = B0;
+    return enqueue_any(c, k, nullptr);
+  }
+  ent->exec = exec;
+  ent->cur = c->cur;
+  ent->tick = ++c->graph_tick;
+  HIPCK(hipGraphLaunch(exec, user));
+  return IFSVGP_OK;
+}
+
+// ------------------------------------------------------------------ API: compute
+static bool bad_common(ifsvgp_ctx *c, const float *ell, const float *sf2, const float *Z,
+                       const float *s, const float *L) {
+  return !c || !ell || !sf2 || !Z || !s || !L;
+}
+
+static CallArgs make_args(const float *X, const float *y, int B, double N, const float *ell,
+                          const float *sf2, const float *noise, const float *Z, const float *m,
+                          const float *s, float *L, const float *gammas, int n_ng) {
+  CallArgs a{};
+  a.X = X; a.y = y; a.ell = ell; a.sf2 = sf2; a.noise = noise; a.Z = Z; a.m = m; a.s = s;
+  a.L = L;
+  a.c = B > 0 ? N / (double)B : 0.0;
+  for (int k = 0; k < std::min(n_ng, MAX_NG_LATCH); ++k) a.gammas[k] = gammas[k];
+  return a;
+}
+
+extern "C" int ifsvgp_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, const float *sf2,
+                              const float *s_tilde, float *L, const float *gammas, int n_ng,
+                              double *out_resid) {
+  if (bad_common(c, ell, sf2, Z, s_tilde, L) || !gammas || n_ng < 1) return IFSVGP_EINVAL;
+  CallArgs a = make_args(nullptr, nullptr, 0, 0.0, ell, sf2, nullptr, Z, nullptr, s_tilde, L,
+                         gammas, n_ng);
+  a.out_resid = out_resid;
+  Call k{true, false, false, 0, n_ng, gammas, false, false, false};
+  return run_call(c, k, a);
+}
+
+static int check_bound_args(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
+                            const float *ell, const float *sf2, const float *noise,
+                            const float *Z, const float *m, const float *s, const float *L) {
+  if (bad_common(c, ell, sf2, Z, s, L) || !X || !y || !m) return IFSVGP_EINVAL;
+  if (B < 1 || B > c->Bmax || !(N > 0.0)) return IFSVGP_EINVAL;
+  if (c->lik == IFSVGP_LIK_GAUSSIAN && !noise) return IFSVGP_EINVAL;
+  return IFSVGP_OK;
+}
+
 extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
                             const float *ell, const float *sf2, const float *noise,
                             const float *Z, const float *m, const float *s, const float *L,
@@ -823,9 +1020,11 @@ extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
   if (!out_bound) return IFSVGP_EINVAL;
-  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
-                out_bound, out_terms, nullptr, true, false, nullptr, nullptr, nullptr, nullptr,
-                nullptr, nullptr, nullptr)
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
+  a.out_bound = out_bound;
+  a.out_terms = out_terms;
+  Call k{true, true, false, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, false, false};
+  return run_call(c, k, a);
 }
 
 extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -835,9 +1034,13 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
                                 float *g_noise, float *g_Z, float *g_m, float *g_s) {
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
-  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0,
-                nullptr, nullptr, nullptr, false, true, grad_scale, g_ell, g_sf2, g_noise, g_Z,
-                g_m, g_s)
+  if (!c->fwd_valid || c->fwd_B != B) return IFSVGP_ESTATE;
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
+  a.grad_scale = grad_scale;
+  a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
+  Call k{false, false, true, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
+         g_s != nullptr};
+  return run_call(c, k, a);
 }
 
 extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B, double N,
@@ -849,6 +1052,23 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
   if (n_ng < 0 || (n_ng > 0 && !gammas) || !out_bound) return IFSVGP_EINVAL;
-  PREC_DISPATCH(do_step, c, X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng, out_bound,
-                out_terms, out_resid, true, true, nullptr, g_ell, g_sf2, g_noise, g_Z, g_m, g_s)
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng);
+  a.out_bound = out_bound;
+  a.out_terms = out_terms;
+  a.out_resid = out_resid;
+  a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
+  Call k{true, true, true, B, n_ng, gammas, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
+         g_s != nullptr};
+  return run_call(c, k, a);
+}
+
+extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {
+  if (!c) return IFSVGP_EINVAL;
+  c->use_graphs = enable != 0;
+  if (!c->use_graphs) {
+    hipError_t e = hipStreamSynchronize(c->st);
+    graphs_clear(c);
+    if (e != hipSuccess) return IFSVGP_EHIP;
+  }
+  return IFSVGP_OK;
 }

@@ -48,12 +48,14 @@ IFS_DEV bool arrive_last(int *counter, int *s_flag) {
 //    triangle, strict upper 0), operand copy, both transposes, and the
 //    transpose scaled by s~ along k (operand of L^T S~ L).
 struct SetupArgs {
-  const float *Z, *ell, *sf2, *noise, *s;
+  CallArgs cav;        // the call's arguments when latch is set
+  int latch;           // 1: read cav and copy it to *ca; 0: *ca already holds them
+  CallArgs *ca;        // Z, ell, sf2, noise, s~ and the caller's L
   int M, D, need_noise;
   float *Zs, *inv_ell, *sP, *Kt;
+  float *sfn;          // workspace copies {sf2, noise_var} for the later kernels
   void *KtT;
   long ld;
-  const float *Lin;  // caller's L (leading dimension M), or null
   float *L32, *Lt32;
   void *LT, *LtT, *LstT;
   double *scal;
@@ -68,6 +70,9 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   __shared__ double sh[NTB / 64];
   const int b = blockIdx.x;
   const int M = a.M, D = a.D;
+  const CallArgs *ca = a.latch ? &a.cav : a.ca;
+  if (a.latch && b == 0 && threadIdx.x == 0) *a.ca = a.cav;
+  const float *Zc = ca->Z, *ellc = ca->ell, *sc = ca->s;
   if (b < a.nK) {
     // 64 x 64 tile; thread (tx, ty) owns rows ty + 16 p and columns tx + 16 q
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -79,9 +84,9 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
       for (int u = 0; u < 4; ++u) {
         const int e = e0 + u * NTB + (int)threadIdx.x, r = e / D, d = e % D;
         const bool in = e < 64 * D;
-        const float il = 1.0f / ld_or0(a.ell, d, in);
-        vi[u] = ld_or0(a.Z, (long)(i0 + r) * D + d, in && i0 + r < M) * il;
-        vj[u] = ld_or0(a.Z, (long)(j0 + r) * D + d, in && j0 + r < M) * il;
+        const float il = 1.0f / ld_or0(ellc, d, in);
+        vi[u] = ld_or0(Zc, (long)(i0 + r) * D + d, in && i0 + r < M) * il;
+        vj[u] = ld_or0(Zc, (long)(j0 + r) * D + d, in && j0 + r < M) * il;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -94,7 +99,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
       }
     }
     if (bj == 0 && threadIdx.x < 64 && i0 + threadIdx.x < M)
-      a.sP[i0 + threadIdx.x] = a.s[i0 + threadIdx.x];
+      a.sP[i0 + threadIdx.x] = sc[i0 + threadIdx.x];
     __syncthreads();
     float d2[4][4];
 #pragma unroll
@@ -115,11 +120,11 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
           d2[p][q] = fmaf(df, df, d2[p][q]);
         }
     }
-    const float sf2 = *a.sf2;
+    const float sf2 = *ca->sf2;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int i = i0 + ty + 16 * p;
-      const float si = ld_or0(a.s, i, i < M);
+      const float si = ld_or0(sc, i, i < M);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + tx + 16 * q;
@@ -135,21 +140,23 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
     if (b == 0) {
       int bad = 0;
       for (int d = threadIdx.x; d < D; d += NTB) {
-        const float l = a.ell[d];
+        const float l = ellc[d];
         if (!(l > 0.f) || !isfinite(l)) bad = 1;
         a.inv_ell[d] = 1.0f / l;
       }
       if (threadIdx.x == 0) {
-        const float v = *a.sf2;
+        const float v = *ca->sf2;
         if (!(v > 0.f) || !isfinite(v)) bad = 1;
+        a.sfn[0] = v;
         if (a.need_noise) {
-          const float n = *a.noise;
+          const float n = *ca->noise;
           if (!(n > 0.f) || !isfinite(n)) bad = 1;
+          a.sfn[1] = n;
         }
       }
       double acc = 0.0;
       for (int q = threadIdx.x; q < M; q += NTB) {
-        const float v = a.s[q];
+        const float v = sc[q];
         if (!(v > 0.f) || !isfinite(v)) bad = 1;
         acc += log((double)v);
       }
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int i = i0 + ty + 8 * u, j = j0 + tx;
-    lv[u] = ld_or0(a.Lin, (long)i * M + j, i < M && j < M && i >= j);
+    lv[u] = ld_or0((const float *)ca->L, (long)i * M + j, i < M && j < M && i >= j);
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
     }
   }
   __syncthreads();
-  const float si = ld_or0(a.s, i0 + tx, i0 + tx < M);
+  const float si = ld_or0(sc, i0 + tx, i0 + tx < M);
   for (int r = ty; r < 32; r += 8) {
     const int j = j0 + r, i = i0 + tx;  // transposes: [j][i] = L[i][j]
     if (i < M && j < M) {
@@ -207,7 +214,7 @@ constexpr int KUF_T = 128;
 __host__ __device__ inline int kuf_ldz(int D) { return ((D + 3) & ~3) + 1; }
 __host__ __device__ inline int kuf_smem(int D) { return (2 * KUF_T * kuf_ldz(D) + 2 * KUF_T + D) * 4; }
 template <typename T>
-__global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
+__global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const CallArgs *ca,
                                              const float *inv_ell, int M, int B, int D,
                                              const float *sf2, float *Xs, T *Kft, long ld) {
   extern __shared__ __attribute__((aligned(16))) float ksm[];
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const float *X,
   if (t < D) il[t] = inv_ell[t];
   // stage Zs rows and raw X rows, then scale X by 1/ell in LDS
   stage_rows<NTB>(zs, LDZ, Zs, k0, KUF_T, M, D, -1);
-  stage_rows<NTB>(xs, LDZ, X, n0, KUF_T, B, D, -1);
+  stage_rows<NTB>(xs, LDZ, ca->X, n0, KUF_T, B, D, -1);
   __syncthreads();
   for (int i = t; i < KUF_T * D; i += NTB) {
     const int r = i / D, d = i % D;
@@ -349,13 +356,22 @@ IFS_DEV float row_dot(const float *a, const float *x, const float *xs, int cend)
   return wave_sum(s);
 }
 
-// y[i] = scale * sum_j A[i][j] x[j] over j < Cn (lower: j <= i); one wave per row.
-__global__ void k_gemv_rows(const float *A, long ld, int R, int Cn, const float *x, int lower,
-                            const double *scale, float *y) {
+// y[i] = scale * sum_j A[i][j] (x[j] - xs[j]) over j < Cn (lower: j <= i;
+// xs and scale optional); one wave per row.
+__global__ void k_gemv_rows(const float *A, long ld, int R, int Cn, const float *x,
+                            const float *xs, int lower, const double *scale, float *y) {
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= R) return;
-  const float s = row_dot(A + (long)row * ld, x, nullptr, lower ? min(Cn, row + 1) : Cn);
+  const float s = row_dot(A + (long)row * ld, x, xs, lower ? min(Cn, row + 1) : Cn);
   if ((threadIdx.x & 63) == 0) y[row] = scale ? (float)(*scale * s) : s;
+}
+
+// a = L^T m~ (rows of the fp32 transpose Lt), m~ from the call's arguments.
+__global__ void k_lt_m(const float *Lt, long ld, int M, const CallArgs *ca, float *a) {
+  const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
+  if (row >= M) return;
+  const float s = row_dot(Lt + (long)row * ld, ca->m, nullptr, M);
+  if ((threadIdx.x & 63) == 0) a[row] = s;
 }
 
 // Lb = L b (lower) for rows [0, M) and Wub = Wu b for rows [M, 2M), one wave
@@ -408,14 +424,14 @@ __global__ void k_vec_lb_wub(const float *L, const float *Wu, long ld, int M, co
 //   KL = 1/2 (-tr(Q Wu) + tr W - M + quad - log|T| - sum log s~).
 struct LikArgs {
   const float *mu_part; int n_mu; const float *var_part; int n_var; long ldp;
-  const float *y; int B; int Bp; const float *sf2; const float *noise; double c;
+  const CallArgs *ca;  // y, N / B, out_bound, out_terms
+  int B; int Bp; const float *sfn;  // {sf2, noise_var}
   int lik; const double *gh; int ngh;  // gh: nodes[ngh] then weights[ngh]
   float *mu, *var, *alpha, *beta, *sqnb;  // sqnb = sqrt(max(0, -beta))
   double *part;  // [nblocks][4]
   const double *gram_part; int n_gram;  // [n_gram][3]: tr W, sum Q o Wu, ||W - I||^2
   const double *vec_part; int n_vec;    // [n_vec][2]: b^T Wu b, sum log|L_ii|
   double *scal; int M;
-  double *out_bound, *out_terms;
   int *flag, *counter;
 };
 
@@ -456,11 +472,11 @@ __global__ void k_lik(LikArgs a) {
   if (n < a.B) {
     float m, vp;
     slot_sum2(a.mu_part + n, a.n_mu, a.ldp, a.var_part + n, a.n_var, a.ldp, m, vp);
-    const double mu = m, var = (double)(*a.sf2) - (double)vp;
-    const double y = a.y[n];
+    const double mu = m, var = (double)a.sfn[0] - (double)vp;
+    const double y = a.ca->y[n];
     double E, dmu, dv;
     if (a.lik == 0) {
-      const double s2 = *a.noise;
+      const double s2 = a.sfn[1];
       const double r = y - mu;
       E = -0.5 * log(2.0 * M_PI * s2) - (r * r + var) / (2.0 * s2);
       dmu = r / s2;
@@ -471,12 +487,13 @@ __global__ void k_lik(LikArgs a) {
     }
     a.mu[n] = (float)mu;
     a.var[n] = (float)var;
-    a.alpha[n] = (float)(a.c * dmu);
-    a.beta[n] = (float)(a.c * dv);
-    a.sqnb[n] = (float)sqrt(fmax(0.0, -a.c * dv));
+    const double c = a.ca->c;
+    a.alpha[n] = (float)(c * dmu);
+    a.beta[n] = (float)(c * dv);
+    a.sqnb[n] = (float)sqrt(fmax(0.0, -c * dv));
     e = E;
     vs = var;
-    bs = a.c * dv;
+    bs = c * dv;
   } else if (n < a.Bp) {
     a.alpha[n] = 0.f;
     a.beta[n] = 0.f;
@@ -519,12 +536,12 @@ __global__ void k_lik(LikArgs a) {
     a.scal[S_LOGDET] = 2.0 * ldt;
     const double quad = qd, logdet = 2.0 * ldt, sls = a.scal[S_SUMLOGS];
     const double KL = 0.5 * (-qwu + trw - (double)a.M + quad - logdet - sls);
-    const double data = a.c * e;
+    const double data = a.ca->c * e;
     const double F = data - KL;
     if (!isfinite(F)) atomicOr(a.flag, FLAG_NONFINITE);
-    if (a.out_bound) *a.out_bound = F;
-    if (a.out_terms) {
-      double *o = a.out_terms;
+    if (a.ca->out_bound) *a.ca->out_bound = F;
+    if (a.ca->out_terms) {
+      double *o = a.ca->out_terms;
       o[0] = data; o[1] = KL; o[2] = vs; o[3] = sqrt(r2 / a.M);
       o[4] = trw; o[5] = qwu; o[6] = quad; o[7] = logdet;
     }
@@ -628,7 +645,8 @@ __global__ void k_valpha(const T *V, long ld, int M, int Bp, const float *alpha,
 // dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and dF/dnoise = c sum dE/dnoise.
 struct GradArgs {
   int M, B, D;
-  const float *Zs, *Xs, *inv_ell, *sf2;
+  const CallArgs *ca;  // N / B, grad_scale and the gradient outputs
+  const float *Zs, *Xs, *inv_ell, *sfn;
   const float *hrow, *hx; int n_uf_nt;          // [n_uf_nt][M], [n_uf_nt][M][D]
   const float *hzrow, *hz; int nb;              // [nb][M], [nb][M][D]
   const float *hcol; int n_uf_mt; long ldc;     // [n_uf_mt][ldc]
@@ -636,17 +654,19 @@ struct GradArgs {
   const double *uu_part; int n_uu_tiles;
   const double *lik_part; int n_lik;
   const float *Q, *Va, *Wub; long ld; float *t2;
-  double c;
-  const double *grad_scale;
-  float *g_Z, *g_ell, *g_sf2, *g_noise;
   double *ell_part;  // [rb + cb][D]
   int rb, cb;
-  // gradient with respect to s~ (g_s null: skipped)
+  // gradient with respect to s~ (skipped without g_s)
   const float *gdiag, *pdiag; long ldpd;  // diag(G_uu); [nb][ldpd] partials of diag(P)
   const float *Lb, *s_in;
-  float *g_s;
 };
 
+// Gradient reductions:
+//  * blocks [0, rb): dF/dZ rows (R = NTB / D rows of D per block) from the
+//    per-tile partials of H_uf and H_uu, and lengthscale partials;
+//  * blocks [rb, rb + cb): lengthscale partials of the data side (column sums
+//    of H_uf against Xs^2);
+//  * the remaining blocks: t2 = Q (V alpha - Wu b), one wave per row.
 __global__ void k_grad(GradArgs g) {
   __shared__ double sh[NTB];
   const int blk = blockIdx.x, t = threadIdx.x;
@@ -654,7 +674,8 @@ __global__ void k_grad(GradArgs g) {
   if (blk < g.rb) {
     const int r = t / g.D, d = t % g.D;
     const int i = blk * R + r;
-    const double scale = g.grad_scale ? *g.grad_scale : 1.0;
+    const CallArgs &ca = *g.ca;
+    const double scale = ca.grad_scale ? *ca.grad_scale : 1.0;
     double contrib = 0.0;
     if (r < R && i < g.M) {
       const long e = (long)i * g.D + d, MD = (long)g.M * g.D;
@@ -663,7 +684,7 @@ __global__ void k_grad(GradArgs g) {
       slot_sum2(g.hx + e, g.n_uf_nt, MD, g.hz + e, g.nb, MD, hx, hz);
       const double zs = g.Zs[e];
       const double gz = -(double)g.inv_ell[d] * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
-      if (g.g_Z) g.g_Z[e] = (float)(scale * gz);
+      if (ca.g_Z) ca.g_Z[e] = (float)(scale * gz);
       contrib = ruf * zs * zs - 2.0 * zs * hx + 2.0 * (ruu * zs * zs - zs * hz);
     }
     sh[t] = contrib;
@@ -699,23 +720,25 @@ __global__ void k_grad(GradArgs g) {
 }
 
 // Tail of the gradient: blocks [0, rows) form dF/dm~ = scale * L t2 and
-// dF/ds~ (one wave per row, when requested); the last block forms
-// dF/dell_d = (1/ell_d) sum of partials, dF/dsf2 = (sum H_uu + sum H_uf)/sf2 +
-// sum beta and dF/dnoise = c sum dE/dnoise.
-__global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
-  __shared__ double sh[NTB / 64];
+// dF/ds~ (one wave per row, each when requested):
+//   dF/ds~_i = diag(G_Kt)_i + 1/(2 s~_i),
+//   diag(G_Kt) = diag(G_uu) - diag(P)/2 + (L b)_i^2 / 2,
+// diag(P) summed from the per-tile partials of L Q with J <= i/64; the last
+// block forms dF/dell_d = (1/ell_d) sum of the partials,
+// dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and dF/dnoise = c sum dE/dnoise.
+__global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
+  __shared__ double sh[NTB];
   const int t = threadIdx.x;
-  const double scale = g.grad_scale ? *g.grad_scale : 1.0;
+  const CallArgs &ca = *g.ca;
+  const double scale = ca.grad_scale ? *ca.grad_scale : 1.0;
   if ((int)blockIdx.x < rows) {
     const int row = blockIdx.x * (NTB / 64) + (t >> 6), lane = t & 63;
     if (row < g.M) {
-      if (g_m) {
+      if (ca.g_m) {
         const float s = row_dot(L + (long)row * g.ld, g.t2, nullptr, row + 1);
-        if (lane == 0) g_m[row] = (float)(scale * s);
+        if (lane == 0) ca.g_m[row] = (float)(scale * s);
       }
-      if (g.g_s) {
-        // dF/ds~_i = diag(G_Kt)_i + 1/(2 s~_i), diag(G_Kt) = diag(G_uu) - diag(P)/2 + (P m~)_i^2/2
-        // with P m~ = L b; diag(P) from the per-tile partials of L Q with J <= i/64
+      if (ca.g_s) {
         float pd = 0.f;
         for (int J = lane; J <= row / 64; J += 64) pd += g.pdiag[(long)J * g.ldpd + row];
         pd = wave_sum(pd);
@@ -723,7 +746,7 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
           const double lb = g.Lb[row];
           const double gs = (double)g.gdiag[row] - 0.5 * (double)pd + 0.5 * lb * lb +
                             0.5 / (double)g.s_in[row];
-          g.g_s[row] = (float)(scale * gs);
+          ca.g_s[row] = (float)(scale * gs);
         }
       }
     }
@@ -731,7 +754,6 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
   }
   // lengthscale partials: thread (slice, d) sums every R-th block partial of d
   const int nparts = g.rb + g.cb, R = NTB / g.D;
-  __shared__ double sd[NTB];
   {
     const int slice = t / g.D, d = t % g.D;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -745,14 +767,15 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
       }
       for (; p < nparts; p += R) s0 += g.ell_part[(long)p * g.D + d];
     }
-    sd[t] = (s0 + s1) + (s2 + s3);
+    sh[t] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   if (t < g.D) {
     double s = 0.0;
-    for (int q = 0; q < R; ++q) s += sd[q * g.D + t];
-    if (g.g_ell) g.g_ell[t] = (float)(scale * s * g.inv_ell[t]);
+    for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
+    if (ca.g_ell) ca.g_ell[t] = (float)(scale * s * g.inv_ell[t]);
   }
+  __syncthreads();
   double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
   for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
   for (int i = t; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
@@ -765,7 +788,7 @@ __global__ void k_grad_tail(GradArgs g, const float *L, float *g_m, int rows) {
   dn = block_sum<NTB>(dn, sh);
   bs = block_sum<NTB>(bs, sh);
   if (t == 0) {
-    if (g.g_sf2) *g.g_sf2 = (float)(scale * ((huf + huu) / (double)(*g.sf2) + bs));
-    if (g.g_noise) *g.g_noise = (float)(scale * g.c * dn);
+    if (ca.g_sf2) *ca.g_sf2 = (float)(scale * ((huf + huu) / (double)g.sfn[0] + bs));
+    if (ca.g_noise) *ca.g_noise = (float)(scale * ca.c * dn);
   }
 }

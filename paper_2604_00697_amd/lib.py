@@ -33,6 +33,7 @@ _SIGS = {
     "ifsvgp_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _I]),
     "ifsvgp_destroy": (None, [_P]),
     "ifsvgp_set_stream": (_I, [_P, _P]),
+    "ifsvgp_set_graphs": (_I, [_P, _I]),
     "ifsvgp_status": (_I, [_P]),
     "ifsvgp_gh_rule": (_I, [_I, _P, _P]),
     "ifsvgp_natgrad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
@@ -145,6 +146,11 @@ class Context:
         import torch
         s = torch.cuda.current_stream(self.device).cuda_stream
         _check(self._lib.ifsvgp_set_stream(self._h, s), "ifsvgp_set_stream")
+
+    def set_graphs(self, enable):
+        """Record and replay repeated calls as HIP graphs (default on), or
+        run every call directly."""
+        _check(self._lib.ifsvgp_set_graphs(self._h, 1 if enable else 0), "ifsvgp_set_graphs")
 
     def status(self):
         """Synchronise and return (and clear) the device error flag code."""
