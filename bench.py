@@ -91,7 +91,7 @@ def schedule(n, g0=1e-5, g1=1.0, ramp=10):
     return out
 
 
-def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=True):
+def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=False):
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
@@ -183,15 +183,18 @@ def cpu_baseline(w, p, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    # enough untimed steps (about half a second at M=1024) for the GPU clocks
+    # to settle before the timed region
+    ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp16", "fp32"])
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
-    ap.add_argument("--no-graphs", action="store_true",
-                    help="run every call directly instead of replaying recorded HIP graphs")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay recorded HIP graphs instead of direct calls (the dominant "
+                         "kernel's timing then runs the timed steps directly anyway)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (the "
                          "reference dispatch for scaling HBM byte counters)")
@@ -223,7 +226,7 @@ def main():
     for prec in forms:
         log(f"bench: timing {prec}: {args.warmup} warmup + {args.steps} steps")
         res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup, dominant, dev,
-                              graphs=not args.no_graphs)
+                              graphs=args.graphs)
         log(f"bench: {prec} {res[prec]['ms_per_step']:.3f} ms/step, {dominant} "
             f"{res[prec]['dom_ms'] * 1e3:.1f} us, status {res[prec]['status']}")
     main_r = res[args.prec]

@@ -105,16 +105,19 @@ void ifsvgp_destroy(ifsvgp_ctx *ctx);
 /* Bind the context to a HIP stream (hipStream_t passed as void*). */
 int ifsvgp_set_stream(ifsvgp_ctx *ctx, void *hip_stream);
 
-/* Recorded calls (HIP graphs).  Enabled by default: the second call on a
- * context with the same launch structure (entry point, B, n_ng up to 64,
- * which of g_m / g_s are requested) records that call's launches into a HIP
- * graph, and later calls with that structure replay it with one graph launch
- * on the context's stream, for any argument buffers: the caller's pointers
- * and scalars reach the kernels through a small device block written by one
- * kernel at the start of every call.  Results are identical to direct
- * execution.  enable = 0 synchronises the stream, frees the recorded graphs
- * and runs every later call directly; calls with timing enabled always run
- * directly.  Up to 16 structures are kept (least recently used replaced). */
+/* Recorded calls (HIP graphs).  Off by default.  With enable = 1, the
+ * second call on a context with the same launch structure (entry point, B,
+ * n_ng up to 64, which of g_m / g_s are requested, and for ifsvgp_bound_bwd
+ * the preceding forward's NG step parity) records that call's launches into
+ * a HIP graph, and later calls with that structure replay it with one graph
+ * launch on the context's stream, for any argument buffers: the caller's
+ * pointers and scalars reach the kernels through a small device block
+ * written at the start of every call.  Results are bit-identical to direct
+ * execution.  A replay takes the host less time than the direct launches but
+ * the GPU somewhat more, so it helps callers whose launch rate limits them.
+ * enable = 0 synchronises the stream, frees the recorded graphs and runs
+ * every later call directly; calls with timing enabled always run directly.
+ * Up to 16 structures are kept (least recently used replaced). */
 int ifsvgp_set_graphs(ifsvgp_ctx *ctx, int enable);
 
 /* Synchronise the stream, then report and clear the sticky device flag:

@@ -517,12 +517,14 @@ struct EpiV {
 
 // ---------------------------------------------------------------- U = Q V
 // Ut[n][i] = U[i][n], and over the tile's rows the partials of
-// sigma^2: sum_i V_in U_in and of the mean mu_n = (K_fu L b)_n = sum_i V_in b_i.
+// sigma^2: sum_i V_in U_in and of the mean mu_n = (K_fu L b)_n = sum_i V_in b_i
+// = sum_i U_in a_i (b = Q a with Q symmetric), formed from the U tile so that
+// U does not wait for b.
 template <typename T>
 struct EpiU {
   T *Ut;
   const T *V;
-  const float *b;   // Q L^T m~, zero-padded to Mp
+  const float *a;   // L^T m~, zero-padded to Mp
   long ldv, ldt;
   int M, B;
   float *var_part;  // [m-tiles][ldp]
@@ -532,13 +534,13 @@ struct EpiU {
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
     float vv[K::N][VEC];  // the V tile, loaded before anything waits on it
-    float bv[K::N];
+    float av[K::N];
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
       int r, c;
       K::row(k, r, c);
       ld_pack(V + (long)(t.m0 + r) * ldv + t.n0 + c, vv[k]);
-      bv[k] = b[t.m0 + r];
+      av[k] = a[t.m0 + r];
     }
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
@@ -550,13 +552,19 @@ struct EpiU {
       st_pack(Ut + (long)gj * ldt + gi, x);
     }
     __syncthreads();
-    // V o U in place (V padding is zero), column sums; then V b the same way
+    // V o U in place (V padding is zero), column sums; then diag(a) U the
+    // same way (a padding is zero), from registers
+    float ua[K::N][VEC];
 #pragma unroll
     for (int k = 0; k < K::N; ++k) {
       int r, c;
       K::row(k, r, c);
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + c + q] = vv[k][q] * CS(r, c + q);
+      for (int q = 0; q < VEC; ++q) {
+        const float u = CS(r, c + q);
+        ua[k][q] = u * av[k];
+        Cs[r * C::LDC + c + q] = vv[k][q] * u;
+      }
     }
     __syncthreads();
     const int c = threadIdx.x % C::BN, gj = t.n0 + c;
@@ -570,7 +578,7 @@ struct EpiU {
       int r, cc;
       K::row(k, r, cc);
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + cc + q] = vv[k][q] * bv[k];
+      for (int q = 0; q < VEC; ++q) Cs[r * C::LDC + cc + q] = ua[k][q];
     }
     __syncthreads();
     {

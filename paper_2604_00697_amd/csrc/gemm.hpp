@@ -44,7 +44,7 @@ struct Cfg {
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert((BM + BN) % (8 * NW) == 0 && BM % 8 == 0,
                 "each wave loads whole 8-row groups");
-  static_assert((S & (S - 1)) == 0 && S >= 2, "power-of-two stage count");
+  static_assert(S >= 2, "at least two stages");
   static_assert(IPW * (S - 1) <= 63, "outstanding loads must fit the vmcnt counter");
   static_assert(SMEM_MAIN <= 160 * 1024, "LDS capacity");
 };
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
   const T *srcA = A.p + (long)(m0 + (lane >> 3)) * A.ld + dchunk * C::KPL + kb;
   const T *srcB = Bt.p + (long)(n0 - BM + (lane >> 3)) * Bt.ld + dchunk * C::KPL + kb;
   auto issue = [&](int j) {
-    unsigned char *dst = smem_raw + (j & (S - 1)) * C::STAGE + drow0 * ROWB;
+    unsigned char *dst = smem_raw + (j % S) * C::STAGE + drow0 * ROWB;
     if constexpr (BM % (8 * IPW) == 0) {
       // every wave's rows lie in one operand: one base pointer and stride
       const bool dA = drow0 < BM;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
   V fa[2][2][TM], fb[2][2][TN];  // [register set][k half][tile]
   auto read = [&](auto set_c, int j) {
     constexpr int SET = decltype(set_c)::value;
-    const unsigned char *st = smem_raw + (j & (S - 1)) * C::STAGE;
+    const unsigned char *st = smem_raw + (j % S) * C::STAGE;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int sw = h ? sw1 : sw0;

@@ -71,6 +71,7 @@ struct ifsvgp_ctx {
   hipEvent_t evs[kEvents];  // fork / join points of one call, in order
   int ev_next;
   bool side_open;           // the side stream has work not yet joined into st
+  bool capturing;           // launches are being recorded into a graph
   // device argument block of the current call, written by its k_latch
   CallArgs *dca;
   float *sfn;  // {sf2, noise_var} copied by the set-up
@@ -171,11 +172,11 @@ struct Timed {
 // Side-stream branches.  fork_side makes the side stream wait for all work
 // enqueued on st so far; join_side makes st wait for all work enqueued on the
 // side stream so far; OnSide redirects the enqueues of its scope (kernels and
-// timing events) to the side stream.  The side stream is forked only when it
-// has no work that st has not joined, so each branch's dependencies are
-// exactly its fork point, both in direct execution and when the launches are
-// recorded into a graph.  Every fork and join point of a call uses its own
-// event.
+// timing events) to the side stream.  In direct execution a branch also
+// follows the side stream's earlier work in stream order.  While launches are
+// recorded into a graph, a fork first joins the side stream's open work, so
+// that every recorded branch depends exactly on its fork point.  Every fork
+// and join point of a call uses its own event.
 static hipEvent_t next_event(ifsvgp_ctx *c) {
   hipEvent_t e = c->evs[c->ev_next % ifsvgp_ctx::kEvents];
   ++c->ev_next;
@@ -190,7 +191,7 @@ static hipError_t join_side(ifsvgp_ctx *c) {
   return e;
 }
 static hipError_t fork_side(ifsvgp_ctx *c) {
-  hipError_t e = join_side(c);
+  hipError_t e = c->capturing ? join_side(c) : hipSuccess;
   if (e != hipSuccess) return e;
   hipEvent_t ev = next_event(c);
   e = hipEventRecord(ev, c->st);
@@ -321,7 +322,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   c->Bp = rup(B_max, PAD);
   c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
-  c->use_graphs = 1;
+  c->use_graphs = 0;
   c->graph_tick = 0;
   bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cst, hipStreamNonBlocking) == hipSuccess;
@@ -516,16 +517,18 @@ template <typename T>
 struct Ops {
   // TW: operand type of the two products with C (fp32 in the fp16 form)
   using TW = typename std::conditional<std::is_same<T, _Float16>::value, float, T>::type;
-  // M x M products: two stages keep the LDS small enough for several
-  // workgroups per CU, which hides more latency than deeper staging
-  using CS = Cfg<64, 64, 2, 2, T, 2>;
-  using CSW = Cfg<64, 64, 2, 2, TW, 2>;
+  // M x M products: three stages (48 KB) give two k-steps of load lookahead
+  // and still leave room for three workgroups per CU
+  using CS = Cfg<64, 64, 2, 2, T, 3>;
+  using CSW = Cfg<64, 64, 2, 2, TW, 3>;
   // M x B products, two stages.  CR: V and U on 128 x 64 tiles (twice the
   // workgroups of 128 x 128, so several share a CU and one's epilogue overlaps
   // another's main loop; their partial sums are per 128-row block).  CRG: R on
   // 128 x 128 tiles, whose gradient partials are per 128-column block.
   using CR = Cfg<128, 64, 2, 2, T, 2>;
   using CRG = Cfg<128, 128, 2, 2, T, 2>;
+  // Ys = (V D)(V D)^T: lower tiles, split-K over the batch
+  using CSY = Cfg<64, 64, 2, 2, T, 3>;
   static_assert(CR::BM == 128 && CRG::BM == 128 && CRG::BN == 128, "partial-sum layout");
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
@@ -585,7 +588,7 @@ struct Ops {
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
     Opnd<T> a{(const T *)c->QT, c->Mp}, b{(const T *)c->Vt, c->Mp};
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, 0};
-    EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->vb, c->Bp, c->Mp, c->M, B, c->var_part,
+    EpiU<T> e{(T *)c->Ut, (const T *)c->V, c->va, c->Bp, c->Mp, c->M, B, c->var_part,
               c->mu_part, c->Bp};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
@@ -603,15 +606,17 @@ struct Ops {
   // log-concave Gaussian and probit likelihoods.
   // split-K pieces: enough workgroups for about four per CU, each piece at
   // least 4 k-steps long; every piece costs an fp32 M x M partial
+  static constexpr int kSyrkWG = 1024;  // workgroups the split-K aims for
   static int syrk_splits(ifsvgp_ctx *c, int B) {
-    const int nt = nb(c) * (nb(c) + 1) / 2;
-    return std::max(1, std::min({c->nsplit, cdiv(B, 4 * CS::BK), cdiv(1024, nt)}));
+    const int n = cdiv(c->M, CSY::BM), nt = n * (n + 1) / 2;
+    return std::max(1, std::min({c->nsplit, cdiv(B, 4 * CSY::BK), cdiv(kSyrkWG, nt)}));
   }
   static hipError_t syrk(ifsvgp_ctx *c, int B) {
     Opnd<T> a{(const T *)c->Vs, c->Bp}, b{(const T *)c->Vs, c->Bp};
-    Sched sc{nb(c), nb(c), 1, syrk_splits(c, B), B, 0};
+    const int n = cdiv(c->M, CSY::BM);
+    Sched sc{n, n, 1, syrk_splits(c, B), B, 0};
     EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, 1, (long)c->Mp * c->Mp};
-    return launch_gemm<CS>(lnc(c), a, b, sc, e);
+    return launch_gemm<CSY>(lnc(c), a, b, sc, e);
   }
   // Y2 = L C (k < m0+BM), C symmetric
   static hipError_t gemm_Y2(ifsvgp_ctx *c, int cur) {
@@ -735,23 +740,20 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
   { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
   { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, cur)); }
   { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, cur)); }
+  // V = L^T K_uf and a = L^T m~ come from the side stream; U takes the mean
+  // from a, then b = Q a and Lb = L b, Wub = Wu b (with partials of quad and
+  // log|T|)
   HIPCK(join_side(c));
-  const int rows = cdiv(M, NTB / 64);
+  { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
-    // b = Q a
     Timed t(c, KK_VEC);
-    hipLaunchKernelGGL(k_gemv_rows, dim3(rows), dim3(NTB), 0, c->st, (const float *)c->Q32, Mp,
-                       M, M, (const float *)c->va, (const float *)nullptr, 0,
-                       (const double *)nullptr, c->vb);
-  }
-  {
-    // Lb = L b, Wub = Wu b, with partials of quad and log|T|
-    Timed t(c, KK_VEC);
+    hipLaunchKernelGGL(k_gemv_rows, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+                       (const float *)c->Q32, Mp, M, M, (const float *)c->va,
+                       (const float *)nullptr, 0, (const double *)nullptr, c->vb);
     hipLaunchKernelGGL(k_vec_lb_wub, dim3(cdiv(2 * M, NTB / 64)), dim3(NTB), 0, c->st, L,
                        (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
                        c->vec_part, c->flag);
   }
-  { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_LIK);
     const int nb = cdiv(M, 64);
@@ -891,12 +893,14 @@ static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
 }
 
 // ------------------------------------------------------------------ graphs
-// A call whose launch structure (stages, B, NG step count, requested
-// outputs) has been seen before is recorded once into a HIP graph on the
-// private capture stream, then replayed on c->st with one launch; the
-// caller's buffers reach the kernels through the argument block, so replays
-// serve any buffers.  Structures seen once run directly, so changing shapes
-// cost no recording.
+// With recording on, a call whose launch structure (stages, B, NG step
+// count, requested outputs) has been seen before is recorded once into a HIP
+// graph on the private capture stream, then replayed on c->st with one
+// launch; the caller's buffers reach the kernels through the argument block,
+// so replays serve any buffers.  Structures seen once run directly, so
+// changing shapes cost no recording.  A replay costs the host less than the
+// direct launches but runs somewhat longer on the GPU, so recording is for
+// callers whose issue rate, not the GPU, limits them.
 static bool same_key(const GraphKey &a, const GraphKey &b) {
   return a.setup == b.setup && a.fwd == b.fwd && a.bwd == b.bwd && a.B == b.B &&
          a.n_ng == b.n_ng && a.need_noise == b.need_noise && a.want_gm == b.want_gm &&
@@ -953,7 +957,9 @@ static int run_call(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
   r = IFSVGP_EHIP;
   if (e == hipSuccess) {
     c->st = c->cst;
+    c->capturing = true;
     r = enqueue_any(c, k, nullptr);
+    c->capturing = false;
     c->st = user;
     e = hipStreamEndCapture(c->cst, &graph);
   }

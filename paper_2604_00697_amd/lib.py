@@ -148,8 +148,8 @@ class Context:
         _check(self._lib.ifsvgp_set_stream(self._h, s), "ifsvgp_set_stream")
 
     def set_graphs(self, enable):
-        """Record and replay repeated calls as HIP graphs (default on), or
-        run every call directly."""
+        """Record and replay repeated calls as HIP graphs (enable=True), or run
+        every call directly (the default)."""
         _check(self._lib.ifsvgp_set_graphs(self._h, 1 if enable else 0), "ifsvgp_set_graphs")
 
     def status(self):

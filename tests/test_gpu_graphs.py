@@ -59,6 +59,7 @@ def test_step_replays_match_direct(prec, shape):
     batches, par, L0 = _inputs(M, B, D, 3, seed=M + B)
     ctxs = {"direct": Context(M, B, D, prec), "graph": Context(M, B, D, prec)}
     ctxs["direct"].set_graphs(False)
+    ctxs["graph"].set_graphs(True)
     L = {k: L0.clone() for k in ctxs}
     want = ("ell", "sf2", "noise_var", "Z", "m", "s")
     for it in range(6):
@@ -93,6 +94,7 @@ def test_split_calls_replay_match_direct():
     batches, par, L0 = _inputs(M, B, D, 2, seed=7)
     ctxs = {"direct": Context(M, B, D, "bf16"), "graph": Context(M, B, D, "bf16")}
     ctxs["direct"].set_graphs(False)
+    ctxs["graph"].set_graphs(True)
     L = {k: L0.clone() for k in ctxs}
     scale = torch.tensor([0.75], dtype=torch.float64, device=dev)
     for it in range(5):
