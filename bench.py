@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "train iters/sec (bound+backward+T natgrad) M=1024,B=4096, BF16 vs FP32; MFMA %"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}
 N_BATCHES = 8
+REPEATS = 5
 
 
 # MFMA products of one step (the flop count of the MFMA percentage); the s~
@@ -114,22 +115,75 @@ def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=Fa
         raise RuntimeError(f"{prec}: device status flag set during warmup")
     ctx.timing([dominant])
     ctx.timing_read()
+    # REPEATS equal chunks of the timed steps, split by events on the stream
+    # (no synchronisation inside the timed region)
+    bounds = [round(k * steps / REPEATS) for k in range(REPEATS + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in bounds]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
-        step(warmup + i)
+    evs[0].record()
+    for k in range(REPEATS):
+        for i in range(bounds[k], bounds[k + 1]):
+            step(warmup + i)
+        evs[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    chunks = sorted(evs[k].elapsed_time(evs[k + 1]) / max(1, bounds[k + 1] - bounds[k])
+                    for k in range(REPEATS))
     ctx.timing(False)
     kt = ctx.timing_read()
     status = ctx.status()
     flops = ctx.kernel_flops(w.B)
     ms, cnt = kt[dominant]
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps, iters_per_s=steps / (t1 - t0),
+               repeats=dict(n=REPEATS, median_ms=round(chunks[REPEATS // 2], 4),
+                            p10_ms=round(chunks[0], 4), p90_ms=round(chunks[-1], 4)),
                dom_ms=ms / max(cnt, 1), dom_count=cnt, flops=flops, status=status,
                F=F.item(), resid=terms[3].item())
     ctx.close()
     return res
+
+
+def one_step(prec, w, batches, par, L0):
+    """One iteration (NG step gamma = 1, bound, gradient) of the `prec` form
+    from L0 on the first batch; host float64 copies of its outputs."""
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    ctx = Context(w.M, w.B, w.D, prec, w.lik)
+    L = L0.clone()
+    X, y = batches[0]
+    F, terms, _, g = ctx.step(X, y, w.N, par["ell"], par["sf2"], par["noise"], par["Z"],
+                              par["m"], par["s"], L, [1.0])
+    torch.cuda.synchronize()
+    out = dict(F=F.item(), data=terms[0].item(), KL=terms[1].item(),
+               L=L.double().cpu().numpy(), status=ctx.status())
+    out.update({k: v.double().cpu().numpy() for k, v in g.items()})
+    ctx.close()
+    return out
+
+
+def accuracy(w, par, batches, L0, gpu):
+    """Relative error of each form's F, terms, updated L and gradient blocks
+    against one float64 oracle iteration from the same state and batch."""
+    import numpy as np
+    from oracle import svgp
+    h = lambda t: t.double().cpu().numpy()
+    X, y = batches[0]
+    L_ref, _, ref = svgp.training_iteration(
+        h(X), h(y), w.N, h(par["ell"]), h(par["sf2"])[0], h(par["noise"])[0], h(par["Z"]),
+        h(par["m"]), h(par["s"]), h(L0), [1.0], lik=w.lik)
+    b = ref["bound"]
+    rel = lambda a, r: float(np.linalg.norm(np.ravel(a) - np.ravel(r)) /
+                             max(np.linalg.norm(np.ravel(r)), 1e-300))
+    out = {"reference": "float64 oracle, one iteration from the timed state on batch 0"}
+    for prec, o in gpu.items():
+        e = {"F": rel(o["F"], b["F"]), "data": rel(o["data"], b["data"]),
+             "KL": rel(o["KL"], b["KL"]), "L": rel(o["L"], L_ref)}
+        for k in ("ell", "sf2", "noise_var", "Z", "m"):
+            if k in o:
+                e["grad_" + k] = rel(o[k], ref[k])
+        out[prec] = {k: float(f"{v:.3g}") for k, v in e.items()}
+    return out
 
 
 def kernel_breakdown(prec, w, batches, par, L0, steps, dev):
@@ -175,9 +229,17 @@ def cpu_baseline(w, p, budget_s=20.0):
         el = time.perf_counter() - t0
         if el >= budget_s or n >= 20:
             break
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return dict(value=round(n / el, 4), unit="iters/s", cores=int(threads), kind="oracle",
                 sample=f"{n} full iterations (NG step + bound + gradient) of the same "
-                       f"workload in float64 NumPy/OpenBLAS, {el:.1f} s")
+                       f"workload in float64 NumPy, {el:.1f} s, BLAS threads {threads}, "
+                       f"{aff} cores in the affinity mask, {model}")
 
 
 def main():
@@ -242,6 +304,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(main_r["ms_per_step"], 4),
+        "repeats": main_r["repeats"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -273,6 +336,9 @@ def main():
     if not args.no_cpu:
         log("bench: cpu_baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(w, p)
+        log("bench: accuracy of each form against one oracle iteration")
+        gpu = {f: one_step(f, w, batches, par, L0) for f in forms}
+        out["accuracy"] = accuracy(w, par, batches, L0, gpu)
     if args.copy_calibration > 0:
         n = args.copy_calibration // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)

@@ -654,6 +654,27 @@ struct EpiGradUf {
       // the cross term lands in the accumulators' lane layout
       const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
       const int ib = (wave / C::WGN) * C::WM, jb = (wave % C::WGN) * C::WN;
+      // this lane's rows (16 ii + 4 l4 + q) and columns (16 jj + l16): their
+      // staged values in registers, read once and unconditionally
+      float zr[C::TM][4], lr[C::TM][4], xc[C::TN], ac[C::TN], bc[C::TN];
+      bool rok[C::TM][4], cok[C::TN];
+#pragma unroll
+      for (int ii = 0; ii < C::TM; ++ii)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = ib + 16 * ii + 4 * l4 + q;
+          zr[ii][q] = lds_get(zn + i);
+          lr[ii][q] = lds_get(lb + i);
+          rok[ii][q] = t.m0 + i < M;
+        }
+#pragma unroll
+      for (int jj = 0; jj < C::TN; ++jj) {
+        const int n = jb + 16 * jj + l16;
+        xc[jj] = lds_get(xn + n);
+        ac[jj] = lds_get(al + n);
+        bc[jj] = lds_get(be + n);
+        cok[jj] = t.n0 + n < B;
+      }
       f32x4 c[C::TM][C::TN];
       cross_block<C::TM, C::TN>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
 #pragma unroll
@@ -661,17 +682,13 @@ struct EpiGradUf {
 #pragma unroll
         for (int jj = 0; jj < C::TN; ++jj) {
           const int n = jb + 16 * jj + l16;
-          const bool nok = t.n0 + n < B;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int i = ib + 16 * ii + 4 * l4 + q;
-            float h = 0.f;
-            if (nok && t.m0 + i < M) {
-              const float kuf = kern_se(s2f, zn[i], xn[n], c[ii][jj][q]);
-              const float g = lb[i] * al[n] - 2.f * acc[ii][jj][q] * be[n];
-              h = g * kuf;
-              hs += h;
-            }
+            const float kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
+            const float g = lr[ii][q] * ac[jj] - 2.f * acc[ii][jj][q] * bc[jj];
+            const float h = (rok[ii][q] && cok[jj]) ? g * kuf : 0.f;
+            hs += h;
             Cs[i * C::LDC + n] = h;
           }
         }
