@@ -336,6 +336,14 @@ def main():
     if not args.no_cpu:
         log("bench: cpu_baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(w, p)
+        try:
+            from threadpoolctl import threadpool_limits
+            log("bench: cpu_baseline on one thread")
+            with threadpool_limits(limits=1):
+                one = cpu_baseline(w, p, budget_s=10.0)
+            out["cpu_baseline_1thread"] = {k: one[k] for k in ("value", "unit", "sample")}
+        except ImportError:
+            pass
         log("bench: accuracy of each form against one oracle iteration")
         gpu = {f: one_step(f, w, batches, par, L0) for f in forms}
         out["accuracy"] = accuracy(w, par, batches, L0, gpu)

@@ -179,6 +179,20 @@ int ifsvgp_step(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N
                 float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
                 float *g_m, float *g_s);
 
+/* One Adam step (Kingma and Ba's algorithm, with bias correction) on n fp32
+ * parameters, enqueued on the context's stream: with g' = grad (or -grad when
+ * ascend != 0, to maximise F), m = beta1 m + (1-beta1) g',
+ * v = beta2 v + (1-beta2) g'^2 and
+ * param -= lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * param, m, v are updated in place (device fp32 arrays of n elements; m and v
+ * start at zero before step 1); step >= 1 counts this parameter's updates.
+ * Positivity of constrained parameters is the caller's transform.  For
+ * callers that want a training loop without other device compute; it is not
+ * part of the timed iteration.  Returns IFSVGP_EINVAL for a bad size, step,
+ * rate or decay. */
+int ifsvgp_adam(ifsvgp_ctx *ctx, float *param, const float *grad, float *m, float *v, long n,
+                float lr, float beta1, float beta2, float eps, int step, int ascend);
+
 /* Per-kernel timing for profiling.  kind_mask selects kernel kinds (bit k
  * for kind k, as indexed by ifsvgp_timing_read; -1 for all, 0 to stop);
  * every launch of a selected kind is bracketed by HIP events on the

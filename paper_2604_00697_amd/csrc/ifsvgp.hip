@@ -1078,3 +1078,18 @@ extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {
   }
   return IFSVGP_OK;
 }
+
+extern "C" int ifsvgp_adam(ifsvgp_ctx *c, float *param, const float *grad, float *m, float *v,
+                           long n, float lr, float beta1, float beta2, float eps, int step,
+                           int ascend) {
+  if (!c || n < 0 || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return IFSVGP_EINVAL;
+  if (n == 0) return IFSVGP_OK;
+  if (!param || !grad || !m || !v) return IFSVGP_EINVAL;
+  const double bc1 = 1.0 - std::pow((double)beta1, step), bc2 = 1.0 - std::pow((double)beta2, step);
+  hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(NTB), 0, c->st, param, grad, m, v, n, lr, beta1,
+                     beta2, eps, (float)(1.0 / bc1), (float)(1.0 / bc2), ascend ? -1.f : 1.f);
+  HIPCK(hipGetLastError());
+  return IFSVGP_OK;
+}

@@ -792,3 +792,20 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
     if (ca.g_noise) *ca.g_noise = (float)(scale * ca.c * dn);
   }
 }
+
+// ---------------------------------------------------------------- optimiser
+// One Adam step (Kingma and Ba's algorithm with bias correction) on n fp32
+// parameters: g' = sign g, m = b1 m + (1 - b1) g', v = b2 v + (1 - b2) g'^2,
+// p -= lr (m / bc1) / (sqrt(v / bc2) + eps), with bc1 = 1 - b1^t and
+// bc2 = 1 - b2^t of step t (from the host, in fp64); sign = -1 ascends.
+__global__ void k_adam(float *p, const float *g, float *m, float *v, long n, float lr, float b1,
+                       float b2, float eps, float inv_bc1, float inv_bc2, float sign) {
+  for (long i = blockIdx.x * (long)NTB + threadIdx.x; i < n; i += (long)gridDim.x * NTB) {
+    const float gi = sign * g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * inv_bc1) / (sqrtf(vi * inv_bc2) + eps);
+  }
+}

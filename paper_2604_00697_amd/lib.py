@@ -34,6 +34,8 @@ _SIGS = {
     "ifsvgp_destroy": (None, [_P]),
     "ifsvgp_set_stream": (_I, [_P, _P]),
     "ifsvgp_set_graphs": (_I, [_P, _I]),
+    "ifsvgp_adam": (_I, [_P, _P, _P, _P, _P, ctypes.c_long, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, ctypes.c_float, _I, _I]),
     "ifsvgp_status": (_I, [_P]),
     "ifsvgp_gh_rule": (_I, [_I, _P, _P]),
     "ifsvgp_natgrad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
@@ -146,6 +148,17 @@ class Context:
         import torch
         s = torch.cuda.current_stream(self.device).cuda_stream
         _check(self._lib.ifsvgp_set_stream(self._h, s), "ifsvgp_set_stream")
+
+    def adam(self, param, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+             ascend=False):
+        """One in-place Adam step on fp32 CUDA tensors of one shape (m, v start
+        at zero; step >= 1)."""
+        n = param.numel()
+        ptrs = [_ptr(t, tuple(param.shape), nm) for t, nm in
+                ((param, "param"), (grad, "grad"), (m, "m"), (v, "v"))]
+        self._stream()
+        _check(self._lib.ifsvgp_adam(self._h, *ptrs, n, lr, beta1, beta2, eps, int(step),
+                                     1 if ascend else 0), "ifsvgp_adam")
 
     def set_graphs(self, enable):
         """Record and replay repeated calls as HIP graphs (enable=True), or run
