@@ -140,6 +140,20 @@ int ifsvgp_natgrad(ifsvgp_ctx *ctx, const float *Z, const float *ell, const floa
                    const float *s_tilde, float *L, const float *gammas, int n_ng,
                    double *out_resid);
 
+/* Adaptive natural-gradient loop (Section 3.3, eq. stopping_frobenius): up to
+ * n_max steps as in ifsvgp_natgrad, where before step t the residual
+ * r_t = ||L^T K~ L - I||_F / sqrt(M) of the current iterate is formed from the
+ * step's own W, and the loop stops, without applying step t, as soon as
+ * r_t < tol.  No host synchronisation: after the stop the remaining launches
+ * skip their products and pass L through unchanged, so L holds the last
+ * applied update.  out_resid: device fp64[n_max] (may be NULL) receiving r_t
+ * for the checked steps and the stopping residual for the steps after it.
+ * out_steps: device int[1] (may be NULL) receiving the number of updates
+ * applied (0..n_max).  gammas: HOST array of n_max floats.  tol >= 0. */
+int ifsvgp_natgrad_tol(ifsvgp_ctx *ctx, const float *Z, const float *ell, const float *sf2,
+                       const float *s_tilde, float *L, const float *gammas, int n_max,
+                       float tol, double *out_resid, int *out_steps);
+
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is
  * read only for the Gaussian likelihood (may be NULL for probit).

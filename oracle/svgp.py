@@ -86,6 +86,26 @@ def ng_steps(L, A, gammas):
     return L, np.array(res)
 
 
+def ng_steps_adaptive(L, A, gammas, tol):
+    """NG steps stopped by the residual (Section 3.3, eq. stopping_frobenius).
+
+    Before step t the residual r_t of the current iterate is measured from the
+    same W = L^T A L that the step would use; the loop stops, without applying
+    step t, as soon as r_t < tol, and otherwise applies step t with gammas[t].
+    At most len(gammas) steps.  Returns (L, residuals measured, steps applied).
+    """
+    L = np.array(L, np.float64)
+    res = []
+    for g in gammas:
+        r = ng_residual(L, A)
+        res.append(r)
+        if r < tol:
+            break
+        L = L - g * natgrad_direction(L, A)
+    applied = len(res) - (1 if res and res[-1] < tol else 0)
+    return L, np.array(res), applied
+
+
 def loglinear_gammas(n, g0=1e-5, g1=1.0, ramp=10, start=0):
     """Log-linear step-size schedule of Section 3.4: g0 -> g1 over `ramp` steps.
 

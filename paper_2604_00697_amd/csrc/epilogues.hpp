@@ -318,6 +318,7 @@ struct EpiNgUpdate {
   const CallArgs *ca;  // step size gammas[gidx]; the caller's L (leading
                        // dimension M) when write_out; out_resid[step] if given
   int gidx, step, write_out;
+  int resid_here;      // form this step's residual here (else a check kernel did)
   const double *gram_part;
   int n_gram;
   double *scal;
@@ -372,7 +373,7 @@ struct EpiNgUpdate {
       for (int q = 0; q < VEC; ++q) x[q] *= sv[q];
       st_pack(LnsT + (long)gj * ld + gi0, x);
     }
-    if (t.ti == 0) {
+    if (t.ti == 0 && resid_here) {
       double s = 0.0;
       for (int i = threadIdx.x; i < n_gram; i += C::NT) s += gram_part[i];
       s = tile_sum<C>(s, Cs);

@@ -68,9 +68,12 @@ enum : int { K_LO_M0 = 1, K_LO_N0 = 2, K_HI_M1 = 4, K_HI_N1 = 8 };
 // XCD streams one slice of the B operand against the whole A operand.
 // rule: K_* bounds (k >= m0, k >= n0, k < m0+BM, k < n0+BN) skipping blocks of
 // a triangular operand known to be zero.  nsplit > 1 splits the k-range into
-// BK-aligned pieces (split-K) selected by blockIdx.y.
+// BK-aligned pieces (split-K) selected by blockIdx.y.  skip (optional): a
+// device flag; when it is set, every tile skips its k-loop (zero accumulators)
+// and only the epilogue runs.
 struct Sched {
   int mt, nt, sym, nsplit, K, rule;
+  const int *skip;
   template <class C>
   IFS_DEV void tile(int &m0, int &n0, int &kb, int &ke, int &ti) const {
     const int ntile = sym ? mt * (mt + 1) / 2 : mt * nt;
@@ -163,7 +166,8 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
 
   int m0, n0, kb, ke, ti;
   sc.tile<C>(m0, n0, kb, ke, ti);
-  const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+  int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+  if (sc.skip && *sc.skip) nk = 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;

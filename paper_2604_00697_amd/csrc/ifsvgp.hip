@@ -45,7 +45,7 @@ struct TimingRec {
 struct GraphKey {
   bool setup, fwd, bwd;
   int B, n_ng;
-  bool need_noise, want_gm, want_gs;
+  bool need_noise, want_gm, want_gs, adaptive;
   int cur0;  // L slot a backward-only call starts from (0 otherwise)
 };
 struct GraphEnt {
@@ -95,6 +95,7 @@ struct ifsvgp_ctx {
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
   double *gh;
   int *flag, *counters;
+  int *ngskip;  // stop flag of an adaptive NG loop
   // last forward state for the backward
   int fwd_valid, fwd_B;
   int cur;  // which L32/LT/LtT slot holds the bound's L
@@ -412,6 +413,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->flag, (size_t)1);
   ALLOC(c->counters, (size_t)CNT_N);
   ALLOC(c->dca, (size_t)1);
+  ALLOC(c->ngskip, (size_t)1);
   ALLOC(c->sfn, (size_t)2);
 #undef ALLOC
 #undef ALLOCB
@@ -539,28 +541,30 @@ struct Ops {
   static int nb(ifsvgp_ctx *c) { return cdiv(c->M, 64); }
 
   // Y = K~ L on lower tiles (k >= n0), stored transposed: Yt[j][i] = Y[i][j]
-  static hipError_t gram_Y(ifsvgp_ctx *c, int cur) {
+  static hipError_t gram_Y(ifsvgp_ctx *c, int cur, const int *skip = nullptr) {
     Opnd<T> a{(const T *)c->KtT, c->Mp}, b{LtT(c, cur), c->Mp};
-    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0, skip};
     EpiStoreT<T> e{(T *)c->Yt, c->Mp, c->M, c->M};
     return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // W = L^T Y on lower tiles (k >= m0) -> natural-gradient factor + residual
-  static hipError_t ng_W(ifsvgp_ctx *c, int cur) {
+  static hipError_t ng_W(ifsvgp_ctx *c, int cur, const int *skip = nullptr) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
-    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0, skip};
     EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
     return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM, gamma the call's
-  // step size gidx; also the residual of NG step `step` and (write_out) the
+  // step size gidx; also the residual of NG step `step` (unless a check
+  // kernel forms it: skip non-null, the adaptive loop) and (write_out) the
   // caller's L
-  static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, int gidx, int step, int write_out) {
+  static hipError_t ng_L(ifsvgp_ctx *c, int cur, int nxt, int gidx, int step, int write_out,
+                         const int *skip = nullptr) {
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Xgt, c->Mp};
-    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0 | K_HI_M1};
+    Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0 | K_HI_M1, skip};
     EpiNgUpdate<T> e{c->L32[cur], c->L32[nxt], c->Lt32[nxt], LT(c, nxt), LtT(c, nxt),
                      c->sP, (T *)c->LstT[nxt], c->Mp, c->M, c->dca, gidx, step, write_out,
-                     c->tp_ng, nb(c) * (nb(c) + 1) / 2, c->scal};
+                     skip ? 0 : 1, c->tp_ng, nb(c) * (nb(c) + 1) / 2, c->scal};
     return launch_gemm<CS>(lnc(c), a, b, sc, e);
   }
   // W' = L^T Y (lower tiles, fp32)
@@ -652,6 +656,7 @@ struct Call {
   int B, n_ng;
   const float *gammas;   // host, n_ng values
   bool need_noise, want_gm, want_gs;
+  bool adaptive;         // NG steps stop on the residual (tolerance in the block)
 };
 
 // Copies NG step sizes [s0, s0 + n) into the device block (stream ordered
@@ -688,8 +693,11 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
 
 // n_ng natural-gradient steps from slot 0; the last writes the caller's L.
 // Step sizes beyond the first MAX_NG_LATCH are latched window by window.
+// adaptive: a check kernel after each W product applies the stopping rule;
+// once it has fired, the remaining products skip their k-loops.
 template <typename T>
-static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng) {
+static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng, bool adaptive) {
+  const int *skip = adaptive ? c->ngskip : nullptr;
   int cur = 0;
   for (int s = 0; s < n_ng; ++s) {
     if (s > 0 && s % MAX_NG_LATCH == 0) {
@@ -699,11 +707,17 @@ static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng) {
       hipLaunchKernelGGL(k_latch_gammas, dim3(1), dim3(MAX_NG_LATCH), 0, c->st, g, n, c->dca);
       HIPCK(hipGetLastError());
     }
-    { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
-    { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, cur)); }
+    { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gram_Y(c, cur, skip)); }
+    { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, cur, skip)); }
+    if (adaptive) {
+      const int nbk = Ops<T>::nb(c);
+      hipLaunchKernelGGL(k_ng_check, dim3(1), dim3(NTB), 0, c->st, (const double *)c->tp_ng,
+                         nbk * (nbk + 1) / 2, c->M, s, c->ngskip, c->scal,
+                         (const CallArgs *)c->dca);
+    }
     {
       Timed t(c, KK_NG_L);
-      HIPCK(Ops<T>::ng_L(c, cur, 1 - cur, s % MAX_NG_LATCH, s, s == n_ng - 1));
+      HIPCK(Ops<T>::ng_L(c, cur, 1 - cur, s % MAX_NG_LATCH, s, s == n_ng - 1, skip));
     }
     cur = 1 - cur;
   }
@@ -834,13 +848,13 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
     if (r) return r;
     if (!k.fwd) {
       c->fwd_valid = 0;
-      return stage_natgrad<T>(c, k.gammas, k.n_ng);
+      return stage_natgrad<T>(c, k.gammas, k.n_ng, k.adaptive);
     }
     // side stream: K_uf tiles need only Z / ell and the batch ...
     HIPCK(fork_side(c));
     r = launch_kuf<T>(c, k.B);
     if (r) return r;
-    r = stage_natgrad<T>(c, k.gammas, k.n_ng);
+    r = stage_natgrad<T>(c, k.gammas, k.n_ng, false);
     if (r) return r;
     // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
     // K_uf tiles first), so all of them run beside the Gram products
@@ -904,7 +918,7 @@ static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
 static bool same_key(const GraphKey &a, const GraphKey &b) {
   return a.setup == b.setup && a.fwd == b.fwd && a.bwd == b.bwd && a.B == b.B &&
          a.n_ng == b.n_ng && a.need_noise == b.need_noise && a.want_gm == b.want_gm &&
-         a.want_gs == b.want_gs && a.cur0 == b.cur0;
+         a.want_gs == b.want_gs && a.adaptive == b.adaptive && a.cur0 == b.cur0;
 }
 
 static void graphs_clear(ifsvgp_ctx *c) {
@@ -916,7 +930,7 @@ static void graphs_clear(ifsvgp_ctx *c) {
 static int run_call(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
   const GraphKey key{k.setup, k.fwd,     k.bwd,     k.B,
                      k.n_ng,  k.need_noise, k.want_gm, k.want_gs,
-                     k.setup ? 0 : c->cur};
+                     k.adaptive, k.setup ? 0 : c->cur};
   if (!c->use_graphs || c->timing || k.n_ng > MAX_NG_LATCH) return run_direct(c, k, ca);
   GraphEnt *ent = nullptr;
   for (auto &g : c->graphs)
@@ -1006,7 +1020,7 @@ extern "C" int ifsvgp_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, c
   CallArgs a = make_args(nullptr, nullptr, 0, 0.0, ell, sf2, nullptr, Z, nullptr, s_tilde, L,
                          gammas, n_ng);
   a.out_resid = out_resid;
-  Call k{true, false, false, 0, n_ng, gammas, false, false, false};
+  Call k{true, false, false, 0, n_ng, gammas, false, false, false, false};
   return run_call(c, k, a);
 }
 
@@ -1029,7 +1043,7 @@ extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B
   CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
   a.out_bound = out_bound;
   a.out_terms = out_terms;
-  Call k{true, true, false, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, false, false};
+  Call k{true, true, false, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, false, false, false};
   return run_call(c, k, a);
 }
 
@@ -1045,7 +1059,7 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
   a.grad_scale = grad_scale;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
   Call k{false, false, true, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
-         g_s != nullptr};
+         g_s != nullptr, false};
   return run_call(c, k, a);
 }
 
@@ -1064,7 +1078,22 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   a.out_resid = out_resid;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
   Call k{true, true, true, B, n_ng, gammas, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
-         g_s != nullptr};
+         g_s != nullptr, false};
+  return run_call(c, k, a);
+}
+
+extern "C" int ifsvgp_natgrad_tol(ifsvgp_ctx *c, const float *Z, const float *ell,
+                                  const float *sf2, const float *s_tilde, float *L,
+                                  const float *gammas, int n_max, float tol, double *out_resid,
+                                  int *out_steps) {
+  if (bad_common(c, ell, sf2, Z, s_tilde, L) || !gammas || n_max < 1 || !(tol >= 0.f))
+    return IFSVGP_EINVAL;
+  CallArgs a = make_args(nullptr, nullptr, 0, 0.0, ell, sf2, nullptr, Z, nullptr, s_tilde, L,
+                         gammas, n_max);
+  a.out_resid = out_resid;
+  a.out_steps = out_steps;
+  a.ng_tol = tol;
+  Call k{true, false, false, 0, n_max, gammas, false, false, false, true};
   return run_call(c, k, a);
 }
 

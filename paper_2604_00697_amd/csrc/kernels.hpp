@@ -793,6 +793,42 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
   }
 }
 
+// ---------------------------------------------------------------- adaptive NG
+// Stopping rule of an adaptive NG loop (eq. stopping_frobenius), one block,
+// between the W product of step `step` and its update: r = ||W - I||_F / sqrt(M)
+// from the per-tile partials; once r < tol the flag is set and the remaining
+// products of the loop skip their k-loops (the updates then pass L through).
+// Step 0 clears the flag.  out_resid[step] receives r, or the stopping
+// residual once the loop has stopped; *out_steps the updates applied so far.
+__global__ void k_ng_check(const double *gram_part, int n_gram, int M, int step, int *flag,
+                           double *scal, const CallArgs *ca) {
+  __shared__ double sh[NTB / 64];
+  __shared__ int stopped;
+  if (threadIdx.x == 0) {
+    if (step == 0) *flag = 0;
+    stopped = step > 0 && *flag;
+  }
+  __syncthreads();
+  if (stopped) {
+    if (threadIdx.x == 0 && ca->out_resid) ca->out_resid[step] = scal[S_RESID];
+    return;
+  }
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_gram; i += NTB) s += gram_part[i];
+  s = block_sum<NTB>(s, sh);
+  if (threadIdx.x == 0) {
+    const double r = sqrt(s / M);
+    scal[S_RESID] = r;
+    if (ca->out_resid) ca->out_resid[step] = r;
+    if (r < (double)ca->ng_tol) {
+      *flag = 1;
+      if (ca->out_steps) *ca->out_steps = step;
+    } else if (ca->out_steps) {
+      *ca->out_steps = step + 1;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- optimiser
 // One Adam step (Kingma and Ba's algorithm with bias correction) on n fp32
 // parameters: g' = sign g, m = b1 m + (1 - b1) g', v = b2 v + (1 - b2) g'^2,

@@ -345,3 +345,45 @@ def test_minibatch_scaling_of_data_term():
     b = bound(q, L)
     assert np.isclose(b["data"], 2 * a["data"], rtol=1e-14)
     assert np.isclose(b["KL"], a["KL"], rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# adaptive NG loop (Section 3.3, eq. stopping_frobenius)
+def _ng_problem(M=24, seed=5):
+    g = np.random.Generator(np.random.PCG64(seed))
+    Z = g.standard_normal((M, 3))
+    A = svgp.ktilde(Z, np.array([1.2, 0.8, 1.0]), 1.3, g.uniform(1e-2, 5e-2, M))
+    return A, np.eye(M) / np.sqrt(1.3)
+
+
+def test_adaptive_ng_tol_zero_is_the_fixed_loop():
+    A, L0 = _ng_problem()
+    gam = svgp.loglinear_gammas(15)
+    La, ra, na = svgp.ng_steps_adaptive(L0, A, gam, 0.0)
+    Lf, rf = svgp.ng_steps(L0, A, gam)
+    assert na == 15
+    np.testing.assert_array_equal(La, Lf)
+    np.testing.assert_array_equal(ra, rf)
+
+
+def test_adaptive_ng_large_tol_applies_nothing():
+    A, L0 = _ng_problem()
+    r0 = svgp.ng_residual(L0, A)
+    La, ra, na = svgp.ng_steps_adaptive(L0, A, [1.0] * 4, 2.0 * r0)
+    assert na == 0 and len(ra) == 1 and ra[0] == r0
+    np.testing.assert_array_equal(La, L0)
+
+
+def test_adaptive_ng_is_the_fixed_loop_cut_at_the_first_small_residual():
+    A, L0 = _ng_problem()
+    gam = svgp.loglinear_gammas(25)
+    _, rf = svgp.ng_steps(L0, A, gam)
+    tol = 1e-6
+    first = int(np.argmax(rf < tol))           # first step whose residual is below tol
+    assert rf[first] < tol and np.all(rf[:first] >= tol) and 0 < first < 25
+    La, ra, na = svgp.ng_steps_adaptive(L0, A, gam, tol)
+    Lc, rc = svgp.ng_steps(L0, A, gam[:first])
+    assert na == first
+    np.testing.assert_array_equal(La, Lc)
+    np.testing.assert_array_equal(ra, rf[:first + 1])
+    assert ra[-1] < tol
