@@ -10,6 +10,8 @@ paper says the bound must agree with or stay below:
                               solves; the R-SVGP bound equals it at T = K~^{-1}
                               (Section 2, R-SVGP paragraph and Section 3.2) and
                               is a valid ELBO below it for any T.
+* ``cholesky_predict``     -- M-SVGP predictive marginals of an explicit q(u)
+                              at new inputs, via Cholesky solves.
 * ``induced_q``            -- the q(u) that a given T induces when substituted
                               into M-SVGP (Section 3.2, text before eq.
                               rsvgp_precond): m = K_uu P m~, S = K_uu - K_uu P K_uu.
@@ -63,6 +65,21 @@ def cholesky_elbo(X, y, N, ell, sf2, noise_var, Z, qm, qS, lik="gaussian",
     E, _, _, _ = expectation(lik, y, mu, var, noise_var, n_gh)
     KL = gauss_kl(qm, qS, Kuu)
     return dict(F=(N / B) * np.sum(E) - KL, KL=KL, mu=mu, var=var)
+
+
+def cholesky_predict(Xt, ell, sf2, Z, qm, qS):
+    """M-SVGP predictive marginals of q(u) = N(qm, qS) at test inputs
+    (Section 2, M-SVGP): mu = k_*u K_uu^{-1} qm and
+    sigma^2 = k_** - k_*u K_uu^{-1} k_u* + k_*u K_uu^{-1} qS K_uu^{-1} k_u*,
+    via Cholesky solves."""
+    Xt, ell, Z, qm, qS = [np.asarray(a, np.float64) for a in (Xt, ell, Z, qm, qS)]
+    Kuu = se_ard(Z, Z, ell, sf2)
+    Kus = se_ard(Z, Xt, ell, sf2)
+    _, cK = _logdet_chol(Kuu)
+    A = cho_solve(cK, Kus)
+    mu = A.T @ qm
+    var = sf2 - np.sum(Kus * A, axis=0) + np.sum(A * (qS @ A), axis=0)
+    return mu, var
 
 
 def induced_q(ell, sf2, Z, m, s, L):

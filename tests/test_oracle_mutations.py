@@ -23,6 +23,11 @@ MUTATIONS = [
     ("svgp.py", "data = (N / B) * np.sum(E)", "data = np.sum(E)"),
     ("svgp.py", "g_Z[:, d] = -(np.sum((Huu + Huu.T) * dzz, axis=1)",
      "g_Z[:, d] = -(np.sum(Huu * dzz, axis=1)"),
+    ("svgp.py", "P = 2.0 * T - T @ (Kt @ T)", "P = T - T @ (Kt @ T)"),
+    ("svgp.py", "mu = Kus.T @ (P @ m)", "mu = Kus.T @ (T @ m)"),
+    ("svgp.py", "var = sf2 - np.sum(Kus * (P @ Kus), axis=0)", "var = sf2 - np.sum(Kus * (T @ Kus), axis=0)"),
+    ("svgp.py", "vy = var + float(noise_var)", "vy = var"),
+    ("svgp.py", "lpd = log_ndtr(y * mu / np.sqrt(1.0 + var))", "lpd = log_ndtr(y * mu / np.sqrt(var))"),
     ("quadrature.py", "* y / np.sqrt(2.0 * v)", "* y / np.sqrt(v)"),
     ("quadrature.py", "np.exp(log_phi - log_ndtr(z))", "np.exp(log_phi + log_ndtr(z))"),
     ("quadrature.py", "E = -0.5 * LOG_2PI - 0.5 * np.log(s2) - (r * r + v) / (2.0 * s2)",

@@ -387,3 +387,84 @@ def test_adaptive_ng_is_the_fixed_loop_cut_at_the_first_small_residual():
     np.testing.assert_array_equal(La, Lc)
     np.testing.assert_array_equal(ra, rf[:first + 1])
     assert ra[-1] < tol
+
+
+# ---------------------------------------------------------------- prediction
+def _test_inputs(seed, n, D):
+    return 1.2 * _rng(seed).standard_normal((n, D))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_predict_equals_cholesky_predictive_of_induced_q(seed):
+    """For any T, mu_* and sigma_*^2 are the M-SVGP predictive marginals of
+    the q(u) that T induces (Section 2, R-SVGP paragraph), computed here by
+    Cholesky solves of K_uu at inputs away from the training batch."""
+    p = small_problem(seed)
+    Xt = _test_inputs(50 + seed, 11, 2)
+    for k in range(5):
+        L = random_L(6, 300 + 10 * seed + k, scale=0.6)
+        mu, var, _ = svgp.predict(Xt, p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L)
+        qm, qS = ref.induced_q(p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L)
+        cm, cv = ref.cholesky_predict(Xt, p["ell"], p["sf2"], p["Z"], qm, qS)
+        assert np.allclose(mu, cm, rtol=1e-8, atol=1e-10)
+        assert np.allclose(var, cv, rtol=1e-8, atol=1e-10)
+
+
+def test_predict_variance_bounds_lsvgp_variance_with_equality_at_inverse():
+    """eq. lsvgp_ub: sigma_*^2 >= k_** - k_*u K~^{-1} k_u* (eq. pv) for every
+    T, with equality (and mu_* = k_*u K~^{-1} m~) at T = K~^{-1}."""
+    p = small_problem(3)
+    Xt = _test_inputs(7, 13, 2)
+    Kus = svgp.se_ard(p["Z"], Xt, p["ell"], p["sf2"])
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    var_l = p["sf2"] - np.sum(Kus * np.linalg.solve(Kt, Kus), axis=0)
+    mu_l = Kus.T @ np.linalg.solve(Kt, p["m"])
+    mu, var, _ = svgp.predict(Xt, p["ell"], p["sf2"], p["Z"], p["m"], p["s"], chol_Kinv(p))
+    assert np.allclose(var, var_l, rtol=1e-9, atol=1e-12)
+    assert np.allclose(mu, mu_l, rtol=1e-9, atol=1e-12)
+    for k in range(20):
+        _, v, _ = svgp.predict(Xt, p["ell"], p["sf2"], p["Z"], p["m"], p["s"],
+                               random_L(6, 400 + k, scale=0.6))
+        assert np.all(v >= var_l - 1e-12)
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_predict_on_the_batch_gives_the_bound_marginals(lik):
+    """At the training inputs the predictive marginals are the bound's mu_n,
+    sigma_n^2 (eq. elbo)."""
+    p = small_problem(5, lik=lik)
+    L = random_L(6, 77)
+    mu, var, _ = svgp.predict(p["X"], p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L)
+    bd = bound(p, L)
+    assert np.allclose(mu, bd["mu"], rtol=1e-12, atol=1e-13)
+    assert np.allclose(var, bd["var"], rtol=1e-12, atol=1e-13)
+
+
+def test_gaussian_log_predictive_density_is_the_normal_log_density():
+    """Gaussian likelihood: p(y_* | x_*) = N(y_*; mu_*, sigma_*^2 + noise)."""
+    from scipy.stats import norm
+    p = small_problem(6)
+    Xt = _test_inputs(8, 9, 2)
+    yt = np.sin(Xt.sum(1))
+    L = random_L(6, 88)
+    mu, var, lpd = svgp.predict(Xt, p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L,
+                                y=yt, noise_var=p["noise_var"])
+    assert np.allclose(lpd, norm.logpdf(yt, mu, np.sqrt(var + p["noise_var"])),
+                       rtol=1e-12, atol=1e-12)
+
+
+def test_probit_log_predictive_density_is_the_integrated_probit():
+    """Probit likelihood: p(y_* | x_*) = integral of Phi(y_* f) N(f; mu_*,
+    sigma_*^2) df, checked by adaptive quadrature."""
+    p = small_problem(7, lik="probit")
+    Xt = _test_inputs(9, 6, 2)
+    yt = np.array([1.0, -1.0, 1.0, -1.0, 1.0, -1.0])
+    L = random_L(6, 99)
+    mu, var, lpd = svgp.predict(Xt, p["ell"], p["sf2"], p["Z"], p["m"], p["s"], L,
+                                y=yt, lik="probit")
+    for n in range(6):
+        sd = np.sqrt(var[n])
+        f = lambda t: np.exp(log_ndtr(yt[n] * t)) * np.exp(-0.5 * ((t - mu[n]) / sd) ** 2) \
+            / (sd * np.sqrt(2 * np.pi))
+        val, _ = integrate.quad(f, mu[n] - 12 * sd, mu[n] + 12 * sd, epsabs=1e-13, epsrel=1e-12)
+        assert np.isclose(lpd[n], np.log(val), rtol=1e-9, atol=1e-11)
