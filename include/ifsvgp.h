@@ -154,6 +154,28 @@ int ifsvgp_natgrad_tol(ifsvgp_ctx *ctx, const float *Z, const float *ell, const 
                        const float *s_tilde, float *L, const float *gammas, int n_max,
                        float tol, double *out_resid, int *out_steps);
 
+/* Prediction at n >= 0 test inputs (Section 2: the marginals mu_n, sigma_n^2
+ * of eq. elbo at new inputs, with P = 2T - T K~ T of eq. rsvgp_precond and
+ * T = L L^T as given, no NG step; Section 4 reports the NLPD built from
+ * them):
+ *   mu[i]  = k(x_i, Z) P m~,   var[i] = sf2 - k(x_i, Z) P k(Z, x_i)   (latent f),
+ * and with targets y_test the log predictive density of each point,
+ *   Gaussian: lpd[i] = log N(y_i; mu[i], var[i] + noise_var),
+ *   probit:   lpd[i] = log Phi(y_i mu[i] / sqrt(1 + var[i])), y_i in {-1, +1},
+ * and *nlpd = -(1/n) sum_i lpd[i] (fp64 sum).
+ * X_test: device fp32 [n][D] row-major; y_test: device fp32 [n] or NULL;
+ * mu, var: device fp32 [n] (required); lpd: device fp32 [n] or NULL;
+ * nlpd: device fp64 [1] or NULL.  lpd / nlpd require y_test; noise_var is
+ * required with y_test for the Gaussian likelihood and otherwise unread.
+ * Points are processed in chunks of B_max; n may exceed B_max.  The call
+ * reuses the bound's workspace, so a following ifsvgp_bound_bwd needs a new
+ * forward first (IFSVGP_ESTATE otherwise).  n = 0 does nothing (and is
+ * IFSVGP_EINVAL when nlpd is requested). */
+int ifsvgp_predict(ifsvgp_ctx *ctx, const float *X_test, int n, const float *y_test,
+                   const float *ell, const float *sf2, const float *noise_var,
+                   const float *Z, const float *m_tilde, const float *s_tilde,
+                   const float *L, float *mu, float *var, float *lpd, double *nlpd);
+
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is
  * read only for the Gaussian likelihood (may be NULL for probit).

@@ -242,7 +242,8 @@ def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
                 abs_terms=dict(ell=a_ell, Z=a_Z, sf2=a_sf2, s=a_s))
 
 
-def predict(Xt, ell, sf2, Z, m, s, L, y=None, noise_var=None, lik="gaussian"):
+def predict(Xt, ell, sf2, Z, m, s, L, y=None, noise_var=None, lik="gaussian",
+            perturb=None):
     """Predictive marginals at test inputs, literally (Section 2, eq. elbo's
     mu_n and sigma_n^2, with P of eq. rsvgp_precond):
         mu_* = k_*u P m~,  sigma_*^2 = k_** - k_*u P k_u*,  P = 2T - T K~ T,
@@ -250,11 +251,13 @@ def predict(Xt, ell, sf2, Z, m, s, L, y=None, noise_var=None, lik="gaussian"):
     (its negated mean is the NLPD of Section 4's UCI experiments):
         Gaussian:  log N(y; mu_*, sigma_*^2 + noise_var),
         probit:    log Phi(y mu_* / sqrt(1 + sigma_*^2)),  y in {-1, +1}.
-    Returns (mu, var, lpd); lpd is None without y."""
+    Returns (mu, var, lpd); lpd is None without y.
+    perturb: optional relative perturbations of the formed K_uu ('Kuu') and
+    K_u* ('Kus'), as in rsvgp_bound."""
     Xt, ell, Z, m, s, L = _as64(Xt, ell, Z, m, s, L)
     sf2 = float(sf2)
-    Kus = se_ard(Z, Xt, ell, sf2)
-    Kt = se_ard(Z, Z, ell, sf2) + np.diag(s)
+    Kus = _perturbed(se_ard(Z, Xt, ell, sf2), perturb, "Kus")
+    Kt = _perturbed(se_ard(Z, Z, ell, sf2), perturb, "Kuu") + np.diag(s)
     T = L @ L.T
     P = 2.0 * T - T @ (Kt @ T)
     mu = Kus.T @ (P @ m)

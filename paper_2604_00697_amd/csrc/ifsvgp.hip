@@ -899,6 +899,75 @@ static int latch(ifsvgp_ctx *c, const CallArgs &ca) {
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
+// Prediction at n test points in chunks of at most B_max: the set-up and the
+// Gram products for Q once (no NG step, T = L L^T as given), then per chunk
+// K_u* and V_* = L^T K_u* (side stream), U_* = Q V_* with its mean and
+// variance partials, and the predictive kernel.  Later chunks latch their own
+// X / y into the argument block after the previous chunk's kernels.
+struct PredOut {
+  const float *X, *y;
+  int n;
+  float *mu, *var, *lpd;
+  double *nlpd;
+};
+
+template <typename T>
+static int enqueue_predict(ifsvgp_ctx *c, const CallArgs &ca0, const PredOut &o) {
+  c->ev_next = 0;
+  c->side_open = false;
+  const bool want_lpd = o.y != nullptr;
+  int r = stage_setup<T>(c, want_lpd && c->lik == IFSVGP_LIK_GAUSSIAN, &ca0);
+  if (r) return r;
+  c->cur = 0;
+  c->fwd_valid = 0;
+  const int nchunks = cdiv(o.n, c->Bmax);
+  for (int q = 0; q < nchunks; ++q) {
+    const int off = q * c->Bmax, nb = std::min(c->Bmax, o.n - off);
+    if (q > 0) {
+      CallArgs a = ca0;
+      a.X = o.X + (long)off * c->D;
+      a.y = want_lpd ? o.y + off : nullptr;
+      r = latch(c, a);
+      if (r) return r;
+    }
+    HIPCK(fork_side(c));
+    r = launch_kuf<T>(c, nb);
+    if (r) return r;
+    {
+      OnSide side(c);
+      {
+        Timed t(c, KK_V);
+        HIPCK(Ops<T>::gemm_V(c, 0, nb));
+      }
+      if (q == 0) {
+        Timed t(c, KK_VEC);
+        hipLaunchKernelGGL(k_lt_m, dim3(cdiv(c->M, NTB / 64)), dim3(NTB), 0, c->st,
+                           (const float *)c->Lt32[0], (long)c->Mp, c->M,
+                           (const CallArgs *)c->dca, c->va);
+      }
+    }
+    if (q == 0) {
+      { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::gram_Y(c, 0)); }
+      { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, 0)); }
+      { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, 0)); }
+    }
+    HIPCK(join_side(c));
+    { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, nb)); }
+    Timed t(c, KK_LIK);
+    const int nblk = cdiv(nb, NTB);
+    PredArgs a{c->mu_part, cdiv(c->M, 128), c->var_part, cdiv(c->M, 128), (long)c->Bp,
+               nb, c->sfn, c->lik, want_lpd ? o.y + off : nullptr,
+               o.mu + off, o.var + off, o.lpd ? o.lpd + off : nullptr, c->lik_part};
+    hipLaunchKernelGGL(k_predict, dim3(nblk), dim3(NTB), 0, c->st, a);
+    if (want_lpd)
+      hipLaunchKernelGGL(k_predict_sum, dim3(1), dim3(NTB), 0, c->st, (const double *)c->lik_part,
+                         nblk, c->scal, q == 0 ? 1 : 0, q == nchunks - 1 ? 1 : 0,
+                         (double)o.n, o.nlpd);
+    HIPCK(hipGetLastError());
+  }
+  return IFSVGP_OK;
+}
+
 // direct execution: the set-up latches the arguments when there is one
 static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
   if (k.setup) return enqueue_any(c, k, &ca);
@@ -1095,6 +1164,22 @@ extern "C" int ifsvgp_natgrad_tol(ifsvgp_ctx *c, const float *Z, const float *el
   a.ng_tol = tol;
   Call k{true, false, false, 0, n_max, gammas, false, false, false, true};
   return run_call(c, k, a);
+}
+
+extern "C" int ifsvgp_predict(ifsvgp_ctx *c, const float *X_test, int n, const float *y_test,
+                              const float *ell, const float *sf2, const float *noise,
+                              const float *Z, const float *m, const float *s_tilde,
+                              const float *L, float *mu, float *var, float *lpd,
+                              double *nlpd) {
+  if (bad_common(c, ell, sf2, Z, s_tilde, L) || !m || n < 0) return IFSVGP_EINVAL;
+  if (n == 0) return nlpd ? IFSVGP_EINVAL : IFSVGP_OK;
+  if (!X_test || !mu || !var) return IFSVGP_EINVAL;
+  if ((lpd || nlpd) && !y_test) return IFSVGP_EINVAL;
+  if (y_test && c->lik == IFSVGP_LIK_GAUSSIAN && !noise) return IFSVGP_EINVAL;
+  CallArgs a = make_args(X_test, y_test, 0, 0.0, ell, sf2, noise, Z, m, s_tilde, (float *)L,
+                         nullptr, 0);
+  PredOut o{X_test, y_test, n, mu, var, lpd, nlpd};
+  PREC_DISPATCH(enqueue_predict, c, a, o)
 }
 
 extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {

@@ -14,6 +14,7 @@ enum : int {
   S_LOGDET = 1,    // log|T| = 2 sum log|L_ii|
   S_QUAD = 2,      // b^T Wu b   (= m~^T P K_uu P m~)
   S_RESID = 3,     // residual of the last NG step
+  S_LPD = 4,       // running sum of log predictive densities over a prediction's chunks
   S_NSLOT = 8
 };
 
@@ -545,6 +546,70 @@ __global__ void k_lik(LikArgs a) {
       o[0] = data; o[1] = KL; o[2] = vs; o[3] = sqrt(r2 / a.M);
       o[4] = trw; o[5] = qwu; o[6] = quad; o[7] = logdet;
     }
+  }
+}
+
+// ---------------------------------------------------------------- prediction
+// Predictive marginals at test inputs (one chunk of at most B_max points):
+//   mu_* = k_*u P m~ = a^T U_*,  sigma_*^2 = k_** - k_*u P k_u* = sf2 - sum V_* o U_*,
+// from the per-128-row partials of the U epilogue, and with targets the log
+// predictive density of each point,
+//   Gaussian: log N(y; mu_*, sigma_*^2 + noise),
+//   probit:   log Phi(y mu_* / sqrt(1 + sigma_*^2)),
+// with fp64 per-workgroup partial sums of it.
+struct PredArgs {
+  const float *mu_part; int n_mu; const float *var_part; int n_var; long ldp;
+  int n; const float *sfn; int lik;
+  const float *y;            // chunk targets (optional)
+  float *mu, *var, *lpd;     // chunk outputs (lpd optional, needs y)
+  double *part;              // [blocks] partial sums of the log densities
+};
+
+// log Phi(z), in the two forms that keep it accurate on either side of 0
+__device__ __forceinline__ double log_Phi(double z) {
+  const double u = -z * 0.70710678118654752440;  // -z / sqrt(2)
+  if (z < 0.0) return log(0.5 * erfcx(u)) - u * u;  // Phi(z) = erfcx(u) exp(-u^2) / 2
+  return log1p(-0.5 * erfc(-u));
+}
+
+__global__ void k_predict(PredArgs a) {
+  __shared__ double sh[NTB / 64];
+  const int n = blockIdx.x * NTB + threadIdx.x;
+  double l = 0.0;
+  if (n < a.n) {
+    float m, vp;
+    slot_sum2(a.mu_part + n, a.n_mu, a.ldp, a.var_part + n, a.n_var, a.ldp, m, vp);
+    const double mu = m, var = (double)a.sfn[0] - (double)vp;
+    a.mu[n] = (float)mu;
+    a.var[n] = (float)var;
+    if (a.y) {
+      const double y = a.y[n];
+      if (a.lik == 0) {
+        const double vy = var + (double)a.sfn[1], r = y - mu;
+        l = -0.5 * log(2.0 * M_PI * vy) - r * r / (2.0 * vy);
+      } else {
+        l = log_Phi(y * mu / sqrt(1.0 + var));
+      }
+      if (a.lpd) a.lpd[n] = (float)l;
+    }
+  }
+  if (!a.y) return;
+  l = block_sum<NTB>(l, sh);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = l;
+}
+
+// Adds one chunk's partials to the running sum in scal[S_LPD] (first chunk:
+// starts it) and, after the last chunk, writes NLPD = -sum / n_total.
+__global__ void k_predict_sum(const double *part, int nparts, double *scal, int first,
+                              int last, double n_total, double *nlpd) {
+  __shared__ double sh[NTB / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NTB) s += part[i];
+  s = block_sum<NTB>(s, sh);
+  if (threadIdx.x == 0) {
+    const double tot = (first ? 0.0 : scal[S_LPD]) + s;
+    scal[S_LPD] = tot;
+    if (last && nlpd) *nlpd = -tot / n_total;
   }
 }
 

@@ -45,6 +45,7 @@ _SIGS = {
                               _P, _P, _P, _P, _P, _P]),
     "ifsvgp_step": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
                          _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_predict": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_timing_enable": (_I, [_P, ctypes.c_longlong]),
     "ifsvgp_timing_read": (_I, [_P, _I, _P, _P, _P]),
     "ifsvgp_kernel_flops": (_I, [_P, _I, _I, _P, _P]),
@@ -265,6 +266,29 @@ class Context:
             *self._grad_ptrs(g)), "ifsvgp_step")
         self.generation += 1
         return out, terms, resid, g
+
+    def predict(self, X, ell, sf2, Z, m, s, L, y=None, noise=None):
+        """Predictive mean and variance of f at the rows of X (any count), and
+        with targets y the per-point log predictive density and the NLPD.
+        Returns (mu, var, lpd, nlpd); lpd and nlpd are None without y."""
+        import torch
+        n = X.shape[0]
+        M, D = self.M, self.D
+        mu = torch.empty(n, dtype=torch.float32, device=self.device)
+        var = torch.empty(n, dtype=torch.float32, device=self.device)
+        lpd = nlpd = None
+        if y is not None:
+            lpd = torch.empty(n, dtype=torch.float32, device=self.device)
+            nlpd = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._stream()
+        _check(self._lib.ifsvgp_predict(
+            self._h, _ptr(X, (n, D), "X"), n, _ptr(y, (n,), "y", optional=True),
+            _ptr(ell, (D,), "ell"), _ptr(sf2, (1,), "sf2"),
+            _ptr(noise, (1,), "noise_var", optional=True), _ptr(Z, (M, D), "Z"),
+            _ptr(m, (M,), "m_tilde"), _ptr(s, (M,), "s_tilde"), _ptr(L, (M, M), "L"),
+            mu.data_ptr(), var.data_ptr(), None if lpd is None else lpd.data_ptr(),
+            None if nlpd is None else nlpd.data_ptr()), "ifsvgp_predict")
+        return mu, var, lpd, nlpd
 
     def _grad_buffers(self, want):
         import torch
