@@ -109,6 +109,36 @@ def ng_steps_adaptive(L, A, gammas, tol):
     return L, np.array(res), applied
 
 
+def variance_gap(L, A, Kuf, sigma2):
+    """G = sum_n ||(I - K~ T) k_un||^2 / sigma^2 with T = L L^T and A = K~
+    (Prop. 3 and the text after it): the summed slack between the upper
+    bound U_n of eq. lsvgp_ub and the lower bound L_n of eq. lsvgp_lb, where
+    sigma^2 splits S~ = S~' + sigma^2 I (0 < sigma^2 < min s~)."""
+    L, A, Kuf = _as64(L, A, Kuf)
+    T = L @ L.T
+    R = Kuf - A @ (T @ Kuf)
+    return float(np.sum(R * R)) / float(sigma2)
+
+
+def ng_steps_gap(L, A, Kuf, gammas, sigma2, noise_obs, eps):
+    """NG steps stopped by the variance gap (Section 3.3, Gaussian likelihood):
+    before step t the gap G_t of the current iterate is measured, and the loop
+    stops, without applying step t, as soon as G_t <= 2 sigma_obs^2 eps;
+    otherwise it applies step t with gammas[t].  At most len(gammas) steps.
+    Returns (L, gaps measured, steps applied)."""
+    L = np.array(L, np.float64)
+    thr = 2.0 * float(noise_obs) * float(eps)
+    gaps = []
+    for g in gammas:
+        G = variance_gap(L, A, Kuf, sigma2)
+        gaps.append(G)
+        if G <= thr:
+            break
+        L = L - g * natgrad_direction(L, A)
+    applied = len(gaps) - (1 if gaps and gaps[-1] <= thr else 0)
+    return L, np.array(gaps), applied
+
+
 def loglinear_gammas(n, g0=1e-5, g1=1.0, ramp=10, start=0):
     """Log-linear step-size schedule of Section 3.4: g0 -> g1 over `ramp` steps.
 

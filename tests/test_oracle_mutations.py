@@ -28,6 +28,9 @@ MUTATIONS = [
     ("svgp.py", "var = sf2 - np.sum(Kus * (P @ Kus), axis=0)", "var = sf2 - np.sum(Kus * (T @ Kus), axis=0)"),
     ("svgp.py", "vy = var + float(noise_var)", "vy = var"),
     ("svgp.py", "lpd = log_ndtr(y * mu / np.sqrt(1.0 + var))", "lpd = log_ndtr(y * mu / np.sqrt(var))"),
+    ("svgp.py", "R = Kuf - A @ (T @ Kuf)", "R = Kuf - T @ (A @ Kuf)"),
+    ("svgp.py", "return float(np.sum(R * R)) / float(sigma2)", "return float(np.sum(R * R))"),
+    ("svgp.py", "thr = 2.0 * float(noise_obs) * float(eps)", "thr = float(noise_obs) * float(eps)"),
     ("quadrature.py", "* y / np.sqrt(2.0 * v)", "* y / np.sqrt(v)"),
     ("quadrature.py", "np.exp(log_phi - log_ndtr(z))", "np.exp(log_phi + log_ndtr(z))"),
     ("quadrature.py", "E = -0.5 * LOG_2PI - 0.5 * np.log(s2) - (r * r + v) / (2.0 * s2)",

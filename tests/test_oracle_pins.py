@@ -468,3 +468,78 @@ def test_probit_log_predictive_density_is_the_integrated_probit():
             / (sd * np.sqrt(2 * np.pi))
         val, _ = integrate.quad(f, mu[n] - 12 * sd, mu[n] + 12 * sd, epsabs=1e-13, epsrel=1e-12)
         assert np.isclose(lpd[n], np.log(val), rtol=1e-9, atol=1e-11)
+
+
+# ---------------------------------------------------------------- variance gap
+def test_variance_gap_is_the_sum_of_prop3_bound_differences():
+    """G = sum_n (U_n - L_n), with U_n from eq. lsvgp_ub (the bound's own
+    variance) and L_n from eq. lsvgp_lb written out with K~_- = K~ - sigma^2 I,
+    for random T and two splits sigma^2 of S~; both bounds sandwich the exact
+    L-SVGP variance of eq. pv."""
+    p = small_problem(12)
+    for k in range(6):
+        L = random_L(6, 500 + k, 0.5)
+        out = svgp.rsvgp_bound(p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                               p["Z"], p["m"], p["s"], L, return_parts=True)
+        Kt, T, Kuf = out["Kt"], out["T"], out["Kuf"]
+        var_L = p["sf2"] - np.sum(Kuf * np.linalg.solve(Kt, Kuf), axis=0)
+        for frac in (0.3, 0.9):
+            sig2 = frac * p["s"].min()
+            Km = Kt - sig2 * np.eye(6)
+            Ln = p["sf2"] - (np.sum(Kuf * Kuf, 0) - 2 * np.sum(Kuf * (T @ Km @ Kuf), 0)
+                             + np.sum(Kuf * (T @ Km @ Kt @ T @ Kuf), 0)) / sig2
+            assert np.all(Ln <= var_L + 1e-10) and np.all(var_L <= out["var"] + 1e-10)
+            G = svgp.variance_gap(L, Kt, Kuf, sig2)
+            assert np.isclose(G, np.sum(out["var"] - Ln), rtol=1e-9, atol=1e-12)
+
+
+def test_variance_gap_vanishes_at_Ktilde_inverse_and_scales_with_split():
+    p = small_problem(13)
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    Kuf = svgp.se_ard(p["Z"], p["X"], p["ell"], p["sf2"])
+    assert svgp.variance_gap(chol_Kinv(p), Kt, Kuf, 0.01) < 1e-20
+    L = random_L(6, 9)
+    assert np.isclose(svgp.variance_gap(L, Kt, Kuf, 0.01),
+                      2.0 * svgp.variance_gap(L, Kt, Kuf, 0.02), rtol=1e-13)
+
+
+def _gap_problem():
+    p = small_problem(14)
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    Kuf = svgp.se_ard(p["Z"], p["X"], p["ell"], p["sf2"])
+    L0 = chol_Kinv(p) * (1.0 + 0.05 * np.tril(_rng(15).standard_normal((6, 6))))
+    return p, Kt, Kuf, L0
+
+
+def test_gap_loop_with_eps_zero_is_the_fixed_loop_until_exact():
+    p, Kt, Kuf, L0 = _gap_problem()
+    gam = [1.0] * 4
+    Lf, _ = svgp.ng_steps(L0, Kt, gam)
+    La, gaps, applied = svgp.ng_steps_gap(L0, Kt, Kuf, gam, 0.5 * p["s"].min(), 0.1, 0.0)
+    assert applied == 4 and len(gaps) == 4
+    assert np.allclose(La, Lf, rtol=0, atol=0)
+    # each gap is the one of the fixed loop's iterate before that step
+    L = L0.copy()
+    for t in range(4):
+        assert np.isclose(gaps[t], svgp.variance_gap(L, Kt, Kuf, 0.5 * p["s"].min()), rtol=1e-14)
+        L = L - natgrad_step(L, Kt)
+
+
+def natgrad_step(L, Kt):
+    return svgp.natgrad_direction(L, Kt)
+
+
+def test_gap_loop_cut_at_the_first_small_gap():
+    """The loop stops before the first step whose gap is <= 2 sigma_obs^2 eps
+    (the gap decreases along the converging NG sequence here)."""
+    p, Kt, Kuf, L0 = _gap_problem()
+    gam = [1.0] * 5
+    sig2, nobs = 0.5 * p["s"].min(), 0.1
+    _, gaps, applied = svgp.ng_steps_gap(L0, Kt, Kuf, gam, sig2, nobs, 0.0)
+    assert np.all(np.diff(gaps) < 0)
+    for k in (0, 1, 2):
+        eps = gaps[k] / (2 * nobs) * 1.0000001   # G_k <= threshold < G_{k-1}
+        Lk, gk, ak = svgp.ng_steps_gap(L0, Kt, Kuf, gam, sig2, nobs, eps)
+        Lf, _ = svgp.ng_steps(L0, Kt, gam[:k])
+        assert ak == k and len(gk) == k + 1
+        assert np.allclose(Lk, Lf, rtol=0, atol=0)
