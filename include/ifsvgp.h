@@ -176,6 +176,25 @@ int ifsvgp_predict(ifsvgp_ctx *ctx, const float *X_test, int n, const float *y_t
                    const float *Z, const float *m_tilde, const float *s_tilde,
                    const float *L, float *mu, float *var, float *lpd, double *nlpd);
 
+/* Adaptive natural-gradient loop with the variance-gap rule (Section 3.3,
+ * Prop. 3; Gaussian likelihood only): as ifsvgp_natgrad_tol, but before step t
+ * the gap of the current iterate on the batch X (B <= B_max rows),
+ *   G_t = sum_n ||(I - K~ T) k(Z, x_n)||^2 / sigma2,   T = L L^T,
+ * is formed (from V = L^T K_uf, Y = K~ L and K_uf - Y V: two M x M x B and one
+ * M x M x M product per step), and the loop stops, without applying step t,
+ * as soon as G_t <= 2 noise_var eps.  sigma2 splits S~ = S~' + sigma2 I with
+ * S~' positive, so 0 < sigma2 < min s_tilde makes G the summed slack between
+ * the bounds of eq. lsvgp_ub and eq. lsvgp_lb (only sigma2 > 0 is checked).
+ * noise_var: device fp32[1], the Gaussian noise variance.  out_gap: device
+ * fp64[n_max] (may be NULL) receiving G_t for the checked steps and the
+ * stopping value after the stop; out_steps as in ifsvgp_natgrad_tol.
+ * IFSVGP_EINVAL for a probit context, B outside 1..B_max, sigma2 <= 0 or
+ * eps < 0. */
+int ifsvgp_natgrad_gap(ifsvgp_ctx *ctx, const float *X, int B, const float *Z,
+                       const float *ell, const float *sf2, const float *noise_var,
+                       const float *s_tilde, float *L, const float *gammas, int n_max,
+                       float sigma2, float eps, double *out_gap, int *out_steps);
+
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is
  * read only for the Gaussian likelihood (may be NULL for probit).

@@ -189,7 +189,8 @@ struct CallArgs {
   double *out_bound, *out_terms, *out_resid;
   float *g_ell, *g_sf2, *g_noise, *g_Z, *g_m, *g_s;
   double c;                     // N / B, the data term's scale
-  float ng_tol;                 // stopping residual of an adaptive NG loop
+  float ng_tol;                 // stopping threshold of an adaptive NG loop
+  float gap_sigma2;             // split sigma^2 of S~ for the variance-gap rule
   int *out_steps;               // NG updates applied by an adaptive loop, or null
   float gammas[MAX_NG_LATCH];   // NG step sizes, from the latch's first step on
 };

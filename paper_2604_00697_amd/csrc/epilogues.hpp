@@ -299,6 +299,38 @@ struct EpiNgGram {
   }
 };
 
+// ---------------------------------------------------------------- variance gap
+// R = Y V with Y = K~ L and V = L^T K_uf, i.e. K~ T K_uf: per-tile partial sums
+// of (K_uf - R)^2 over the valid entries (Prop. 3's gap before the division by
+// sigma^2), with K_uf read from its transposed operand copy Kft[n][i].
+template <typename T>
+struct EpiGap {
+  const T *Kft;
+  long ldk;
+  int M, B;
+  double *part;  // [ntiles]
+  template <class C>
+  IFS_DEV void run(const float *Cs, const TileInfo &t) const {
+    using K = Chunks<C>;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K::N; ++k) {
+      int r, c;
+      K::col(k, r, c);
+      const int gi0 = t.m0 + r, gj = t.n0 + c;
+      float kv[VEC];
+      ld_pack(Kft + (long)gj * ldk + gi0, kv);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const double d = (double)kv[q] - (double)CS(r + q, c);
+        if (gi0 + q < M && gj < B) s += d * d;
+      }
+    }
+    s = tile_sum<C>(s, Cs);
+    if (threadIdx.x == 0) part[t.ti] = s;
+  }
+};
+
 // ---------------------------------------------------------------- NG update
 // Lnew = L - gamma * (L X) on lower tiles (strict upper inside diagonal tiles
 // written as 0; upper tiles are never touched and stay zero).  Writes the fp32

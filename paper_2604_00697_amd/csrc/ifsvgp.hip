@@ -42,10 +42,14 @@ struct TimingRec {
 };
 
 // Launch structure of a call (what a recorded graph depends on).
+// stopping rule of the NG steps of a call
+enum : int { NG_FIXED = 0, NG_RESID = 1, NG_GAP = 2 };
+
 struct GraphKey {
   bool setup, fwd, bwd;
   int B, n_ng;
-  bool need_noise, want_gm, want_gs, adaptive;
+  bool need_noise, want_gm, want_gs;
+  int adapt;
   int cur0;  // L slot a backward-only call starts from (0 otherwise)
 };
 struct GraphEnt {
@@ -93,6 +97,7 @@ struct ifsvgp_ctx {
   float *hrow, *hcol, *hx, *hzrow, *hz;
   float *gdiag, *pdiag;  // diag(G_uu) [Mp]; partials of diag(L Q L^T) [nb64][Mp]
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
+  double *tp_gap;  // per-tile partials of the variance gap [nb128][cdiv(Bp, 64)]
   double *gh;
   int *flag, *counters;
   int *ngskip;  // stop flag of an adaptive NG loop
@@ -406,6 +411,7 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->tp_gram, (size_t)3 * nt_sym64);
   ALLOC(c->tp_uf, (size_t)nb128 * nbB);
   ALLOC(c->tp_uu, (size_t)nt_sym64);
+  ALLOC(c->tp_gap, (size_t)nb128 * cdiv(Bp, 64));
   ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
   ALLOC(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
   ALLOC(c->ell_part, (size_t)(M + B_max + 64) * D);
@@ -582,10 +588,26 @@ struct Ops {
     return launch_gemm<CS>(lnc(c), a, b, sc, e, CS::BM * CS::LDC * 4);
   }
   // V = L^T K_uf (k >= m0) -> V, Vt
-  static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B) {
+  static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B, const int *skip = nullptr) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Kft, c->Mp};
-    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0, skip};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+  }
+  // variance gap: Y = K~ L on all tiles (k >= n0), plain layout, in the Y2
+  // buffer (idle outside the backward) ...
+  static T *Yfull(ifsvgp_ctx *c) { return (T *)c->Y2; }
+  static hipError_t gap_Y(ifsvgp_ctx *c, int cur, const int *skip) {
+    Opnd<T> a{(const T *)c->KtT, c->Mp}, b{LtT(c, cur), c->Mp};
+    Sched sc{nb(c), nb(c), 0, 1, c->M, K_LO_N0, skip};
+    EpiStore<T> e{Yfull(c), c->Mp, c->M, c->M, 0, 0};
+    return launch_gemm<CS>(lnc(c), a, b, sc, e);
+  }
+  // ... then (K_uf - Y V)^2 partials per tile
+  static hipError_t gap_R(ifsvgp_ctx *c, int B, const int *skip) {
+    Opnd<T> a{(const T *)Yfull(c), c->Mp}, b{(const T *)c->Vt, c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, 0, skip};
+    EpiGap<T> e{(const T *)c->Kft, c->Mp, c->M, B, c->tp_gap};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
@@ -656,7 +678,7 @@ struct Call {
   int B, n_ng;
   const float *gammas;   // host, n_ng values
   bool need_noise, want_gm, want_gs;
-  bool adaptive;         // NG steps stop on the residual (tolerance in the block)
+  int adapt;             // NG_FIXED, or the stopping rule of the NG steps (threshold in the block)
 };
 
 // Copies NG step sizes [s0, s0 + n) into the device block (stream ordered
@@ -693,11 +715,21 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
 
 // n_ng natural-gradient steps from slot 0; the last writes the caller's L.
 // Step sizes beyond the first MAX_NG_LATCH are latched window by window.
-// adaptive: a check kernel after each W product applies the stopping rule;
-// once it has fired, the remaining products skip their k-loops.
+// NG_RESID: a check kernel after each W product applies the residual rule;
+// NG_GAP: before each step V = L^T K_uf, Y = K~ L and the gap partials of
+// K~ L V against K_uf (batch of B columns) feed the variance-gap rule.  Once a
+// rule has fired, the remaining products skip their k-loops.
 template <typename T>
-static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng, bool adaptive) {
-  const int *skip = adaptive ? c->ngskip : nullptr;
+static int launch_kuf(ifsvgp_ctx *c, int B);
+template <typename T>
+static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng, int rule, int B) {
+  const int *skip = rule != NG_FIXED ? c->ngskip : nullptr;
+  if (rule == NG_GAP) {
+    HIPCK(fork_side(c));
+    int r = launch_kuf<T>(c, B);
+    if (r) return r;
+    HIPCK(join_side(c));
+  }
   int cur = 0;
   for (int s = 0; s < n_ng; ++s) {
     if (s > 0 && s % MAX_NG_LATCH == 0) {
@@ -707,13 +739,21 @@ static int stage_natgrad(ifsvgp_ctx *c, const float *gammas, int n_ng, bool adap
       hipLaunchKernelGGL(k_latch_gammas, dim3(1), dim3(MAX_NG_LATCH), 0, c->st, g, n, c->dca);
       HIPCK(hipGetLastError());
     }
+    if (rule == NG_GAP) {
+      { Timed t(c, KK_V); HIPCK(Ops<T>::gemm_V(c, cur, B, skip)); }
+      { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gap_Y(c, cur, skip)); }
+      { Timed t(c, KK_U); HIPCK(Ops<T>::gap_R(c, B, skip)); }
+      hipLaunchKernelGGL(k_ng_check, dim3(1), dim3(NTB), 0, c->st, (const double *)c->tp_gap,
+                         cdiv(c->M, 128) * cdiv(B, 64), c->M, s, c->ngskip, c->scal,
+                         (const CallArgs *)c->dca, 1);
+    }
     { Timed t(c, KK_NG_Y); HIPCK(Ops<T>::gram_Y(c, cur, skip)); }
     { Timed t(c, KK_NG_W); HIPCK(Ops<T>::ng_W(c, cur, skip)); }
-    if (adaptive) {
+    if (rule == NG_RESID) {
       const int nbk = Ops<T>::nb(c);
       hipLaunchKernelGGL(k_ng_check, dim3(1), dim3(NTB), 0, c->st, (const double *)c->tp_ng,
                          nbk * (nbk + 1) / 2, c->M, s, c->ngskip, c->scal,
-                         (const CallArgs *)c->dca);
+                         (const CallArgs *)c->dca, 0);
     }
     {
       Timed t(c, KK_NG_L);
@@ -848,13 +888,13 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
     if (r) return r;
     if (!k.fwd) {
       c->fwd_valid = 0;
-      return stage_natgrad<T>(c, k.gammas, k.n_ng, k.adaptive);
+      return stage_natgrad<T>(c, k.gammas, k.n_ng, k.adapt, k.B);
     }
     // side stream: K_uf tiles need only Z / ell and the batch ...
     HIPCK(fork_side(c));
     r = launch_kuf<T>(c, k.B);
     if (r) return r;
-    r = stage_natgrad<T>(c, k.gammas, k.n_ng, false);
+    r = stage_natgrad<T>(c, k.gammas, k.n_ng, NG_FIXED, k.B);
     if (r) return r;
     // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
     // K_uf tiles first), so all of them run beside the Gram products
@@ -987,7 +1027,7 @@ static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
 static bool same_key(const GraphKey &a, const GraphKey &b) {
   return a.setup == b.setup && a.fwd == b.fwd && a.bwd == b.bwd && a.B == b.B &&
          a.n_ng == b.n_ng && a.need_noise == b.need_noise && a.want_gm == b.want_gm &&
-         a.want_gs == b.want_gs && a.adaptive == b.adaptive && a.cur0 == b.cur0;
+         a.want_gs == b.want_gs && a.adapt == b.adapt && a.cur0 == b.cur0;
 }
 
 static void graphs_clear(ifsvgp_ctx *c) {
@@ -999,7 +1039,7 @@ static void graphs_clear(ifsvgp_ctx *c) {
 static int run_call(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
   const GraphKey key{k.setup, k.fwd,     k.bwd,     k.B,
                      k.n_ng,  k.need_noise, k.want_gm, k.want_gs,
-                     k.adaptive, k.setup ? 0 : c->cur};
+                     k.adapt, k.setup ? 0 : c->cur};
   if (!c->use_graphs || c->timing || k.n_ng > MAX_NG_LATCH) return run_direct(c, k, ca);
   GraphEnt *ent = nullptr;
   for (auto &g : c->graphs)
@@ -1089,7 +1129,7 @@ extern "C" int ifsvgp_natgrad(ifsvgp_ctx *c, const float *Z, const float *ell, c
   CallArgs a = make_args(nullptr, nullptr, 0, 0.0, ell, sf2, nullptr, Z, nullptr, s_tilde, L,
                          gammas, n_ng);
   a.out_resid = out_resid;
-  Call k{true, false, false, 0, n_ng, gammas, false, false, false, false};
+  Call k{true, false, false, 0, n_ng, gammas, false, false, false, NG_FIXED};
   return run_call(c, k, a);
 }
 
@@ -1112,7 +1152,7 @@ extern "C" int ifsvgp_bound(ifsvgp_ctx *c, const float *X, const float *y, int B
   CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
   a.out_bound = out_bound;
   a.out_terms = out_terms;
-  Call k{true, true, false, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, false, false, false};
+  Call k{true, true, false, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, false, false, NG_FIXED};
   return run_call(c, k, a);
 }
 
@@ -1128,7 +1168,7 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
   a.grad_scale = grad_scale;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
   Call k{false, false, true, B, 0, nullptr, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
-         g_s != nullptr, false};
+         g_s != nullptr, NG_FIXED};
   return run_call(c, k, a);
 }
 
@@ -1147,7 +1187,7 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   a.out_resid = out_resid;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
   Call k{true, true, true, B, n_ng, gammas, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
-         g_s != nullptr, false};
+         g_s != nullptr, NG_FIXED};
   return run_call(c, k, a);
 }
 
@@ -1162,7 +1202,7 @@ extern "C" int ifsvgp_natgrad_tol(ifsvgp_ctx *c, const float *Z, const float *el
   a.out_resid = out_resid;
   a.out_steps = out_steps;
   a.ng_tol = tol;
-  Call k{true, false, false, 0, n_max, gammas, false, false, false, true};
+  Call k{true, false, false, 0, n_max, gammas, false, false, false, NG_RESID};
   return run_call(c, k, a);
 }
 
@@ -1180,6 +1220,24 @@ extern "C" int ifsvgp_predict(ifsvgp_ctx *c, const float *X_test, int n, const f
                          nullptr, 0);
   PredOut o{X_test, y_test, n, mu, var, lpd, nlpd};
   PREC_DISPATCH(enqueue_predict, c, a, o)
+}
+
+extern "C" int ifsvgp_natgrad_gap(ifsvgp_ctx *c, const float *X, int B, const float *Z,
+                                  const float *ell, const float *sf2, const float *noise,
+                                  const float *s_tilde, float *L, const float *gammas, int n_max,
+                                  float sigma2, float eps, double *out_gap, int *out_steps) {
+  if (bad_common(c, ell, sf2, Z, s_tilde, L) || !X || !noise || !gammas || n_max < 1)
+    return IFSVGP_EINVAL;
+  if (c->lik != IFSVGP_LIK_GAUSSIAN || B < 1 || B > c->Bmax || !(sigma2 > 0.f) || !(eps >= 0.f))
+    return IFSVGP_EINVAL;
+  CallArgs a = make_args(X, nullptr, B, 0.0, ell, sf2, noise, Z, nullptr, s_tilde, L, gammas,
+                         n_max);
+  a.out_resid = out_gap;
+  a.out_steps = out_steps;
+  a.ng_tol = eps;
+  a.gap_sigma2 = sigma2;
+  Call k{true, false, false, B, n_max, gammas, true, false, false, NG_GAP};
+  return run_call(c, k, a);
 }
 
 extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {

@@ -859,14 +859,18 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
 }
 
 // ---------------------------------------------------------------- adaptive NG
-// Stopping rule of an adaptive NG loop (eq. stopping_frobenius), one block,
-// between the W product of step `step` and its update: r = ||W - I||_F / sqrt(M)
-// from the per-tile partials; once r < tol the flag is set and the remaining
-// products of the loop skip their k-loops (the updates then pass L through).
-// Step 0 clears the flag.  out_resid[step] receives r, or the stopping
-// residual once the loop has stopped; *out_steps the updates applied so far.
+// Stopping rule of an adaptive NG loop, one block, before the update of step
+// `step`, from per-tile partial sums s:
+//   rule 0 (eq. stopping_frobenius): r = sqrt(s / M) = ||W - I||_F / sqrt(M),
+//          stop when r < tol;
+//   rule 1 (Prop. 3, Gaussian likelihood): r = G = s / sigma^2 with
+//          s = sum_n ||(I - K~ T) k_n||^2, stop when G <= 2 sigma_obs^2 tol.
+// Once it stops the flag is set and the remaining products of the loop skip
+// their k-loops (the updates then pass L through).  Step 0 clears the flag.
+// out_resid[step] receives r, or the stopping value once the loop has
+// stopped; *out_steps the updates applied so far.
 __global__ void k_ng_check(const double *gram_part, int n_gram, int M, int step, int *flag,
-                           double *scal, const CallArgs *ca) {
+                           double *scal, const CallArgs *ca, int rule) {
   __shared__ double sh[NTB / 64];
   __shared__ int stopped;
   if (threadIdx.x == 0) {
@@ -882,10 +886,12 @@ __global__ void k_ng_check(const double *gram_part, int n_gram, int M, int step,
   for (int i = threadIdx.x; i < n_gram; i += NTB) s += gram_part[i];
   s = block_sum<NTB>(s, sh);
   if (threadIdx.x == 0) {
-    const double r = sqrt(s / M);
+    const double r = rule == 0 ? sqrt(s / M) : s / (double)ca->gap_sigma2;
+    const bool stop = rule == 0 ? r < (double)ca->ng_tol
+                                : r <= 2.0 * (double)*ca->noise * (double)ca->ng_tol;
     scal[S_RESID] = r;
     if (ca->out_resid) ca->out_resid[step] = r;
-    if (r < (double)ca->ng_tol) {
+    if (stop) {
       *flag = 1;
       if (ca->out_steps) *ca->out_steps = step;
     } else if (ca->out_steps) {

@@ -40,6 +40,8 @@ _SIGS = {
     "ifsvgp_gh_rule": (_I, [_I, _P, _P]),
     "ifsvgp_natgrad": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, _P]),
     "ifsvgp_natgrad_tol": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, ctypes.c_float, _P, _P]),
+    "ifsvgp_natgrad_gap": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.c_float,
+                                ctypes.c_float, _P, _P]),
     "ifsvgp_bound": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
                               _P, _P, _P, _P, _P, _P]),
@@ -217,6 +219,25 @@ class Context:
             _ptr(resid, (n,), "resid", torch.float64), _ptr(steps, (1,), "steps", torch.int32)),
             "ifsvgp_natgrad_tol")
         return resid, steps
+
+    def natgrad_gap(self, X, Z, ell, sf2, noise, s, L, gammas, sigma2, eps):
+        """Up to len(gammas) NG steps on L in place, stopping once the variance
+        gap on the batch X falls to 2 noise eps or below (Gaussian only);
+        returns (gaps fp64 tensor, steps applied int32 tensor of one element)."""
+        import torch
+        g = np.ascontiguousarray(np.asarray(gammas, np.float32).reshape(-1))
+        n = g.shape[0]
+        B = X.shape[0]
+        gaps = torch.empty(n, dtype=torch.float64, device=self.device)
+        steps = torch.empty(1, dtype=torch.int32, device=self.device)
+        self._stream()
+        _check(self._lib.ifsvgp_natgrad_gap(
+            self._h, _ptr(X, (B, self.D), "X"), B, _ptr(Z, (self.M, self.D), "Z"),
+            _ptr(ell, (self.D,), "ell"), _ptr(sf2, (1,), "sf2"), _ptr(noise, (1,), "noise_var"),
+            _ptr(s, (self.M,), "s_tilde"), _ptr(L, (self.M, self.M), "L"), g.ctypes.data, n,
+            float(sigma2), float(eps), _ptr(gaps, (n,), "gaps", torch.float64),
+            _ptr(steps, (1,), "steps", torch.int32)), "ifsvgp_natgrad_gap")
+        return gaps, steps
 
     def bound(self, X, y, N, ell, sf2, noise, Z, m, s, L, out=None, terms=None):
         """F (fp64 tensor (1,)) and terms (fp64 tensor (8,)) at the given L."""
