@@ -207,6 +207,64 @@ def kernel_breakdown(prec, w, batches, par, L0, steps, dev):
     return {k: round(ms / steps * 1e3, 2) for k, (ms, c) in kt.items() if c}
 
 
+def next_rows(prec, w, batches, par, L0, dev, reps=5):
+    """Timing of the entry points beside the iteration, on the same workload
+    (median over `reps` calls, each bracketed by events on the stream):
+    prediction at 4 B test points with their log densities and NLPD, the
+    adaptive NG loop with the residual rule (4 checked steps, none stopped),
+    the NG loop with the variance-gap rule (3 checked steps on one batch),
+    and one Adam step on Z."""
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    ctx = Context(w.M, w.B, w.D, prec, w.lik)
+    Xt = torch.cat([b[0] for b in batches[:4]])
+    yt = torch.cat([b[1] for b in batches[:4]])
+    noise = par["noise"] if w.lik == "gaussian" else None
+
+    def timed(fn, setup=None):
+        ts = []
+        for _ in range(reps + 1):
+            a = setup() if setup else None
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            fn(a)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts = sorted(ts[1:])
+        return ts[len(ts) // 2]
+
+    out = {}
+    ms = timed(lambda _: ctx.predict(Xt, par["ell"], par["sf2"], par["Z"], par["m"], par["s"],
+                                     L0, y=yt, noise=noise))
+    out["predict"] = {"points": int(Xt.shape[0]), "ms": round(ms, 4),
+                      "points_per_s": round(Xt.shape[0] / (ms * 1e-3), 1)}
+    ms_fix = timed(lambda L: ctx.natgrad(par["Z"], par["ell"], par["sf2"], par["s"], L,
+                                         [1.0] * 4), setup=L0.clone)
+    ms_tol = timed(lambda L: ctx.natgrad_tol(par["Z"], par["ell"], par["sf2"], par["s"], L,
+                                             [1.0] * 4, 0.0), setup=L0.clone)
+    out["natgrad_residual_rule"] = {"steps": 4, "ms_per_step": round(ms_tol / 4, 4),
+                                    "fixed_loop_ms_per_step": round(ms_fix / 4, 4)}
+    if w.lik == "gaussian":
+        sig2 = 0.5 * float(par["s"].min().item())
+        ms_gap = timed(lambda L: ctx.natgrad_gap(batches[0][0], par["Z"], par["ell"], par["sf2"],
+                                                 par["noise"], par["s"], L, [1.0] * 3, sig2, 0.0),
+                       setup=L0.clone)
+        out["natgrad_gap_rule"] = {"steps": 3, "B": w.B, "ms_per_step": round(ms_gap / 3, 4)}
+    g = torch.zeros_like(par["Z"]) + 1e-3
+
+    def adam_setup():
+        return (par["Z"].clone(), torch.zeros_like(par["Z"]), torch.zeros_like(par["Z"]))
+    ms_adam = timed(lambda a: ctx.adam(a[0], g, a[1], a[2], 1, ascend=True), setup=adam_setup)
+    out["adam_Z"] = {"params": int(par["Z"].numel()), "us": round(ms_adam * 1e3, 2)}
+    torch.cuda.synchronize()
+    if ctx.status() != 0:
+        raise RuntimeError("device status flag set in the entry-point timings")
+    ctx.close()
+    return out
+
+
 def cpu_baseline(w, p, budget_s=20.0):
     """The float64 oracle (as it stands) on the host cores: iterations per second
     on the same workload, timed over a bounded number of full iterations."""
@@ -254,6 +312,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the fp32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the timings of prediction, the adaptive NG loops and Adam")
     ap.add_argument("--graphs", action="store_true",
                     help="replay recorded HIP graphs instead of direct calls (the dominant "
                          "kernel's timing then runs the timed steps directly anyway)")
@@ -331,6 +391,9 @@ def main():
                                          (PEAK_TFLOPS["fp32"] * 1e12), 3),
                        "F": r32["F"]}
         out["F"] = main_r["F"]
+    if not args.no_next:
+        log("bench: prediction, adaptive NG loops, Adam")
+        out["entry_points"] = next_rows(args.prec, w, batches, par, L0, dev)
     if args.breakdown:
         out["kernel_us"] = kernel_breakdown(args.prec, w, batches, par, L0, 20, dev)
     if not args.no_cpu:
