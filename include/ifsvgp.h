@@ -208,8 +208,8 @@ int ifsvgp_bound(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double 
 
 /* Gradient of the bound evaluated by the immediately preceding
  * ifsvgp_bound / ifsvgp_step on this context, which must have received the
- * same arguments (IFSVGP_ESTATE if there was none or B differs); it reuses
- * that forward's K_uf tiles from the workspace.  grad_scale: device fp64[1] multiplying every
+ * same arguments (IFSVGP_ESTATE if there was none or B differs).  K_uf tiles
+ * are recomputed, not stored.  grad_scale: device fp64[1] multiplying every
  * gradient (e.g. the incoming adjoint), or NULL for 1.  Gradient outputs are
  * device fp32 arrays shaped like their parameters; each may be NULL to skip
  * it.  g_s (dF/ds~) adds one triangular M^3 product, diag(L Q L^T) with

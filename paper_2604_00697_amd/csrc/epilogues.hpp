@@ -18,11 +18,6 @@ template <typename T>
 struct alignas(VEC * sizeof(T)) Pack {
   T v[VEC];
 };
-// four consecutive elements (one accumulator lane's rows q = 0..3)
-template <typename T>
-struct alignas(4 * sizeof(T)) Pack4 {
-  T v[4];
-};
 
 template <typename T>
 IFS_DEV void ld_pack(const T *p, float (&x)[VEC]) {
@@ -634,9 +629,9 @@ __host__ __device__ inline int dpof(int D) { return (D + 15) / 16 * 16; }
 
 // ---------------------------------------------------------------- backward K_uf side
 // Tile of R = L U, taken straight from the accumulators.  Forms
-// G_uf = (L b) alpha^T - 2 R diag(beta), takes the K_uf tile from the
-// forward's operand copy Kft[n][i] (the values V was formed from), and
-// reduces H = G_uf o K_uf to
+// G_uf = (L b) alpha^T - 2 R diag(beta), recomputes the K_uf tile (norms plus
+// an fp32 MFMA cross term, as in the forward), and reduces
+// H = G_uf o K_uf to
 //   hrow[i]    = sum_n H_in                 (per n-tile partial)
 //   hcol[n]    = sum_i H_in                 (per m-tile partial)
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
@@ -644,15 +639,13 @@ __host__ __device__ inline int dpof(int D) { return (D + 15) / 16 * 16; }
 // hx comes from an fp32 MFMA product H Xs, the row and column sums from LDS.
 // Extra LDS: graduf_extra(BM, BN, D) bytes.
 __host__ __device__ inline int graduf_extra(int BM, int BN, int D) {
-  const int LDX = dpof(D) + 1;
-  return (BN * LDX + BM + 2 * BN) * 4;
+  const int D4 = d4of(D), LDX = dpof(D) + 1;
+  return (BM * (D4 + 1) + BN * LDX + 2 * BM + 3 * BN) * 4;
 }
-template <typename T>
 struct EpiGradUf {
   const float *Lb, *alpha, *beta;
-  const T *Kft;     // K_uf^T in the operand type, [Bp][ldk]
-  long ldk;
-  const float *Xs;  // [B][D]  (inputs / lengthscales)
+  const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
+  const float *sf2;
   int M, B, D;
   float *hrow;  // [n-tiles][M]
   float *hcol;  // [m-tiles][ldc]
@@ -663,53 +656,60 @@ struct EpiGradUf {
   template <class C>
   IFS_DEV void run_regs(const f32x4 (&acc)[C::TM][C::TN], float *Cs, const TileInfo &t) const {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
-    const int DP = dpof(D), LDX = DP + 1;
-    float *xs = Cs + BM * C::LDC + 4 * NT;  // [BN][LDX]
-    float *lb = xs + BN * LDX;              // [BM]
-    float *al = lb + BM;                    // [BN]
+    const int D4 = d4of(D), DP = dpof(D), LDZ = D4 + 1, LDX = DP + 1;
+    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][LDZ]
+    float *xs = zs + BM * LDZ;              // [BN][LDX]
+    float *zn = xs + BN * LDX;              // [BM]
+    float *lb = zn + BM;                    // [BM]
+    float *xn = lb + BM;                    // [BN]
+    float *al = xn + BN;                    // [BN]
     float *be = al + BN;                    // [BN]
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
-    const int ib = (wave / C::WGN) * C::WM, jb = (wave % C::WGN) * C::WN;
-    // the K_uf values of this lane's rows (16 ii + 4 l4 + q) and columns
-    // (16 jj + l16): four consecutive rows of one Kft row per load, issued
-    // before anything waits on them (rows and columns stay inside the padded
-    // [Bp][ldk] copy; values outside [B) x [M) are masked below)
-    Pack4<T> kp[C::TM][C::TN];
-#pragma unroll
-    for (int ii = 0; ii < C::TM; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < C::TN; ++jj)
-        kp[ii][jj] = *(const Pack4<T> *)(Kft + (long)(t.n0 + jb + 16 * jj + l16) * ldk + t.m0 +
-                                         ib + 16 * ii + 4 * l4);
     for (int i = tid; i < BM; i += NT) lb[i] = Lb[t.m0 + i];    // padded to Mp
     for (int i = tid; i < BN; i += NT) {
       al[i] = alpha[t.n0 + i];                                   // padded to Bp
       be[i] = beta[t.n0 + i];
     }
+    stage_rows<NT>(zs, LDZ, Zs, t.m0, BM, M, D, -1);
     stage_rows<NT>(xs, LDX, Xs, t.n0, BN, B, D, -1);
     __syncthreads();
+    for (int i = tid; i < BM + BN; i += NT) {
+      const float *row = i < BM ? zs + i * LDZ : xs + (i - BM) * LDX;
+      float s = 0.f;
+      for (int d = 0; d < D4; ++d) s = fmaf(row[d], row[d], s);
+      (i < BM ? zn : xn)[i < BM ? i : i - BM] = s;
+    }
+    __syncthreads();
+    const float s2f = *sf2;
     double hs = 0.0;
     {
       // wave (wm, wn) owns the WM x WN sub-block it accumulated in the product;
-      // this lane's staged values in registers, read once and unconditionally
-      float lr[C::TM][4], ac[C::TN], bc[C::TN];
+      // the cross term lands in the accumulators' lane layout
+      const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+      const int ib = (wave / C::WGN) * C::WM, jb = (wave % C::WGN) * C::WN;
+      // this lane's rows (16 ii + 4 l4 + q) and columns (16 jj + l16): their
+      // staged values in registers, read once and unconditionally
+      float zr[C::TM][4], lr[C::TM][4], xc[C::TN], ac[C::TN], bc[C::TN];
       bool rok[C::TM][4], cok[C::TN];
 #pragma unroll
       for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int i = ib + 16 * ii + 4 * l4 + q;
+          zr[ii][q] = lds_get(zn + i);
           lr[ii][q] = lds_get(lb + i);
           rok[ii][q] = t.m0 + i < M;
         }
 #pragma unroll
       for (int jj = 0; jj < C::TN; ++jj) {
         const int n = jb + 16 * jj + l16;
+        xc[jj] = lds_get(xn + n);
         ac[jj] = lds_get(al + n);
         bc[jj] = lds_get(be + n);
         cok[jj] = t.n0 + n < B;
       }
+      f32x4 c[C::TM][C::TN];
+      cross_block<C::TM, C::TN>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
 #pragma unroll
       for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
@@ -718,7 +718,7 @@ struct EpiGradUf {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int i = ib + 16 * ii + 4 * l4 + q;
-            const float kuf = to_f32(kp[ii][jj].v[q]);
+            const float kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
             const float g = lr[ii][q] * ac[jj] - 2.f * acc[ii][jj][q] * bc[jj];
             const float h = (rok[ii][q] && cok[jj]) ? g * kuf : 0.f;
             hs += h;

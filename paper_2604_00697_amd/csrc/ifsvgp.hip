@@ -504,7 +504,7 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
   f[KK_GR_E] = M * M * M / 3.0;
   f[KK_V] = M * M * Bd;                 // L^T K_uf, triangular
   f[KK_U] = 2.0 * M * M * Bd;           // Q V
-  f[KK_R] = M * M * Bd + 2.0 * M * Bd * D;  // L U, + H Xs
+  f[KK_R] = M * M * Bd + 4.0 * M * Bd * D;  // L U, + K_uf cross term and H [Xs | 1]
   f[KK_SYRK] = M * M * Bd;              // lower half of (V D)(V D)^T
   f[KK_Y2] = M * M * M;                 // L C
   f[KK_GUU] = M * M * M / 3.0 + 2.0 * M * M * D;  // lower half of Y2 L^T (+ H Z)
@@ -623,7 +623,7 @@ struct Ops {
     const int D = c->D;
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Ut, c->Mp};
     Sched sc{cdiv(c->M, CRG::BM), cdiv(B, CRG::BN), 0, 1, c->M, K_HI_M1};
-    EpiGradUf<T> e{c->vLb, c->alpha, c->beta, (const T *)c->Kft, c->Mp, c->Xs, c->M, B, D,
+    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, c->sfn, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
     return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D));
   }
