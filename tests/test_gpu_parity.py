@@ -148,13 +148,13 @@ def sensitivity(c, gammas, eps, nsamp=3, seed=99):
     return base, spread, cond
 
 
-def gate(case, prec, gpu, ref, spread, cond):
+def gate(case, prec, gpu, ref, spread, cond, base=None, acc=ACC):
     """tol = max(base, mult * spread, acc * 2^-24 * summation condition);
-    reports every quantity, then asserts."""
+    reports every quantity, then asserts.  base: optional per-class override."""
     bad = []
     for q in ref:
-        b = BASE[prec][klass(q)]
-        tol = max(b, MULT[prec] * spread[q], ACC * 2.0 ** -24 * cond.get(q, 0.0))
+        b = (base or BASE[prec])[klass(q)]
+        tol = max(b, MULT[prec] * spread[q], acc * 2.0 ** -24 * cond.get(q, 0.0))
         err = relerr(gpu[q], ref[q], 1.0 if q == "KL" else 0.0)
         print(f"PARITY {case} {q} {err:.3e} tol {tol:.2e} spread {spread[q]:.2e} "
               f"cond {cond.get(q, 1.0):.1f}", flush=True)
@@ -184,11 +184,11 @@ def run_gpu(c, prec="fp32", gammas=(1.0,)):
     return out, code
 
 
-def compare(case, c, prec="fp32", gammas=(1.0,), nsamp=3):
+def compare(case, c, prec="fp32", gammas=(1.0,), nsamp=3, base=None, acc=ACC):
     gpu, code = run_gpu(c, prec, gammas)
     assert code == 0, f"device status {code}"
     ref, spread, cond = sensitivity(c, gammas, EPS[prec], nsamp=nsamp)
-    gate(case, prec, gpu, ref, spread, cond)
+    gate(case, prec, gpu, ref, spread, cond, base, acc)
 
 
 CASES_FP32 = {
@@ -200,7 +200,26 @@ CASES_FP32 = {
     "C2_M512_B1024_D8": (512, 1024, 8, {}),
     "C2_M512_B1024_D8_s0": (512, 1024, 8, dict(state="s0")),
     "M1_B1": (1, 1, 2, {}),
+    "maxD_M96_B200_D64": (96, 200, 64, {}),
 }
+
+# The paper's largest UCI configuration (M = 4000 inducing points, batch 100),
+# fp32, against the oracle with one spread sample (the oracle iteration takes
+# ~10 s); s~ in [0.05, 0.1] keeps cond(K~) near 1e5.  Every product here is a
+# 4000-long fp32 dot product, so the accumulation error that the base and
+# summation-condition terms cover at the smaller sizes grows: a plain float32
+# evaluation of the same L-space algorithm (NumPy, blocked BLAS sums) is off
+# by 6.2e-6 on F at this case, and the GPU's sequential MFMA accumulation over
+# k = 4000 by about three times that; the F / term / gradient base is
+# therefore 3e-5 (dF/dnoise is a sum of the same data-term quantities) and
+# the summation allowance doubles (acc 256, sums of ~64K terms).  The bf16
+# form is not checked at this size: with 4000 inducing points in 8 dimensions
+# its spread-based gates exceed 100 % on the gradients, i.e. bf16 operands
+# cannot resolve this K~.
+def test_uci_size_M4000_B100_fp32(require_gpu):
+    c = make_case(4000, 100, 8, seed=4000, s_range=(0.05, 0.1))
+    base = dict(BASE["fp32"], F=3e-5, term=3e-5, grad=3e-5)
+    compare("uci_M4000_B100_D8_fp32", c, "fp32", (1.0,), nsamp=1, base=base, acc=256.0)
 
 
 @pytest.mark.parametrize("name", list(CASES_FP32))
