@@ -49,12 +49,12 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def dominant_traffic(workload, prec):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
-    counter's reading for a plain copy of known size), or None when there is
-    none for this workload or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"gemm_U_{workload}_{prec}_hbm_traffic.md")
+def kernel_traffic(kernel, workload, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the counter's reading
+    for a plain copy of known size), or None when there is none for this
+    workload or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{prec}_hbm_traffic.md")
     try:
         with open(path) as fh:
             kv = dict(line.strip()[2:].split(": ", 1) for line in fh
@@ -92,7 +92,7 @@ def schedule(n, g0=1e-5, g1=1.0, ramp=10):
     return out
 
 
-def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=False):
+def time_form(prec, w, batches, par, L0, steps, warmup, kinds, dev, graphs=False):
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
@@ -113,7 +113,7 @@ def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=Fa
     torch.cuda.synchronize()
     if ctx.status() != 0:
         raise RuntimeError(f"{prec}: device status flag set during warmup")
-    ctx.timing([dominant])
+    ctx.timing(list(kinds))
     ctx.timing_read()
     # REPEATS equal chunks of the timed steps, split by events on the stream
     # (no synchronisation inside the timed region)
@@ -134,11 +134,11 @@ def time_form(prec, w, batches, par, L0, steps, warmup, dominant, dev, graphs=Fa
     kt = ctx.timing_read()
     status = ctx.status()
     flops = ctx.kernel_flops(w.B)
-    ms, cnt = kt[dominant]
+    per_launch = {k: kt[k][0] / max(kt[k][1], 1) for k in kinds}
     res = dict(ms_per_step=1e3 * (t1 - t0) / steps, iters_per_s=steps / (t1 - t0),
                repeats=dict(n=REPEATS, median_ms=round(chunks[REPEATS // 2], 4),
                             p10_ms=round(chunks[0], 4), p90_ms=round(chunks[-1], 4)),
-               dom_ms=ms / max(cnt, 1), dom_count=cnt, flops=flops, status=status,
+               launch_ms=per_launch, flops=flops, status=status,
                F=F.item(), resid=terms[3].item())
     ctx.close()
     return res
@@ -342,20 +342,36 @@ def main():
     log(f"bench: NG schedule residuals first/last {r[0].item():.3e} / {r[-1].item():.3e}")
     c32.close()
 
-    dominant = "gemm_U"
+    # the kernel with the longest launches in the profiles of both workloads
+    # (R = L U and its gradient epilogue, on the side stream), and the forward's
+    # largest product for comparison
+    dominant, second = "gemm_R_grad_uf", "gemm_U"
     forms = [args.prec] + ([] if args.no_fp32 or args.prec == "fp32" else ["fp32"])
     res = {}
     for prec in forms:
         log(f"bench: timing {prec}: {args.warmup} warmup + {args.steps} steps")
-        res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup, dominant, dev,
+        res[prec] = time_form(prec, w, batches, par, L0, args.steps, args.warmup,
+                              (dominant,), dev,
                               graphs=args.graphs)
         log(f"bench: {prec} {res[prec]['ms_per_step']:.3f} ms/step, {dominant} "
-            f"{res[prec]['dom_ms'] * 1e3:.1f} us, status {res[prec]['status']}")
+            f"{res[prec]['launch_ms'][dominant] * 1e3:.1f} us, status {res[prec]['status']}")
     main_r = res[args.prec]
+    # the comparison kernel's launches, timed in a short run of their own so
+    # that the timed region above stamps events on one kind only
+    log(f"bench: {args.prec} {second} launches")
+    sec = time_form(args.prec, w, batches, par, L0, 200, 50, (second,), dev, graphs=args.graphs)
+    main_r["launch_ms"][second] = sec["launch_ms"][second]
     flops = main_r["flops"]
     f_iter = sum(flops[k] for k in STEP_GEMMS)
     peak = PEAK_TFLOPS[args.prec]
-    dom_tflops = flops[dominant] / (main_r["dom_ms"] * 1e-3) / 1e12
+
+    def roofline(kernel):
+        ms = main_r["launch_ms"][kernel]
+        tf = flops[kernel] / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": kernel, "achieved": round(tf, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                "traffic": kernel_traffic(kernel, args.workload, args.prec),
+                "flops_per_launch": flops[kernel], "avg_launch_us": round(ms * 1e3, 3)}
     out = {
         "metric": METRIC,
         "value": round(main_r["iters_per_s"], 3),
@@ -377,11 +393,8 @@ def main():
                    "M": w.M, "B": w.B, "D": w.D, "N": w.N, "state": "S1"},
         "mfma_pct": round(100.0 * f_iter / (main_r["ms_per_step"] * 1e-3) / (peak * 1e12), 3),
         "flops_per_step": f_iter,
-        "roofline": {"bound": "mfma", "kernel": dominant, "achieved": round(dom_tflops, 3),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(dom_tflops / peak, 4),
-                     "traffic": dominant_traffic(args.workload, args.prec),
-                     "flops_per_launch": flops[dominant],
-                     "avg_launch_us": round(main_r["dom_ms"] * 1e3, 3)},
+        "roofline": roofline(dominant),
+        "roofline_" + second: roofline(second),
     }
     if "fp32" in res and args.prec != "fp32":
         r32 = res["fp32"]
