@@ -74,6 +74,30 @@ IFS_DEV double wave_sum(double v) {
   return v;
 }
 
+// Block-wide sums of N doubles per thread with one LDS exchange (the same
+// summation order as N separate block_sum calls); results valid in thread 0.
+template <int NT, int N>
+IFS_DEV void block_sums(double (&v)[N], double *sh /* >= N * NT/64 */) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k * (NT / 64) + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double r = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT / 64; ++i) r += sh[k * (NT / 64) + i];
+      v[k] = r;
+    }
+  }
+  __syncthreads();
+}
+
 // Block-wide sum of one double per thread; result valid in thread 0.
 template <int NT>
 IFS_DEV double block_sum(double v, double *sh /* >= NT/64 */) {

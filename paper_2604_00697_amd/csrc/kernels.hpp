@@ -466,10 +466,23 @@ __device__ __forceinline__ void probit_terms(double y, double mu, double v, cons
 }
 
 __global__ void k_lik(LikArgs a) {
-  __shared__ double sh[NTB / 64];
+  __shared__ double sh[9 * (NTB / 64)];
   __shared__ int s_last;
   const int n = blockIdx.x * NTB + threadIdx.x;
   double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
+  // the KL's scalars from the earlier kernels' partials (traces, ||W - I||^2,
+  // b^T Wu b, log|L_ii|), summed by every workgroup before its arrival so that
+  // the last one's finalisation waits only on this kernel's own partials
+  double trw = 0.0, qwu = 0.0, r2 = 0.0, qd = 0.0, ldt = 0.0;
+  for (int i = threadIdx.x; i < a.n_gram; i += NTB) {
+    trw += a.gram_part[3 * i];
+    qwu += a.gram_part[3 * i + 1];
+    r2 += a.gram_part[3 * i + 2];
+  }
+  for (int i = threadIdx.x; i < a.n_vec; i += NTB) {
+    qd += a.vec_part[2 * i];
+    ldt += a.vec_part[2 * i + 1];
+  }
   if (n < a.B) {
     float m, vp;
     slot_sum2(a.mu_part + n, a.n_mu, a.ldp, a.var_part + n, a.n_var, a.ldp, m, vp);
@@ -500,39 +513,23 @@ __global__ void k_lik(LikArgs a) {
     a.beta[n] = 0.f;
     a.sqnb[n] = 0.f;
   }
-  e = block_sum<NTB>(e, sh);
-  vs = block_sum<NTB>(vs, sh);
-  dn = block_sum<NTB>(dn, sh);
-  bs = block_sum<NTB>(bs, sh);
+  double v[9] = {e, vs, dn, bs, trw, qwu, r2, qd, ldt};
+  block_sums<NTB, 9>(v, sh);
   if (threadIdx.x == 0) {
     double *p = a.part + 4 * blockIdx.x;
-    p[0] = e; p[1] = vs; p[2] = dn; p[3] = bs;
+    p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
   }
   if (!arrive_last(a.counter, &s_last)) return;
-  double trw = 0.0, qwu = 0.0, r2 = 0.0, qd = 0.0, ldt = 0.0;
-  e = 0.0;
-  vs = 0.0;
-  for (int i = threadIdx.x; i < a.n_gram; i += NTB) {
-    trw += a.gram_part[3 * i];
-    qwu += a.gram_part[3 * i + 1];
-    r2 += a.gram_part[3 * i + 2];
-  }
+  double w2[2] = {0.0, 0.0};
   for (int i = threadIdx.x; i < (int)gridDim.x; i += NTB) {
-    e += a.part[4 * i];
-    vs += a.part[4 * i + 1];
+    w2[0] += a.part[4 * i];
+    w2[1] += a.part[4 * i + 1];
   }
-  for (int i = threadIdx.x; i < a.n_vec; i += NTB) {
-    qd += a.vec_part[2 * i];
-    ldt += a.vec_part[2 * i + 1];
-  }
-  trw = block_sum<NTB>(trw, sh);
-  qwu = block_sum<NTB>(qwu, sh);
-  r2 = block_sum<NTB>(r2, sh);
-  e = block_sum<NTB>(e, sh);
-  vs = block_sum<NTB>(vs, sh);
-  qd = block_sum<NTB>(qd, sh);
-  ldt = block_sum<NTB>(ldt, sh);
+  block_sums<NTB, 2>(w2, sh);
   if (threadIdx.x == 0) {
+    trw = v[4]; qwu = v[5]; r2 = v[6]; qd = v[7]; ldt = v[8];
+    e = w2[0];
+    vs = w2[1];
     a.scal[S_QUAD] = qd;
     a.scal[S_LOGDET] = 2.0 * ldt;
     const double quad = qd, logdet = 2.0 * ldt, sls = a.scal[S_SUMLOGS];
@@ -817,6 +814,15 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
     }
     return;
   }
+  // the scalar sums' partials first (their loads overlap the lengthscale
+  // reduction below)
+  double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
+  for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
+  for (int i = t; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
+  for (int i = t; i < g.n_lik; i += NTB) {
+    dn += g.lik_part[4 * i + 2];
+    bs += g.lik_part[4 * i + 3];
+  }
   // lengthscale partials: thread (slice, d) sums every R-th block partial of d
   const int nparts = g.rb + g.cb, R = NTB / g.D;
   {
@@ -841,17 +847,9 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
     if (ca.g_ell) ca.g_ell[t] = (float)(scale * s * g.inv_ell[t]);
   }
   __syncthreads();
-  double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
-  for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
-  for (int i = t; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
-  for (int i = t; i < g.n_lik; i += NTB) {
-    dn += g.lik_part[4 * i + 2];
-    bs += g.lik_part[4 * i + 3];
-  }
-  huf = block_sum<NTB>(huf, sh);
-  huu = block_sum<NTB>(huu, sh);
-  dn = block_sum<NTB>(dn, sh);
-  bs = block_sum<NTB>(bs, sh);
+  double v4[4] = {huf, huu, dn, bs};
+  block_sums<NTB, 4>(v4, sh);
+  huf = v4[0]; huu = v4[1]; dn = v4[2]; bs = v4[3];
   if (t == 0) {
     if (ca.g_sf2) *ca.g_sf2 = (float)(scale * ((huf + huu) / (double)g.sfn[0] + bs));
     if (ca.g_noise) *ca.g_noise = (float)(scale * ca.c * dn);
