@@ -708,7 +708,8 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);
-  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + a.nLx * a.nLx), dim3(NTB), 0, c->st, a);
+  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + a.nLx * (a.nLx + 1) / 2), dim3(NTB), 0,
+                     c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }

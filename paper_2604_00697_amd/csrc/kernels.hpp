@@ -167,10 +167,16 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
     }
     return;
   }
-  // caller's L -> L32, LT, LtT, Lt32
+  // caller's L -> L32, LT, LtT, Lt32, LstT on the 32 x 32 tiles with I >= J
+  // only: the strictly upper tiles of L (and the strictly lower ones of the
+  // transposes) are zero from the workspace's allocation and no kernel ever
+  // writes them
   const int bl = b - a.nK;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  const int i0 = (bl / a.nLx) * 32, j0 = (bl % a.nLx) * 32;
+  int I = (int)((sqrtf(8.0f * bl + 1.0f) - 1.0f) * 0.5f);
+  while ((I + 1) * (I + 2) / 2 <= bl) ++I;
+  while (I * (I + 1) / 2 > bl) --I;
+  const int i0 = I * 32, j0 = (bl - I * (I + 1) / 2) * 32;
   float lv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
