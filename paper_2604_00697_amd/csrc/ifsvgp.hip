@@ -704,7 +704,7 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
   a.ld = c->Mp;
   a.L32 = c->L32[0]; a.Lt32 = c->Lt32[0]; a.LT = c->LT[0]; a.LtT = c->LtT[0];
   a.LstT = c->LstT[0];
-  a.scal = c->scal; a.flag = c->flag;
+  a.scal = c->scal; a.flag = c->flag; a.ngskip = c->ngskip;
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);

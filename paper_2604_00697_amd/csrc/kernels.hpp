@@ -61,6 +61,7 @@ struct SetupArgs {
   void *LT, *LtT, *LstT;
   double *scal;
   int *flag;
+  int *ngskip;         // stop flag of an adaptive NG loop, cleared for the call
   int nKx, nK, nLx;
 };
 
@@ -72,7 +73,11 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   const int b = blockIdx.x;
   const int M = a.M, D = a.D;
   const CallArgs *ca = a.latch ? &a.cav : a.ca;
-  if (a.latch && b == 0 && threadIdx.x == 0) *a.ca = a.cav;
+  if (b == 0 && threadIdx.x == 0) {
+    if (a.latch) *a.ca = a.cav;
+    // a stop of an earlier call must not skip this call's first products
+    *a.ngskip = 0;
+  }
   const float *Zc = ca->Z, *ellc = ca->ell, *sc = ca->s;
   if (b < a.nK) {
     // 64 x 64 tile; thread (tx, ty) owns rows ty + 16 p and columns tx + 16 q

@@ -73,3 +73,27 @@ def test_adaptive_ng_parity(prec, M, D, seed, k, pert):
     if nr < n_max:
         np.testing.assert_array_equal(rg[nchk:], np.full(n_max - nchk, rg[nchk - 1]))
     ctx.close()
+
+
+def test_adaptive_calls_in_a_row_are_independent(require_gpu):
+    """A loop that stopped early leaves its stop flag set; the next adaptive
+    call on the same context must start from its own first step regardless
+    (same inputs twice -> identical residuals, steps and L)."""
+    from paper_2604_00697_amd.lib import Context
+    dev = torch.device("cuda", 0)
+    Z, ell, sf2, s, Kt, L0 = _problem(100, 3, 4, 0.02)
+    gam = [1.0] * 6
+    _, rf = svgp.ng_steps(L0.astype(np.float64), Kt, gam)
+    tol = float(np.sqrt(rf[1] * rf[2]))
+    ctx = Context(100, 8, 3, "fp32")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(dev)
+    outs = []
+    for _ in range(2):
+        L = t(L0)
+        r, k = ctx.natgrad_tol(t(Z), t(ell), t([sf2]), t(s), L, gam, tol)
+        outs.append((r.clone(), k.clone(), L))
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    assert int(outs[0][1].item()) == 2
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)

@@ -121,3 +121,52 @@ def test_split_calls_replay_match_direct():
     for ctx in ctxs.values():
         assert ctx.status() == 0
         ctx.close()
+
+
+def test_adaptive_loop_replays_match_direct():
+    """The adaptive NG loops (residual rule and variance-gap rule) replayed
+    from recorded graphs, with the stopping threshold changing between calls
+    (it reaches the kernels through the argument block), so the replays stop
+    at different steps; residuals, steps applied and L compared bitwise."""
+    from paper_2604_00697_amd.lib import Context
+    M, B, D = 160, 256, 3
+    dev = torch.device("cuda", 0)
+    batches, par, L0 = _inputs(M, B, D, 2, seed=11)
+    # start away from the fixed point so the loops take several steps
+    g = np.random.Generator(np.random.PCG64(5))
+    pert = torch.from_numpy(np.tril(0.05 * g.standard_normal((M, M))).astype(np.float32)).to(dev)
+    L0 = L0 * (1.0 + pert)
+    ctxs = {"direct": Context(M, B, D, "fp32"), "graph": Context(M, B, D, "fp32")}
+    ctxs["direct"].set_graphs(False)
+    ctxs["graph"].set_graphs(True)
+    sig2 = 0.5 * float(par["s"].min().item())
+    tols = [1e-3, 1e-1, 1e-5, 3e-2, 1e-3]
+    first = {}
+    for it, tol in enumerate(tols):
+        X, _ = batches[it % 2]
+        outs = {}
+        for k, ctx in ctxs.items():
+            La, Lb = L0.clone(), L0.clone()
+            r1, s1 = ctx.natgrad_tol(par["Z"], par["ell"], par["sf2"], par["s"], La, [1.0] * 5, tol)
+            r2, s2 = ctx.natgrad_gap(X, par["Z"], par["ell"], par["sf2"], par["noise"], par["s"],
+                                     Lb, [1.0] * 5, sig2, tol)
+            outs[k] = (r1, s1, La, r2, s2, Lb)
+        _eager_noise(dev, it)
+        torch.cuda.synchronize()
+        d, q = outs["direct"], outs["graph"]
+        print(f"GRAPH adaptive it={it} tol={tol} steps {d[1].item()} / {d[4].item()} "
+              f"resid {d[0].cpu().numpy()} gaps {d[3].cpu().numpy()}", flush=True)
+        assert torch.isfinite(d[2]).all() and torch.isfinite(d[5]).all(), it
+        for a, b in zip(d, q):
+            assert torch.equal(a, b), it
+        # every call starts from the same L0: the measure before the first step
+        # does not depend on where earlier calls stopped
+        first.setdefault("r", d[0][:1].clone())
+        assert torch.equal(d[0][:1], first["r"]), it
+        if it == 4:
+            assert torch.equal(d[2], first["L_tol3"]) and torch.equal(d[1], first["s_tol3"])
+        if it == 0:
+            first["L_tol3"], first["s_tol3"] = d[2].clone(), d[1].clone()
+    for ctx in ctxs.values():
+        assert ctx.status() == 0
+        ctx.close()
