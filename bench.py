@@ -347,6 +347,9 @@ def main():
     # largest product for comparison
     dominant, second = "gemm_R_grad_uf", "gemm_U"
     forms = [args.prec] + ([] if args.no_fp32 or args.prec == "fp32" else ["fp32"])
+    # the fp16-operand variant of the precision form, beside bf16
+    if args.prec == "bf16" and not args.no_fp32 and w.lik == "gaussian":
+        forms.append("fp16")
     res = {}
     for prec in forms:
         log(f"bench: timing {prec}: {args.warmup} warmup + {args.steps} steps")
@@ -404,6 +407,13 @@ def main():
                                          (PEAK_TFLOPS["fp32"] * 1e12), 3),
                        "F": r32["F"]}
         out["F"] = main_r["F"]
+    if "fp16" in res and args.prec != "fp16":
+        r16 = res["fp16"]
+        out["fp16"] = {"value": round(r16["iters_per_s"], 3),
+                       "ms_per_step": round(r16["ms_per_step"], 4),
+                       "mfma_pct": round(100.0 * f_iter / (r16["ms_per_step"] * 1e-3) /
+                                         (PEAK_TFLOPS["fp16"] * 1e12), 3),
+                       "F": r16["F"]}
     if not args.no_next:
         log("bench: prediction, adaptive NG loops, Adam")
         out["entry_points"] = next_rows(args.prec, w, batches, par, L0, dev)

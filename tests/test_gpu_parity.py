@@ -342,8 +342,8 @@ def full_size_case(name):
                 noise=np.float32(p.noise_var), Z=Z, m=m, s=s, L=f32(L), lik=w.lik)
 
 
-@pytest.mark.parametrize("name,prec", [("C3", "bf16"), ("C3", "fp32"), ("C5", "bf16"),
-                                       ("C4", "bf16"), ("C4", "fp32")])
+@pytest.mark.parametrize("name,prec", [("C3", "bf16"), ("C3", "fp32"), ("C3", "fp16"),
+                                       ("C5", "bf16"), ("C4", "bf16"), ("C4", "fp32")])
 def test_full_size_workloads(require_gpu, name, prec):
     c = full_size_case(name)
     compare(f"full_{name}_{prec}", c, prec, nsamp=1 if name == "C4" else 3)
