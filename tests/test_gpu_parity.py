@@ -300,7 +300,8 @@ def test_bf16_probit_parity(require_gpu):
 
 def test_argument_errors_and_domain_flag(require_gpu):
     import torch
-    from paper_2604_00697_amd.lib import Context, IFSVGPError, EINVAL, EDOMAIN, ESTATE
+    from paper_2604_00697_amd.lib import (Context, IFSVGPError, EINVAL, EDOMAIN, ESTATE,
+                                          ENONFINITE)
     c = make_case(20, 30, 2, seed=1)
     ctx = Context(20, 30, 2, "fp32", "gaussian")
     d = to_dev(c)
@@ -319,6 +320,30 @@ def test_argument_errors_and_domain_flag(require_gpu):
               d["L"])
     assert ctx.status() == EDOMAIN
     assert ctx.status() == 0          # the flag is cleared by the read
+    # a zero on the diagonal of L (log|T| undefined) and a non-positive
+    # lengthscale are domain errors; a NaN target gives a non-finite bound
+    L_bad = d["L"].clone()
+    L_bad[5, 5] = 0.0
+    ctx.bound(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"], d["s"],
+              L_bad)
+    assert ctx.status() == EDOMAIN
+    ell_bad = d["ell"].clone()
+    ell_bad[0] = 0.0
+    ctx.bound(d["X"], d["y"], c["N"], ell_bad, d["sf2"], d["noise"], d["Z"], d["m"], d["s"],
+              d["L"])
+    assert ctx.status() == EDOMAIN
+    y_nan = d["y"].clone()
+    y_nan[7] = float("nan")
+    F, _ = ctx.bound(d["X"], y_nan, c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"],
+                     d["s"], d["L"])
+    torch.cuda.synchronize()
+    assert not torch.isfinite(F).all()
+    assert ctx.status() == ENONFINITE
+    # a clean call afterwards is unaffected
+    F, _ = ctx.bound(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"],
+                     d["s"], d["L"])
+    torch.cuda.synchronize()
+    assert torch.isfinite(F).all() and ctx.status() == 0
     ctx.close()
 
 
