@@ -201,6 +201,47 @@ def rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
     return out
 
 
+def rsvgp_bound_hutchinson(X, y, N, ell, sf2, noise_var, Z, m, s, L, Omega,
+                           lik="gaussian", n_gh=20):
+    """The bound with its cubic trace terms replaced by Hutchinson estimates
+    (Section 3.4, bound evaluation), literally.
+
+    Omega: M x K probe matrix (its columns are the probes, E[w w^T] = I).  The
+    traces are those of the L-space products
+        W = L^T K~ L   (tr W = tr(K~ T))  and  Wu = L^T K_uu L,
+    with tr(P K_uu) = 2 tr(Wu) - tr(W Wu), each estimated as
+    tr(A) ~ (1/K) sum_k w_k^T A w_k (for W Wu: (W w_k)^T (Wu w_k)).  The data
+    term, m~^T P K_uu P m~, log|T| and log|S~| are exact.  Returns the dict of
+    rsvgp_bound (F, data, KL, sum_var, mu, var, E) plus the estimated traces
+    trW, trWu, trWWu."""
+    X, y, ell, Z, m, s, L, Omega = _as64(X, y, ell, Z, m, s, L, Omega)
+    sf2 = float(sf2)
+    B = X.shape[0]
+    M, K = Omega.shape
+    Kuu = se_ard(Z, Z, ell, sf2)
+    Kuf = se_ard(Z, X, ell, sf2)
+    Kt = Kuu + np.diag(s)
+    T = L @ L.T
+    P = T @ (2.0 * np.eye(M) - Kt @ T)
+    Pm = P @ m
+    mu = Kuf.T @ Pm
+    var = sf2 - np.einsum("in,in->n", Kuf, P @ Kuf)
+    E, _, _, _ = expectation(lik, y, mu, var, noise_var, n_gh)
+    data = N / B * E.sum()
+    W = L.T @ Kt @ L
+    Wu = L.T @ Kuu @ L
+    WO, WuO = W @ Omega, Wu @ Omega
+    trW = np.sum(Omega * WO) / K
+    trWu = np.sum(Omega * WuO) / K
+    trWWu = np.sum(WO * WuO) / K
+    trPK = 2.0 * trWu - trWWu
+    quad = Pm @ Kuu @ Pm
+    logdet = 2.0 * np.log(np.abs(np.diag(L))).sum()
+    KL = 0.5 * (trW - trPK - M + quad - logdet - np.log(s).sum())
+    return dict(F=data - KL, data=data, KL=KL, sum_var=np.sum(var), mu=mu, var=var, E=E,
+                trW=trW, trWu=trWu, trWWu=trWWu)
+
+
 def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
                      n_gh=20, perturb=None):
     """Gradient of rsvgp_bound w.r.t. xi at fixed T (adjoint of the literal form).

@@ -31,6 +31,9 @@ MUTATIONS = [
     ("svgp.py", "R = Kuf - A @ (T @ Kuf)", "R = Kuf - T @ (A @ Kuf)"),
     ("svgp.py", "return float(np.sum(R * R)) / float(sigma2)", "return float(np.sum(R * R))"),
     ("svgp.py", "thr = 2.0 * float(noise_obs) * float(eps)", "thr = float(noise_obs) * float(eps)"),
+    ("svgp.py", "trPK = 2.0 * trWu - trWWu", "trPK = trWu - trWWu"),
+    ("svgp.py", "trWWu = np.sum(WO * WuO) / K", "trWWu = np.sum(WO * WO) / K"),
+    ("svgp.py", "P = T @ (2.0 * np.eye(M) - Kt @ T)", "P = T @ (2.0 * np.eye(M) - Kuu @ T)"),
     ("quadrature.py", "* y / np.sqrt(2.0 * v)", "* y / np.sqrt(v)"),
     ("quadrature.py", "np.exp(log_phi - log_ndtr(z))", "np.exp(log_phi + log_ndtr(z))"),
     ("quadrature.py", "E = -0.5 * LOG_2PI - 0.5 * np.log(s2) - (r * r + v) / (2.0 * s2)",

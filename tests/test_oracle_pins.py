@@ -543,3 +543,50 @@ def test_gap_loop_cut_at_the_first_small_gap():
         Lf, _ = svgp.ng_steps(L0, Kt, gam[:k])
         assert ak == k and len(gk) == k + 1
         assert np.allclose(Lk, Lf, rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------- Hutchinson
+def _hutch(p, L, Omega):
+    return svgp.rsvgp_bound_hutchinson(p["X"], p["y"], p["N"], p["ell"], p["sf2"],
+                                       p["noise_var"], p["Z"], p["m"], p["s"], L, Omega,
+                                       lik=p["lik"])
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_hutchinson_with_scaled_unit_probes_is_the_exact_bound(lik):
+    """With the M probes sqrt(M) e_i every trace estimate is exact, so the
+    estimated bound is the bound of eq. rsvgp_precond."""
+    p = small_problem(20, lik=lik)
+    for k in range(3):
+        L = random_L(6, 600 + k)
+        h = _hutch(p, L, np.sqrt(6.0) * np.eye(6))
+        b = bound(p, L)
+        assert np.isclose(h["F"], b["F"], rtol=1e-12, atol=1e-12)
+        assert np.isclose(h["KL"], b["KL"], rtol=1e-12, atol=1e-12)
+        assert np.allclose(h["var"], b["var"], rtol=1e-12, atol=1e-14)
+
+
+def test_hutchinson_estimate_is_unbiased():
+    """Rademacher probes: the mean of the estimated bound over many
+    independent single-probe draws is the exact bound (within 4 standard
+    errors), and its spread matches the Hutchinson variance
+    Var(w^T A w) = 2 (||A||_F^2 - sum_i A_ii^2) of the estimated combination."""
+    p = small_problem(21)
+    L = random_L(6, 77, 0.4)
+    exact = bound(p, L)["F"]
+    g = _rng(5)
+    vals = []
+    for _ in range(4000):
+        w = g.choice([-1.0, 1.0], size=(6, 1))
+        vals.append(_hutch(p, L, w)["F"])
+    vals = np.array(vals)
+    se = vals.std(ddof=1) / np.sqrt(len(vals))
+    assert abs(vals.mean() - exact) <= 4.0 * se
+    # the estimated part of -KL is -1/2 (w^T A w) with the symmetric matrix
+    # A = W - 2 Wu + sym(W Wu) (from tr W - tr(P K_uu)), so Var F = Var(w^T A w) / 4
+    Kt = svgp.ktilde(p["Z"], p["ell"], p["sf2"], p["s"])
+    Kuu = Kt - np.diag(p["s"])
+    W, Wu = L.T @ Kt @ L, L.T @ Kuu @ L
+    A = W - 2.0 * Wu + 0.5 * (W @ Wu + Wu @ W)
+    var_th = 2.0 * (np.sum(A * A) - np.sum(np.diag(A) ** 2)) / 4.0
+    assert np.isclose(vals.var(ddof=1), var_th, rtol=0.1)
