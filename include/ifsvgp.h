@@ -195,6 +195,26 @@ int ifsvgp_natgrad_gap(ifsvgp_ctx *ctx, const float *X, int B, const float *Z,
                        const float *s_tilde, float *L, const float *gammas, int n_max,
                        float sigma2, float eps, double *out_gap, int *out_steps);
 
+/* Bound evaluation with Hutchinson trace estimates (Section 3.4, bound
+ * evaluation): as ifsvgp_bound, but the cubic trace terms of the KL bound are
+ * replaced by unbiased estimates from K probe vectors, so no M x M x M product
+ * is formed (cost O((B + K) M^2)).  With W = L^T K~ L and Wu = L^T K_uu L,
+ *   tr W ~ (1/K) sum_k w_k^T W w_k,  tr Wu ~ (1/K) sum_k w_k^T Wu w_k,
+ *   tr(W Wu) ~ (1/K) sum_k (W w_k)^T (Wu w_k),
+ * and tr(P K_uu) = 2 tr Wu - tr(W Wu), tr(K~ T) = tr W.  The data term, the
+ * mean term m~^T P K_uu P m~ and log|T| are exact (sigma_n^2 from
+ * U = 2V - W V, V = L^T K_uf).  Omega_t: device fp32 [K][M] row-major, probe k
+ * in row k (draw them with E[w w^T] = I, e.g. Rademacher; the caller's draw is
+ * used as given).  Requires round_up(B, 64) + round_up(K + 1, 64) <=
+ * round_up(B_max, 128) (IFSVGP_EINVAL otherwise).  out_terms as for
+ * ifsvgp_bound, with the NG residual entry 0.  Forward only: the call reuses
+ * the workspace, so a following ifsvgp_bound_bwd needs a new ifsvgp_bound. */
+int ifsvgp_bound_hutch(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
+                       const float *ell, const float *sf2, const float *noise_var,
+                       const float *Z, const float *m_tilde, const float *s_tilde,
+                       const float *L, const float *Omega_t, int K, double *out_bound,
+                       double *out_terms);
+
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is
  * read only for the Gaussian likelihood (may be NULL for probit).

@@ -202,7 +202,7 @@ def rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
 
 
 def rsvgp_bound_hutchinson(X, y, N, ell, sf2, noise_var, Z, m, s, L, Omega,
-                           lik="gaussian", n_gh=20):
+                           lik="gaussian", n_gh=20, perturb=None):
     """The bound with its cubic trace terms replaced by Hutchinson estimates
     (Section 3.4, bound evaluation), literally.
 
@@ -213,13 +213,13 @@ def rsvgp_bound_hutchinson(X, y, N, ell, sf2, noise_var, Z, m, s, L, Omega,
     tr(A) ~ (1/K) sum_k w_k^T A w_k (for W Wu: (W w_k)^T (Wu w_k)).  The data
     term, m~^T P K_uu P m~, log|T| and log|S~| are exact.  Returns the dict of
     rsvgp_bound (F, data, KL, sum_var, mu, var, E) plus the estimated traces
-    trW, trWu, trWWu."""
+    trW, trWu, trWWu.  perturb: as in rsvgp_bound."""
     X, y, ell, Z, m, s, L, Omega = _as64(X, y, ell, Z, m, s, L, Omega)
     sf2 = float(sf2)
     B = X.shape[0]
     M, K = Omega.shape
-    Kuu = se_ard(Z, Z, ell, sf2)
-    Kuf = se_ard(Z, X, ell, sf2)
+    Kuu = _perturbed(se_ard(Z, Z, ell, sf2), perturb, "Kuu")
+    Kuf = _perturbed(se_ard(Z, X, ell, sf2), perturb, "Kuf")
     Kt = Kuu + np.diag(s)
     T = L @ L.T
     P = T @ (2.0 * np.eye(M) - Kt @ T)

@@ -98,6 +98,8 @@ struct ifsvgp_ctx {
   float *gdiag, *pdiag;  // diag(G_uu) [Mp]; partials of diag(L Q L^T) [nb64][Mp]
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
   double *tp_gap;  // per-tile partials of the variance gap [nb128][cdiv(Bp, 64)]
+  float *hwx, *hex;  // Hutchinson bound: W Xc and E Omega (fp32, [Bp][Mp])
+  double *hp;        // Hutchinson bound: per-probe sums [Bp][4]
   double *gh;
   int *flag, *counters;
   int *ngskip;  // stop flag of an adaptive NG loop
@@ -412,6 +414,9 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->tp_uf, (size_t)nb128 * nbB);
   ALLOC(c->tp_uu, (size_t)nt_sym64);
   ALLOC(c->tp_gap, (size_t)nb128 * cdiv(Bp, 64));
+  ALLOC(c->hwx, MB);
+  ALLOC(c->hex, MB);
+  ALLOC(c->hp, (size_t)4 * Bp);
   ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
   ALLOC(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
   ALLOC(c->ell_part, (size_t)(M + B_max + 64) * D);
@@ -608,6 +613,34 @@ struct Ops {
     Opnd<T> a{(const T *)Yfull(c), c->Mp}, b{(const T *)c->Vt, c->Mp};
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, 0, skip};
     EpiGap<T> e{(const T *)c->Kft, c->Mp, c->M, B, c->tp_gap};
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+  }
+  // Hutchinson bound: with NC columns Xc in the batch operand (Vt rows),
+  // Y1 = L Xc -> Ut, Y2 = K~ Y1 -> Kft, W Xc = L^T Y2 -> hwx (fp32), and for
+  // the K probe columns E Omega = L^T S~ Y1 -> hex (fp32); all stored
+  // transposed ([column][row]).
+  static hipError_t hutch_L(ifsvgp_ctx *c, int NC) {
+    Opnd<T> a{LT(c, 0), c->Mp}, b{(const T *)c->Vt, c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, K_HI_M1};
+    EpiStoreT<T> e{(T *)c->Ut, c->Mp, c->M, NC};
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+  }
+  static hipError_t hutch_K(ifsvgp_ctx *c, int NC) {
+    Opnd<T> a{(const T *)c->KtT, c->Mp}, b{(const T *)c->Ut, c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, 0};
+    EpiStoreT<T> e{(T *)c->Kft, c->Mp, c->M, NC};
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+  }
+  static hipError_t hutch_Lt(ifsvgp_ctx *c, int NC) {
+    Opnd<T> a{LtT(c, 0), c->Mp}, b{(const T *)c->Kft, c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, K_LO_M0};
+    EpiStoreT<float> e{c->hwx, c->Mp, c->M, NC};
+    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+  }
+  static hipError_t hutch_E(ifsvgp_ctx *c, int B, int K) {
+    Opnd<T> a{(const T *)c->LstT[0], c->Mp}, b{(const T *)c->Ut + (long)B * c->Mp, c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(K, CR::BN), 0, 1, c->M, K_LO_M0};
+    EpiStoreT<float> e{c->hex, c->Mp, c->M, K};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
@@ -1009,6 +1042,68 @@ static int enqueue_predict(ifsvgp_ctx *c, const CallArgs &ca0, const PredOut &o)
   return IFSVGP_OK;
 }
 
+// Bound evaluation with Hutchinson trace estimates (K probes, Omt [K][M] on
+// the device): set-up, K_uf tiles and V = L^T K_uf, a = L^T m~ (side stream),
+// then the thin products with Xc = [V | Omega | a], the row reductions, the
+// trace estimates, b^T Wu b by matrix-vector products, and the likelihood
+// kernel's finalisation of F.  No M x M x M product.
+template <typename T>
+static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Omt, int K) {
+  c->ev_next = 0;
+  c->side_open = false;
+  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca);
+  if (r) return r;
+  c->cur = 0;
+  c->fwd_valid = 0;
+  const int M = c->M, NC = B + K + 1;
+  const long Mp = c->Mp;
+  HIPCK(fork_side(c));
+  r = launch_kuf<T>(c, B);
+  if (r) return r;
+  {
+    OnSide side(c);
+    HIPCK(Ops<T>::gemm_V(c, 0, B));
+    hipLaunchKernelGGL(k_lt_m, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+                       (const float *)c->Lt32[0], Mp, M, (const CallArgs *)c->dca, c->va);
+  }
+  HIPCK(join_side(c));
+  hipLaunchKernelGGL((k_hutch_fill<T>), dim3(cdiv(c->Mp, NTB), K + 1), dim3(NTB), 0, c->st,
+                     (T *)c->Vt, Mp, B, K, Omt, (const float *)c->va, M, c->Mp);
+  HIPCK(Ops<T>::hutch_L(c, NC));
+  HIPCK(Ops<T>::hutch_K(c, NC));
+  HIPCK(Ops<T>::hutch_Lt(c, NC));
+  HIPCK(Ops<T>::hutch_E(c, B, K));
+  HutchArgs h{c->Vt, Mp, c->hwx, c->hex, Omt, c->va, M, B, K, c->var_part, c->mu_part, c->hp,
+              c->vb};
+  hipLaunchKernelGGL((k_hutch_rows<T>), dim3(cdiv(NC, NTB / 64)), dim3(NTB), 0, c->st, h);
+  hipLaunchKernelGGL(k_hutch_final, dim3(1), dim3(NTB), 0, c->st, (const double *)c->hp, K,
+                     c->tp_gram);
+  // b^T Wu b with Wu b = L^T (K~ - S~) L b
+  const dim3 gv(cdiv(M, NTB / 64));
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->L32[0], Mp, M, M,
+                     (const float *)c->vb, (const float *)nullptr, 1, (const double *)nullptr,
+                     c->vLb);
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->Kt, Mp, M, M,
+                     (const float *)c->vLb, (const float *)nullptr, 0, (const double *)nullptr,
+                     c->vt2);
+  hipLaunchKernelGGL(k_hutch_sub_diag, dim3(cdiv(M, NTB)), dim3(NTB), 0, c->st, c->vt2,
+                     (const float *)c->sP, (const float *)c->vLb, M);
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->Lt32[0], Mp, M, M,
+                     (const float *)c->vt2, (const float *)nullptr, 0, (const double *)nullptr,
+                     c->vWub);
+  hipLaunchKernelGGL(k_hutch_quad, dim3(1), dim3(NTB), 0, c->st, (const float *)c->vb,
+                     (const float *)c->vWub, (const float *)c->L32[0], Mp, M, c->vec_part,
+                     c->flag);
+  LikArgs a{c->mu_part, 1, c->var_part, 1, (long)c->Bp,
+            c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
+            c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
+            c->tp_gram, 1, c->vec_part, 1,
+            c->scal, M, c->flag, c->counters + CNT_LIK};
+  hipLaunchKernelGGL(k_lik, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
+  HIPCK(hipGetLastError());
+  return IFSVGP_OK;
+}
+
 // direct execution: the set-up latches the arguments when there is one
 static int run_direct(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
   if (k.setup) return enqueue_any(c, k, &ca);
@@ -1239,6 +1334,21 @@ extern "C" int ifsvgp_natgrad_gap(ifsvgp_ctx *c, const float *X, int B, const fl
   a.gap_sigma2 = sigma2;
   Call k{true, false, false, B, n_max, gammas, true, false, false, NG_GAP};
   return run_call(c, k, a);
+}
+
+extern "C" int ifsvgp_bound_hutch(ifsvgp_ctx *c, const float *X, const float *y, int B,
+                                  double N, const float *ell, const float *sf2,
+                                  const float *noise, const float *Z, const float *m,
+                                  const float *s, const float *L, const float *Omega_t, int K,
+                                  double *out_bound, double *out_terms) {
+  int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
+  if (r) return r;
+  if (!Omega_t || K < 1 || !out_bound) return IFSVGP_EINVAL;
+  if (rup(B, 64) + rup(K + 1, 64) > c->Bp) return IFSVGP_EINVAL;
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
+  a.out_bound = out_bound;
+  a.out_terms = out_terms;
+  PREC_DISPATCH(enqueue_hutch, c, a, B, Omega_t, K)
 }
 
 extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {

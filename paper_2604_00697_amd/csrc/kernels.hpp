@@ -621,6 +621,128 @@ __global__ void k_predict_sum(const double *part, int nparts, double *scal, int 
   }
 }
 
+// ---------------------------------------------------------------- Hutchinson bound
+// Bound evaluation with the cubic traces replaced by probe estimates.  With
+// Xc = [V | Omega | a] (columns: the batch, the K probes, a = L^T m~) and
+// WX = L^T K~ L Xc, EX = L^T S~ L Omega (fp32, stored transposed [column][row]):
+//   U = 2V - W V gives sigma^2_n = sf2 - sum_i V_in U_in and mu_n = a^T U_n,
+//   per probe w: w^T W w, w^T E w, |W w|^2, (W w)^T (E w) for the estimates of
+//   tr W, tr Wu = tr(W - E) and tr(W Wu), and b = 2a - W a.
+// The probes as operands: rows [B, B + K) of the batch operand take Omega^T,
+// row B + K takes a; k >= M is zero.
+template <typename T>
+__global__ void k_hutch_fill(T *Vt, long ld, int B, int K, const float *Omt, const float *a,
+                             int M, int Mp) {
+  const int r = blockIdx.y;  // 0..K: probe rows, then a
+  for (int i = blockIdx.x * NTB + threadIdx.x; i < Mp; i += gridDim.x * NTB) {
+    float v = 0.f;
+    if (i < M) v = r < K ? Omt[(long)r * M + i] : a[i];
+    Vt[(long)(B + r) * ld + i] = from_f32<T>(v);
+  }
+}
+
+struct HutchArgs {
+  const void *Vt; long ld;  // batch operand rows (type T) [n][i]
+  const float *wx, *ex;     // [B + K + 1][ld], [K][ld]
+  const float *Omt;         // caller's probes [K][M]
+  const float *a;           // L^T m~
+  int M, B, K;
+  float *var_part, *mu_part;  // [n]: sum_i V o U and sum_i a o U
+  double *hp;                 // [K][4]
+  float *b;                   // 2a - W a, zero-padded to ld
+};
+
+template <typename T>
+__global__ void k_hutch_rows(HutchArgs h) {
+  const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= h.B + h.K + 1) return;
+  const float *wx = h.wx + (long)row * h.ld;
+  if (row < h.B) {
+    const T *vt = (const T *)h.Vt + (long)row * h.ld;
+    float sv = 0.f, sm = 0.f;
+    for (int i = lane; i < h.M; i += 64) {
+      const float v = to_f32(vt[i]);
+      const float u = 2.f * v - wx[i];
+      sv = fmaf(v, u, sv);
+      sm = fmaf(h.a[i], u, sm);
+    }
+    sv = wave_sum(sv);
+    sm = wave_sum(sm);
+    if (lane == 0) {
+      h.var_part[row] = sv;
+      h.mu_part[row] = sm;
+    }
+  } else if (row < h.B + h.K) {
+    const int k = row - h.B;
+    const float *om = h.Omt + (long)k * h.M, *ex = h.ex + (long)k * h.ld;
+    double w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0;
+    for (int i = lane; i < h.M; i += 64) {
+      const double o = om[i], w = wx[i], e = ex[i];
+      w1 += o * w;
+      w2 += o * e;
+      w3 += w * w;
+      w4 += w * e;
+    }
+    w1 = wave_sum(w1);
+    w2 = wave_sum(w2);
+    w3 = wave_sum(w3);
+    w4 = wave_sum(w4);
+    if (lane == 0) {
+      double *p = h.hp + 4 * (long)k;
+      p[0] = w1; p[1] = w2; p[2] = w3; p[3] = w4;
+    }
+  } else {
+    for (int i = lane; i < (int)h.ld; i += 64) h.b[i] = i < h.M ? 2.f * h.a[i] - wx[i] : 0.f;
+  }
+}
+
+// The trace estimates as the bound's Gram partial {tr W, tr(Q Wu), 0}, with
+// tr(Q Wu) = 2 tr Wu - tr(W Wu) (one block).
+__global__ void k_hutch_final(const double *hp, int K, double *gram_part) {
+  __shared__ double sh[3 * (NTB / 64)];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += NTB) {
+    const double *p = hp + 4 * (long)k;
+    v[0] += p[0];
+    v[1] += p[0] - p[1];
+    v[2] += p[2] - p[3];
+  }
+  block_sums<NTB, 3>(v, sh);
+  if (threadIdx.x == 0) {
+    gram_part[0] = v[0] / K;
+    gram_part[1] = 2.0 * v[1] / K - v[2] / K;
+    gram_part[2] = 0.0;
+  }
+}
+
+// y -= s~ o x  (K~ L b -> K_uu L b)
+__global__ void k_hutch_sub_diag(float *y, const float *sP, const float *x, int M) {
+  const int i = blockIdx.x * NTB + threadIdx.x;
+  if (i < M) y[i] -= sP[i] * x[i];
+}
+
+// The bound's vector partial {b^T Wu b, sum log|L_ii|} in one block, with the
+// domain check on the diagonal of L.
+__global__ void k_hutch_quad(const float *b, const float *Wub, const float *L, long ld, int M,
+                             double *vec_part, int *flag) {
+  __shared__ double sh[2 * (NTB / 64)];
+  double v[2] = {0.0, 0.0};
+  int bad = 0;
+  for (int i = threadIdx.x; i < M; i += NTB) {
+    v[0] += (double)b[i] * (double)Wub[i];
+    const float d = L[(long)i * ld + i];
+    if (d == 0.f || !isfinite(d)) bad = 1;
+    v[1] += log(fabs((double)d));
+  }
+  if (bad) atomicOr(flag, FLAG_DOMAIN);
+  block_sums<NTB, 2>(v, sh);
+  if (threadIdx.x == 0) {
+    vec_part[0] = v[0];
+    vec_part[1] = v[1];
+  }
+}
+
 // ---------------------------------------------------------------- backward
 // C = -sym((V alpha) a^T) + V diag(beta) V^T - 1/2 (Wu + I - Wub a^T - a Wub^T)
 //     + 1/2 (Q - b b^T), with V diag(beta) V^T = -sum_s Ys[s] (split-K pieces of

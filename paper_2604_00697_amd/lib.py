@@ -42,6 +42,8 @@ _SIGS = {
     "ifsvgp_natgrad_tol": (_I, [_P, _P, _P, _P, _P, _P, _P, _I, ctypes.c_float, _P, _P]),
     "ifsvgp_natgrad_gap": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _I, ctypes.c_float,
                                 ctypes.c_float, _P, _P]),
+    "ifsvgp_bound_hutch": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
+                                _P, _P]),
     "ifsvgp_bound": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
                               _P, _P, _P, _P, _P, _P]),
@@ -251,6 +253,22 @@ class Context:
             a["m"], a["s"], a["L"], _ptr(out, (1,), "out", torch.float64),
             _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound")
         self.generation += 1
+        return out, terms
+
+    def bound_hutch(self, X, y, N, ell, sf2, noise, Z, m, s, L, Omega_t, out=None, terms=None):
+        """Bound with Hutchinson trace estimates from the probes in the rows of
+        Omega_t (fp32 [K, M]); F (fp64 (1,)) and terms (fp64 (8,))."""
+        import torch
+        a = self._inputs(X, y, ell, sf2, noise, Z, m, s, L)
+        K = Omega_t.shape[0]
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        terms = torch.empty(N_TERMS, dtype=torch.float64, device=self.device) if terms is None else terms
+        self._stream()
+        _check(self._lib.ifsvgp_bound_hutch(
+            self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
+            a["m"], a["s"], a["L"], _ptr(Omega_t, (K, self.M), "Omega_t"), K,
+            _ptr(out, (1,), "out", torch.float64),
+            _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound_hutch")
         return out, terms
 
     def bound_bwd(self, X, y, N, ell, sf2, noise, Z, m, s, L, grad_scale=None,

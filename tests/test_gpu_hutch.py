@@ -1,0 +1,126 @@
+"""GPU parity of ifsvgp_bound_hutch (the bound with Hutchinson trace
+estimates, Section 3.4) against the float64 oracle
+(oracle.svgp.rsvgp_bound_hutchinson) on the same probes: F, the data and KL
+terms and the summed variance.  With the M probes sqrt(M) e_i the estimate is
+the exact bound, which also ties the entry point to ifsvgp_bound.
+
+Gates as in test_gpu_parity.py: err <= max(base, mult * spread), spread being
+the oracle's own change when its inputs, the probes and the formed K_uu, K_uf
+carry independent rounding of the operand precision; fp32 base 1e-5 (F and
+terms), mult 30; bf16 base 1e-3 (F), 1e-2 (terms), mult 4."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import svgp
+from test_gpu_parity import make_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EPS = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -9}
+BASE = {"fp32": dict(F=1e-5, term=1e-5), "bf16": dict(F=1e-3, term=1e-2)}
+MULT = {"fp32": 30.0, "bf16": 4.0}
+QS = ("F", "data", "KL", "sum_var")
+
+
+def _oracle(c, Om, perturb=None, scale=None):
+    q = {k: np.asarray(c[k], np.float64) for k in ("X", "Z", "ell", "m", "s", "L")}
+    if scale:
+        q = {k: v * scale[k] for k, v in q.items()}
+    om = np.asarray(Om, np.float64) * (scale["Om"] if scale else 1.0)
+    r = svgp.rsvgp_bound_hutchinson(q["X"], c["y"], c["N"], q["ell"], float(c["sf2"]),
+                                    float(c["noise"]), q["Z"], q["m"], q["s"], q["L"], om.T,
+                                    lik=c["lik"], perturb=perturb)
+    return {k: r[k] for k in QS}
+
+
+def _spread(c, Om, eps, nsamp=3, seed=3):
+    base = _oracle(c, Om)
+    g = np.random.Generator(np.random.PCG64(seed))
+    M, B = c["Z"].shape[0], c["X"].shape[0]
+    sp = {k: 0.0 for k in QS}
+    for _ in range(nsamp):
+        scale = {k: 1.0 + eps * g.standard_normal(np.shape(c[k])) for k in ("X", "Z", "ell", "m", "s", "L")}
+        scale["Om"] = 1.0 + eps * g.standard_normal(np.shape(Om))
+        du = eps * g.standard_normal((M, M))
+        pert = dict(Kuu=np.tril(du) + np.tril(du, -1).T, Kuf=eps * g.standard_normal((M, B)))
+        out = _oracle(c, Om, pert, scale)
+        for k in QS:
+            sp[k] = max(sp[k], abs(out[k] - base[k]) / max(abs(base[k]), 1e-300))
+    return base, sp
+
+
+CASES = {
+    # name: (prec, lik, M, B, D, B_max, K, probes)
+    "fp32_gauss_M130_B96_K20": ("fp32", "gaussian", 130, 96, 3, 256, 20, "rademacher"),
+    "fp32_probit_M64_B50_K64": ("fp32", "probit", 64, 50, 2, 192, 64, "rademacher"),
+    "fp32_exact_probes_M40_B30": ("fp32", "gaussian", 40, 30, 2, 128, 40, "unit"),
+    "bf16_gauss_M200_B128_K32": ("bf16", "gaussian", 200, 128, 4, 256, 32, "rademacher"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hutchinson_bound_parity(require_gpu, name):
+    from paper_2604_00697_amd.lib import Context
+    prec, lik, M, B, D, Bmax, K, kind = CASES[name]
+    seed = zlib.crc32(name.encode()) % 1000
+    c = make_case(M, B, D, seed=seed, lik=lik, s_range=(0.05, 0.1))
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    Om = (np.sqrt(M) * np.eye(M) if kind == "unit"
+          else g.choice([-1.0, 1.0], size=(K, M))).astype(np.float32)
+    print(f"HUTCH case {name} prec={prec} M={M} B={B} K={K}", flush=True)
+    ctx = Context(M, Bmax, D, prec, lik)
+    d = to_dev(c)
+    Omd = torch.from_numpy(Om).to(d["X"].device)
+    F, terms = ctx.bound_hutch(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"],
+                               d["m"], d["s"], d["L"], Omd)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    t = terms.cpu().numpy()
+    gpu = dict(F=F.item(), data=t[0], KL=t[1], sum_var=t[2])
+    ref, sp = _spread(c, Om, EPS[prec], nsamp=2 if M > 150 else 3)
+    bad = []
+    for q in QS:
+        err = abs(gpu[q] - ref[q]) / max(abs(ref[q]), 1e-300)
+        tol = max(BASE[prec]["F" if q == "F" else "term"], MULT[prec] * sp[q])
+        print(f"PARITY {name} {q} {err:.3e} tol {tol:.2e} spread {sp[q]:.2e}", flush=True)
+        if not err <= tol:
+            bad.append(f"{q}: {err:.3e} > {tol:.2e}")
+    assert not bad, "; ".join(bad)
+    if kind == "unit":
+        # the exact-probe estimate is the exact bound of ifsvgp_bound
+        F2, _ = ctx.bound(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"],
+                          d["m"], d["s"], d["L"])
+        torch.cuda.synchronize()
+        assert abs(F2.item() - F.item()) <= 1e-5 * abs(F2.item())
+
+
+def test_hutchinson_bound_argument_errors(require_gpu):
+    from paper_2604_00697_amd import lib
+    from paper_2604_00697_amd.lib import Context, IFSVGPError
+    c = make_case(40, 60, 2, seed=3)
+    ctx = Context(40, 128, 2, "fp32")
+    d = to_dev(c)
+    dev = d["X"].device
+    F = torch.empty(1, dtype=torch.float64, device=dev)
+    args = lambda Om, K: (ctx._h, d["X"].data_ptr(), d["y"].data_ptr(), 60, c["N"],
+                          d["ell"].data_ptr(), d["sf2"].data_ptr(), d["noise"].data_ptr(),
+                          d["Z"].data_ptr(), d["m"].data_ptr(), d["s"].data_ptr(),
+                          d["L"].data_ptr(), Om, K, F.data_ptr(), None)
+    Om = torch.ones(64, 40, device=dev)
+    f = ctx._lib.ifsvgp_bound_hutch
+    assert f(*args(Om.data_ptr(), 0)) == lib.EINVAL
+    assert f(*args(None, 8)) == lib.EINVAL
+    # round_up(60, 64) + round_up(64 + 1, 64) = 192 > 128
+    assert f(*args(Om.data_ptr(), 64)) == lib.EINVAL
+    assert f(*args(Om.data_ptr(), 63)) == lib.OK
+    # the call replaces the forward state kept for the backward
+    with pytest.raises(IFSVGPError) as e:
+        ctx.bound_bwd(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"],
+                      d["s"], d["L"])
+    assert e.value.code == lib.ESTATE
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
