@@ -252,6 +252,37 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
                                                  par["noise"], par["s"], L, [1.0] * 3, sig2, 0.0),
                        setup=L0.clone)
         out["natgrad_gap_rule"] = {"steps": 3, "B": w.B, "ms_per_step": round(ms_gap / 3, 4)}
+    # the paper's Hutchinson setting (Appendix on approximate bound evaluation):
+    # B = 100, K = 256 probes; exact bound vs the estimate on the same inputs
+    # (D = 8 synthetic regression data), at the paper's M = 2000 and at
+    # M = 8192, where the cubic traces outweigh the launches
+    if w.lik == "gaussian":
+        import numpy as np
+        from paper_2604_00697_amd import synth
+        out["hutchinson_bound"] = []
+        for Mh in (2000, 8192):
+            wu = synth.Workload(f"M{Mh}_B100_D8", D=8, N=40_000, B=100, M=Mh)
+            pu = synth.params_s1(wu)
+            tt = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(dev)
+            Xu, yu = wu.batch(0)
+            du = dict(X=tt(Xu), y=tt(yu), ell=tt(pu.ell), sf2=tt([pu.sf2]),
+                      noise=tt([pu.noise_var]), Z=tt(pu.Z), m=tt(pu.m), s=tt(pu.s), L=tt(pu.L))
+            Kp = 256
+            om = tt(synth.rng(synth.SEED_PERTURB + 29).choice([-1.0, 1.0], size=(Kp, wu.M)))
+            cu = Context(wu.M, 448, wu.D, prec, "gaussian")
+            args = (du["X"], du["y"], wu.N, du["ell"], du["sf2"], du["noise"], du["Z"], du["m"],
+                    du["s"], du["L"])
+            ms_ex = timed(lambda _: cu.bound(*args))
+            ms_hu = timed(lambda _: cu.bound_hutch(*args, om))
+            out["hutchinson_bound"].append(
+                {"M": wu.M, "B": wu.B, "K": Kp, "exact_ms": round(ms_ex, 4),
+                 "hutchinson_ms": round(ms_hu, 4), "speedup": round(ms_ex / ms_hu, 3)})
+            torch.cuda.synchronize()
+            if cu.status() != 0:
+                raise RuntimeError("device status flag set in the Hutchinson timing")
+            cu.close()
+            del cu, du, om
+            torch.cuda.empty_cache()
     g = torch.zeros_like(par["Z"]) + 1e-3
 
     def adam_setup():

@@ -542,6 +542,7 @@ struct Ops {
   using CRG = Cfg<128, 128, 2, 2, T, 2>;
   // Ys = (V D)(V D)^T: lower tiles, split-K over the batch
   using CSY = Cfg<64, 64, 2, 2, T, 3>;
+  using CH = Cfg<64, 64, 2, 2, T, 3>;  // the Hutchinson bound's thin products
   static_assert(CR::BM == 128 && CRG::BM == 128 && CRG::BN == 128, "partial-sum layout");
 
   static T *LT(ifsvgp_ctx *c, int i) { return (T *)c->LT[i]; }
@@ -616,32 +617,34 @@ struct Ops {
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // Hutchinson bound: with NC columns Xc in the batch operand (Vt rows),
+  // on 64 x 64 tiles (NC is a few hundred columns: the larger tiles leave
+  // most CUs idle),
   // Y1 = L Xc -> Ut, Y2 = K~ Y1 -> Kft, W Xc = L^T Y2 -> hwx (fp32), and for
   // the K probe columns E Omega = L^T S~ Y1 -> hex (fp32); all stored
   // transposed ([column][row]).
   static hipError_t hutch_L(ifsvgp_ctx *c, int NC) {
     Opnd<T> a{LT(c, 0), c->Mp}, b{(const T *)c->Vt, c->Mp};
-    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, K_HI_M1};
+    Sched sc{cdiv(c->M, CH::BM), cdiv(NC, CH::BN), 0, 1, c->M, K_HI_M1};
     EpiStoreT<T> e{(T *)c->Ut, c->Mp, c->M, NC};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+    return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
   static hipError_t hutch_K(ifsvgp_ctx *c, int NC) {
     Opnd<T> a{(const T *)c->KtT, c->Mp}, b{(const T *)c->Ut, c->Mp};
-    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, 0};
+    Sched sc{cdiv(c->M, CH::BM), cdiv(NC, CH::BN), 0, 1, c->M, 0};
     EpiStoreT<T> e{(T *)c->Kft, c->Mp, c->M, NC};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+    return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
   static hipError_t hutch_Lt(ifsvgp_ctx *c, int NC) {
     Opnd<T> a{LtT(c, 0), c->Mp}, b{(const T *)c->Kft, c->Mp};
-    Sched sc{cdiv(c->M, CR::BM), cdiv(NC, CR::BN), 0, 1, c->M, K_LO_M0};
+    Sched sc{cdiv(c->M, CH::BM), cdiv(NC, CH::BN), 0, 1, c->M, K_LO_M0};
     EpiStoreT<float> e{c->hwx, c->Mp, c->M, NC};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+    return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
   static hipError_t hutch_E(ifsvgp_ctx *c, int B, int K) {
     Opnd<T> a{(const T *)c->LstT[0], c->Mp}, b{(const T *)c->Ut + (long)B * c->Mp, c->Mp};
-    Sched sc{cdiv(c->M, CR::BM), cdiv(K, CR::BN), 0, 1, c->M, K_LO_M0};
+    Sched sc{cdiv(c->M, CH::BM), cdiv(K, CH::BN), 0, 1, c->M, K_LO_M0};
     EpiStoreT<float> e{c->hex, c->Mp, c->M, K};
-    return launch_gemm<CR>(lnc(c), a, b, sc, e);
+    return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
