@@ -243,12 +243,14 @@ def rsvgp_bound_hutchinson(X, y, N, ell, sf2, noise_var, Z, m, s, L, Omega,
 
 
 def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
-                     n_gh=20, perturb=None):
+                     n_gh=20, perturb=None, Omega=None):
     """Gradient of rsvgp_bound w.r.t. xi at fixed T (adjoint of the literal form).
 
     Returns dict: ell (D), sf2, noise_var (Gaussian only, else 0), Z (MxD),
     m (M), s (M), plus the bound dict under key 'bound'.  perturb: as in
-    rsvgp_bound.
+    rsvgp_bound.  Omega (M x K probes, optional): the gradient of the
+    Hutchinson-estimated bound of rsvgp_bound_hutchinson instead, at fixed
+    probes.
     """
     X, y, ell, Z, m, s, L = _as64(X, y, ell, Z, m, s, L)
     sf2 = float(sf2)
@@ -269,13 +271,27 @@ def rsvgp_bound_grad(X, y, N, ell, sf2, noise_var, Z, m, s, L, lik="gaussian",
     Ka = Kuf @ alpha
     G_P = 0.5 * (np.outer(Ka, m) + np.outer(m, Ka))
     G_P -= (Kuf * beta[None, :]) @ Kuf.T
-    G_P += 0.5 * Kuu
+    if Omega is None:
+        G_P += 0.5 * Kuu
     KPm = Kuu @ Pm
     G_P -= 0.5 * (np.outer(KPm, m) + np.outer(m, KPm))
-    # dP = -T dK~ T (T fixed); plus -KL's -1/2 tr(T dK~)
-    G_Kt = -T @ G_P @ T - 0.5 * T
-    # direct K_uu dependence of -KL: +1/2 tr(P dK_uu) - 1/2 (Pm)^T dK_uu (Pm)
-    G_Kuu = 0.5 * P - 0.5 * np.outer(Pm, Pm) + G_Kt
+    if Omega is None:
+        # dP = -T dK~ T (T fixed); plus -KL's -1/2 tr(T dK~)
+        G_Kt = -T @ G_P @ T - 0.5 * T
+        # direct K_uu dependence of -KL: +1/2 tr(P dK_uu) - 1/2 (Pm)^T dK_uu (Pm)
+        G_Kuu = 0.5 * P - 0.5 * np.outer(Pm, Pm) + G_Kt
+    else:
+        # the estimated traces, with T_Om = L (Omega Omega^T / K) L^T:
+        # -KL's trace part = tr(K_uu T_Om) - 1/2 tr(K~ T K_uu T_Om) - 1/2 tr(K~ T_Om)
+        Om = np.asarray(Omega, np.float64)
+        TO = L @ (Om @ Om.T / Om.shape[1]) @ L.T
+        A1 = T @ Kuu @ TO     # d/dK~ of tr(K~ T K_uu T_Om) is A1^T (symmetrised below)
+        A2 = T @ bd["Kt"] @ TO  # d/dK_uu (direct) of the same trace is A2
+        G_Kt = -T @ G_P @ T - 0.25 * (A1 + A1.T) - 0.5 * TO
+        G_Kuu = TO - 0.25 * (A2 + A2.T) - 0.5 * np.outer(Pm, Pm) + G_Kt
+        bd = dict(bd, **{k: v for k, v in rsvgp_bound_hutchinson(
+            X, y, N, ell, sf2, noise_var, Z, m, s, L, Om, lik, n_gh, perturb).items()
+            if k in ("F", "data", "KL")})
     # K_uf: alpha_n (P m~)^T dk_n  - 2 beta_n (P k_n)^T dk_n
     G_Kuf = np.outer(Pm, alpha) - 2.0 * (P @ Kuf) * beta[None, :]
     # m~: sum_n alpha_n k_n^T P dm~  - (P K_uu P m~)^T dm~

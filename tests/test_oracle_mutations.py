@@ -34,6 +34,9 @@ MUTATIONS = [
     ("svgp.py", "trPK = 2.0 * trWu - trWWu", "trPK = trWu - trWWu"),
     ("svgp.py", "trWWu = np.sum(WO * WuO) / K", "trWWu = np.sum(WO * WO) / K"),
     ("svgp.py", "P = T @ (2.0 * np.eye(M) - Kt @ T)", "P = T @ (2.0 * np.eye(M) - Kuu @ T)"),
+    ("svgp.py", "G_Kuu = TO - 0.25 * (A2 + A2.T)", "G_Kuu = TO + 0.25 * (A2 + A2.T)"),
+    ("svgp.py", "A1 = T @ Kuu @ TO ", "A1 = T @ T @ TO "),
+    ("svgp.py", "- 0.25 * (A1 + A1.T) - 0.5 * TO", "- 0.25 * (A1 + A1.T) + 0.5 * TO"),
     ("quadrature.py", "* y / np.sqrt(2.0 * v)", "* y / np.sqrt(v)"),
     ("quadrature.py", "np.exp(log_phi - log_ndtr(z))", "np.exp(log_phi + log_ndtr(z))"),
     ("quadrature.py", "E = -0.5 * LOG_2PI - 0.5 * np.log(s2) - (r * r + v) / (2.0 * s2)",

@@ -590,3 +590,39 @@ def test_hutchinson_estimate_is_unbiased():
     A = W - 2.0 * Wu + 0.5 * (W @ Wu + Wu @ W)
     var_th = 2.0 * (np.sum(A * A) - np.sum(np.diag(A) ** 2)) / 4.0
     assert np.isclose(vals.var(ddof=1), var_th, rtol=0.1)
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_hutchinson_gradient_matches_central_differences(lik):
+    """The gradient of the estimated bound (fixed probes, fixed T) against
+    central differences of rsvgp_bound_hutchinson in every coordinate."""
+    p = small_problem(22, M=5, B=7, D=2, lik=lik)
+    L = random_L(5, 44, 0.4)
+    Om = _rng(6).choice([-1.0, 1.0], size=(5, 3))
+    g = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                              p["Z"], p["m"], p["s"], L, lik=lik, Omega=Om)
+
+    def F_of(key, x):
+        q = dict(p)
+        q[key] = x
+        return _hutch(q, L, Om)["F"]
+    for key in ("ell", "Z", "m", "s"):
+        x0 = np.asarray(p[key], np.float64)
+        fd = ref.central_fd(lambda x: F_of(key, x.reshape(x0.shape)), x0.ravel(),
+                            list(range(x0.size)), 1e-6)
+        assert np.allclose(np.ravel(g[key]), fd, rtol=1e-6, atol=1e-7), key
+    for key in ("sf2",) + (("noise_var",) if lik == "gaussian" else ()):
+        fd = (F_of(key, p[key] + 1e-6) - F_of(key, p[key] - 1e-6)) / 2e-6
+        assert np.isclose(g[key], fd, rtol=1e-6, atol=1e-7), key
+    assert np.isclose(g["bound"]["F"], _hutch(p, L, Om)["F"], rtol=1e-14)
+
+
+def test_hutchinson_gradient_with_scaled_unit_probes_is_the_exact_gradient():
+    p = small_problem(23)
+    L = random_L(6, 45)
+    ge = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                               p["Z"], p["m"], p["s"], L)
+    gh = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                               p["Z"], p["m"], p["s"], L, Omega=np.sqrt(6.0) * np.eye(6))
+    for k in ("ell", "sf2", "noise_var", "Z", "m", "s"):
+        assert np.allclose(gh[k], ge[k], rtol=1e-10, atol=1e-12), k
