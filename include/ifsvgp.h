@@ -207,13 +207,33 @@ int ifsvgp_natgrad_gap(ifsvgp_ctx *ctx, const float *X, int B, const float *Z,
  * in row k (draw them with E[w w^T] = I, e.g. Rademacher; the caller's draw is
  * used as given).  Requires round_up(B, 64) + round_up(K + 1, 64) <=
  * round_up(B_max, 128) (IFSVGP_EINVAL otherwise).  out_terms as for
- * ifsvgp_bound, with the NG residual entry 0.  Forward only: the call reuses
- * the workspace, so a following ifsvgp_bound_bwd needs a new ifsvgp_bound. */
+ * ifsvgp_bound, with the NG residual entry 0.  Its gradient comes from
+ * ifsvgp_bound_hutch_bwd; ifsvgp_bound_bwd after it needs a new ifsvgp_bound
+ * (IFSVGP_ESTATE otherwise). */
 int ifsvgp_bound_hutch(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N_total,
                        const float *ell, const float *sf2, const float *noise_var,
                        const float *Z, const float *m_tilde, const float *s_tilde,
                        const float *L, const float *Omega_t, int K, double *out_bound,
                        double *out_terms);
+
+/* Gradient of the preceding ifsvgp_bound_hutch's estimate F_K (Section 3.4)
+ * with the probes and T = L L^T held fixed, with respect to ell, sf2,
+ * noise_var, Z and m_tilde (outputs as in ifsvgp_bound_bwd, each may be
+ * NULL; grad_scale likewise).  The trace part of the adjoint of the
+ * cubic traces becomes, in L-space, (1/4K) [Omega (Omega - G)^T + its
+ * transpose] with G = (W + Wu) Omega; the data side is that of the exact
+ * backward.  Omega_t, K, B and the inputs must be those of the forward
+ * (IFSVGP_ESTATE when the last forward on ctx was not a Hutchinson bound
+ * with this B and K; the probes themselves are not compared).  The
+ * gradient with respect to s_tilde is not offered: g_s must be NULL
+ * (IFSVGP_EINVAL otherwise).  The backward forms L C and L C L^T as the
+ * exact backward does (two M x M x M products). */
+int ifsvgp_bound_hutch_bwd(ifsvgp_ctx *ctx, const float *X, const float *y, int B,
+                           double N_total, const float *ell, const float *sf2,
+                           const float *noise_var, const float *Z, const float *m_tilde,
+                           const float *s_tilde, const float *L, const float *Omega_t, int K,
+                           const double *grad_scale, float *g_ell, float *g_sf2,
+                           float *g_noise_var, float *g_Z, float *g_m, float *g_s);
 
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is

@@ -100,10 +100,13 @@ struct ifsvgp_ctx {
   double *tp_gap;  // per-tile partials of the variance gap [nb128][cdiv(Bp, 64)]
   float *hwx, *hex;  // Hutchinson bound: W Xc and E Omega (fp32, [Bp][Mp])
   double *hp;        // Hutchinson bound: per-probe sums [Bp][4]
+  void *hom, *hdm;   // its backward: Omega and Omega - G, [Mp][Bp] operand type
+  float *hx1, *hx2;  // its backward: vectors [Mp]
+  int fwd_K;         // probes of the last Hutchinson forward
   double *gh;
   int *flag, *counters;
   int *ngskip;  // stop flag of an adaptive NG loop
-  // last forward state for the backward
+  // last forward state for the backward: 1 exact bound, 2 Hutchinson bound
   int fwd_valid, fwd_B;
   int cur;  // which L32/LT/LtT slot holds the bound's L
   // timing
@@ -417,6 +420,10 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->hwx, MB);
   ALLOC(c->hex, MB);
   ALLOC(c->hp, (size_t)4 * Bp);
+  ALLOCB(c->hom, MB * os);
+  ALLOCB(c->hdm, MB * os);
+  ALLOC(c->hx1, Mp);
+  ALLOC(c->hx2, Mp);
   ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
   ALLOC(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
   ALLOC(c->ell_part, (size_t)(M + B_max + 64) * D);
@@ -644,6 +651,13 @@ struct Ops {
     Opnd<T> a{(const T *)c->LstT[0], c->Mp}, b{(const T *)c->Ut + (long)B * c->Mp, c->Mp};
     Sched sc{cdiv(c->M, CH::BM), cdiv(K, CH::BN), 0, 1, c->M, K_LO_M0};
     EpiStoreT<float> e{c->hex, c->Mp, c->M, K};
+    return launch_gemm<CH>(lnc(c), a, b, sc, e);
+  }
+  // Hutchinson backward: Omega (Omega - G)^T (M x M, fp32) into Q32
+  static hipError_t hutch_C(ifsvgp_ctx *c, int K) {
+    Opnd<T> a{(const T *)c->hom, c->Bp}, b{(const T *)c->hdm, c->Bp};
+    Sched sc{nb(c), nb(c), 0, 1, K, 0};
+    EpiStore<float> e{c->Q32, c->Mp, c->M, c->M, 0, 0};
     return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
   // U = Q V -> Ut, sigma^2 partials
@@ -1076,7 +1090,7 @@ static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
   HIPCK(Ops<T>::hutch_K(c, NC));
   HIPCK(Ops<T>::hutch_Lt(c, NC));
   HIPCK(Ops<T>::hutch_E(c, B, K));
-  HutchArgs h{c->Vt, Mp, c->hwx, c->hex, Omt, c->va, M, B, K, c->var_part, c->mu_part, c->hp,
+  HutchArgs h{c->Vt, Mp, c->Ut, c->hwx, c->hex, Omt, c->va, M, B, K, c->var_part, c->mu_part, c->hp,
               c->vb};
   hipLaunchKernelGGL((k_hutch_rows<T>), dim3(cdiv(NC, NTB / 64)), dim3(NTB), 0, c->st, h);
   hipLaunchKernelGGL(k_hutch_final, dim3(1), dim3(NTB), 0, c->st, (const double *)c->hp, K,
@@ -1103,6 +1117,78 @@ static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
             c->tp_gram, 1, c->vec_part, 1,
             c->scal, M, c->flag, c->counters + CNT_LIK};
   hipLaunchKernelGGL(k_lik, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
+  HIPCK(hipGetLastError());
+  c->fwd_valid = 2;
+  c->fwd_B = B;
+  c->fwd_K = K;
+  return IFSVGP_OK;
+}
+
+// Backward of the Hutchinson bound at the forward's probes: the data side as
+// in the exact backward (R = L U with U = 2V - W V from the forward, the
+// batch product of V diag(sqrt(-beta))), the trace part of C from
+// Omega (Omega - G)^T, G = 2 W Omega - E Omega (W Omega and E Omega kept by
+// the forward), then G_uu = L C L^T and the reductions; t2 = Q (V alpha - Wu b)
+// by matrix-vector products, Q not being formed.  The cubic products
+// L C and (L C) L^T remain.
+template <typename T>
+static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Omt, int K,
+                             bool want_gm) {
+  using TW = typename Ops<T>::TW;
+  c->ev_next = 0;
+  c->side_open = false;
+  int r = latch(c, ca);
+  if (r) return r;
+  const int M = c->M, D = c->D;
+  const long Mp = c->Mp;
+  HIPCK(fork_side(c));
+  {
+    OnSide side(c);
+    Timed t(c, KK_R);
+    HIPCK(Ops<T>::gemm_R(c, 0, B));
+  }
+  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+                     (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa);
+  HIPCK(Ops<T>::syrk(c, B));
+  hipLaunchKernelGGL((k_hutch_trans<T>), dim3(grid1((long)c->Mp * c->Bp)), dim3(NTB), 0, c->st,
+                     Omt, (const float *)c->hwx, (const float *)c->hex, B, K, M, Mp, c->Mp,
+                     c->Bp, (long)c->Bp, (T *)c->hom, (T *)c->hdm);
+  HIPCK(Ops<T>::hutch_C(c, K));
+  hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0, c->st,
+                     (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
+                     (const float *)nullptr, (const float *)nullptr, (const float *)c->va,
+                     (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M, Mp,
+                     (TW *)c->Cm, (const float *)c->Q32, (float)(0.25 / K));
+  HIPCK(Ops<T>::gemm_Y2(c, 0));
+  HIPCK(Ops<T>::gemm_Guu(c, 0, nullptr));
+  // W x = L^T K~ L x for x = V alpha - Wu b
+  const dim3 gv(cdiv(M, NTB / 64));
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->L32[0], Mp, M, M,
+                     (const float *)c->vVa, (const float *)c->vWub, 1, (const double *)nullptr,
+                     c->hx1);
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->Kt, Mp, M, M,
+                     (const float *)c->hx1, (const float *)nullptr, 0, (const double *)nullptr,
+                     c->hx2);
+  hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->Lt32[0], Mp, M, M,
+                     (const float *)c->hx2, (const float *)nullptr, 0, (const double *)nullptr,
+                     c->hx1);
+  hipLaunchKernelGGL(k_hutch_t2, dim3(cdiv(M, NTB)), dim3(NTB), 0, c->st, c->vt2,
+                     (const float *)c->vVa, (const float *)c->vWub, (const float *)c->hx1, M);
+  HIPCK(join_side(c));
+  const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
+  const int R = NTB / D;
+  const int rb = cdiv(M, R), cb = cdiv(B, R);
+  GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
+             c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
+             c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
+             c->lik_part, cdiv(c->Bp, NTB),
+             nullptr, c->vVa, c->vWub, Mp, c->vt2, c->ell_part, rb, cb,
+             nullptr, nullptr, (long)Mp, c->vLb, c->sP};
+  hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
+  const int mrows = want_gm ? cdiv(M, NTB / 64) : 0;
+  hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
+                     (const float *)c->L32[0], mrows);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
@@ -1262,7 +1348,7 @@ extern "C" int ifsvgp_bound_bwd(ifsvgp_ctx *c, const float *X, const float *y, i
                                 float *g_noise, float *g_Z, float *g_m, float *g_s) {
   int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
   if (r) return r;
-  if (!c->fwd_valid || c->fwd_B != B) return IFSVGP_ESTATE;
+  if (c->fwd_valid != 1 || c->fwd_B != B) return IFSVGP_ESTATE;
   CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
   a.grad_scale = grad_scale;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
@@ -1352,6 +1438,23 @@ extern "C" int ifsvgp_bound_hutch(ifsvgp_ctx *c, const float *X, const float *y,
   a.out_bound = out_bound;
   a.out_terms = out_terms;
   PREC_DISPATCH(enqueue_hutch, c, a, B, Omega_t, K)
+}
+
+extern "C" int ifsvgp_bound_hutch_bwd(ifsvgp_ctx *c, const float *X, const float *y, int B,
+                                      double N, const float *ell, const float *sf2,
+                                      const float *noise, const float *Z, const float *m,
+                                      const float *s, const float *L, const float *Omega_t,
+                                      int K, const double *grad_scale, float *g_ell,
+                                      float *g_sf2, float *g_noise, float *g_Z, float *g_m,
+                                      float *g_s) {
+  int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
+  if (r) return r;
+  if (!Omega_t || K < 1 || g_s) return IFSVGP_EINVAL;
+  if (c->fwd_valid != 2 || c->fwd_B != B || c->fwd_K != K) return IFSVGP_ESTATE;
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, (float *)L, nullptr, 0);
+  a.grad_scale = grad_scale;
+  a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m;
+  PREC_DISPATCH(enqueue_hutch_bwd, c, a, B, Omega_t, K, g_m != nullptr)
 }
 
 extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {

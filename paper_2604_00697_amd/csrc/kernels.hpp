@@ -625,7 +625,8 @@ __global__ void k_predict_sum(const double *part, int nparts, double *scal, int 
 // Bound evaluation with the cubic traces replaced by probe estimates.  With
 // Xc = [V | Omega | a] (columns: the batch, the K probes, a = L^T m~) and
 // WX = L^T K~ L Xc, EX = L^T S~ L Omega (fp32, stored transposed [column][row]):
-//   U = 2V - W V gives sigma^2_n = sf2 - sum_i V_in U_in and mu_n = a^T U_n,
+//   U = 2V - W V gives sigma^2_n = sf2 - sum_i V_in U_in and mu_n = a^T U_n
+//   (U kept for the backward's R = L U),
 //   per probe w: w^T W w, w^T E w, |W w|^2, (W w)^T (E w) for the estimates of
 //   tr W, tr Wu = tr(W - E) and tr(W Wu), and b = 2a - W a.
 // The probes as operands: rows [B, B + K) of the batch operand take Omega^T,
@@ -643,6 +644,7 @@ __global__ void k_hutch_fill(T *Vt, long ld, int B, int K, const float *Omt, con
 
 struct HutchArgs {
   const void *Vt; long ld;  // batch operand rows (type T) [n][i]
+  void *Ut;                 // rows [0, B) get U = 2V - W V (type T, zero beyond M)
   const float *wx, *ex;     // [B + K + 1][ld], [K][ld]
   const float *Omt;         // caller's probes [K][M]
   const float *a;           // L^T m~
@@ -660,10 +662,16 @@ __global__ void k_hutch_rows(HutchArgs h) {
   const float *wx = h.wx + (long)row * h.ld;
   if (row < h.B) {
     const T *vt = (const T *)h.Vt + (long)row * h.ld;
+    T *ut = (T *)h.Ut + (long)row * h.ld;
     float sv = 0.f, sm = 0.f;
-    for (int i = lane; i < h.M; i += 64) {
+    for (int i = lane; i < (int)h.ld; i += 64) {
+      if (i >= h.M) {
+        ut[i] = from_f32<T>(0.f);
+        continue;
+      }
       const float v = to_f32(vt[i]);
       const float u = 2.f * v - wx[i];
+      ut[i] = from_f32<T>(u);
       sv = fmaf(v, u, sv);
       sm = fmaf(h.a[i], u, sm);
     }
@@ -716,6 +724,30 @@ __global__ void k_hutch_final(const double *hp, int K, double *gram_part) {
   }
 }
 
+// The backward's probe operands, [M][K] in the operand type (zero beyond M
+// and K): Omega and Omega - G with G = (W + Wu) Omega = 2 W Omega - E Omega.
+template <typename T>
+__global__ void k_hutch_trans(const float *Omt, const float *wx, const float *ex, int B, int K,
+                              int M, long ldx, int Mp, int Kp, long ldk, T *Om, T *Dm) {
+  const long n = (long)Mp * Kp;
+  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
+    const int i = (int)(e / Kp), k = (int)(e % Kp);
+    float o = 0.f, d = 0.f;
+    if (i < M && k < K) {
+      o = Omt[(long)k * M + i];
+      d = o - (2.f * wx[(long)(B + k) * ldx + i] - ex[(long)k * ldx + i]);
+    }
+    Om[(long)i * ldk + k] = from_f32<T>(o);
+    Dm[(long)i * ldk + k] = from_f32<T>(d);
+  }
+}
+
+// t2 = Q x = 2x - W x for x = V alpha - Wu b, given W x = L^T K~ L x
+__global__ void k_hutch_t2(float *t2, const float *Va, const float *Wub, const float *Wx, int M) {
+  const int i = blockIdx.x * NTB + threadIdx.x;
+  if (i < M) t2[i] = 2.f * (Va[i] - Wub[i]) - Wx[i];
+}
+
 // y -= s~ o x  (K~ L b -> K_uu L b)
 __global__ void k_hutch_sub_diag(float *y, const float *sP, const float *x, int M) {
   const int i = blockIdx.x * NTB + threadIdx.x;
@@ -753,7 +785,10 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
                                                     long split_stride, const float *Wu,
                                                     const float *Q, const float *a, const float *b,
                                                     const float *Wub, const float *Va, int M,
-                                                    long ld, TC *Cm) {
+                                                    long ld, TC *Cm, const float *Ctr = nullptr,
+                                                    float ctr_scale = 0.f) {
+  // Ctr (the Hutchinson bound's backward): the trace part -1/2 (Wu + I) + 1/2 Q
+  // is replaced by ctr_scale (Ctr + Ctr^T), Ctr = Omega (Omega - G)^T (Wu, Q unread)
   // one thread per 4 consecutive columns of a row; the padded columns
   // (j >= M, inputs zero there) come out as zeros
   const int cpr = (M + 3) / 4;
@@ -764,16 +799,24 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
     f32x4 ys = *(const f32x4 *)(Ys + ij);
 #pragma unroll 4
     for (int s = 1; s < nsplit; ++s) ys += *(const f32x4 *)(Ys + s * split_stride + ij);
-    const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
     const f32x4 aj = *(const f32x4 *)(a + j0), bj = *(const f32x4 *)(b + j0);
     const f32x4 wj = *(const f32x4 *)(Wub + j0), vj = *(const f32x4 *)(Va + j0);
     const float ai = a[i], bi = b[i], wi = Wub[i], vi = Va[i];
+    f32x4 tr;
+    if (Ctr) {
+      const f32x4 c0 = *(const f32x4 *)(Ctr + ij);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tr[u] = ctr_scale * (c0[u] + Ctr[(long)(j0 + u) * ld + i]);
+    } else {
+      const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tr[u] = -0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f)) + 0.5f * q[u];
+    }
     TC out[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] -
-                      0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f) - wi * aj[u] - ai * wj[u]) +
-                      0.5f * (q[u] - bi * bj[u]);
+      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] +
+                      0.5f * (wi * aj[u] + ai * wj[u]) + tr[u] - 0.5f * bi * bj[u];
       out[u] = from_f32<TC>(c);
     }
     if constexpr (sizeof(TC) == 4) {

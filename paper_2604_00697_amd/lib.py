@@ -44,6 +44,8 @@ _SIGS = {
                                 ctypes.c_float, _P, _P]),
     "ifsvgp_bound_hutch": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
                                 _P, _P]),
+    "ifsvgp_bound_hutch_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    _I, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
                               _P, _P, _P, _P, _P, _P]),
@@ -270,6 +272,24 @@ class Context:
             _ptr(out, (1,), "out", torch.float64),
             _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound_hutch")
         return out, terms
+
+    def bound_hutch_bwd(self, X, y, N, ell, sf2, noise, Z, m, s, L, Omega_t, grad_scale=None,
+                        want=("ell", "sf2", "noise_var", "Z", "m")):
+        """Gradients of the preceding bound_hutch's estimate at its probes
+        Omega_t (fp32 [K, M]); dict of fp32 tensors (no "s")."""
+        import torch
+        if "s" in want:
+            raise ValueError("bound_hutch_bwd offers no gradient with respect to s~")
+        a = self._inputs(X, y, ell, sf2, noise, Z, m, s, L)
+        K = Omega_t.shape[0]
+        g = self._grad_buffers(want)
+        self._stream()
+        gs = None if grad_scale is None else _ptr(grad_scale, (1,), "grad_scale", torch.float64)
+        _check(self._lib.ifsvgp_bound_hutch_bwd(
+            self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
+            a["m"], a["s"], a["L"], _ptr(Omega_t, (K, self.M), "Omega_t"), K, gs,
+            *self._grad_ptrs(g)), "ifsvgp_bound_hutch_bwd")
+        return g
 
     def bound_bwd(self, X, y, N, ell, sf2, noise, Z, m, s, L, grad_scale=None,
                   want=("ell", "sf2", "noise_var", "Z", "m")):

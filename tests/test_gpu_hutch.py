@@ -2,7 +2,11 @@
 estimates, Section 3.4) against the float64 oracle
 (oracle.svgp.rsvgp_bound_hutchinson) on the same probes: F, the data and KL
 terms and the summed variance.  With the M probes sqrt(M) e_i the estimate is
-the exact bound, which also ties the entry point to ifsvgp_bound.
+the exact bound, which also ties the entry point to ifsvgp_bound.  The
+backward (ifsvgp_bound_hutch_bwd) is checked against the oracle's gradient of
+the same estimate at the same probes (oracle.svgp.rsvgp_bound_grad with
+Omega), under the gradient gate of test_gpu_parity.py (base, spread and the
+summation condition of each gradient block).
 
 Gates as in test_gpu_parity.py: err <= max(base, mult * spread), spread being
 the oracle's own change when its inputs, the probes and the formed K_uu, K_uf
@@ -14,7 +18,7 @@ import numpy as np
 import pytest
 
 from oracle import svgp
-from test_gpu_parity import make_case, to_dev
+from test_gpu_parity import make_case, to_dev, gate
 
 pytestmark = pytest.mark.gpu
 
@@ -124,3 +128,114 @@ def test_hutchinson_bound_argument_errors(require_gpu):
     assert e.value.code == lib.ESTATE
     torch.cuda.synchronize()
     assert ctx.status() == 0
+
+
+HGRADS = ("ell", "sf2", "noise_var", "Z", "m")
+
+
+def _grad_oracle(c, Om, perturb=None, scale=None):
+    q = {k: np.asarray(c[k], np.float64) for k in ("X", "Z", "ell", "m", "s", "L")}
+    if scale:
+        q = {k: v * scale[k] for k, v in q.items()}
+    om = np.asarray(Om, np.float64) * (scale["Om"] if scale else 1.0)
+    r = svgp.rsvgp_bound_grad(q["X"], c["y"], c["N"], q["ell"], float(c["sf2"]),
+                              float(c["noise"]), q["Z"], q["m"], q["s"], q["L"], lik=c["lik"],
+                              perturb=perturb, Omega=om.T)
+    keys = [k for k in HGRADS if k != "noise_var" or c["lik"] == "gaussian"]
+    out = {"grad_" + k: np.asarray(r[k], np.float64) for k in keys}
+    cond = {"grad_" + k: np.linalg.norm(np.ravel(v)) / max(np.linalg.norm(np.ravel(r[k])), 1e-300)
+            for k, v in r["abs_terms"].items() if k in keys}
+    return out, cond
+
+
+def _grad_spread(c, Om, eps, nsamp=3, seed=5):
+    base, cond = _grad_oracle(c, Om)
+    g = np.random.Generator(np.random.PCG64(seed))
+    M, B = c["Z"].shape[0], c["X"].shape[0]
+    sp = {k: 0.0 for k in base}
+    for _ in range(nsamp):
+        scale = {k: 1.0 + eps * g.standard_normal(np.shape(c[k])) for k in ("X", "Z", "ell", "m", "s", "L")}
+        scale["Om"] = 1.0 + eps * g.standard_normal(np.shape(Om))
+        du = eps * g.standard_normal((M, M))
+        pert = dict(Kuu=np.tril(du) + np.tril(du, -1).T, Kuf=eps * g.standard_normal((M, B)))
+        out, _ = _grad_oracle(c, Om, pert, scale)
+        for k in base:
+            a, b = np.ravel(out[k]), np.ravel(base[k])
+            sp[k] = max(sp[k], float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+    return base, sp, cond
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hutchinson_gradient_parity(require_gpu, name):
+    from paper_2604_00697_amd.lib import Context
+    prec, lik, M, B, D, Bmax, K, kind = CASES[name]
+    seed = zlib.crc32(name.encode()) % 1000
+    c = make_case(M, B, D, seed=seed, lik=lik, s_range=(0.05, 0.1))
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    Om = (np.sqrt(M) * np.eye(M) if kind == "unit"
+          else g.choice([-1.0, 1.0], size=(K, M))).astype(np.float32)
+    print(f"HUTCH-BWD case {name} prec={prec} M={M} B={B} K={Om.shape[0]}", flush=True)
+    ctx = Context(M, Bmax, D, prec, lik)
+    d = to_dev(c)
+    Omd = torch.from_numpy(Om).to(d["X"].device)
+    want = [k for k in HGRADS if k != "noise_var" or lik == "gaussian"]
+    ctx.bound_hutch(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"],
+                    d["s"], d["L"], Omd)
+    gg = ctx.bound_hutch_bwd(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"],
+                             d["m"], d["s"], d["L"], Omd, want=want)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    gpu = {"grad_" + k: v.double().cpu().numpy() for k, v in gg.items()}
+    for k, v in gpu.items():
+        assert np.all(np.isfinite(v)), k
+    ref, sp, cond = _grad_spread(c, Om, EPS[prec], nsamp=2 if M > 150 else 3)
+    gate(name, prec, gpu, ref, sp, cond)
+
+
+def test_hutchinson_backward_state_and_scale(require_gpu):
+    from paper_2604_00697_amd import lib
+    from paper_2604_00697_amd.lib import Context, IFSVGPError
+    M, B, K = 60, 70, 16
+    c = make_case(M, B, 3, seed=21, s_range=(0.05, 0.1))
+    ctx = Context(M, 256, 3, "fp32")
+    d = to_dev(c)
+    dev = d["X"].device
+    g = np.random.Generator(np.random.PCG64(22))
+    Omd = torch.from_numpy(g.choice([-1.0, 1.0], size=(K, M)).astype(np.float32)).to(dev)
+    args = (d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["m"], d["s"], d["L"])
+    # no Hutchinson forward yet, then an exact forward: both refused
+    for fwd in (None, "exact"):
+        if fwd:
+            ctx.bound(*args)
+        with pytest.raises(IFSVGPError) as e:
+            ctx.bound_hutch_bwd(*args, Omd)
+        assert e.value.code == lib.ESTATE
+    ctx.bound_hutch(*args, Omd)
+    # another probe count than the forward's
+    with pytest.raises(IFSVGPError) as e:
+        ctx.bound_hutch_bwd(*args, Omd[:K - 1].contiguous())
+    assert e.value.code == lib.ESTATE
+    with pytest.raises(ValueError):
+        ctx.bound_hutch_bwd(*args, Omd, want=("ell", "s"))
+    # through the C-ABI: g_s is refused
+    gs = torch.empty(M, device=dev)
+    h = ctx._h
+    assert ctx._lib.ifsvgp_bound_hutch_bwd(
+        h, d["X"].data_ptr(), d["y"].data_ptr(), B, c["N"], d["ell"].data_ptr(),
+        d["sf2"].data_ptr(), d["noise"].data_ptr(), d["Z"].data_ptr(), d["m"].data_ptr(),
+        d["s"].data_ptr(), d["L"].data_ptr(), Omd.data_ptr(), K, None, None, None, None, None,
+        None, gs.data_ptr()) == lib.EINVAL
+    # repeated backward calls agree, and grad_scale multiplies exactly
+    g1 = ctx.bound_hutch_bwd(*args, Omd)
+    scale = torch.tensor([-2.0], dtype=torch.float64, device=dev)
+    g2 = ctx.bound_hutch_bwd(*args, Omd, grad_scale=scale)
+    g3 = ctx.bound_hutch_bwd(*args, Omd)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for k in g1:
+        assert torch.equal(g1[k], g3[k]), k
+        assert torch.equal(g2[k], -2.0 * g1[k]), k
+    # the exact backward still needs its own forward
+    with pytest.raises(IFSVGPError) as e:
+        ctx.bound_bwd(*args)
+    assert e.value.code == lib.ESTATE
