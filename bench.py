@@ -253,7 +253,8 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
                        setup=L0.clone)
         out["natgrad_gap_rule"] = {"steps": 3, "B": w.B, "ms_per_step": round(ms_gap / 3, 4)}
     # the paper's Hutchinson setting (Appendix on approximate bound evaluation):
-    # B = 100, K = 256 probes; exact bound vs the estimate on the same inputs
+    # B = 100, K = 256 probes; exact bound vs the estimate on the same inputs,
+    # alone and with the gradient
     # (D = 8 synthetic regression data), at the paper's M = 2000 and at
     # M = 8192, where the cubic traces outweigh the launches
     if w.lik == "gaussian":
@@ -274,9 +275,15 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
                     du["s"], du["L"])
             ms_ex = timed(lambda _: cu.bound(*args))
             ms_hu = timed(lambda _: cu.bound_hutch(*args, om))
+            # bound and gradient (ell, sf2, noise, Z, m~) at fixed L
+            ms_exg = timed(lambda _: (cu.bound(*args), cu.bound_bwd(*args)))
+            ms_hug = timed(lambda _: (cu.bound_hutch(*args, om), cu.bound_hutch_bwd(*args, om)))
             out["hutchinson_bound"].append(
                 {"M": wu.M, "B": wu.B, "K": Kp, "exact_ms": round(ms_ex, 4),
-                 "hutchinson_ms": round(ms_hu, 4), "speedup": round(ms_ex / ms_hu, 3)})
+                 "hutchinson_ms": round(ms_hu, 4), "speedup": round(ms_ex / ms_hu, 3),
+                 "exact_with_grad_ms": round(ms_exg, 4),
+                 "hutchinson_with_grad_ms": round(ms_hug, 4),
+                 "speedup_with_grad": round(ms_exg / ms_hug, 3)})
             torch.cuda.synchronize()
             if cu.status() != 0:
                 raise RuntimeError("device status flag set in the Hutchinson timing")

@@ -226,8 +226,9 @@ int ifsvgp_bound_hutch(ifsvgp_ctx *ctx, const float *X, const float *y, int B, d
  * (IFSVGP_ESTATE when the last forward on ctx was not a Hutchinson bound
  * with this B and K; the probes themselves are not compared).  The
  * gradient with respect to s_tilde is not offered: g_s must be NULL
- * (IFSVGP_EINVAL otherwise).  The backward forms L C and L C L^T as the
- * exact backward does (two M x M x M products). */
+ * (IFSVGP_EINVAL otherwise).  No M x M x M product is formed: the adjoint
+ * C of the bound with respect to L^T K~ L is a rank-(B + 2K + 3) form
+ * X S X^T, so L C L^T = (L X) S (L X)^T costs O((B + K) M^2). */
 int ifsvgp_bound_hutch_bwd(ifsvgp_ctx *ctx, const float *X, const float *y, int B,
                            double N_total, const float *ell, const float *sf2,
                            const float *noise_var, const float *Z, const float *m_tilde,

@@ -100,7 +100,8 @@ struct ifsvgp_ctx {
   double *tp_gap;  // per-tile partials of the variance gap [nb128][cdiv(Bp, 64)]
   float *hwx, *hex;  // Hutchinson bound: W Xc and E Omega (fp32, [Bp][Mp])
   double *hp;        // Hutchinson bound: per-probe sums [Bp][4]
-  void *hom, *hdm;   // its backward: Omega and Omega - G, [Mp][Bp] operand type
+  void *hxt;         // its backward: X^T of C = X S X^T, [2 Bp][Mp] operand type
+  void *hy1, *hy2;   // L X and L X S, [Mp][2 Bp] wide type
   float *hx1, *hx2;  // its backward: vectors [Mp]
   int fwd_K;         // probes of the last Hutchinson forward
   double *gh;
@@ -420,8 +421,9 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->hwx, MB);
   ALLOC(c->hex, MB);
   ALLOC(c->hp, (size_t)4 * Bp);
-  ALLOCB(c->hom, MB * os);
-  ALLOCB(c->hdm, MB * os);
+  ALLOCB(c->hxt, 2 * MB * os);
+  ALLOCB(c->hy1, 2 * MB * ws);
+  ALLOCB(c->hy2, 2 * MB * ws);
   ALLOC(c->hx1, Mp);
   ALLOC(c->hx2, Mp);
   ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
@@ -653,12 +655,21 @@ struct Ops {
     EpiStoreT<float> e{c->hex, c->Mp, c->M, K};
     return launch_gemm<CH>(lnc(c), a, b, sc, e);
   }
-  // Hutchinson backward: Omega (Omega - G)^T (M x M, fp32) into Q32
-  static hipError_t hutch_C(ifsvgp_ctx *c, int K) {
-    Opnd<T> a{(const T *)c->hom, c->Bp}, b{(const T *)c->hdm, c->Bp};
-    Sched sc{nb(c), nb(c), 0, 1, K, 0};
-    EpiStore<float> e{c->Q32, c->Mp, c->M, c->M, 0, 0};
+  // Hutchinson backward: Y1 = L X for the r columns of X (k < m0+BM), then
+  // G_uu = Y1 (Y1 S)^T on lower tiles (k < r) -> H_uu reductions
+  static long ldr(ifsvgp_ctx *c) { return 2 * (long)c->Bp; }
+  static hipError_t hutch_LX(ifsvgp_ctx *c, int r) {
+    Opnd<T> a{LT(c, 0), c->Mp}, b{(const T *)c->hxt, c->Mp};
+    Sched sc{cdiv(c->M, CH::BM), cdiv(r, CH::BN), 0, 1, c->M, K_HI_M1};
+    EpiStore<TW> e{(TW *)c->hy1, ldr(c), c->M, r, 0, 0};
     return launch_gemm<CH>(lnc(c), a, b, sc, e);
+  }
+  static hipError_t hutch_Guu(ifsvgp_ctx *c, int r) {
+    const int D = c->D;
+    Opnd<TW> a{(const TW *)c->hy1, ldr(c)}, b{(const TW *)c->hy2, ldr(c)};
+    Sched sc{nb(c), nb(c), 1, 1, r, 0};
+    EpiGradUu e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, nullptr};
+    return launch_gemm<CSW>(lnc(c), a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
   // U = Q V -> Ut, sigma^2 partials
   static hipError_t gemm_U(ifsvgp_ctx *c, int B) {
@@ -1124,13 +1135,13 @@ static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
   return IFSVGP_OK;
 }
 
-// Backward of the Hutchinson bound at the forward's probes: the data side as
-// in the exact backward (R = L U with U = 2V - W V from the forward, the
-// batch product of V diag(sqrt(-beta))), the trace part of C from
-// Omega (Omega - G)^T, G = 2 W Omega - E Omega (W Omega and E Omega kept by
-// the forward), then G_uu = L C L^T and the reductions; t2 = Q (V alpha - Wu b)
-// by matrix-vector products, Q not being formed.  The cubic products
-// L C and (L C) L^T remain.
+// Backward of the Hutchinson bound at the forward's probes, with no
+// M x M x M product: the data side's R = L U as in the exact backward (U =
+// 2V - W V kept by the forward), and C = X S X^T in low-rank form (columns
+// V, Omega, Omega - G, x = V alpha - Wu b, a, b; G = 2 W Omega - E Omega
+// from the forward's W Omega and E Omega), so G_uu = L C L^T = Y1 (Y1 S)^T
+// with Y1 = L X: two products of inner size r = B + 2K + 3; t2 = Q x by
+// matrix-vector products, Q not being formed.
 template <typename T>
 static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Omt, int K,
                              bool want_gm) {
@@ -1139,7 +1150,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
   c->side_open = false;
   int r = latch(c, ca);
   if (r) return r;
-  const int M = c->M, D = c->D;
+  const int M = c->M, D = c->D, nr = B + 2 * K + 3;
   const long Mp = c->Mp;
   HIPCK(fork_side(c));
   {
@@ -1150,18 +1161,15 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
   hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
                      (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                      (const float *)c->sqnb, (T *)c->Vs, c->vVa);
-  HIPCK(Ops<T>::syrk(c, B));
-  hipLaunchKernelGGL((k_hutch_trans<T>), dim3(grid1((long)c->Mp * c->Bp)), dim3(NTB), 0, c->st,
-                     Omt, (const float *)c->hwx, (const float *)c->hex, B, K, M, Mp, c->Mp,
-                     c->Bp, (long)c->Bp, (T *)c->hom, (T *)c->hdm);
-  HIPCK(Ops<T>::hutch_C(c, K));
-  hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0, c->st,
-                     (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
-                     (const float *)nullptr, (const float *)nullptr, (const float *)c->va,
-                     (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M, Mp,
-                     (TW *)c->Cm, (const float *)c->Q32, (float)(0.25 / K));
-  HIPCK(Ops<T>::gemm_Y2(c, 0));
-  HIPCK(Ops<T>::gemm_Guu(c, 0, nullptr));
+  hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), rup(nr, 64)), dim3(NTB), 0, c->st,
+                     (const T *)c->Vt, Omt, (const float *)c->hwx, (const float *)c->hex,
+                     (const float *)c->vVa, (const float *)c->vWub, (const float *)c->va,
+                     (const float *)c->vb, B, K, M, c->Mp, (T *)c->hxt);
+  HIPCK(Ops<T>::hutch_LX(c, nr));
+  hipLaunchKernelGGL((k_hutch_mix<TW>), dim3(grid1((long)c->Mp * Ops<T>::ldr(c))), dim3(NTB), 0,
+                     c->st, (const TW *)c->hy1, (TW *)c->hy2, Ops<T>::ldr(c), M, c->Mp, B, K,
+                     (const float *)c->beta, (float)(0.25 / K));
+  HIPCK(Ops<T>::hutch_Guu(c, nr));
   // W x = L^T K~ L x for x = V alpha - Wu b
   const dim3 gv(cdiv(M, NTB / 64));
   hipLaunchKernelGGL(k_gemv_rows, gv, dim3(NTB), 0, c->st, (const float *)c->L32[0], Mp, M, M,

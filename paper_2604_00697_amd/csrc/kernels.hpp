@@ -724,21 +724,63 @@ __global__ void k_hutch_final(const double *hp, int K, double *gram_part) {
   }
 }
 
-// The backward's probe operands, [M][K] in the operand type (zero beyond M
-// and K): Omega and Omega - G with G = (W + Wu) Omega = 2 W Omega - E Omega.
+// The backward's low-rank form of C (the adjoint of G_uu = L C L^T in
+// L-space): C = X S X^T with the r = B + 2K + 3 columns
+//   X = [V | Omega | Omega - G | x | a | b],  G = 2 W Omega - E Omega,
+//   x = V alpha - Wu b, b = Q a,
+// and S pairing them: beta_n on V_n, 1/(4K) between Omega_k and
+// (Omega - G)_k, -1/2 between x and a, -1/2 on b.  This kernel writes X^T in
+// the operand type, rows [0, rp) of length Mp (zero beyond M and r).
 template <typename T>
-__global__ void k_hutch_trans(const float *Omt, const float *wx, const float *ex, int B, int K,
-                              int M, long ldx, int Mp, int Kp, long ldk, T *Om, T *Dm) {
-  const long n = (long)Mp * Kp;
-  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
-    const int i = (int)(e / Kp), k = (int)(e % Kp);
-    float o = 0.f, d = 0.f;
-    if (i < M && k < K) {
-      o = Omt[(long)k * M + i];
-      d = o - (2.f * wx[(long)(B + k) * ldx + i] - ex[(long)k * ldx + i]);
+__global__ void k_hutch_X(const T *Vt, const float *Omt, const float *wx, const float *ex,
+                          const float *Va, const float *Wub, const float *a, const float *b,
+                          int B, int K, int M, int Mp, T *Xt) {
+  const int q = blockIdx.y;
+  const long ld = Mp;
+  for (int i = blockIdx.x * NTB + threadIdx.x; i < Mp; i += gridDim.x * NTB) {
+    float v = 0.f;
+    if (i < M) {
+      if (q < B) {
+        v = to_f32(Vt[(long)q * ld + i]);
+      } else if (q < B + K) {
+        v = Omt[(long)(q - B) * M + i];
+      } else if (q < B + 2 * K) {
+        const int k = q - B - K;
+        v = Omt[(long)k * M + i] - (2.f * wx[(long)(B + k) * ld + i] - ex[(long)k * ld + i]);
+      } else if (q == B + 2 * K) {
+        v = Va[i] - Wub[i];
+      } else if (q == B + 2 * K + 1) {
+        v = a[i];
+      } else if (q == B + 2 * K + 2) {
+        v = b[i];
+      }
     }
-    Om[(long)i * ldk + k] = from_f32<T>(o);
-    Dm[(long)i * ldk + k] = from_f32<T>(d);
+    Xt[(long)q * ld + i] = from_f32<T>(v);
+  }
+}
+
+// Y2 = Y1 S for Y1 = L X ([Mp][ldr], columns as in X): column c of Y2 takes
+// S's partner column of Y1 times its coefficient; zero beyond M and r.
+template <typename TW>
+__global__ void k_hutch_mix(const TW *Y1, TW *Y2, long ldr, int M, int Mp, int B, int K,
+                            const float *beta, float inv4k) {
+  const int r = B + 2 * K + 3;
+  const long n = (long)Mp * ldr;
+  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
+    const int i = (int)(e / ldr), c = (int)(e % ldr);
+    float v = 0.f;
+    if (i < M && c < r) {
+      int src;
+      float w;
+      if (c < B) { src = c; w = beta[c]; }
+      else if (c < B + K) { src = c + K; w = inv4k; }
+      else if (c < B + 2 * K) { src = c - K; w = inv4k; }
+      else if (c == B + 2 * K) { src = c + 1; w = -0.5f; }
+      else if (c == B + 2 * K + 1) { src = c - 1; w = -0.5f; }
+      else { src = c; w = -0.5f; }
+      v = w * to_f32(Y1[(long)i * ldr + src]);
+    }
+    Y2[e] = from_f32<TW>(v);
   }
 }
 
@@ -785,10 +827,7 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
                                                     long split_stride, const float *Wu,
                                                     const float *Q, const float *a, const float *b,
                                                     const float *Wub, const float *Va, int M,
-                                                    long ld, TC *Cm, const float *Ctr = nullptr,
-                                                    float ctr_scale = 0.f) {
-  // Ctr (the Hutchinson bound's backward): the trace part -1/2 (Wu + I) + 1/2 Q
-  // is replaced by ctr_scale (Ctr + Ctr^T), Ctr = Omega (Omega - G)^T (Wu, Q unread)
+                                                    long ld, TC *Cm) {
   // one thread per 4 consecutive columns of a row; the padded columns
   // (j >= M, inputs zero there) come out as zeros
   const int cpr = (M + 3) / 4;
@@ -799,24 +838,16 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
     f32x4 ys = *(const f32x4 *)(Ys + ij);
 #pragma unroll 4
     for (int s = 1; s < nsplit; ++s) ys += *(const f32x4 *)(Ys + s * split_stride + ij);
+    const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
     const f32x4 aj = *(const f32x4 *)(a + j0), bj = *(const f32x4 *)(b + j0);
     const f32x4 wj = *(const f32x4 *)(Wub + j0), vj = *(const f32x4 *)(Va + j0);
     const float ai = a[i], bi = b[i], wi = Wub[i], vi = Va[i];
-    f32x4 tr;
-    if (Ctr) {
-      const f32x4 c0 = *(const f32x4 *)(Ctr + ij);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tr[u] = ctr_scale * (c0[u] + Ctr[(long)(j0 + u) * ld + i]);
-    } else {
-      const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tr[u] = -0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f)) + 0.5f * q[u];
-    }
     TC out[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] +
-                      0.5f * (wi * aj[u] + ai * wj[u]) + tr[u] - 0.5f * bi * bj[u];
+      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] -
+                      0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f) - wi * aj[u] - ai * wj[u]) +
+                      0.5f * (q[u] - bi * bj[u]);
       out[u] = from_f32<TC>(c);
     }
     if constexpr (sizeof(TC) == 4) {
