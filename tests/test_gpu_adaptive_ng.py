@@ -36,7 +36,9 @@ def _problem(M, D, seed, pert=0.01):
 # above the residual floor that bf16 operands put under W (about 1e-2 here)
 @pytest.mark.parametrize("prec,M,D,seed,k,pert", [("fp32", 130, 3, 1, 2, 0.01),
                                                   ("fp32", 257, 5, 2, 1, 0.01),
-                                                  ("bf16", 200, 4, 3, 1, 0.04)])
+                                                  ("bf16", 200, 4, 3, 1, 0.04),
+                                                  # the largest configuration's M and D
+                                                  ("fp32", 2048, 32, 6, 1, 0.01)])
 def test_adaptive_ng_parity(prec, M, D, seed, k, pert):
     from paper_2604_00697_amd.lib import Context
     dev = torch.device("cuda", 0)

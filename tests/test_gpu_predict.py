@@ -154,3 +154,41 @@ def test_predict_argument_errors_and_state(require_gpu):
     assert e.value.code == lib.ESTATE
     torch.cuda.synchronize()
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_predict_full_size_sampled(require_gpu, prec):
+    """The iteration's largest single-batch shape (M = 1024, B_max = 4096,
+    D = 16) with 4 B + 77 test points (five chunks, a ragged last one), as the
+    benchmark's prediction row runs it; the oracle checks 64 sampled points
+    (chunk edges included) one by one, under the gates above."""
+    from paper_2604_00697_amd.lib import Context
+    M, Bmax, D = 1024, 4096, 16
+    n = 4 * Bmax + 77
+    c = make_case(M, 8, D, seed=1024, s_range=(5e-2, 1e-1))
+    Xt, yt = _test_points(n, D, "gaussian", 1025)
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(np.atleast_1d(np.asarray(a, np.float32)))).to(dev)
+    print(f"PREDICT full size prec={prec} M={M} B_max={Bmax} n={n}", flush=True)
+    ctx = Context(M, Bmax, D, prec, "gaussian")
+    mu, var, lpd, nlpd = ctx.predict(t(Xt), t(c["ell"]), t([c["sf2"]]), t(c["Z"]), t(c["m"]),
+                                     t(c["s"]), t(c["L"]), y=t(yt), noise=t([c["noise"]]))
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    g = np.random.Generator(np.random.PCG64(7))
+    edges = [0, Bmax - 1, Bmax, 2 * Bmax, 4 * Bmax - 1, 4 * Bmax, n - 1]
+    idx = np.unique(np.concatenate([edges, g.choice(n, 64 - len(edges), replace=False)]))
+    ref, sp = _spread(c, Xt[idx], yt[idx], "gaussian", EPS[prec], nsamp=2)
+    gpu = dict(mu=mu.cpu().numpy()[idx], var=var.cpu().numpy()[idx],
+               lpd=lpd.cpu().numpy()[idx])
+    for q in ("mu", "var", "lpd"):
+        assert np.all(np.isfinite(gpu[q])), q
+        err = _rel(gpu[q], ref[q])
+        tol = max(BASE[prec], MULT[prec] * sp[q])
+        print(f"PARITY predict_full_{prec} {q} {err:.3e} tol {tol:.3e} spread {sp[q]:.3e}", flush=True)
+        assert err <= tol, (q, err, tol)
+    # the NLPD is the mean of all n log densities
+    l_all = lpd.double().cpu().numpy()
+    assert np.isfinite(nlpd.item())
+    assert abs(nlpd.item() + l_all.mean()) <= 1e-6 * max(1.0, abs(nlpd.item()))
+    ctx.close()
