@@ -377,3 +377,39 @@ def training_iteration(X, y, N, ell, sf2, noise_var, Z, m, s, L, gammas,
         out = dict(bound=rsvgp_bound(X, y, N, ell, sf2, noise_var, Z, m, s,
                                      L_new, lik, n_gh, perturb=perturb))
     return L_new, res, out
+
+
+def multi_output_bound(X, Y, N, ell, sf2, noise_var, Z, Mt, s, L, lik="gaussian", n_gh=20,
+                       perturb=None):
+    """Q outputs sharing Z, the kernel hyperparameters and one S~, hence one
+    T = L L^T (Section 4, multi-output layers with S~ tied across outputs);
+    output q has its own inducing mean m~_q (row q of Mt, Q x M) and targets
+    Y[:, q] (Y is B x Q).  The outputs are independent SVGPs given these
+    shared quantities, so the bound is the sum over q of eq. rsvgp_precond's
+    bound, each with its whole KL.  Returns F, data, KL (sums over outputs),
+    sum_var (sum_n sigma_n^2, the same for every output) and mu (Q x B)."""
+    Y = np.asarray(Y, np.float64).reshape(np.shape(X)[0], -1)
+    Mt = np.atleast_2d(np.asarray(Mt, np.float64))
+    parts = [rsvgp_bound(X, Y[:, q], N, ell, sf2, noise_var, Z, Mt[q], s, L, lik, n_gh,
+                         perturb=perturb) for q in range(Mt.shape[0])]
+    return dict(F=sum(p["F"] for p in parts), data=sum(p["data"] for p in parts),
+                KL=sum(p["KL"] for p in parts), sum_var=parts[0]["sum_var"],
+                mu=np.stack([p["mu"] for p in parts]), var=parts[0]["var"])
+
+
+def multi_output_bound_grad(X, Y, N, ell, sf2, noise_var, Z, Mt, s, L, lik="gaussian",
+                            n_gh=20, perturb=None):
+    """Gradient of multi_output_bound at fixed T: for the shared parameters
+    (ell, sf2, noise_var, Z, s~) the sum of the per-output gradients, for m~_q
+    output q's own (m: Q x M).  abs_terms: the per-output absolute term sums
+    added up (a bound on the scale of the combined sums)."""
+    Y = np.asarray(Y, np.float64).reshape(np.shape(X)[0], -1)
+    Mt = np.atleast_2d(np.asarray(Mt, np.float64))
+    gs = [rsvgp_bound_grad(X, Y[:, q], N, ell, sf2, noise_var, Z, Mt[q], s, L, lik, n_gh,
+                           perturb=perturb) for q in range(Mt.shape[0])]
+    out = {k: sum(g[k] for g in gs) for k in ("ell", "sf2", "noise_var", "Z", "s")}
+    out["m"] = np.stack([g["m"] for g in gs])
+    out["abs_terms"] = {k: sum(g["abs_terms"][k] for g in gs) for k in gs[0]["abs_terms"]}
+    out["bound"] = multi_output_bound(X, Y, N, ell, sf2, noise_var, Z, Mt, s, L, lik, n_gh,
+                                      perturb=perturb)
+    return out

@@ -626,3 +626,74 @@ def test_hutchinson_gradient_with_scaled_unit_probes_is_the_exact_gradient():
                                p["Z"], p["m"], p["s"], L, Omega=np.sqrt(6.0) * np.eye(6))
     for k in ("ell", "sf2", "noise_var", "Z", "m", "s"):
         assert np.allclose(gh[k], ge[k], rtol=1e-10, atol=1e-12), k
+
+
+# ---------------------------------------------------------------- multi-output
+def _multi_problem(seed, Q=3, lik="gaussian"):
+    p = small_problem(seed, lik=lik)
+    g = _rng(seed + 100)
+    B, M = p["X"].shape[0], p["Z"].shape[0]
+    if lik == "gaussian":
+        Y = np.sin(p["X"] @ g.standard_normal((p["X"].shape[1], Q))) + 0.1 * g.standard_normal((B, Q))
+    else:
+        Y = np.where(g.standard_normal((B, Q)) > 0, 1.0, -1.0)
+    return p, Y, g.standard_normal((Q, M))
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_multi_output_bound_at_Ktilde_inverse_is_sum_of_cholesky_elbos(lik):
+    """With S~ tied across outputs and T = K~^{-1}, each output's bound is the
+    Cholesky ELBO of its own q_q(u) = N(K_uu K~^{-1} m~_q, (K_uu^{-1} + S~^{-1})^{-1});
+    the outputs being independent given the shared parameters, the bound is
+    the sum of those ELBOs."""
+    p, Y, Mt = _multi_problem(31, lik=lik)
+    out = svgp.multi_output_bound(p["X"], Y, p["N"], p["ell"], p["sf2"], p["noise_var"],
+                                  p["Z"], Mt, p["s"], chol_Kinv(p), lik=lik)
+    tot = 0.0
+    for q in range(Mt.shape[0]):
+        qm, qS = ref.lsvgp_q(p["ell"], p["sf2"], p["Z"], Mt[q], p["s"])
+        ch = ref.cholesky_elbo(p["X"], Y[:, q], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                               p["Z"], qm, qS, lik=lik)
+        tot += ch["F"]
+        assert np.allclose(out["mu"][q], ch["mu"], rtol=1e-9, atol=1e-12)
+    assert np.isclose(out["F"], tot, rtol=1e-10, atol=1e-10)
+
+
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_multi_output_gradient_matches_central_differences(lik):
+    """The multi-output gradient (shared parameters summed over outputs, m~_q
+    per output) against central differences of multi_output_bound in every
+    coordinate: a gradient routed to the wrong output or a KL counted once
+    instead of per output fails here."""
+    p, Y, Mt = _multi_problem(32, lik=lik)
+    L = random_L(6, 47, 0.4)
+    args = lambda q: (p["X"], Y, p["N"], q["ell"], q["sf2"], q["noise_var"], q["Z"], q["Mt"],
+                      q["s"], L)
+    base = dict(p, Mt=Mt)
+    g = svgp.multi_output_bound_grad(*args(base), lik=lik)
+
+    def F_of(key, x):
+        q = dict(base)
+        q[key] = x
+        return svgp.multi_output_bound(*args(q), lik=lik)["F"]
+    for key, gk in (("ell", "ell"), ("Z", "Z"), ("Mt", "m"), ("s", "s")):
+        x0 = np.asarray(base[key], np.float64)
+        fd = ref.central_fd(lambda x: F_of(key, x.reshape(x0.shape)), x0.ravel(),
+                            list(range(x0.size)), 1e-6)
+        assert np.allclose(np.ravel(g[gk]), fd, rtol=1e-6, atol=1e-7), key
+    for key in ("sf2",) + (("noise_var",) if lik == "gaussian" else ()):
+        fd = (F_of(key, p[key] + 1e-6) - F_of(key, p[key] - 1e-6)) / 2e-6
+        assert np.isclose(g[key], fd, rtol=1e-6, atol=1e-7), key
+
+
+def test_multi_output_with_one_output_is_the_single_output_bound():
+    p = small_problem(33)
+    L = random_L(6, 48)
+    one = svgp.multi_output_bound_grad(p["X"], p["y"][:, None], p["N"], p["ell"], p["sf2"],
+                                       p["noise_var"], p["Z"], p["m"][None, :], p["s"], L)
+    sg = svgp.rsvgp_bound_grad(p["X"], p["y"], p["N"], p["ell"], p["sf2"], p["noise_var"],
+                               p["Z"], p["m"], p["s"], L)
+    assert np.isclose(one["bound"]["F"], sg["bound"]["F"], rtol=1e-14)
+    for k in ("ell", "sf2", "noise_var", "Z", "s"):
+        assert np.allclose(one[k], sg[k], rtol=1e-14, atol=0), k
+    assert np.allclose(one["m"][0], sg["m"], rtol=1e-14, atol=0)
