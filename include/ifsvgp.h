@@ -236,6 +236,37 @@ int ifsvgp_bound_hutch_bwd(ifsvgp_ctx *ctx, const float *X, const float *y, int 
                            const double *grad_scale, float *g_ell, float *g_sf2,
                            float *g_noise_var, float *g_Z, float *g_m, float *g_s);
 
+/* Multi-output bound (Section 4, multi-output layers with S~ tied across
+ * outputs): Q outputs (1 <= Q <= 16) share Z, ell, sf2, noise_var, s_tilde and
+ * so one T = L L^T; output q has its own inducing mean (row q of Mt, device
+ * fp32 [Q][M]) and targets (column q of Y, device fp32 [B][Q] row-major).
+ * The outputs are independent SVGPs given the shared quantities, so F is the
+ * sum of the single-output bounds of eq. rsvgp_precond, each with its own KL
+ * (trace and log-determinant terms included).  sigma_n^2 is shared; the means
+ * are mu_qn = k_n^T P m~_q.  out_terms: data and KL summed over outputs,
+ * sum_n sigma_n^2, the NG residual of W, tr W and tr(Q Wu) of one output, the
+ * summed mean terms sum_q m~_q^T P K_uu P m~_q and log|T|.  Other arguments
+ * as for ifsvgp_bound; IFSVGP_EINVAL for Q outside 1..16. */
+int ifsvgp_bound_multi(ifsvgp_ctx *ctx, const float *X, const float *Y, int B, int Q,
+                       double N_total, const float *ell, const float *sf2,
+                       const float *noise_var, const float *Z, const float *Mt,
+                       const float *s_tilde, const float *L, double *out_bound,
+                       double *out_terms);
+
+/* Gradient of the preceding ifsvgp_bound_multi's F at fixed T: the shared
+ * parameters' gradients (ell, sf2, noise_var, Z) are sums over outputs, g_M
+ * (device fp32 [Q][M]) holds dF/dm~_q in row q; each output may be NULL,
+ * grad_scale as for ifsvgp_bound_bwd.  The gradient with respect to s_tilde
+ * is not offered (g_s must be NULL, IFSVGP_EINVAL otherwise).  One backward
+ * per forward: the call consumes the forward state (IFSVGP_ESTATE when the
+ * last call on ctx was not an ifsvgp_bound_multi with this B and Q). */
+int ifsvgp_bound_multi_bwd(ifsvgp_ctx *ctx, const float *X, const float *Y, int B, int Q,
+                           double N_total, const float *ell, const float *sf2,
+                           const float *noise_var, const float *Z, const float *Mt,
+                           const float *s_tilde, const float *L, const double *grad_scale,
+                           float *g_ell, float *g_sf2, float *g_noise_var, float *g_Z,
+                           float *g_M, float *g_s);
+
 /* Bound only, at the given L (eq. rsvgp_precond).  B <= B_max rows, N_total
  * the data-set size (the data term is scaled by N_total / B).  noise_var is
  * read only for the Gaussian likelihood (may be NULL for probit).

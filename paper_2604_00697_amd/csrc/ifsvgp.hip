@@ -104,10 +104,16 @@ struct ifsvgp_ctx {
   void *hy1, *hy2;   // L X and L X S, [Mp][2 Bp] wide type
   float *hx1, *hx2;  // its backward: vectors [Mp]
   int fwd_K;         // probes of the last Hutchinson forward
+  // multi-output: per-output vectors [MO_QMAX][Mp] (a = L^T m~_q, b = Q a,
+  // Wu b, x = V alpha_q - Wu b, t2 = Q x) and [MO_QMAX][Bp] (mu, dF/dmu),
+  // a zero [Mp] and a -1/2 [Bp] vector for the R epilogue
+  float *mo_m, *mo_a, *mo_b, *mo_wub, *mo_x, *mo_t2, *mo_mu, *mo_al, *mo_zero, *mo_half;
+  int fwd_Q;
   double *gh;
   int *flag, *counters;
   int *ngskip;  // stop flag of an adaptive NG loop
-  // last forward state for the backward: 1 exact bound, 2 Hutchinson bound
+  // last forward state for the backward: 1 exact bound, 2 Hutchinson bound,
+  // 3 multi-output bound
   int fwd_valid, fwd_B;
   int cur;  // which L32/LT/LtT slot holds the bound's L
   // timing
@@ -422,6 +428,16 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   ALLOC(c->hex, MB);
   ALLOC(c->hp, (size_t)4 * Bp);
   ALLOCB(c->hxt, 2 * MB * os);
+  ALLOC(c->mo_m, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_a, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_b, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_wub, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_x, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_t2, (size_t)MO_QMAX * Mp);
+  ALLOC(c->mo_mu, (size_t)MO_QMAX * Bp);
+  ALLOC(c->mo_al, (size_t)MO_QMAX * Bp);
+  ALLOC(c->mo_zero, Mp);
+  ALLOC(c->mo_half, Bp);
   ALLOCB(c->hy1, 2 * MB * ws);
   ALLOCB(c->hy2, 2 * MB * ws);
   ALLOC(c->hx1, Mp);
@@ -680,11 +696,13 @@ struct Ops {
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // R = L U (k < m0+BM) -> H_uf reductions
-  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B) {
+  // (lb, al, be: the epilogue's L b, alpha, beta, by default the context's)
+  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *lb = nullptr,
+                           const float *al = nullptr, const float *be = nullptr) {
     const int D = c->D;
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Ut, c->Mp};
     Sched sc{cdiv(c->M, CRG::BM), cdiv(B, CRG::BN), 0, 1, c->M, K_HI_M1};
-    EpiGradUf e{c->vLb, c->alpha, c->beta, c->Zs, c->Xs, c->sfn, c->M, B, D,
+    EpiGradUf e{lb ? lb : c->vLb, al ? al : c->alpha, be ? be : c->beta, c->Zs, c->Xs, c->sfn, c->M, B, D,
                 c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
     return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D));
   }
@@ -1463,6 +1481,149 @@ extern "C" int ifsvgp_bound_hutch_bwd(ifsvgp_ctx *c, const float *X, const float
   a.grad_scale = grad_scale;
   a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m;
   PREC_DISPATCH(enqueue_hutch_bwd, c, a, B, Omega_t, K, g_m != nullptr)
+}
+
+// Multi-output bound (Q outputs sharing Z, the kernel, S~ and T; Y [B][Q],
+// Mt [Q][M] on the device): the single-output forward's set-up, K_uf tiles,
+// V (side stream) and Gram products, then per output a = L^T m~_q,
+// b = Q a, Wu b (batched matrix-vector products), U = Q V for the shared
+// variances, mu_q = V^T b_q, and the multi-output likelihood kernel.
+template <typename T>
+static int enqueue_multi(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Y,
+                         const float *Mt, int Q) {
+  c->ev_next = 0;
+  c->side_open = false;
+  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca);
+  if (r) return r;
+  c->cur = 0;
+  c->fwd_valid = 0;
+  const int M = c->M;
+  const long Mp = c->Mp, Bp = c->Bp;
+  HIPCK(fork_side(c));
+  r = launch_kuf<T>(c, B);
+  if (r) return r;
+  {
+    OnSide side(c);
+    HIPCK(Ops<T>::gemm_V(c, 0, B));
+  }
+  HIPCK(Ops<T>::gram_Y(c, 0));
+  HIPCK(Ops<T>::gr_W(c, 0));
+  HIPCK(Ops<T>::gr_E(c, 0));
+  const dim3 gq(cdiv(M, NTB / 64), Q);
+  hipLaunchKernelGGL(k_mo_pack, dim3(cdiv(c->Mp, NTB), Q), dim3(NTB), 0, c->st, Mt, M, Mp,
+                     c->mo_m);
+  hipLaunchKernelGGL(k_mo_gemv, gq, dim3(NTB), 0, c->st, (const float *)c->Lt32[0], Mp, M, M,
+                     (const float *)c->mo_m, Mp, 0, (const double *)nullptr, c->mo_a, Mp);
+  hipLaunchKernelGGL(k_mo_gemv, gq, dim3(NTB), 0, c->st, (const float *)c->Q32, Mp, M, M,
+                     (const float *)c->mo_a, Mp, 0, (const double *)nullptr, c->mo_b, Mp);
+  hipLaunchKernelGGL(k_mo_gemv, gq, dim3(NTB), 0, c->st, (const float *)c->Wu32, Mp, M, M,
+                     (const float *)c->mo_b, Mp, 0, (const double *)nullptr, c->mo_wub, Mp);
+  HIPCK(join_side(c));
+  HIPCK(Ops<T>::gemm_U(c, B));
+  hipLaunchKernelGGL((k_mo_mu<T>), dim3(cdiv(B, NTB / 64)), dim3(NTB), 0, c->st,
+                     (const T *)c->Vt, Mp, M, B, (const float *)c->mo_b, Mp, Q, c->mo_mu, Bp);
+  LikMoArgs a{c->var_part, cdiv(M, 128), Bp, c->dca, Y, Q, B, c->Bp, c->sfn, c->lik, c->gh,
+              c->ngh, c->mo_mu, c->mo_al, Bp, c->alpha, c->beta, c->sqnb, c->lik_part,
+              c->tp_gram, cdiv(M, 64) * (cdiv(M, 64) + 1) / 2, c->mo_b, c->mo_wub, Mp,
+              c->L32[0], Mp, M, c->scal, c->flag, c->counters + CNT_LIK};
+  hipLaunchKernelGGL(k_lik_mo, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
+  HIPCK(hipGetLastError());
+  c->fwd_valid = 3;
+  c->fwd_B = B;
+  c->fwd_Q = Q;
+  return IFSVGP_OK;
+}
+
+// Its backward at fixed T: R = L U3 with U3 = sum_q b_q alpha_q^T -
+// 2 U diag(beta), so the R epilogue (given L b = 0 and beta = -1/2) forms
+// H_uf from G_uf directly; C with the per-output vector terms summed and the
+// trace part counted Q times; G_uu = L C L^T; dF/dm~_q = L Q x_q.
+template <typename T>
+static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, float *g_M,
+                             const double *grad_scale) {
+  using TW = typename Ops<T>::TW;
+  c->ev_next = 0;
+  c->side_open = false;
+  int r = latch(c, ca);
+  if (r) return r;
+  const int M = c->M, D = c->D;
+  const long Mp = c->Mp, Bp = c->Bp;
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Mp, NTB)), dim3(NTB), 0, c->st, c->mo_zero, c->Mp, 0.f);
+  hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, c->mo_half, c->Bp,
+                     -0.5f);
+  hipLaunchKernelGGL((k_mo_u3<T>), dim3(cdiv(M, NTB), B), dim3(NTB), 0, c->st, (T *)c->Ut, Mp,
+                     M, (const float *)c->mo_b, Mp, (const float *)c->mo_al, Bp, Q,
+                     (const float *)c->beta);
+  HIPCK(fork_side(c));
+  {
+    OnSide side(c);
+    HIPCK(Ops<T>::gemm_R(c, 0, B, c->mo_zero, c->mo_half, c->mo_half));
+  }
+  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+                     (const T *)c->V, Bp, M, c->Bp, (const float *)c->alpha,
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa);
+  HIPCK(Ops<T>::syrk(c, B));
+  hipLaunchKernelGGL((k_mo_x<T>), dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+                     (const T *)c->V, Bp, M, c->Bp, (const float *)c->mo_al, Bp, Q,
+                     (const float *)c->mo_wub, Mp, c->mo_x);
+  hipLaunchKernelGGL(k_assemble_C_mo<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0,
+                     c->st, (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
+                     (const float *)c->Wu32, (const float *)c->Q32, (const float *)c->mo_a,
+                     (const float *)c->mo_b, (const float *)c->mo_x, Mp, Q, M, Mp, (TW *)c->Cm);
+  HIPCK(Ops<T>::gemm_Y2(c, 0));
+  HIPCK(Ops<T>::gemm_Guu(c, 0, nullptr));
+  if (g_M) {
+    const dim3 gq(cdiv(M, NTB / 64), Q);
+    hipLaunchKernelGGL(k_mo_gemv, gq, dim3(NTB), 0, c->st, (const float *)c->Q32, Mp, M, M,
+                       (const float *)c->mo_x, Mp, 0, (const double *)nullptr, c->mo_t2, Mp);
+    hipLaunchKernelGGL(k_mo_gemv, gq, dim3(NTB), 0, c->st, (const float *)c->L32[0], Mp, M, M,
+                       (const float *)c->mo_t2, Mp, 1, grad_scale, g_M, (long)M);
+  }
+  HIPCK(join_side(c));
+  const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
+  const int R = NTB / D;
+  const int rb = cdiv(M, R), cb = cdiv(B, R);
+  GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
+             c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
+             c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
+             c->lik_part, cdiv(c->Bp, NTB),
+             nullptr, nullptr, nullptr, Mp, nullptr, c->ell_part, rb, cb,
+             nullptr, nullptr, (long)Mp, nullptr, c->sP};
+  hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
+  hipLaunchKernelGGL(k_grad_tail, dim3(1), dim3(NTB), 0, c->st, g, (const float *)c->L32[0], 0);
+  HIPCK(hipGetLastError());
+  c->fwd_valid = 0;  // U was overwritten in place: one backward per forward
+  return IFSVGP_OK;
+}
+
+extern "C" int ifsvgp_bound_multi(ifsvgp_ctx *c, const float *X, const float *Y, int B, int Q,
+                                  double N, const float *ell, const float *sf2,
+                                  const float *noise, const float *Z, const float *Mt,
+                                  const float *s, const float *L, double *out_bound,
+                                  double *out_terms) {
+  int r = check_bound_args(c, X, Y, B, N, ell, sf2, noise, Z, Mt, s, L);
+  if (r) return r;
+  if (Q < 1 || Q > MO_QMAX || !out_bound) return IFSVGP_EINVAL;
+  CallArgs a = make_args(X, Y, B, N, ell, sf2, noise, Z, Mt, s, (float *)L, nullptr, 0);
+  a.out_bound = out_bound;
+  a.out_terms = out_terms;
+  PREC_DISPATCH(enqueue_multi, c, a, B, Y, Mt, Q)
+}
+
+extern "C" int ifsvgp_bound_multi_bwd(ifsvgp_ctx *c, const float *X, const float *Y, int B,
+                                      int Q, double N, const float *ell, const float *sf2,
+                                      const float *noise, const float *Z, const float *Mt,
+                                      const float *s, const float *L, const double *grad_scale,
+                                      float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
+                                      float *g_M, float *g_s) {
+  int r = check_bound_args(c, X, Y, B, N, ell, sf2, noise, Z, Mt, s, L);
+  if (r) return r;
+  if (Q < 1 || Q > MO_QMAX || g_s) return IFSVGP_EINVAL;
+  if (c->fwd_valid != 3 || c->fwd_B != B || c->fwd_Q != Q) return IFSVGP_ESTATE;
+  CallArgs a = make_args(X, Y, B, N, ell, sf2, noise, Z, Mt, s, (float *)L, nullptr, 0);
+  a.grad_scale = grad_scale;
+  a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z;
+  PREC_DISPATCH(enqueue_multi_bwd, c, a, B, Q, g_M, grad_scale)
 }
 
 extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {

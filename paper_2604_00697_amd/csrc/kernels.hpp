@@ -1121,3 +1121,239 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, long n, flo
     p[i] -= lr * (mi * inv_bc1) / (sqrtf(vi * inv_bc2) + eps);
   }
 }
+
+// ---------------------------------------------------------------- multi-output
+// Q outputs sharing Z, the kernel, S~ and so T = L L^T, each with its own m~_q
+// and targets (Section 4's multi-output layers with S~ tied across outputs).
+// Per-output vectors are rows of [Q][ld] fp32 arrays, zero beyond M.
+constexpr int MO_QMAX = 16;
+
+__global__ void k_fill(float *p, int n, float v) {
+  const int i = blockIdx.x * NTB + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// the caller's [Q][M] rows into a zero-padded [Q][ld] array
+__global__ void k_mo_pack(const float *src, int M, long ld, float *dst) {
+  const int q = blockIdx.y;
+  for (int i = blockIdx.x * NTB + threadIdx.x; i < ld; i += gridDim.x * NTB)
+    dst[q * ld + i] = i < M ? src[(long)q * M + i] : 0.f;
+}
+
+// Y[q] = scale * A X[q] over j < Cn (lower: j <= i), one wave per row, grid.y = q
+__global__ void k_mo_gemv(const float *A, long lda, int R, int Cn, const float *X, long ldx,
+                          int lower, const double *scale, float *Y, long ldy) {
+  const int q = blockIdx.y;
+  const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const float s = row_dot(A + (long)row * lda, X + q * ldx, nullptr,
+                          lower ? min(Cn, row + 1) : Cn);
+  if ((threadIdx.x & 63) == 0) Y[q * ldy + row] = scale ? (float)(*scale * (double)s) : s;
+}
+
+// mu[q][n] = b_q^T V_n = k_n^T P m~_q (V_n: row n of the operand-type Vt), one
+// wave per batch point
+template <typename T>
+__global__ void k_mo_mu(const T *Vt, long ld, int M, int B, const float *Bh, long ldb, int Q,
+                        float *mu, long ldm) {
+  const int n = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (n >= B) return;
+  float acc[MO_QMAX];
+#pragma unroll
+  for (int q = 0; q < MO_QMAX; ++q) acc[q] = 0.f;
+  const T *v = Vt + (long)n * ld;
+  for (int i = lane; i < M; i += 64) {
+    const float x = to_f32(v[i]);
+#pragma unroll
+    for (int q = 0; q < MO_QMAX; ++q)
+      if (q < Q) acc[q] = fmaf(x, Bh[q * ldb + i], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < MO_QMAX; ++q)
+    if (q < Q) {
+      const float s = wave_sum(acc[q]);
+      if (lane == 0) mu[q * ldm + n] = s;
+    }
+}
+
+// x_q = V alpha_q - Wu b_q, one wave per row of the operand-type V ([Mp][Bp];
+// alpha_q zero for n >= B)
+template <typename T>
+__global__ void k_mo_x(const T *V, long ld, int M, int Bp, const float *al, long lda, int Q,
+                       const float *Wub, long ldw, float *Xq) {
+  const int i = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= M) return;
+  float acc[MO_QMAX];
+#pragma unroll
+  for (int q = 0; q < MO_QMAX; ++q) acc[q] = 0.f;
+  const T *v = V + (long)i * ld;
+  for (int n = lane; n < Bp; n += 64) {
+    const float x = to_f32(v[n]);
+#pragma unroll
+    for (int q = 0; q < MO_QMAX; ++q)
+      if (q < Q) acc[q] = fmaf(x, al[q * lda + n], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < MO_QMAX; ++q)
+    if (q < Q) {
+      const float s = wave_sum(acc[q]);
+      if (lane == 0) Xq[q * ldw + i] = s - Wub[q * ldw + i];
+    }
+}
+
+// Rows n < B of Ut become sum_q b_q alpha_qn - 2 beta_n U_n, so that L times
+// them is G_uf = sum_q (P m~_q) alpha_q^T - 2 P K_uf diag(beta) directly
+template <typename T>
+__global__ void k_mo_u3(T *Ut, long ld, int M, const float *Bh, long ldb, const float *al,
+                        long lda, int Q, const float *beta) {
+  const int n = blockIdx.y;
+  const float bn = -2.f * beta[n];
+  for (int i = blockIdx.x * NTB + threadIdx.x; i < M; i += gridDim.x * NTB) {
+    float v = bn * to_f32(Ut[(long)n * ld + i]);
+    for (int q = 0; q < Q; ++q) v = fmaf(Bh[q * ldb + i], al[q * lda + n], v);
+    Ut[(long)n * ld + i] = from_f32<T>(v);
+  }
+}
+
+// C = sum_q [-1/2 (x_q a_q^T + a_q x_q^T) - 1/2 b_q b_q^T] + V diag(beta) V^T
+//     + Q [-1/2 (Wu + I) + 1/2 Q],  V diag(beta) V^T = -sum_s Ys[s]
+// (the single-output C with each output's vector terms summed and the trace
+// part, which every output's KL carries, counted Q times)
+template <typename TC>
+__global__ __launch_bounds__(NTB) void k_assemble_C_mo(const float *Ys, int nsplit,
+                                                       long split_stride, const float *Wu,
+                                                       const float *Qm, const float *A,
+                                                       const float *Bh, const float *Xq,
+                                                       long ldv, int Q, int M, long ld,
+                                                       TC *Cm) {
+  const int cpr = (M + 3) / 4;
+  const long n = (long)M * cpr;
+  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
+    const int i = (int)(e / cpr), j0 = (int)(e % cpr) * 4;
+    const long ij = (long)i * ld + j0;
+    f32x4 ys = *(const f32x4 *)(Ys + ij);
+    for (int s = 1; s < nsplit; ++s) ys += *(const f32x4 *)(Ys + s * split_stride + ij);
+    const f32x4 wu = *(const f32x4 *)(Wu + ij), qm = *(const f32x4 *)(Qm + ij);
+    f32x4 vec = {0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < Q; ++q) {
+      const float *a = A + q * ldv, *b = Bh + q * ldv, *x = Xq + q * ldv;
+      const f32x4 aj = *(const f32x4 *)(a + j0), bj = *(const f32x4 *)(b + j0),
+                  xj = *(const f32x4 *)(x + j0);
+      const float ai = a[i], bi = b[i], xi = x[i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vec[u] -= 0.5f * (xi * aj[u] + ai * xj[u] + bi * bj[u]);
+    }
+    TC out[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float tr = -0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f)) + 0.5f * qm[u];
+      out[u] = from_f32<TC>(vec[u] - ys[u] + (float)Q * tr);
+    }
+    if constexpr (sizeof(TC) == 4) {
+      *(f32x4 *)(Cm + ij) = f32x4{(float)out[0], (float)out[1], (float)out[2], (float)out[3]};
+    } else {
+      uint2 raw;
+      __builtin_memcpy(&raw, out, 8);
+      *(uint2 *)(Cm + ij) = raw;
+    }
+  }
+}
+
+// Likelihood of the Q outputs: per batch point the shared sigma_n^2 (from the
+// U epilogue's partials), per output E_qn and dF/dmu_qn = c dE/dmu; beta_n =
+// c sum_q dE/dsigma^2 (sigma^2 is shared) with sqrt(-beta_n) for the batch
+// product; the last workgroup forms F = c sum E - KL with
+//   KL = Q/2 (-tr(Q Wu) + tr W - M - log|T| - sum log s~) + 1/2 sum_q b_q^T Wu b_q.
+struct LikMoArgs {
+  const float *var_part; int n_var; long ldp;
+  const CallArgs *ca;
+  const float *Y; int Q;  // targets [B][Q]
+  int B, Bp;
+  const float *sfn; int lik; const double *gh; int ngh;
+  const float *mu; float *al; long ldm;  // [Q][ldm]
+  float *alpha, *beta, *sqnb;
+  double *part;
+  const double *gram_part; int n_gram;
+  const float *Bh, *Wub; long ldv;
+  const float *L; long ldl; int M;
+  double *scal; int *flag; int *counter;
+};
+
+__global__ void k_lik_mo(LikMoArgs a) {
+  __shared__ double sh[7 * (NTB / 64)];
+  __shared__ int s_last;
+  const int n = blockIdx.x * NTB + threadIdx.x;
+  double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
+  if (n < a.B) {
+    const double var = (double)a.sfn[0] - (double)slot_sum(a.var_part + n, a.n_var, a.ldp);
+    const double c = a.ca->c;
+    double dvs = 0.0;
+    for (int q = 0; q < a.Q; ++q) {
+      const double mu = a.mu[q * a.ldm + n], y = a.Y[(long)n * a.Q + q];
+      double E, dmu, dv;
+      if (a.lik == 0) {
+        const double s2 = a.sfn[1];
+        const double r = y - mu;
+        E = -0.5 * log(2.0 * M_PI * s2) - (r * r + var) / (2.0 * s2);
+        dmu = r / s2;
+        dv = -0.5 / s2;
+        dn += -0.5 / s2 + (r * r + var) / (2.0 * s2 * s2);
+      } else {
+        probit_terms(y, mu, var, a.gh, a.ngh, E, dmu, dv);
+      }
+      a.al[q * a.ldm + n] = (float)(c * dmu);
+      e += E;
+      dvs += dv;
+    }
+    a.alpha[n] = 0.f;
+    a.beta[n] = (float)(c * dvs);
+    a.sqnb[n] = (float)sqrt(fmax(0.0, -c * dvs));
+    vs = var;
+    bs = c * dvs;
+  } else if (n < a.Bp) {
+    a.alpha[n] = 0.f;
+    a.beta[n] = 0.f;
+    a.sqnb[n] = 0.f;
+    for (int q = 0; q < a.Q; ++q) a.al[q * a.ldm + n] = 0.f;
+  }
+  double v[4] = {e, vs, dn, bs};
+  block_sums<NTB, 4>(v, sh);
+  if (threadIdx.x == 0) {
+    double *p = a.part + 4 * blockIdx.x;
+    p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
+  }
+  if (!arrive_last(a.counter, &s_last)) return;
+  double w[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTB) {
+    w[0] += a.part[4 * i];
+    w[1] += a.part[4 * i + 1];
+  }
+  for (int i = threadIdx.x; i < a.n_gram; i += NTB) {
+    w[2] += a.gram_part[3 * i];
+    w[3] += a.gram_part[3 * i + 1];
+    w[4] += a.gram_part[3 * i + 2];
+  }
+  for (int q = 0; q < a.Q; ++q)
+    for (int i = threadIdx.x; i < a.M; i += NTB)
+      w[5] += (double)a.Bh[q * a.ldv + i] * (double)a.Wub[q * a.ldv + i];
+  for (int i = threadIdx.x; i < a.M; i += NTB) w[6] += log(fabs((double)a.L[(long)i * a.ldl + i]));
+  block_sums<NTB, 7>(w, sh);
+  if (threadIdx.x == 0) {
+    const double trw = w[2], qwu = w[3], r2 = w[4], quad = w[5], logdet = 2.0 * w[6];
+    const double sls = a.scal[S_SUMLOGS];
+    a.scal[S_QUAD] = quad;
+    a.scal[S_LOGDET] = logdet;
+    const double KL = 0.5 * ((double)a.Q * (-qwu + trw - (double)a.M - logdet - sls) + quad);
+    const double data = a.ca->c * w[0];
+    const double F = data - KL;
+    if (!isfinite(F)) atomicOr(a.flag, FLAG_NONFINITE);
+    if (a.ca->out_bound) *a.ca->out_bound = F;
+    if (a.ca->out_terms) {
+      double *o = a.ca->out_terms;
+      o[0] = data; o[1] = KL; o[2] = w[1]; o[3] = sqrt(r2 / a.M);
+      o[4] = trw; o[5] = qwu; o[6] = quad; o[7] = logdet;
+    }
+  }
+}

@@ -46,6 +46,9 @@ _SIGS = {
                                 _P, _P]),
     "ifsvgp_bound_hutch_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
                                     _I, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_bound_multi": (_I, [_P, _P, _P, _I, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_bound_multi_bwd": (_I, [_P, _P, _P, _I, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_bound_bwd": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P,
                               _P, _P, _P, _P, _P, _P]),
@@ -289,6 +292,46 @@ class Context:
             self._h, a["X"], a["y"], a["B"], float(N), a["ell"], a["sf2"], a["noise"], a["Z"],
             a["m"], a["s"], a["L"], _ptr(Omega_t, (K, self.M), "Omega_t"), K, gs,
             *self._grad_ptrs(g)), "ifsvgp_bound_hutch_bwd")
+        return g
+
+    def _multi_inputs(self, X, Y, ell, sf2, noise, Z, Mt, s, L):
+        B, Q = X.shape[0], Mt.shape[0]
+        M, D = self.M, self.D
+        return (_ptr(X, (B, D), "X"), _ptr(Y, (B, Q), "Y"), B, Q), (
+            _ptr(ell, (D,), "ell"), _ptr(sf2, (1,), "sf2"),
+            _ptr(noise, (1,), "noise_var", optional=self.lik != "gaussian"),
+            _ptr(Z, (M, D), "Z"), _ptr(Mt, (Q, M), "Mt"), _ptr(s, (M,), "s_tilde"),
+            _ptr(L, (M, M), "L"))
+
+    def bound_multi(self, X, Y, N, ell, sf2, noise, Z, Mt, s, L, out=None, terms=None):
+        """Multi-output bound: targets Y (B, Q), inducing means Mt (Q, M);
+        F (fp64 (1,)) and terms (fp64 (8,))."""
+        import torch
+        (x, y, B, Q), rest = self._multi_inputs(X, Y, ell, sf2, noise, Z, Mt, s, L)
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        terms = torch.empty(N_TERMS, dtype=torch.float64, device=self.device) if terms is None else terms
+        self._stream()
+        _check(self._lib.ifsvgp_bound_multi(
+            self._h, x, y, B, Q, float(N), *rest, _ptr(out, (1,), "out", torch.float64),
+            _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound_multi")
+        return out, terms
+
+    def bound_multi_bwd(self, X, Y, N, ell, sf2, noise, Z, Mt, s, L, grad_scale=None,
+                        want=("ell", "sf2", "noise_var", "Z", "m")):
+        """Gradients of the preceding bound_multi's F; dict of fp32 tensors,
+        "m" of shape (Q, M) (no "s")."""
+        import torch
+        if "s" in want:
+            raise ValueError("bound_multi_bwd offers no gradient with respect to s~")
+        (x, y, B, Q), rest = self._multi_inputs(X, Y, ell, sf2, noise, Z, Mt, s, L)
+        g = self._grad_buffers([k for k in want if k != "m"])
+        if "m" in want:
+            g["m"] = torch.empty((Q, self.M), dtype=torch.float32, device=self.device)
+        self._stream()
+        gs = None if grad_scale is None else _ptr(grad_scale, (1,), "grad_scale", torch.float64)
+        _check(self._lib.ifsvgp_bound_multi_bwd(
+            self._h, x, y, B, Q, float(N), *rest, gs, *self._grad_ptrs(g)),
+            "ifsvgp_bound_multi_bwd")
         return g
 
     def bound_bwd(self, X, y, N, ell, sf2, noise, Z, m, s, L, grad_scale=None,

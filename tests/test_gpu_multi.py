@@ -1,0 +1,175 @@
+"""GPU parity of the multi-output bound and its gradient (ifsvgp_bound_multi,
+ifsvgp_bound_multi_bwd: Q outputs sharing Z, the kernel, S~ and T) against the
+float64 oracle (oracle.svgp.multi_output_bound_grad), under the gate of
+test_gpu_parity.py: err <= max(base, mult * spread, acc * 2^-24 * summation
+condition), the spread being the oracle's own change when its inputs and the
+formed K_uu, K_uf carry independent rounding of the operand precision."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import svgp
+from test_gpu_parity import make_case, gate, EPS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+QS = ("F", "data", "KL", "sum_var")
+GK = ("ell", "sf2", "noise_var", "Z", "m")
+
+
+def _multi_case(M, B, D, Q, seed, lik="gaussian", s_range=(0.05, 0.1)):
+    c = make_case(M, B, D, seed=seed, lik=lik, s_range=s_range)
+    g = np.random.Generator(np.random.PCG64(seed + 7))
+    X = c["X"].astype(np.float64)
+    f = np.sin(X @ g.standard_normal((D, Q)) / np.sqrt(D))
+    if lik == "probit":
+        Y = np.where(f + 0.3 * g.standard_normal((B, Q)) > 0, 1.0, -1.0)
+    else:
+        Y = f + 0.05 * g.standard_normal((B, Q))
+    c["Y"] = Y.astype(np.float32)
+    c["Mt"] = (0.5 * g.standard_normal((Q, M))).astype(np.float32)
+    return c
+
+
+def _oracle(c, perturb=None, scale=None):
+    q = {k: np.asarray(c[k], np.float64) for k in ("X", "Y", "Z", "ell", "Mt", "s", "L")}
+    sf2, noise = float(c["sf2"]), float(c["noise"])
+    if scale:
+        q = {k: v * scale[k] if k in scale else v for k, v in q.items()}
+        sf2 *= scale["sf2"]
+        noise *= scale["noise"]
+    r = svgp.multi_output_bound_grad(q["X"], q["Y"], c["N"], q["ell"], sf2, noise, q["Z"],
+                                     q["Mt"], q["s"], q["L"], lik=c["lik"], perturb=perturb)
+    keys = [k for k in GK if k != "noise_var" or c["lik"] == "gaussian"]
+    out = {k: r["bound"][k] for k in QS}
+    out.update({"grad_" + k: np.asarray(r[k], np.float64) for k in keys})
+    cond = {"grad_" + k: np.linalg.norm(np.ravel(v)) / max(np.linalg.norm(np.ravel(r[k])), 1e-300)
+            for k, v in r["abs_terms"].items() if k in keys}
+    return out, cond
+
+
+def _rel(a, b, floor=0.0):
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), floor, 1e-300))
+
+
+def _sensitivity(c, eps, nsamp, seed=9):
+    base, cond = _oracle(c)
+    g = np.random.Generator(np.random.PCG64(seed))
+    M, B = c["Z"].shape[0], c["X"].shape[0]
+    sp = {k: 0.0 for k in base}
+    for _ in range(nsamp):
+        keys = ("X", "Z", "ell", "Mt", "s", "L") + (("Y",) if c["lik"] == "gaussian" else ())
+        scale = {k: 1.0 + eps * g.standard_normal(np.shape(c[k])) for k in keys}
+        scale["sf2"] = 1.0 + eps * g.standard_normal()
+        scale["noise"] = 1.0 + eps * g.standard_normal()
+        du = eps * g.standard_normal((M, M))
+        pert = dict(Kuu=np.tril(du) + np.tril(du, -1).T, Kuf=eps * g.standard_normal((M, B)))
+        out, _ = _oracle(c, pert, scale)
+        for k in base:
+            sp[k] = max(sp[k], _rel(out[k], base[k], 1.0 if k == "KL" else 0.0))
+    return base, sp, cond
+
+
+def _dev(c):
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(np.atleast_1d(np.asarray(a, np.float32)))).to(dev)
+    return dict(X=t(c["X"]), Y=t(c["Y"]), ell=t(c["ell"]), sf2=t([c["sf2"]]),
+                noise=t([c["noise"]]) if c["lik"] == "gaussian" else None, Z=t(c["Z"]),
+                Mt=t(c["Mt"]), s=t(c["s"]), L=t(c["L"]))
+
+
+def _args(c, d):
+    return (d["X"], d["Y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], d["Mt"], d["s"],
+            d["L"])
+
+
+CASES = {
+    # name: (prec, lik, M, B, D, Q, B_max, s_range)
+    "fp32_gauss_M100_B150_Q3": ("fp32", "gaussian", 100, 150, 3, 3, 150, (0.05, 0.1)),
+    "fp32_probit_M64_B90_Q2": ("fp32", "probit", 64, 90, 2, 2, 128, (0.05, 0.1)),
+    "fp32_gauss_M130_B70_Q16": ("fp32", "gaussian", 130, 70, 4, 16, 96, (0.05, 0.1)),
+    "fp32_gauss_M512_B1024_D8_Q4": ("fp32", "gaussian", 512, 1024, 8, 4, 1024, (0.05, 0.1)),
+    "bf16_gauss_M200_B256_Q4": ("bf16", "gaussian", 200, 256, 4, 4, 256, (0.5, 1.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_multi_output_parity(require_gpu, name):
+    from paper_2604_00697_amd.lib import Context
+    prec, lik, M, B, D, Q, Bmax, sr = CASES[name]
+    c = _multi_case(M, B, D, Q, zlib.crc32(name.encode()) % 1000, lik, sr)
+    print(f"MULTI case {name} prec={prec} M={M} B={B} Q={Q}", flush=True)
+    ctx = Context(M, Bmax, D, prec, lik)
+    d = _dev(c)
+    want = [k for k in GK if k != "noise_var" or lik == "gaussian"]
+    F, terms = ctx.bound_multi(*_args(c, d))
+    g = ctx.bound_multi_bwd(*_args(c, d), want=want)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    t = terms.cpu().numpy()
+    gpu = dict(F=F.item(), data=t[0], KL=t[1], sum_var=t[2])
+    gpu.update({"grad_" + k: v.double().cpu().numpy() for k, v in g.items()})
+    for k, v in gpu.items():
+        assert np.all(np.isfinite(v)), k
+    ref, sp, cond = _sensitivity(c, EPS[prec], nsamp=2 if M > 150 else 3)
+    gate(name, prec, gpu, ref, sp, cond)
+    ctx.close()
+
+
+def test_multi_output_with_one_output_matches_single_output_entry_points(require_gpu):
+    from paper_2604_00697_amd.lib import Context
+    c = _multi_case(90, 120, 3, 1, 41)
+    ctx = Context(90, 128, 3, "fp32")
+    d = _dev(c)
+    F1, _ = ctx.bound_multi(*_args(c, d))
+    g1 = ctx.bound_multi_bwd(*_args(c, d))
+    y, m = d["Y"][:, 0].contiguous(), d["Mt"][0].contiguous()
+    sargs = (d["X"], y, c["N"], d["ell"], d["sf2"], d["noise"], d["Z"], m, d["s"], d["L"])
+    F2, _ = ctx.bound(*sargs)
+    g2 = ctx.bound_bwd(*sargs)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    assert abs(F1.item() - F2.item()) <= 1e-6 * abs(F2.item())
+    for k in g2:
+        a, b = g1[k].reshape(g2[k].shape).double(), g2[k].double()
+        assert float((a - b).norm() / b.norm()) <= 1e-4, k
+
+
+def test_multi_output_argument_errors_and_state(require_gpu):
+    from paper_2604_00697_amd import lib
+    from paper_2604_00697_amd.lib import Context, IFSVGPError
+    c = _multi_case(40, 50, 2, 2, 43)
+    ctx = Context(40, 64, 2, "fp32")
+    d = _dev(c)
+    with pytest.raises(IFSVGPError) as e:
+        ctx.bound_multi_bwd(*_args(c, d))
+    assert e.value.code == lib.ESTATE
+    out = torch.empty(1, dtype=torch.float64, device=d["X"].device)
+    p = lambda k: d[k].data_ptr()
+    f = ctx._lib.ifsvgp_bound_multi
+    for Q in (0, 17):
+        assert f(ctx._h, p("X"), p("Y"), 50, Q, c["N"], p("ell"), p("sf2"), p("noise"), p("Z"),
+                 p("Mt"), p("s"), p("L"), out.data_ptr(), None) == lib.EINVAL
+    ctx.bound_multi(*_args(c, d))
+    gs = torch.empty(40, device=d["X"].device)
+    assert ctx._lib.ifsvgp_bound_multi_bwd(
+        ctx._h, p("X"), p("Y"), 50, 2, c["N"], p("ell"), p("sf2"), p("noise"), p("Z"), p("Mt"),
+        p("s"), p("L"), None, None, None, None, None, None, gs.data_ptr()) == lib.EINVAL
+    with pytest.raises(ValueError):
+        ctx.bound_multi_bwd(*_args(c, d), want=("ell", "s"))
+    # another Q than the forward's
+    g = ctx._lib.ifsvgp_bound_multi_bwd(
+        ctx._h, p("X"), p("Y"), 50, 1, c["N"], p("ell"), p("sf2"), p("noise"), p("Z"), p("Mt"),
+        p("s"), p("L"), None, None, None, None, None, None, None)
+    assert g == lib.ESTATE
+    # one backward per forward; the exact backward needs its own forward
+    ctx.bound_multi_bwd(*_args(c, d))
+    with pytest.raises(IFSVGPError) as e:
+        ctx.bound_multi_bwd(*_args(c, d))
+    assert e.value.code == lib.ESTATE
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
