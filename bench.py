@@ -213,7 +213,8 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
     prediction at 4 B test points with their log densities and NLPD, the
     adaptive NG loop with the residual rule (4 checked steps, none stopped),
     the NG loop with the variance-gap rule (3 checked steps on one batch),
-    and one Adam step on Z."""
+    the Hutchinson bound, the multi-output bound with its gradient, and one
+    Adam step on Z."""
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
@@ -290,6 +291,32 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
             cu.close()
             del cu, du, om
             torch.cuda.empty_cache()
+    # multi-output (Q outputs sharing Z, the kernel, S~ and T) at the workload's
+    # shapes: bound and gradient for Q = 8 outputs in one call, against Q
+    # single-output bound + gradient calls on the same inputs
+    import numpy as np
+    Qm = 8
+    gq = np.random.Generator(np.random.PCG64(8))
+    Xb, yb = batches[0]
+    if w.lik == "gaussian":
+        Yq = yb[:, None] + 0.1 * torch.from_numpy(gq.standard_normal((w.B, Qm)).astype(np.float32)).to(dev)
+    else:
+        Yq = yb[:, None].repeat(1, Qm)
+    Yq = Yq.contiguous()
+    Mq = (par["m"][None, :] + 0.1 * torch.from_numpy(gq.standard_normal((Qm, w.M)).astype(np.float32)).to(dev)).contiguous()
+    margs = (Xb, Yq, w.N, par["ell"], par["sf2"], noise, par["Z"], Mq, par["s"], L0)
+    ms_multi = timed(lambda _: (ctx.bound_multi(*margs), ctx.bound_multi_bwd(*margs)))
+    ycols = [Yq[:, q].contiguous() for q in range(Qm)]
+
+    def singles(_):
+        for q in range(Qm):
+            a1 = (Xb, ycols[q], w.N, par["ell"], par["sf2"], noise, par["Z"], Mq[q], par["s"], L0)
+            ctx.bound(*a1)
+            ctx.bound_bwd(*a1)
+    ms_single = timed(singles)
+    out["multi_output"] = {"Q": Qm, "B": w.B, "with_grad_ms": round(ms_multi, 4),
+                           "single_output_calls_ms": round(ms_single, 4),
+                           "speedup": round(ms_single / ms_multi, 3)}
     g = torch.zeros_like(par["Z"]) + 1e-3
 
     def adam_setup():
