@@ -37,6 +37,9 @@ MUTATIONS = [
     ("svgp.py", "G_Kuu = TO - 0.25 * (A2 + A2.T)", "G_Kuu = TO + 0.25 * (A2 + A2.T)"),
     ("svgp.py", "A1 = T @ Kuu @ TO ", "A1 = T @ T @ TO "),
     ("svgp.py", "- 0.25 * (A1 + A1.T) - 0.5 * TO", "- 0.25 * (A1 + A1.T) + 0.5 * TO"),
+    ("svgp.py", 'out["m"] = np.stack([g["m"] for g in gs])', 'out["m"] = np.stack([g["m"] for g in gs[::-1]])'),
+    ("svgp.py", 'KL=sum(p["KL"] for p in parts)', 'KL=parts[0]["KL"]'),
+    ("svgp.py", "parts = [rsvgp_bound(X, Y[:, q], N", "parts = [rsvgp_bound(X, Y[:, 0], N"),
     ("quadrature.py", "* y / np.sqrt(2.0 * v)", "* y / np.sqrt(v)"),
     ("quadrature.py", "np.exp(log_phi - log_ndtr(z))", "np.exp(log_phi + log_ndtr(z))"),
     ("quadrature.py", "E = -0.5 * LOG_2PI - 0.5 * np.log(s2) - (r * r + v) / (2.0 * s2)",

@@ -649,14 +649,16 @@ def test_multi_output_bound_at_Ktilde_inverse_is_sum_of_cholesky_elbos(lik):
     p, Y, Mt = _multi_problem(31, lik=lik)
     out = svgp.multi_output_bound(p["X"], Y, p["N"], p["ell"], p["sf2"], p["noise_var"],
                                   p["Z"], Mt, p["s"], chol_Kinv(p), lik=lik)
-    tot = 0.0
+    tot = kl = 0.0
     for q in range(Mt.shape[0]):
         qm, qS = ref.lsvgp_q(p["ell"], p["sf2"], p["Z"], Mt[q], p["s"])
         ch = ref.cholesky_elbo(p["X"], Y[:, q], p["N"], p["ell"], p["sf2"], p["noise_var"],
                                p["Z"], qm, qS, lik=lik)
         tot += ch["F"]
+        kl += ch["KL"]
         assert np.allclose(out["mu"][q], ch["mu"], rtol=1e-9, atol=1e-12)
     assert np.isclose(out["F"], tot, rtol=1e-10, atol=1e-10)
+    assert np.isclose(out["KL"], kl, rtol=1e-9, atol=1e-10)
 
 
 @pytest.mark.parametrize("lik", ["gaussian", "probit"])
