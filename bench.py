@@ -388,7 +388,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the iteration's multi-GPU "
+        print("bench.py: the library runs on one GPU only (the iteration's multi-GPU "
               "sharding is a design, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
