@@ -173,3 +173,33 @@ def test_multi_output_argument_errors_and_state(require_gpu):
     assert e.value.code == lib.ESTATE
     torch.cuda.synchronize()
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_multi_output_full_size_C3(require_gpu, prec):
+    """The benchmark's C3 workload (M = 1024, B = 4096, D = 16, inputs from the
+    shared seeded generator, L near the fixed point) with Q = 4 outputs whose
+    targets and inducing means scatter around the workload's, the call the
+    benchmark's multi-output row times, against the oracle (one spread
+    sample: the oracle takes about half a minute here)."""
+    from paper_2604_00697_amd.lib import Context
+    from test_gpu_parity import full_size_case
+    c = full_size_case("C3")
+    Q = 4
+    g = np.random.Generator(np.random.PCG64(44))
+    B, M, D = c["X"].shape[0], c["Z"].shape[0], c["X"].shape[1]
+    c["Y"] = (c["y"][:, None] + 0.1 * g.standard_normal((B, Q))).astype(np.float32)
+    c["Mt"] = (c["m"][None, :] + 0.1 * g.standard_normal((Q, M))).astype(np.float32)
+    print(f"MULTI full size C3 prec={prec} M={M} B={B} Q={Q}", flush=True)
+    ctx = Context(M, B, D, prec, c["lik"])
+    d = _dev(c)
+    F, terms = ctx.bound_multi(*_args(c, d))
+    gg = ctx.bound_multi_bwd(*_args(c, d))
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    t = terms.cpu().numpy()
+    gpu = dict(F=F.item(), data=t[0], KL=t[1], sum_var=t[2])
+    gpu.update({"grad_" + k: v.double().cpu().numpy() for k, v in gg.items()})
+    ref, sp, cond = _sensitivity(c, EPS[prec], nsamp=1)
+    gate(f"multi_full_C3_{prec}", prec, gpu, ref, sp, cond)
+    ctx.close()
