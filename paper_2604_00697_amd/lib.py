@@ -314,6 +314,7 @@ class Context:
         _check(self._lib.ifsvgp_bound_multi(
             self._h, x, y, B, Q, float(N), *rest, _ptr(out, (1,), "out", torch.float64),
             _ptr(terms, (N_TERMS,), "terms", torch.float64)), "ifsvgp_bound_multi")
+        self.generation += 1
         return out, terms
 
     def bound_multi_bwd(self, X, Y, N, ell, sf2, noise, Z, Mt, s, L, grad_scale=None,

@@ -203,3 +203,22 @@ def test_multi_output_full_size_C3(require_gpu, prec):
     ref, sp, cond = _sensitivity(c, EPS[prec], nsamp=1)
     gate(f"multi_full_C3_{prec}", prec, gpu, ref, sp, cond)
     ctx.close()
+
+
+def test_multi_output_autograd_matches_backward_entry_point(require_gpu):
+    from paper_2604_00697_amd.autograd import ifsvgp_bound_multi
+    from paper_2604_00697_amd.lib import Context
+    c = _multi_case(80, 100, 3, 3, 45)
+    ctx = Context(80, 128, 3, "fp32")
+    d = _dev(c)
+    leaves = {k: d[k].clone().requires_grad_(True) for k in ("ell", "sf2", "noise", "Z", "Mt")}
+    F, _ = ifsvgp_bound_multi(ctx, d["X"], d["Y"], c["N"], leaves["ell"], leaves["sf2"],
+                              leaves["noise"], leaves["Z"], leaves["Mt"], d["s"], d["L"])
+    (-2.0 * F).backward()
+    ctx.bound_multi(*_args(c, d))
+    g = ctx.bound_multi_bwd(*_args(c, d))
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for k, name in (("ell", "ell"), ("sf2", "sf2"), ("noise", "noise_var"), ("Z", "Z"),
+                    ("Mt", "m")):
+        assert torch.equal(leaves[k].grad, -2.0 * g[name]), k
