@@ -916,7 +916,7 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
   }
   {
     Timed t(c, KK_VALPHA);
-    hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+    hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                        (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                        (const float *)c->sqnb, (T *)c->Vs, c->vVa);
   }
@@ -1176,7 +1176,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
     Timed t(c, KK_R);
     HIPCK(Ops<T>::gemm_R(c, 0, B));
   }
-  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                      (const float *)c->sqnb, (T *)c->Vs, c->vVa);
   hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), rup(nr, 64)), dim3(NTB), 0, c->st,
@@ -1559,7 +1559,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
     OnSide side(c);
     HIPCK(Ops<T>::gemm_R(c, 0, B, c->mo_zero, c->mo_half, c->mo_half));
   }
-  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->alpha,
                      (const float *)c->sqnb, (T *)c->Vs, c->vVa);
   HIPCK(Ops<T>::syrk(c, B));

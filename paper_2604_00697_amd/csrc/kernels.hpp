@@ -860,21 +860,24 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
   }
 }
 
-// One wave per row of the operand-type V: (V alpha)_i and the scaled copy
-// Vs[i][n] = V[i][n] sqnb[n] over the whole padded row, the operand of the
-// batch product (V D)(V D)^T.  alpha and sqnb are zero for n >= B (set by the
-// likelihood kernel), so padded entries contribute nothing and Vs is zero there.
+// One workgroup per row of the operand-type V (its four waves split the row):
+// (V alpha)_i and the scaled copy Vs[i][n] = V[i][n] sqnb[n] over the whole
+// padded row, the operand of the batch product (V D)(V D)^T.  alpha and sqnb
+// are zero for n >= B (set by the likelihood kernel), so padded entries
+// contribute nothing and Vs is zero there.  Launch with M workgroups.
 template <typename T>
-__global__ void k_valpha(const T *V, long ld, int M, int Bp, const float *alpha,
-                         const float *sqnb, T *Vs, float *out) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
-  if (row >= M) return;
+__global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int Bp,
+                                                const float *alpha, const float *sqnb, T *Vs,
+                                                float *out) {
+  __shared__ float shw[NTB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x;
+  if (row >= M) return;  // uniform across the workgroup
   constexpr int KPL = 16 / (int)sizeof(T);
   const T *v = V + (long)row * ld;
   T *vs = Vs + (long)row * ld;
   float s = 0.f;
-  for (int n = lane * KPL; n < Bp; n += 64 * KPL) {  // Bp is a multiple of KPL
+  for (int n = (int)threadIdx.x * KPL; n < Bp; n += NTB * KPL) {  // Bp is a multiple of KPL
     const uint4 raw = *(const uint4 *)(v + n);
     const T *e = (const T *)&raw;
     float al[KPL], sq[KPL];
@@ -898,7 +901,14 @@ __global__ void k_valpha(const T *V, long ld, int M, int Bp, const float *alpha,
     *(uint4 *)(vs + n) = sraw;
   }
   s = wave_sum(s);
-  if (lane == 0) out[row] = s;
+  if (lane == 0) shw[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < NTB / 64; ++w) t += shw[w];
+    out[row] = t;
+  }
 }
 
 // All gradient reductions in one launch, with blocks of three roles:
