@@ -1093,6 +1093,9 @@ static int enqueue_predict(ifsvgp_ctx *c, const CallArgs &ca0, const PredOut &o)
 // then the thin products with Xc = [V | Omega | a], the row reductions, the
 // trace estimates, b^T Wu b by matrix-vector products, and the likelihood
 // kernel's finalisation of F.  No M x M x M product.
+// grid.y limit of a launch; kernels with a row index in y loop over it
+static constexpr int kMaxGridY = 65535;
+
 template <typename T>
 static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Omt, int K) {
   c->ev_next = 0;
@@ -1113,7 +1116,8 @@ static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
                        (const float *)c->Lt32[0], Mp, M, (const CallArgs *)c->dca, c->va);
   }
   HIPCK(join_side(c));
-  hipLaunchKernelGGL((k_hutch_fill<T>), dim3(cdiv(c->Mp, NTB), K + 1), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL((k_hutch_fill<T>), dim3(cdiv(c->Mp, NTB), std::min(K + 1, kMaxGridY)),
+                     dim3(NTB), 0, c->st,
                      (T *)c->Vt, Mp, B, K, Omt, (const float *)c->va, M, c->Mp);
   HIPCK(Ops<T>::hutch_L(c, NC));
   HIPCK(Ops<T>::hutch_K(c, NC));
@@ -1179,10 +1183,11 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
   hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                      (const float *)c->sqnb, (T *)c->Vs, c->vVa);
-  hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), rup(nr, 64)), dim3(NTB), 0, c->st,
-                     (const T *)c->Vt, Omt, (const float *)c->hwx, (const float *)c->hex,
-                     (const float *)c->vVa, (const float *)c->vWub, (const float *)c->va,
-                     (const float *)c->vb, B, K, M, c->Mp, (T *)c->hxt);
+  hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), std::min(rup(nr, 64), kMaxGridY)),
+                     dim3(NTB), 0, c->st, (const T *)c->Vt, Omt, (const float *)c->hwx,
+                     (const float *)c->hex, (const float *)c->vVa, (const float *)c->vWub,
+                     (const float *)c->va, (const float *)c->vb, B, K, M, c->Mp, rup(nr, 64),
+                     (T *)c->hxt);
   HIPCK(Ops<T>::hutch_LX(c, nr));
   hipLaunchKernelGGL((k_hutch_mix<TW>), dim3(grid1((long)c->Mp * Ops<T>::ldr(c))), dim3(NTB), 0,
                      c->st, (const TW *)c->hy1, (TW *)c->hy2, Ops<T>::ldr(c), M, c->Mp, B, K,
@@ -1551,9 +1556,9 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
   hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Mp, NTB)), dim3(NTB), 0, c->st, c->mo_zero, c->Mp, 0.f);
   hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, c->mo_half, c->Bp,
                      -0.5f);
-  hipLaunchKernelGGL((k_mo_u3<T>), dim3(cdiv(M, NTB), B), dim3(NTB), 0, c->st, (T *)c->Ut, Mp,
-                     M, (const float *)c->mo_b, Mp, (const float *)c->mo_al, Bp, Q,
-                     (const float *)c->beta);
+  hipLaunchKernelGGL((k_mo_u3<T>), dim3(cdiv(M, NTB), std::min(B, kMaxGridY)), dim3(NTB), 0,
+                     c->st, (T *)c->Ut, Mp, M, B, (const float *)c->mo_b, Mp,
+                     (const float *)c->mo_al, Bp, Q, (const float *)c->beta);
   HIPCK(fork_side(c));
   {
     OnSide side(c);

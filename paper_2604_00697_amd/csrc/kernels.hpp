@@ -634,7 +634,7 @@ __global__ void k_predict_sum(const double *part, int nparts, double *scal, int 
 template <typename T>
 __global__ void k_hutch_fill(T *Vt, long ld, int B, int K, const float *Omt, const float *a,
                              int M, int Mp) {
-  const int r = blockIdx.y;  // 0..K: probe rows, then a
+  for (int r = blockIdx.y; r <= K; r += gridDim.y)  // 0..K: probe rows, then a
   for (int i = blockIdx.x * NTB + threadIdx.x; i < Mp; i += gridDim.x * NTB) {
     float v = 0.f;
     if (i < M) v = r < K ? Omt[(long)r * M + i] : a[i];
@@ -734,9 +734,9 @@ __global__ void k_hutch_final(const double *hp, int K, double *gram_part) {
 template <typename T>
 __global__ void k_hutch_X(const T *Vt, const float *Omt, const float *wx, const float *ex,
                           const float *Va, const float *Wub, const float *a, const float *b,
-                          int B, int K, int M, int Mp, T *Xt) {
-  const int q = blockIdx.y;
+                          int B, int K, int M, int Mp, int rows, T *Xt) {
   const long ld = Mp;
+  for (int q = blockIdx.y; q < rows; q += gridDim.y)
   for (int i = blockIdx.x * NTB + threadIdx.x; i < Mp; i += gridDim.x * NTB) {
     float v = 0.f;
     if (i < M) {
@@ -1216,14 +1216,15 @@ __global__ void k_mo_x(const T *V, long ld, int M, int Bp, const float *al, long
 // Rows n < B of Ut become sum_q b_q alpha_qn - 2 beta_n U_n, so that L times
 // them is G_uf = sum_q (P m~_q) alpha_q^T - 2 P K_uf diag(beta) directly
 template <typename T>
-__global__ void k_mo_u3(T *Ut, long ld, int M, const float *Bh, long ldb, const float *al,
-                        long lda, int Q, const float *beta) {
-  const int n = blockIdx.y;
-  const float bn = -2.f * beta[n];
-  for (int i = blockIdx.x * NTB + threadIdx.x; i < M; i += gridDim.x * NTB) {
-    float v = bn * to_f32(Ut[(long)n * ld + i]);
-    for (int q = 0; q < Q; ++q) v = fmaf(Bh[q * ldb + i], al[q * lda + n], v);
-    Ut[(long)n * ld + i] = from_f32<T>(v);
+__global__ void k_mo_u3(T *Ut, long ld, int M, int B, const float *Bh, long ldb,
+                        const float *al, long lda, int Q, const float *beta) {
+  for (int n = blockIdx.y; n < B; n += gridDim.y) {
+    const float bn = -2.f * beta[n];
+    for (int i = blockIdx.x * NTB + threadIdx.x; i < M; i += gridDim.x * NTB) {
+      float v = bn * to_f32(Ut[(long)n * ld + i]);
+      for (int q = 0; q < Q; ++q) v = fmaf(Bh[q * ldb + i], al[q * lda + n], v);
+      Ut[(long)n * ld + i] = from_f32<T>(v);
+    }
   }
 }
 
