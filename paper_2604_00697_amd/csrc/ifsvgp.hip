@@ -1526,7 +1526,7 @@ static int enqueue_multi(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
   HIPCK(join_side(c));
   HIPCK(Ops<T>::gemm_U(c, B));
   hipLaunchKernelGGL((k_mo_mu<T>), dim3(cdiv(B, NTB / 64)), dim3(NTB), 0, c->st,
-                     (const T *)c->Vt, Mp, M, B, (const float *)c->mo_b, Mp, Q, c->mo_mu, Bp);
+                     (const T *)c->Vt, Mp, c->Mp, B, (const float *)c->mo_b, Mp, Q, c->mo_mu, Bp);
   LikMoArgs a{c->var_part, cdiv(M, 128), Bp, c->dca, Y, Q, B, c->Bp, c->sfn, c->lik, c->gh,
               c->ngh, c->mo_mu, c->mo_al, Bp, c->alpha, c->beta, c->sqnb, c->lik_part,
               c->tp_gram, cdiv(M, 64) * (cdiv(M, 64) + 1) / 2, c->mo_b, c->mo_wub, Mp,
@@ -1568,7 +1568,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->alpha,
                      (const float *)c->sqnb, (T *)c->Vs, c->vVa);
   HIPCK(Ops<T>::syrk(c, B));
-  hipLaunchKernelGGL((k_mo_x<T>), dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL((k_mo_x<T>), dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->mo_al, Bp, Q,
                      (const float *)c->mo_wub, Mp, c->mo_x);
   hipLaunchKernelGGL(k_assemble_C_mo<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0,

@@ -1161,11 +1161,13 @@ __global__ void k_mo_gemv(const float *A, long lda, int R, int Cn, const float *
   if ((threadIdx.x & 63) == 0) Y[q * ldy + row] = scale ? (float)(*scale * (double)s) : s;
 }
 
-// mu[q][n] = b_q^T V_n = k_n^T P m~_q (V_n: row n of the operand-type Vt), one
-// wave per batch point
+// mu[q][n] = b_q^T V_n = k_n^T P m~_q (V_n: row n of the operand-type Vt,
+// zero-padded to cols, a multiple of 16 bytes of it), one wave per batch
+// point, 16-byte loads
 template <typename T>
-__global__ void k_mo_mu(const T *Vt, long ld, int M, int B, const float *Bh, long ldb, int Q,
+__global__ void k_mo_mu(const T *Vt, long ld, int cols, int B, const float *Bh, long ldb, int Q,
                         float *mu, long ldm) {
+  constexpr int KPL = 16 / (int)sizeof(T);
   const int n = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (n >= B) return;
@@ -1173,11 +1175,25 @@ __global__ void k_mo_mu(const T *Vt, long ld, int M, int B, const float *Bh, lon
 #pragma unroll
   for (int q = 0; q < MO_QMAX; ++q) acc[q] = 0.f;
   const T *v = Vt + (long)n * ld;
-  for (int i = lane; i < M; i += 64) {
-    const float x = to_f32(v[i]);
+  for (int i = lane * KPL; i < cols; i += 64 * KPL) {
+    const uint4 raw = *(const uint4 *)(v + i);
+    const T *e = (const T *)&raw;
+    float x[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) x[u] = to_f32(e[u]);
 #pragma unroll
     for (int q = 0; q < MO_QMAX; ++q)
-      if (q < Q) acc[q] = fmaf(x, Bh[q * ldb + i], acc[q]);
+      if (q < Q) {
+        const float *b = Bh + q * ldb + i;
+#pragma unroll
+        for (int u = 0; u < KPL; u += 4) {
+          const f32x4 b4 = *(const f32x4 *)(b + u);
+          acc[q] = fmaf(x[u], b4[0], acc[q]);
+          acc[q] = fmaf(x[u + 1], b4[1], acc[q]);
+          acc[q] = fmaf(x[u + 2], b4[2], acc[q]);
+          acc[q] = fmaf(x[u + 3], b4[3], acc[q]);
+        }
+      }
   }
 #pragma unroll
   for (int q = 0; q < MO_QMAX; ++q)
@@ -1187,30 +1203,56 @@ __global__ void k_mo_mu(const T *Vt, long ld, int M, int B, const float *Bh, lon
     }
 }
 
-// x_q = V alpha_q - Wu b_q, one wave per row of the operand-type V ([Mp][Bp];
-// alpha_q zero for n >= B)
+// x_q = V alpha_q - Wu b_q, one workgroup per row of the operand-type V
+// ([Mp][Bp]; alpha_q zero for n >= B), its waves splitting the row, 16-byte
+// loads.  Launch with M workgroups.
 template <typename T>
-__global__ void k_mo_x(const T *V, long ld, int M, int Bp, const float *al, long lda, int Q,
-                       const float *Wub, long ldw, float *Xq) {
-  const int i = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= M) return;
+__global__ __launch_bounds__(NTB) void k_mo_x(const T *V, long ld, int M, int Bp,
+                                              const float *al, long lda, int Q,
+                                              const float *Wub, long ldw, float *Xq) {
+  constexpr int KPL = 16 / (int)sizeof(T);
+  __shared__ float shq[MO_QMAX][NTB / 64];
+  const int i = blockIdx.x;
+  if (i >= M) return;  // uniform across the workgroup
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float acc[MO_QMAX];
 #pragma unroll
   for (int q = 0; q < MO_QMAX; ++q) acc[q] = 0.f;
   const T *v = V + (long)i * ld;
-  for (int n = lane; n < Bp; n += 64) {
-    const float x = to_f32(v[n]);
+  for (int n = (int)threadIdx.x * KPL; n < Bp; n += NTB * KPL) {  // Bp is a multiple of KPL
+    const uint4 raw = *(const uint4 *)(v + n);
+    const T *e = (const T *)&raw;
+    float x[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) x[u] = to_f32(e[u]);
 #pragma unroll
     for (int q = 0; q < MO_QMAX; ++q)
-      if (q < Q) acc[q] = fmaf(x, al[q * lda + n], acc[q]);
+      if (q < Q) {
+        const float *a = al + q * lda + n;
+#pragma unroll
+        for (int u = 0; u < KPL; u += 4) {
+          const f32x4 a4 = *(const f32x4 *)(a + u);
+          acc[q] = fmaf(x[u], a4[0], acc[q]);
+          acc[q] = fmaf(x[u + 1], a4[1], acc[q]);
+          acc[q] = fmaf(x[u + 2], a4[2], acc[q]);
+          acc[q] = fmaf(x[u + 3], a4[3], acc[q]);
+        }
+      }
   }
 #pragma unroll
   for (int q = 0; q < MO_QMAX; ++q)
     if (q < Q) {
       const float s = wave_sum(acc[q]);
-      if (lane == 0) Xq[q * ldw + i] = s - Wub[q * ldw + i];
+      if (lane == 0) shq[q][wave] = s;
     }
+  __syncthreads();
+  if ((int)threadIdx.x < Q) {
+    const int q = threadIdx.x;
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < NTB / 64; ++w) t += shq[q][w];
+    Xq[q * ldw + i] = t - Wub[q * ldw + i];
+  }
 }
 
 // Rows n < B of Ut become sum_q b_q alpha_qn - 2 beta_n U_n, so that L times
