@@ -1556,7 +1556,9 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
   hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Mp, NTB)), dim3(NTB), 0, c->st, c->mo_zero, c->Mp, 0.f);
   hipLaunchKernelGGL(k_fill, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, c->mo_half, c->Bp,
                      -0.5f);
-  hipLaunchKernelGGL((k_mo_u3<T>), dim3(cdiv(M, NTB), std::min(B, kMaxGridY)), dim3(NTB), 0,
+  hipLaunchKernelGGL((k_mo_u3<T>),
+                     dim3(cdiv(cdiv(M, 16 / (int)sizeof(T)), NTB), std::min(B, kMaxGridY)),
+                     dim3(NTB), 0,
                      c->st, (T *)c->Ut, Mp, M, B, (const float *)c->mo_b, Mp,
                      (const float *)c->mo_al, Bp, Q, (const float *)c->beta);
   HIPCK(fork_side(c));

@@ -1256,16 +1256,40 @@ __global__ __launch_bounds__(NTB) void k_mo_x(const T *V, long ld, int M, int Bp
 }
 
 // Rows n < B of Ut become sum_q b_q alpha_qn - 2 beta_n U_n, so that L times
-// them is G_uf = sum_q (P m~_q) alpha_q^T - 2 P K_uf diag(beta) directly
+// them is G_uf = sum_q (P m~_q) alpha_q^T - 2 P K_uf diag(beta) directly.
+// 16 bytes of a row per thread (rows padded to ld, a multiple of that; U and
+// b_q are zero beyond M, so the padding stays zero).  grid.x covers
+// ceil(M / KPL) chunks, grid.y the rows.
 template <typename T>
 __global__ void k_mo_u3(T *Ut, long ld, int M, int B, const float *Bh, long ldb,
                         const float *al, long lda, int Q, const float *beta) {
+  constexpr int KPL = 16 / (int)sizeof(T);
+  const int chunks = (M + KPL - 1) / KPL;
   for (int n = blockIdx.y; n < B; n += gridDim.y) {
     const float bn = -2.f * beta[n];
-    for (int i = blockIdx.x * NTB + threadIdx.x; i < M; i += gridDim.x * NTB) {
-      float v = bn * to_f32(Ut[(long)n * ld + i]);
-      for (int q = 0; q < Q; ++q) v = fmaf(Bh[q * ldb + i], al[q * lda + n], v);
-      Ut[(long)n * ld + i] = from_f32<T>(v);
+    for (int c = blockIdx.x * NTB + threadIdx.x; c < chunks; c += gridDim.x * NTB) {
+      const int i = c * KPL;
+      T *p = Ut + (long)n * ld + i;
+      uint4 raw = *(const uint4 *)p;
+      T *e = (T *)&raw;
+      float v[KPL];
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) v[u] = bn * to_f32(e[u]);
+      for (int q = 0; q < Q; ++q) {
+        const float a = al[q * lda + n];
+        const float *b = Bh + q * ldb + i;
+#pragma unroll
+        for (int u = 0; u < KPL; u += 4) {
+          const f32x4 b4 = *(const f32x4 *)(b + u);
+          v[u] = fmaf(b4[0], a, v[u]);
+          v[u + 1] = fmaf(b4[1], a, v[u + 1]);
+          v[u + 2] = fmaf(b4[2], a, v[u + 2]);
+          v[u + 3] = fmaf(b4[3], a, v[u + 3]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KPL; ++u) e[u] = from_f32<T>(v[u]);
+      *(uint4 *)p = raw;
     }
   }
 }
