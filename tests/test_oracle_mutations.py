@@ -17,6 +17,8 @@ MUTATIONS = [
     ("svgp.py", "- logdetT - np.sum(np.log(s)))", "- logdetT + np.sum(np.log(s)))"),
     ("svgp.py", "+ m @ P @ Kuu @ P @ m", "+ m @ Kuu @ P @ m"),
     ("svgp.py", "X = np.tril(W) - 0.5", "X = np.tril(W, -1) - 0.5"),
+    ("svgp.py", '"fro") / np.sqrt(M)', '"fro")'),
+    ("svgp.py", '"fro") / np.sqrt(M)', '"fro") / M'),
     ("svgp.py", "return L @ X", "return X @ L"),
     ("svgp.py", "G_Kt = -T @ G_P @ T - 0.5 * T", "G_Kt = -T @ G_P @ T + 0.5 * T"),
     ("svgp.py", "g_m = P @ Ka - P @ KPm", "g_m = P @ Ka - Kuu @ KPm"),

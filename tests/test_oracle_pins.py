@@ -267,6 +267,30 @@ def test_natgrad_fixed_point_and_quadratic_convergence():
     assert np.allclose(Ln @ Ln.T, np.linalg.inv(Kt), rtol=1e-9, atol=1e-9)
 
 
+@pytest.mark.parametrize("M", [1, 4, 9, 37])
+def test_ng_residual_closed_forms(M):
+    """eq. stopping_frobenius divides the Frobenius norm by sqrt(M): with
+    A = I and L = c I every diagonal entry of W - I is c^2 - 1, so the
+    residual is |c^2 - 1| at every M; with L = sqrt(2) chol(A^{-1}) for a
+    random SPD A, W = 2 I and the residual is exactly 1."""
+    for c in (0.5, 1.0, 1.7):
+        assert np.isclose(svgp.ng_residual(c * np.eye(M), np.eye(M)), abs(c * c - 1.0),
+                          rtol=1e-12, atol=1e-15)
+    g = _rng(40 + M)
+    R = g.standard_normal((M, M))
+    A = R @ R.T + M * np.eye(M)
+    L = np.sqrt(2.0) * np.linalg.cholesky(np.linalg.inv(A))
+    assert np.isclose(svgp.ng_residual(L, A), 1.0, rtol=1e-10)
+    # one symmetric off-diagonal perturbation e of W = I: ||.||_F = sqrt(2) e
+    if M > 1:
+        e = 1e-3
+        W = np.eye(M)
+        W[1, 0] = W[0, 1] = e
+        Lw = np.linalg.cholesky(np.linalg.inv(A))
+        Aw = np.linalg.inv(Lw.T) @ W @ np.linalg.inv(Lw)
+        assert np.isclose(svgp.ng_residual(Lw, Aw), np.sqrt(2.0) * e / np.sqrt(M), rtol=1e-6)
+
+
 def test_loglinear_schedule_endpoints():
     gm = svgp.loglinear_gammas(12)
     assert np.isclose(gm[0], 1e-5) and np.isclose(gm[9], 1.0) and np.isclose(gm[11], 1.0)
