@@ -68,7 +68,8 @@ enum ifsvgp_status_code {
   IFSVGP_EHIP = -3,        /* a HIP runtime call failed                        */
   IFSVGP_ENONFINITE = -4,  /* the bound or the updated L is not finite         */
   IFSVGP_ENOMEM = -5,      /* workspace allocation failed                      */
-  IFSVGP_ESTATE = -6       /* ifsvgp_bound_bwd without a matching forward      */
+  IFSVGP_ESTATE = -6,      /* ifsvgp_bound_bwd without a matching forward      */
+  IFSVGP_ESCRATCH = -7     /* too large for ifsvgp_step_noalloc's workspace    */
 };
 
 /* Indices into out_terms[IFSVGP_N_TERMS] (device fp64). */
@@ -305,6 +306,39 @@ int ifsvgp_step(ifsvgp_ctx *ctx, const float *X, const float *y, int B, double N
                 double *out_bound, double *out_terms, double *out_resid,
                 float *g_ell, float *g_sf2, float *g_noise, float *g_Z,
                 float *g_m, float *g_s);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * training iteration of ifsvgp_step without a context.  It calls no
+ * hipMalloc, hipFree, stream or event creation.  Its workspace is a static
+ * device array of 64 MiB (IFSVGP_NOALLOC_SCRATCH_BYTES) that every device
+ * the library runs on holds from module load until the process ends; the
+ * call lays the workspace out for its own (M, B, D, prec, lik), and returns
+ * IFSVGP_ESCRATCH, with nothing enqueued, when that exceeds the array (for
+ * example M = 512, B = 1024, D = 8 fits in fp32; M = 1024, B = 4096 does not).
+ * A fill kernel zeroes the used part at the start of every call, so no state
+ * carries over between calls; the array keeps the last call's contents
+ * until the next one.  All work is enqueued on hip_stream (hipStream_t
+ * passed as void*; the device current at the call must own it), in stream
+ * order, and may be captured into a HIP graph by the caller.  Calls that
+ * overlap on one device race on its array: the host side of calls from
+ * several threads is serialised per device, but the caller must keep the
+ * GPU work of two calls on one device in order (one stream, or events).
+ * Arguments and results are those of ifsvgp_step (device pointers; gammas
+ * on the host; gradient outputs may be NULL; B >= 1 is the batch size, with
+ * no separate B_max), plus the context's creation parameters M, D, prec,
+ * lik and n_gh as in ifsvgp_create.  Device value errors are not kept in a
+ * sticky flag: out_flag (device int[1] or NULL) receives this call's flag
+ * bits, 0 when clean, 1 for a domain error (non-positive ell, sf2,
+ * noise_var or s~, or L_ii == 0), 2 for a non-finite bound or factor. */
+#define IFSVGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ifsvgp_step_noalloc(void *hip_stream, int M, int D, int prec, int lik, int n_gh,
+                        const float *X, const float *y, int B, double N_total,
+                        const float *ell, const float *sf2, const float *noise_var,
+                        const float *Z, const float *m_tilde, const float *s_tilde, float *L,
+                        const float *gammas, int n_ng, double *out_bound, double *out_terms,
+                        double *out_resid, float *g_ell, float *g_sf2, float *g_noise,
+                        float *g_Z, float *g_m, float *g_s, int *out_flag);
 
 /* One Adam step (Kingma and Ba's algorithm, with bias correction) on n fp32
  * parameters, enqueued on the context's stream: with g' = grad (or -grad when

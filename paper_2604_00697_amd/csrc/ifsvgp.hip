@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -75,6 +76,7 @@ struct ifsvgp_ctx {
   hipEvent_t evs[kEvents];  // fork / join points of one call, in order
   int ev_next;
   bool side_open;           // the side stream has work not yet joined into st
+  bool single_stream;       // side is st: branches run in stream order, no events
   bool capturing;           // launches are being recorded into a graph
   // device argument block of the current call, written by its k_latch
   CallArgs *dca;
@@ -209,6 +211,7 @@ static hipError_t join_side(ifsvgp_ctx *c) {
   return e;
 }
 static hipError_t fork_side(ifsvgp_ctx *c) {
+  if (c->single_stream) return hipSuccess;
   hipError_t e = c->capturing ? join_side(c) : hipSuccess;
   if (e != hipSuccess) return e;
   hipEvent_t ev = next_event(c);
@@ -224,28 +227,142 @@ struct OnSide {
   ~OnSide() { c->st = saved; }
 };
 
-static hipError_t dmalloc_bytes(ifsvgp_ctx *c, void **p, size_t bytes) {
-  void *q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 16));
-  if (e != hipSuccess) return e;
-  e = hipMemset(q, 0, std::max<size_t>(bytes, 16));
-  c->allocs.push_back(q);
-  *p = q;
-  return e;
-}
-template <typename T>
-static hipError_t dmalloc(ifsvgp_ctx *c, T **p, size_t n) {
-  void *q = nullptr;
-  hipError_t e = dmalloc_bytes(c, &q, n * sizeof(T));
-  *p = (T *)q;
-  return e;
-}
-
 // bytes of the MFMA operand type and of the wide-range type used for the two
 // products with the backward matrix C (fp16 would overflow there, so the
 // fp16 form runs them in fp32)
 static size_t op_size(int prec) { return prec == IFSVGP_PREC_FP32 ? 4 : 2; }
 static size_t wide_size(int prec) { return prec == IFSVGP_PREC_BF16 ? 2 : 4; }
+
+// ------------------------------------------------------------------ workspace layout
+// Every workspace buffer of a context is carved, 256-byte aligned, from one
+// slab.  layout() assigns the pointers from `base` (null: only count) and
+// returns the slab's size in bytes for (M, B_max, D, prec, lik).  extras
+// adds the buffers of the Hutchinson bound and its gradient; without them
+// the slab serves the training iteration, its split entry points and the
+// multi-output layer only (their pointers are left null).
+struct Carve {
+  char *base;
+  size_t off;
+  void *bytes(size_t n) {
+    void *p = base ? (void *)(base + off) : nullptr;
+    off += (std::max<size_t>(n, 16) + 255) / 256 * 256;
+    return p;
+  }
+  template <typename T>
+  void take(T *&p, size_t n) { p = (T *)bytes(n * sizeof(T)); }
+};
+
+static size_t layout(ifsvgp_ctx *c, char *base, bool extras) {
+  Carve w{base, 0};
+  const int M = c->M, B_max = c->Bmax, D = c->D, prec = c->prec;
+  const size_t Mp = c->Mp, Bp = c->Bp;
+  const size_t MM = Mp * Mp, MB = Mp * Bp;
+  const size_t os = op_size(prec), ws = wide_size(prec);
+  const bool f32 = prec == IFSVGP_PREC_FP32;
+  const int nb64 = cdiv(M, 64), nb128 = cdiv(M, 128), nbB = cdiv(B_max, 128);
+  const int nt_sym64 = nb64 * (nb64 + 1) / 2;
+  w.take(c->Kt, MM);
+  w.take(c->L32[0], MM);
+  w.take(c->L32[1], MM);
+  w.take(c->W32, MM);
+  w.take(c->Q32, MM);
+  w.take(c->Wu32, MM);
+  w.take(c->Ys, MM * c->nsplit);
+  if (f32) {
+    c->KtT = c->Kt; c->LT[0] = c->L32[0]; c->LT[1] = c->L32[1]; c->QT = c->Q32;
+  } else {
+    c->KtT = w.bytes(MM * os);
+    c->LT[0] = w.bytes(MM * os);
+    c->LT[1] = w.bytes(MM * os);
+    c->QT = w.bytes(MM * os);
+  }
+  c->LtT[0] = w.bytes(MM * os);
+  c->LtT[1] = w.bytes(MM * os);
+  c->LstT[0] = w.bytes(MM * os);
+  c->LstT[1] = w.bytes(MM * os);
+  if (f32) {
+    c->Lt32[0] = (float *)c->LtT[0];
+    c->Lt32[1] = (float *)c->LtT[1];
+  } else {
+    w.take(c->Lt32[0], MM);
+    w.take(c->Lt32[1], MM);
+  }
+  c->Yt = w.bytes(MM * os);
+  c->Xgt = w.bytes(MM * os);
+  c->Cm = w.bytes(MM * ws);
+  c->Y2 = w.bytes(MM * ws);
+  c->Kft = w.bytes(MB * os);
+  c->V = w.bytes(MB * os);
+  c->Vt = w.bytes(MB * os);
+  c->Ut = w.bytes(MB * os);
+  c->Vs = w.bytes(MB * os);
+  w.take(c->Zs, (size_t)M * D);
+  w.take(c->Xs, (size_t)B_max * D);
+  w.take(c->inv_ell, (size_t)D);
+  w.take(c->sP, Mp);
+  w.take(c->va, Mp);
+  w.take(c->vb, Mp);
+  w.take(c->vLb, Mp);
+  w.take(c->vWub, Mp);
+  w.take(c->vVa, Mp);
+  w.take(c->vt2, Mp);
+  w.take(c->mu_part, (size_t)nb64 * Bp);
+  w.take(c->var_part, (size_t)nb128 * Bp);
+  w.take(c->mu, Bp);
+  w.take(c->var, Bp);
+  w.take(c->alpha, Bp);
+  w.take(c->beta, Bp);
+  w.take(c->sqnb, Bp);
+  w.take(c->hrow, (size_t)nbB * M);
+  w.take(c->hcol, (size_t)nb128 * Bp);
+  w.take(c->hx, (size_t)nbB * M * D);
+  w.take(c->hzrow, (size_t)nb64 * M);
+  w.take(c->hz, (size_t)nb64 * M * D);
+  w.take(c->gdiag, Mp);
+  w.take(c->pdiag, (size_t)nb64 * Mp);
+  w.take(c->scal, (size_t)S_NSLOT);
+  w.take(c->tp_ng, (size_t)nt_sym64);
+  w.take(c->tp_gram, (size_t)3 * nt_sym64);
+  w.take(c->tp_uf, (size_t)nb128 * nbB);
+  w.take(c->tp_uu, (size_t)nt_sym64);
+  w.take(c->tp_gap, (size_t)nb128 * cdiv(Bp, 64));
+  w.take(c->mo_m, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_a, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_b, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_wub, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_x, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_t2, (size_t)MO_QMAX * Mp);
+  w.take(c->mo_mu, (size_t)MO_QMAX * Bp);
+  w.take(c->mo_al, (size_t)MO_QMAX * Bp);
+  w.take(c->mo_zero, Mp);
+  w.take(c->mo_half, Bp);
+  w.take(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
+  w.take(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
+  w.take(c->ell_part, (size_t)(M + B_max + 64) * D);
+  w.take(c->gh, (size_t)2 * std::max(1, c->ngh));
+  w.take(c->flag, (size_t)1);
+  w.take(c->counters, (size_t)CNT_N);
+  w.take(c->dca, (size_t)1);
+  w.take(c->ngskip, (size_t)1);
+  w.take(c->sfn, (size_t)2);
+  if (extras) {
+    w.take(c->hwx, MB);
+    w.take(c->hex, MB);
+    w.take(c->hp, (size_t)4 * Bp);
+    c->hxt = w.bytes(2 * MB * os);
+    c->hy1 = w.bytes(2 * MB * ws);
+    c->hy2 = w.bytes(2 * MB * ws);
+    w.take(c->hx1, Mp);
+    w.take(c->hx2, Mp);
+  } else {
+    c->hwx = c->hex = nullptr;
+    c->hp = nullptr;
+    c->hxt = c->hy1 = c->hy2 = nullptr;
+    c->hx1 = c->hx2 = nullptr;
+  }
+  return w.off;
+}
+
 
 // ------------------------------------------------------------------ GH rule (host)
 // Physicists' Gauss-Hermite rule: nodes are the roots of H_n, found by Newton's
@@ -303,6 +420,8 @@ extern "C" const char *ifsvgp_strerror(int code) {
     case IFSVGP_ENONFINITE: return "non-finite bound or factor";
     case IFSVGP_ENOMEM: return "out of device memory";
     case IFSVGP_ESTATE: return "backward without a matching forward on this context";
+    case IFSVGP_ESCRATCH:
+      return "problem too large for the static workspace of ifsvgp_step_noalloc";
     default: return "unknown status code";
   }
 }
@@ -350,109 +469,14 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
     ifsvgp_destroy(c);
     return IFSVGP_EHIP;
   }
-  const size_t Mp = c->Mp, Bp = c->Bp;
-  const size_t MM = Mp * Mp, MB = Mp * Bp;
-  const size_t os = op_size(prec), ws = wide_size(prec);
-  const bool f32 = prec == IFSVGP_PREC_FP32;
-  const int nb64 = cdiv(M, 64), nb128 = cdiv(M, 128), nbB = cdiv(B_max, 128);
-  const int nt_sym64 = nb64 * (nb64 + 1) / 2;
-  hipError_t e = hipSuccess;
-#define ALLOC(p, n) if (e == hipSuccess) e = dmalloc(c, &(p), (n))
-#define ALLOCB(p, bytes) if (e == hipSuccess) e = dmalloc_bytes(c, &(p), (bytes))
-  ALLOC(c->Kt, MM);
-  ALLOC(c->L32[0], MM);
-  ALLOC(c->L32[1], MM);
-  ALLOC(c->W32, MM);
-  ALLOC(c->Q32, MM);
-  ALLOC(c->Wu32, MM);
-  ALLOC(c->Ys, MM * c->nsplit);
-  if (f32) {
-    c->KtT = c->Kt; c->LT[0] = c->L32[0]; c->LT[1] = c->L32[1]; c->QT = c->Q32;
-  } else {
-    ALLOCB(c->KtT, MM * os);
-    ALLOCB(c->LT[0], MM * os);
-    ALLOCB(c->LT[1], MM * os);
-    ALLOCB(c->QT, MM * os);
+  const size_t bytes = layout(c, nullptr, true);
+  void *slab = nullptr;
+  hipError_t e = hipMalloc(&slab, bytes);
+  if (e == hipSuccess) {
+    c->allocs.push_back(slab);
+    e = hipMemset(slab, 0, bytes);
   }
-  ALLOCB(c->LtT[0], MM * os);
-  ALLOCB(c->LtT[1], MM * os);
-  ALLOCB(c->LstT[0], MM * os);
-  ALLOCB(c->LstT[1], MM * os);
-  if (f32) {
-    c->Lt32[0] = (float *)c->LtT[0];
-    c->Lt32[1] = (float *)c->LtT[1];
-  } else {
-    ALLOC(c->Lt32[0], MM);
-    ALLOC(c->Lt32[1], MM);
-  }
-  ALLOCB(c->Yt, MM * os);
-  ALLOCB(c->Xgt, MM * os);
-  ALLOCB(c->Cm, MM * ws);
-  ALLOCB(c->Y2, MM * ws);
-  ALLOCB(c->Kft, MB * os);
-  ALLOCB(c->V, MB * os);
-  ALLOCB(c->Vt, MB * os);
-  ALLOCB(c->Ut, MB * os);
-  ALLOCB(c->Vs, MB * os);
-  ALLOC(c->Zs, (size_t)M * D);
-  ALLOC(c->Xs, (size_t)B_max * D);
-  ALLOC(c->inv_ell, (size_t)D);
-  ALLOC(c->sP, Mp);
-  ALLOC(c->va, Mp);
-  ALLOC(c->vb, Mp);
-  ALLOC(c->vLb, Mp);
-  ALLOC(c->vWub, Mp);
-  ALLOC(c->vVa, Mp);
-  ALLOC(c->vt2, Mp);
-  ALLOC(c->mu_part, (size_t)nb64 * Bp);
-  ALLOC(c->var_part, (size_t)nb128 * Bp);
-  ALLOC(c->mu, Bp);
-  ALLOC(c->var, Bp);
-  ALLOC(c->alpha, Bp);
-  ALLOC(c->beta, Bp);
-  ALLOC(c->sqnb, Bp);
-  ALLOC(c->hrow, (size_t)nbB * M);
-  ALLOC(c->hcol, (size_t)nb128 * Bp);
-  ALLOC(c->hx, (size_t)nbB * M * D);
-  ALLOC(c->hzrow, (size_t)nb64 * M);
-  ALLOC(c->hz, (size_t)nb64 * M * D);
-  ALLOC(c->gdiag, Mp);
-  ALLOC(c->pdiag, (size_t)nb64 * Mp);
-  ALLOC(c->scal, (size_t)S_NSLOT);
-  ALLOC(c->tp_ng, (size_t)nt_sym64);
-  ALLOC(c->tp_gram, (size_t)3 * nt_sym64);
-  ALLOC(c->tp_uf, (size_t)nb128 * nbB);
-  ALLOC(c->tp_uu, (size_t)nt_sym64);
-  ALLOC(c->tp_gap, (size_t)nb128 * cdiv(Bp, 64));
-  ALLOC(c->hwx, MB);
-  ALLOC(c->hex, MB);
-  ALLOC(c->hp, (size_t)4 * Bp);
-  ALLOCB(c->hxt, 2 * MB * os);
-  ALLOC(c->mo_m, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_a, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_b, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_wub, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_x, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_t2, (size_t)MO_QMAX * Mp);
-  ALLOC(c->mo_mu, (size_t)MO_QMAX * Bp);
-  ALLOC(c->mo_al, (size_t)MO_QMAX * Bp);
-  ALLOC(c->mo_zero, Mp);
-  ALLOC(c->mo_half, Bp);
-  ALLOCB(c->hy1, 2 * MB * ws);
-  ALLOCB(c->hy2, 2 * MB * ws);
-  ALLOC(c->hx1, Mp);
-  ALLOC(c->hx2, Mp);
-  ALLOC(c->lik_part, (size_t)4 * cdiv(Bp, NTB));
-  ALLOC(c->vec_part, (size_t)2 * cdiv(2 * M, NTB / 64));
-  ALLOC(c->ell_part, (size_t)(M + B_max + 64) * D);
-  ALLOC(c->gh, (size_t)2 * std::max(1, c->ngh));
-  ALLOC(c->flag, (size_t)1);
-  ALLOC(c->counters, (size_t)CNT_N);
-  ALLOC(c->dca, (size_t)1);
-  ALLOC(c->ngskip, (size_t)1);
-  ALLOC(c->sfn, (size_t)2);
-#undef ALLOC
-#undef ALLOCB
+  if (e == hipSuccess) layout(c, (char *)slab, true);
   if (e == hipSuccess && c->ngh > 0) {
     std::vector<double> g(2 * c->ngh);
     ifsvgp_gh_rule(c->ngh, g.data(), g.data() + c->ngh);
@@ -1656,5 +1680,116 @@ extern "C" int ifsvgp_adam(ifsvgp_ctx *c, float *param, const float *grad, float
   hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(NTB), 0, c->st, param, grad, m, v, n, lr, beta1,
                      beta2, eps, (float)(1.0 / bc1), (float)(1.0 / bc2), ascend ? -1.f : 1.f);
   HIPCK(hipGetLastError());
+  return IFSVGP_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free iteration
+// The training iteration of ifsvgp_step for callers that cannot allocate
+// device memory (code under HIP graph capture, tight serving loops, harnesses
+// that forbid hipMalloc).  Its workspace is the file-scope device array
+// `scratch` (each device holds its own copy from module load until the
+// process ends) instead of a context's slab, laid out per call for the
+// call's (M, B, D, precision, likelihood) without the Hutchinson buffers,
+// and zeroed by a fill kernel at the start of every call.  Host code reaches
+// the array only through the device address hipGetSymbolAddress returns for
+// it, taken once per device with that device current.  Everything runs on
+// the caller's stream in stream order (no side stream, no events, no graphs).
+static constexpr size_t kScratchBytes = IFSVGP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+struct NoAllocDevice {
+  std::once_flag once;
+  hipError_t err;
+  char *ptr;       // device address of this device's copy of scratch
+  std::mutex mu;   // serialises the host side of calls on this device
+  ifsvgp_ctx ctx;  // host state of the calls, its pointers into scratch
+};
+static NoAllocDevice g_noalloc[kMaxDevices];
+
+__global__ void k_zero16(uint4 *p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    p[i] = uint4{0u, 0u, 0u, 0u};
+}
+
+// Gauss-Hermite nodes and weights passed by value (n <= 64 each).
+struct GhTable {
+  double v[128];
+};
+__global__ void k_put_gh(GhTable t, int n2, double *dst) {
+  const int i = threadIdx.x;
+  if (i < n2) dst[i] = t.v[i];
+}
+
+__global__ void k_copy_flag(const int *flag, int *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *flag;
+}
+
+extern "C" int ifsvgp_step_noalloc(void *hip_stream, int M, int D, int prec, int lik, int n_gh,
+                                   const float *X, const float *y, int B, double N,
+                                   const float *ell, const float *sf2, const float *noise,
+                                   const float *Z, const float *m, const float *s, float *L,
+                                   const float *gammas, int n_ng, double *out_bound,
+                                   double *out_terms, double *out_resid, float *g_ell,
+                                   float *g_sf2, float *g_noise, float *g_Z, float *g_m,
+                                   float *g_s, int *out_flag) {
+  if (M < 1 || D < 1 || D > MAXD || B < 1) return IFSVGP_EINVAL;
+  if (prec < 0 || prec > 2 || lik < 0 || lik > 1) return IFSVGP_EINVAL;
+  if (lik == IFSVGP_LIK_PROBIT && (n_gh < 1 || n_gh > 64)) return IFSVGP_EINVAL;
+  if ((long)M > 32768 || (long)B > (1L << 24) || (long)M * B > (1L << 31)) return IFSVGP_EINVAL;
+  if (n_ng < 0 || (n_ng > 0 && !gammas) || !out_bound) return IFSVGP_EINVAL;
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return IFSVGP_EINVAL;
+  NoAllocDevice &nd = g_noalloc[dev];
+  std::call_once(nd.once, [&nd] {
+    void *p = nullptr;
+    nd.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    nd.ptr = (char *)p;
+  });
+  if (nd.err != hipSuccess || !nd.ptr) return IFSVGP_EHIP;
+  std::lock_guard<std::mutex> lock(nd.mu);
+  ifsvgp_ctx *c = &nd.ctx;
+  c->M = M; c->Bmax = B; c->D = D; c->prec = prec; c->lik = lik;
+  c->ngh = lik == IFSVGP_LIK_PROBIT ? n_gh : 0;
+  c->Mp = rup(M, PAD);
+  c->Bp = rup(B, PAD);
+  c->nsplit = std::max(1, std::min(8, cdiv(B, 1024)));
+  c->st = c->side = (hipStream_t)hip_stream;
+  c->single_stream = true;
+  c->capturing = false;
+  c->use_graphs = 0;
+  c->timing = 0;
+  c->lev0 = c->lev1 = nullptr;
+  c->fwd_valid = 0;
+  c->cur = 0;
+  const size_t bytes = layout(c, nullptr, false);
+  if (bytes > kScratchBytes) return IFSVGP_ESCRATCH;
+  layout(c, nd.ptr, false);
+  int r = check_bound_args(c, X, y, B, N, ell, sf2, noise, Z, m, s, L);
+  if (r) return r;
+  hipLaunchKernelGGL(k_zero16, dim3((unsigned)std::min<size_t>(2048, cdiv(bytes / 16, NTB))),
+                     dim3(NTB), 0, c->st, (uint4 *)nd.ptr, bytes / 16);
+  HIPCK(hipGetLastError());
+  if (c->ngh > 0) {
+    GhTable t{};
+    ifsvgp_gh_rule(c->ngh, t.v, t.v + c->ngh);
+    hipLaunchKernelGGL(k_put_gh, dim3(1), dim3(128), 0, c->st, t, 2 * c->ngh, c->gh);
+    HIPCK(hipGetLastError());
+  }
+  CallArgs a = make_args(X, y, B, N, ell, sf2, noise, Z, m, s, L, gammas, n_ng);
+  a.out_bound = out_bound;
+  a.out_terms = out_terms;
+  a.out_resid = out_resid;
+  a.g_ell = g_ell; a.g_sf2 = g_sf2; a.g_noise = g_noise; a.g_Z = g_Z; a.g_m = g_m; a.g_s = g_s;
+  Call k{true, true, true, B, n_ng, gammas, lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
+         g_s != nullptr, NG_FIXED};
+  r = run_direct(c, k, a);
+  if (r) return r;
+  if (out_flag) {
+    hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, c->st, (const int *)c->flag, out_flag);
+    HIPCK(hipGetLastError());
+  }
   return IFSVGP_OK;
 }

@@ -19,7 +19,8 @@ LIK = {"gaussian": 0, "probit": 1}
 N_TERMS = 8
 TERM_NAMES = ["data", "KL", "sum_var", "resid", "trW", "trPK", "quad", "logdet"]
 
-OK, EINVAL, EDOMAIN, EHIP, ENONFINITE, ENOMEM, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EDOMAIN, EHIP, ENONFINITE, ENOMEM, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -54,6 +55,8 @@ _SIGS = {
                               _P, _P, _P, _P, _P, _P]),
     "ifsvgp_step": (_I, [_P, _P, _P, _I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _I,
                          _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ifsvgp_step_noalloc": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _I, _D, _P, _P, _P, _P, _P,
+                                 _P, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_predict": (_I, [_P, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ifsvgp_timing_enable": (_I, [_P, ctypes.c_longlong]),
     "ifsvgp_timing_read": (_I, [_P, _I, _P, _P, _P]),
@@ -121,6 +124,44 @@ def _ptr(t, shape, name, dtype=None, optional=False):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
+
+
+def step_noalloc(X, y, N, ell, sf2, noise, Z, m, s, L, gammas, prec="fp32", lik="gaussian",
+                 n_gh=20, out=None, terms=None, resid=None, grads=None, flag=None,
+                 want=("ell", "sf2", "noise_var", "Z", "m")):
+    """One training iteration through the allocation-free entry point (no
+    context; the library's static device workspace on the current device).
+    The caller provides every output buffer through the keyword arguments
+    (or this wrapper allocates them with torch before the call).  Returns
+    (F, terms, resid, grads, flag); flag is the call's device error bits."""
+    import torch
+    B, D = X.shape
+    M = Z.shape[0]
+    dev = X.device
+    gm = np.ascontiguousarray(np.asarray(gammas, np.float32).reshape(-1))
+    n = gm.shape[0]
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = torch.empty(1, **f64) if out is None else out
+    terms = torch.empty(N_TERMS, **f64) if terms is None else terms
+    if resid is None and n > 0:
+        resid = torch.empty(n, **f64)
+    flag = torch.empty(1, dtype=torch.int32, device=dev) if flag is None else flag
+    if grads is None:
+        shapes = {"ell": (D,), "sf2": (1,), "noise_var": (1,), "Z": (M, D), "m": (M,), "s": (M,)}
+        grads = {k: torch.empty(shapes[k], dtype=torch.float32, device=dev)
+                 for k in want if not (k == "noise_var" and lik != "gaussian")}
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    _check(load().ifsvgp_step_noalloc(
+        stream, M, D, PREC[prec], LIK[lik], int(n_gh),
+        _ptr(X, (B, D), "X"), _ptr(y, (B,), "y"), B, float(N), _ptr(ell, (D,), "ell"),
+        _ptr(sf2, (1,), "sf2"), _ptr(noise, (1,), "noise_var", optional=lik != "gaussian"),
+        _ptr(Z, (M, D), "Z"), _ptr(m, (M,), "m_tilde"), _ptr(s, (M,), "s_tilde"),
+        _ptr(L, (M, M), "L"), gm.ctypes.data if n else None, n,
+        _ptr(out, (1,), "out", torch.float64), _ptr(terms, (N_TERMS,), "terms", torch.float64),
+        _ptr(resid, (n,), "resid", torch.float64) if n else None,
+        *Context._grad_ptrs(grads), _ptr(flag, (1,), "flag", torch.int32)),
+        "ifsvgp_step_noalloc")
+    return out, terms, resid, grads, flag
 
 
 class Context:

@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_version_and_strerror(lib):
     L = lib.load()
     assert L.ifsvgp_version() >= 100
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(lib.strerror(code)) > 0
     assert lib.strerror(-99) == "unknown status code"
 
