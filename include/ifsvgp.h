@@ -340,6 +340,42 @@ int ifsvgp_step_noalloc(void *hip_stream, int M, int D, int prec, int lik, int n
                         double *out_resid, float *g_ell, float *g_sf2, float *g_noise,
                         float *g_Z, float *g_m, float *g_s, int *out_flag);
 
+/* Independent problems in one launch per kernel (Section 4: deep GPs give
+ * every layer its own Z, kernel hyperparameters, S~ and so its own T; a layer
+ * with S~ tied across its outputs has one T, see ifsvgp_bound_multi).  A
+ * grouped context holds the workspaces of G problems of the same sizes
+ * (M, B_max, D, prec, lik), one after another; ifsvgp_step_group runs the
+ * training iteration of ifsvgp_step for all G at once, every kernel of the
+ * iteration launched once with the problem as its grid's third index, so G
+ * small problems cost the launches of one.  A grouped context serves only
+ * ifsvgp_step_group (and ifsvgp_adam, ifsvgp_set_stream, ifsvgp_status,
+ * ifsvgp_timing_*); the single-problem entry points return IFSVGP_EINVAL on
+ * it.  ifsvgp_status reports (and clears) the flags of all G problems.
+ * 1 <= G <= IFSVGP_MAX_GROUP (G = 1 is an ordinary context, on which
+ * ifsvgp_step_group with one problem equals ifsvgp_step). */
+#define IFSVGP_MAX_GROUP 64
+int ifsvgp_create_group(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec, int lik,
+                        int n_gh);
+
+/* One problem of a group: the arguments of ifsvgp_step (device pointers). */
+typedef struct ifsvgp_problem {
+  const float *X, *y, *ell, *sf2, *noise_var, *Z, *m_tilde, *s_tilde;
+  float *L;
+  double *out_bound, *out_terms, *out_resid;
+  float *g_ell, *g_sf2, *g_noise, *g_Z, *g_m, *g_s;
+} ifsvgp_problem;
+
+/* The training iteration of ifsvgp_step for the G problems of probs (a HOST
+ * array of G entries, G equal to the context's group size), all on batches of
+ * B rows with the same data-set size N_total and the same NG step sizes
+ * (gammas: host, n_ng <= 64).  Each problem's results go to its own outputs,
+ * as ifsvgp_step would write them.  Every problem must request the same
+ * optional outputs among g_m and g_s (they shape the launches; IFSVGP_EINVAL
+ * otherwise); the others may differ.  Results are bit-identical to G
+ * separate ifsvgp_step calls on ungrouped contexts. */
+int ifsvgp_step_group(ifsvgp_ctx *ctx, const ifsvgp_problem *probs, int G, int B,
+                      double N_total, const float *gammas, int n_ng);
+
 /* One Adam step (Kingma and Ba's algorithm, with bias correction) on n fp32
  * parameters, enqueued on the context's stream: with g' = grad (or -grad when
  * ascend != 0, to maximise F), m = beta1 m + (1-beta1) g',

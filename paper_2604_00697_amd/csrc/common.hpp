@@ -10,6 +10,7 @@
 #define IFS_DEV __device__ __forceinline__
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -45,12 +46,34 @@ IFS_DEV f32x4 mfma16(const f32x4 &a, const f32x4 &b, f32x4 acc) {
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
   return acc;
 }
+// fp32 operands contracted on the fp64 matrix cores: each fp32 value is
+// widened exactly, so the products are exact and only the fp64 sums round.
+// Operands in the fp32 form's lane layout; the result rows interleave
+// across the lane groups instead: acc[i] = C[4*i + l/16][l % 16].
+IFS_DEV f64x4 mfma16(const f32x4 &a, const f32x4 &b, f64x4 acc) {
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[0], (double)b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[1], (double)b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[2], (double)b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[3], (double)b[3], acc, 0, 0, 0);
+  return acc;
+}
 IFS_DEV f32x4 mfma16(const bf16x8 &a, const bf16x8 &b, f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 IFS_DEV f32x4 mfma16(const f16x8 &a, const f16x8 &b, f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
 }
+
+// ---------------------------------------------------------------- grouped launches
+// A grouped launch runs one kernel for G independent problems at once, the
+// problem index in blockIdx.z; problem g's workspace is problem 0's moved by
+// g * gs bytes, so every workspace pointer a kernel receives is moved by
+// goff(gs) (null pointers stay null).  gs = 0 is the ungrouped launch.
+template <class P>
+IFS_DEV P *gsh(P *p, long o) {
+  return p ? (P *)((char *)p + o) : p;
+}
+IFS_DEV long goff(long gs) { return (long)blockIdx.z * gs; }
 
 // ---------------------------------------------------------------- guarded loads
 // p[i] if ok, else 0, without a branch around the load: the address falls back
@@ -166,24 +189,57 @@ IFS_DEV void stage_rows(float *dst, int ld, const float *src, int g0, int R, int
 }
 
 // ---------------------------------------------------------------- SE kernel tiles
+// exp of the kernel matrices.  ACC (the fp32 form): the accurate device
+// library exp, since the gradient's sums amplify relative errors of K_uu and
+// K_uf by their condition; otherwise the hardware exp, whose error is far
+// below the rounding of the reduced-precision operands.
+template <bool ACC>
+IFS_DEV float kexp(float x) {
+  if constexpr (ACC) return expf(x);
+  else return __expf(x);
+}
+
 // Squared scaled distance from norms and cross term (the cross term comes from
-// fp32 MFMA); clamped at 0 against rounding.
+// fp32 MFMA); clamped at 0 against rounding.  Used by the reduced-precision
+// forms; the fp32 form forms the distances from differences (sqdist).
 IFS_DEV float kern_se(float sf2, float zn, float xn, float cross) {
   return sf2 * __expf(-0.5f * fmaxf(zn + xn - 2.f * cross, 0.f));
 }
 
+// sum_d (a_d - b_d)^2 over D values of two LDS rows: no cancellation, unlike
+// |a|^2 + |b|^2 - 2 a.b, whose rounding grows with the norms of the scaled
+// inputs rather than with their distance.
+IFS_DEV float sqdist(const float *a, const float *b, int D) {
+  float s0 = 0.f, s1 = 0.f;
+  int d = 0;
+  for (; d + 1 < D; d += 2) {
+    const float e0 = a[d] - b[d], e1 = a[d + 1] - b[d + 1];
+    s0 = fmaf(e0, e0, s0);
+    s1 = fmaf(e1, e1, s1);
+  }
+  if (d < D) {
+    const float e = a[d] - b[d];
+    s0 = fmaf(e, e, s0);
+  }
+  return s0 + s1;
+}
+
 // Cross terms C[i][j] = sum_d A[i][d] B[j][d] of a (16 TI) x (16 TJ) block
 // from LDS rows A (stride lda) and B (stride ldb), d < D4 (a multiple of 4,
-// zero-padded), with 16x16x4 fp32 MFMA on TI x TJ independent accumulators:
-// acc[i][j][q] = C[16 i + 4 (lane/16) + q][16 j + lane % 16].
-template <int TI, int TJ>
+// zero-padded), with 16x16x4 MFMA on TI x TJ independent accumulators:
+// acc[i][j][q] = C[16 i + r(q)][16 j + lane % 16] with r(q) = 4 (lane/16) + q
+// (fp32 MFMA) or, F64 (fp64 MFMA on the widened values, rounded to fp32 at
+// the end), r(q) = 4 q + lane/16: the row layout of the fp64 accumulators.
+template <int TI, int TJ, bool F64 = false>
 IFS_DEV void cross_block(const float *A, int lda, const float *B, int ldb, int D4,
                          f32x4 (&acc)[TI][TJ]) {
   const int lane = threadIdx.x & 63, l16 = lane & 15, l4 = lane >> 4;
+  using Acc = typename std::conditional<F64, f64x4, f32x4>::type;
+  Acc c[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TJ; ++j) c[i][j] = Acc{0, 0, 0, 0};
   for (int d0 = 0; d0 < D4; d0 += 4) {
     float a[TI], b[TJ];
 #pragma unroll
@@ -193,9 +249,20 @@ IFS_DEV void cross_block(const float *A, int lda, const float *B, int ldb, int D
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < TJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < TJ; ++j) {
+        if constexpr (F64)
+          c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[i], (double)b[j], c[i][j], 0,
+                                                         0, 0);
+        else
+          c[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], c[i][j], 0, 0, 0);
+      }
   }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = (float)c[i][j][q];
 }
 
 // Device-side error flags (sticky until read by the host).

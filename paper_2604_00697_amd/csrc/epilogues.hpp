@@ -92,23 +92,23 @@ IFS_DEV double tile_sum(double v, const float *Cs) {
 }
 
 // Column sums of the staged tile over its BM rows (NT / BN threads per column,
-// partials combined in the scratch LDS).  Valid for threads with g == 0, where
-// c = threadIdx.x % BN.
-template <class C>
-IFS_DEV float tile_colsum(const float *Cs) {
+// partials combined in the scratch LDS), accumulated in A.  Valid for threads
+// with g == 0, where c = threadIdx.x % BN.
+template <class C, typename A = float>
+IFS_DEV A tile_colsum(const float *Cs) {
   constexpr int RG = C::NT / C::BN;
   static_assert(C::NT % C::BN == 0, "column partial layout");
-  float *sh = (float *)(Cs + C::BM * C::LDC);
+  A *sh = (A *)(Cs + C::BM * C::LDC);
   const int c = threadIdx.x % C::BN, g = threadIdx.x / C::BN;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll 4
   for (int r = g; r < C::BM; r += 4 * RG) {
-    s0 += CS(r, c);
-    s1 += CS(r + RG, c);
-    s2 += CS(r + 2 * RG, c);
-    s3 += CS(r + 3 * RG, c);
+    s0 += (A)CS(r, c);
+    s1 += (A)CS(r + RG, c);
+    s2 += (A)CS(r + 2 * RG, c);
+    s3 += (A)CS(r + 3 * RG, c);
   }
-  float s = (s0 + s1) + (s2 + s3);
+  A s = (s0 + s1) + (s2 + s3);
   sh[threadIdx.x] = s;
   __syncthreads();
   if (g == 0)
@@ -117,32 +117,49 @@ IFS_DEV float tile_colsum(const float *Cs) {
   return s;
 }
 
-// Small fp32 MFMA product of LDS operands, used for the D-wide reductions of
-// the gradient epilogues:  Out[i][d] = sum_k A[i][k] Z[k][d],  i < R, d < DP,
+// Small MFMA product of LDS operands, used for the D-wide reductions of the
+// gradient epilogues:  Out[i][d] = sum_k A[i][k] Z[k][d],  i < R, d < DP,
 // with A = H (row-major, stride ldh) or, TRANS, A = H^T.  Z is row-major
 // [K][ldz].  R = 16 * TI * NW (each wave owns TI row tiles), K a multiple of 4,
 // DP a multiple of 16 (d tiles two at a time, then a last single one).  Each
 // output element goes to sink(i, d, value) from the lane that holds it.
-template <int NW, int TI, bool TRANS, class F>
-IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ldz, int DP,
-                          F &&sink) {
+// F64: the fp32 operands are widened and contracted on the fp64 matrix cores
+// (exact products, fp64 sums), for the fp32 form, whose gradient sums cancel;
+// otherwise fp32 MFMA.
+template <bool F64>
+struct RedMfma {
+  using Acc = typename std::conditional<F64, f64x4, f32x4>::type;
+  static IFS_DEV Acc op(float a, float b, Acc c) {
+    if constexpr (F64) return __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, (double)b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 output block that accumulator slot q of lane group l4
+  // holds (the fp64 form interleaves the rows across the lane groups)
+  static IFS_DEV int row(int l4, int q) { return F64 ? 4 * q + l4 : 4 * l4 + q; }
+};
+
+template <int NW, int TI, bool TRANS, bool F64 = false, class F>
+IFS_DEV void lds_mfma(const float *H, int ldh, int K, const float *Z, int ldz, int DP,
+                      F &&sink) {
+  using R = RedMfma<F64>;
+  using Acc = typename R::Acc;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int ib = wave * TI * 16;
   auto a_at = [&](int r, int k) { return TRANS ? H[k * ldh + r] : H[r * ldh + k]; };
   int d0 = 0;
   for (; d0 + 32 <= DP; d0 += 32) {
-    f32x4 acc[TI][2];
+    Acc acc[TI][2];
 #pragma unroll
-    for (int i = 0; i < TI; ++i) acc[i][0] = acc[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < TI; ++i) acc[i][0] = acc[i][1] = Acc{0, 0, 0, 0};
 #pragma unroll 4
     for (int k0 = 0; k0 < K; k0 += 4) {
       const float b0 = Z[(k0 + l4) * ldz + d0 + l16], b1 = Z[(k0 + l4) * ldz + d0 + 16 + l16];
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
         const float a = a_at(ib + 16 * i + l16, k0 + l4);
-        acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[i][0], 0, 0, 0);
-        acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[i][1], 0, 0, 0);
+        acc[i][0] = R::op(a, b0, acc[i][0]);
+        acc[i][1] = R::op(a, b1, acc[i][1]);
       }
     }
 #pragma unroll
@@ -150,46 +167,44 @@ IFS_DEV void lds_mfma_f32(const float *H, int ldh, int K, const float *Z, int ld
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, d0 + 16 * h + l16, acc[i][h][q]);
+        for (int q = 0; q < 4; ++q) sink(ib + 16 * i + R::row(l4, q), d0 + 16 * h + l16, acc[i][h][q]);
   }
   if (d0 < DP) {
-    f32x4 acc[TI];
+    Acc acc[TI];
 #pragma unroll
-    for (int i = 0; i < TI; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < TI; ++i) acc[i] = Acc{0, 0, 0, 0};
 #pragma unroll 4
     for (int k0 = 0; k0 < K; k0 += 4) {
       const float b0 = Z[(k0 + l4) * ldz + d0 + l16];
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_at(ib + 16 * i + l16, k0 + l4), b0,
-                                                      acc[i], 0, 0, 0);
+      for (int i = 0; i < TI; ++i) acc[i] = R::op(a_at(ib + 16 * i + l16, k0 + l4), b0, acc[i]);
     }
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, d0 + l16, acc[i][q]);
+      for (int q = 0; q < 4; ++q) sink(ib + 16 * i + R::row(l4, q), d0 + l16, acc[i][q]);
   }
 }
 
 // Row sums of the staged tile over its BN columns (NT / BM threads per row,
-// partials combined in the scratch LDS).  Valid for threads with
-// threadIdx.x < BM, where the row is threadIdx.x.
-template <class C>
-IFS_DEV float tile_rowsum(const float *Cs) {
+// partials combined in the scratch LDS), accumulated in A.  Valid for threads
+// with threadIdx.x < BM, where the row is threadIdx.x.
+template <class C, typename A = float>
+IFS_DEV A tile_rowsum(const float *Cs) {
   constexpr int CG = C::NT / C::BM;  // column groups per row
   static_assert(C::NT % C::BM == 0 && C::BN % (4 * CG) == 0, "row partial layout");
-  float *sh = (float *)(Cs + C::BM * C::LDC);
+  A *sh = (A *)(Cs + C::BM * C::LDC);
   const int r = threadIdx.x % C::BM, g = threadIdx.x / C::BM;
   constexpr int W = C::BN / CG;  // columns per group
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  A s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll 4
   for (int c = g * W; c < (g + 1) * W; c += 4) {
-    s0 += CS(r, c);
-    s1 += CS(r, c + 1);
-    s2 += CS(r, c + 2);
-    s3 += CS(r, c + 3);
+    s0 += (A)CS(r, c);
+    s1 += (A)CS(r, c + 1);
+    s2 += (A)CS(r, c + 2);
+    s3 += (A)CS(r, c + 3);
   }
-  float s = (s0 + s1) + (s2 + s3);
+  A s = (s0 + s1) + (s2 + s3);
   sh[threadIdx.x] = s;
   __syncthreads();
   if (g == 0)
@@ -208,6 +223,10 @@ struct EpiStore {
   long ld;
   int R, N, mirror;
   long split_stride;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    out = gsh(out, o);
+  }
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -241,6 +260,10 @@ struct EpiStoreT {
   TO *out;
   long ld;
   int R, N;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    out = gsh(out, o);
+  }
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -267,6 +290,11 @@ struct EpiNgGram {
   long ld;
   int M;
   double *part;  // [ntiles]
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    Xt = gsh(Xt, o);
+    part = gsh(part, o);
+  }
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -309,6 +337,11 @@ struct EpiGap {
   long ldk;
   int M, B;
   double *part;  // [ntiles]
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    Kft = gsh(Kft, o);
+    part = gsh(part, o);
+  }
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -354,6 +387,19 @@ struct EpiNgUpdate {
   const double *gram_part;
   int n_gram;
   double *scal;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    L = gsh(L, o);
+    Ln = gsh(Ln, o);
+    Lnt32 = gsh(Lnt32, o);
+    LnT = gsh(LnT, o);
+    LntT = gsh(LntT, o);
+    sP = gsh(sP, o);
+    LnsT = gsh(LnsT, o);
+    ca = gsh(ca, o);
+    gram_part = gsh(gram_part, o);
+    scal = gsh(scal, o);
+  }
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -432,6 +478,14 @@ struct EpiBoundGram {
   long ld;
   int M;
   double *part;  // [ntiles][3]
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    W = gsh(W, o);
+    Q = gsh(Q, o);
+    Wu = gsh(Wu, o);
+    QT = gsh(QT, o);
+    part = gsh(part, o);
+  }
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -524,6 +578,11 @@ struct EpiV {
   T *V, *Vt;
   long ldv, ldt;
   int M, B;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    V = gsh(V, o);
+    Vt = gsh(Vt, o);
+  }
   template <class C>
   IFS_DEV void run(const float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -563,6 +622,14 @@ struct EpiU {
   float *var_part;  // [m-tiles][ldp]
   float *mu_part;   // [m-tiles][ldp]
   long ldp;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    Ut = gsh(Ut, o);
+    V = gsh(V, o);
+    a = gsh(a, o);
+    var_part = gsh(var_part, o);
+    mu_part = gsh(mu_part, o);
+  }
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -647,14 +714,29 @@ struct EpiGradUf {
   const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
   const float *sf2;
   int M, B, D;
-  float *hrow;  // [n-tiles][M]
-  float *hcol;  // [m-tiles][ldc]
+  double *hrow;  // [n-tiles][M]
+  double *hcol;  // [m-tiles][ldc]
   long ldc;
-  float *hx;    // [n-tiles][M][D]
+  double *hx;    // [n-tiles][M][D]
   double *part; // [ntiles]
   static constexpr bool kRegs = true;  // takes the accumulators in registers
-  template <class C>
-  IFS_DEV void run_regs(const f32x4 (&acc)[C::TM][C::TN], float *Cs, const TileInfo &t) const {
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    Lb = gsh(Lb, o);
+    alpha = gsh(alpha, o);
+    beta = gsh(beta, o);
+    Zs = gsh(Zs, o);
+    Xs = gsh(Xs, o);
+    sf2 = gsh(sf2, o);
+    hrow = gsh(hrow, o);
+    hcol = gsh(hcol, o);
+    hx = gsh(hx, o);
+    part = gsh(part, o);
+  }
+  // acc: fp32 or (C::A64) fp64 accumulators; the lane's rows are
+  // 16 ii + 4 (lane/16) + q for fp32 and 16 ii + 4 q + lane/16 for fp64
+  template <class C, class Acc>
+  IFS_DEV void run_regs(const Acc (&acc)[C::TM][C::TN], float *Cs, const TileInfo &t) const {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     const int D4 = d4of(D), DP = dpof(D), LDZ = D4 + 1, LDX = DP + 1;
     float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][LDZ]
@@ -687,15 +769,16 @@ struct EpiGradUf {
       // the cross term lands in the accumulators' lane layout
       const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
       const int ib = (wave / C::WGN) * C::WM, jb = (wave % C::WGN) * C::WN;
-      // this lane's rows (16 ii + 4 l4 + q) and columns (16 jj + l16): their
+      // this lane's rows (16 ii + r(q)) and columns (16 jj + l16): their
       // staged values in registers, read once and unconditionally
+      auto r_of = [&](int q) { return C::A64 ? 4 * q + l4 : 4 * l4 + q; };
       float zr[C::TM][4], lr[C::TM][4], xc[C::TN], ac[C::TN], bc[C::TN];
       bool rok[C::TM][4], cok[C::TN];
 #pragma unroll
       for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int i = ib + 16 * ii + 4 * l4 + q;
+          const int i = ib + 16 * ii + r_of(q);
           zr[ii][q] = lds_get(zn + i);
           lr[ii][q] = lds_get(lb + i);
           rok[ii][q] = t.m0 + i < M;
@@ -708,8 +791,12 @@ struct EpiGradUf {
         bc[jj] = lds_get(be + n);
         cok[jj] = t.n0 + n < B;
       }
+      // the fp32 form recomputes K_uf from differences with the accurate exp
+      // (as its forward does); the others from norms and an MFMA cross term
+      constexpr bool F32 = std::is_same<typename C::T, float>::value;
       f32x4 c[C::TM][C::TN];
-      cross_block<C::TM, C::TN>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
+      if constexpr (!F32)
+        cross_block<C::TM, C::TN, C::A64>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
 #pragma unroll
       for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
@@ -717,9 +804,13 @@ struct EpiGradUf {
           const int n = jb + 16 * jj + l16;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int i = ib + 16 * ii + 4 * l4 + q;
-            const float kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
-            const float g = lr[ii][q] * ac[jj] - 2.f * acc[ii][jj][q] * bc[jj];
+            const int i = ib + 16 * ii + r_of(q);
+            float kuf;
+            if constexpr (F32)
+              kuf = s2f * kexp<true>(-0.5f * sqdist(zs + i * LDZ, xs + n * LDX, D));
+            else
+              kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
+            const float g = lr[ii][q] * ac[jj] - 2.f * (float)acc[ii][jj][q] * bc[jj];
             const float h = (rok[ii][q] && cok[jj]) ? g * kuf : 0.f;
             hs += h;
             Cs[i * C::LDC + n] = h;
@@ -730,20 +821,23 @@ struct EpiGradUf {
     hs = tile_sum<C>(hs, Cs);
     if (tid == 0) part[t.ti] = hs;
     const int nti = t.n0 / BN, mti = t.m0 / BM;
+    // the fp32 form sums on the fp64 matrix cores (the gradient's sums of
+    // these partials cancel), the others in fp32; partials are kept in fp64
+    constexpr bool F64 = std::is_same<typename C::T, float>::value;
     {
-      const float s = tile_colsum<C>(Cs);
+      const double s = tile_colsum<C, double>(Cs);
       const int cl = tid % BN, gj = t.n0 + cl;
       if (tid < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
     }
     {
-      const float s = tile_rowsum<C>(Cs);
+      const double s = tile_rowsum<C, double>(Cs);
       const int gi = t.m0 + tid % BM;
       if (tid < BM && gi < M) hrow[(long)nti * M + gi] = s;
     }
     const int D_ = D, M_ = M;
-    float *hx_ = hx + (long)nti * M * D;
-    lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, C::LDC, BN, xs, LDX, DP,
-                                                [&](int i, int d, float v) {
+    double *hx_ = hx + (long)nti * M * D;
+    lds_mfma<NT / 64, BM / (NT / 4), false, F64>(Cs, C::LDC, BN, xs, LDX, DP,
+                                                [&](int i, int d, double v) {
       const int gi = t.m0 + i;
       if (gi < M_ && d < D_) hx_[(long)gi * D_ + d] = v;
     });
@@ -760,10 +854,20 @@ struct EpiGradUu {
   const float *Kt, *s, *Zs;
   long ld;
   int M, D;
-  float *hz;     // [nb][M][D]
-  float *hzrow;  // [nb][M]
+  double *hz;     // [nb][M][D]
+  double *hzrow;  // [nb][M]
   double *part;  // [ntiles]
   float *gdiag;  // [M]: diagonal of G_uu from the diagonal tiles, or null
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    Kt = gsh(Kt, o);
+    s = gsh(s, o);
+    Zs = gsh(Zs, o);
+    hz = gsh(hz, o);
+    hzrow = gsh(hzrow, o);
+    part = gsh(part, o);
+    gdiag = gsh(gdiag, o);
+  }
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;
@@ -812,15 +916,17 @@ struct EpiGradUu {
     hs = tile_sum<C>(hs, Cs);
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int I = t.m0 / BM, J = t.n0 / BN, D_ = D, M_ = M;
+    // fp64 partials; the fp32 form's reduction products on the fp64 matrix cores
+    constexpr bool F64 = std::is_same<typename C::T, float>::value;
     {
       // rows of block I (slot J): row sums and H Zs_J
-      const float rs = tile_rowsum<C>(Cs);
+      const double rs = tile_rowsum<C, double>(Cs);
       const int gi = t.m0 + threadIdx.x % BM;
       if (threadIdx.x < BM && gi < M) hzrow[(long)J * M + gi] = rs;
-      float *hz_ = hz + (long)J * M * D;
+      double *hz_ = hz + (long)J * M * D;
       const int base = t.m0;
-      lds_mfma_f32<NT / 64, BM / (NT / 4), false>(Cs, LDC_, BN, zj, LDZ, DP,
-                                                  [&](int i, int d, float v) {
+      lds_mfma<NT / 64, BM / (NT / 4), false, F64>(Cs, LDC_, BN, zj, LDZ, DP,
+                                                   [&](int i, int d, double v) {
         const int g = base + i;
         if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
       });
@@ -828,13 +934,13 @@ struct EpiGradUu {
     if (!off) return;
     {
       // rows of block J (slot I) through H^T: column sums and H^T Zs_I
-      const float cs = tile_colsum<C>(Cs);
+      const double cs = tile_colsum<C, double>(Cs);
       const int gj = t.n0 + threadIdx.x % BN;
       if (threadIdx.x < BN && gj < M) hzrow[(long)I * M + gj] = cs;
-      float *hz_ = hz + (long)I * M * D;
+      double *hz_ = hz + (long)I * M * D;
       const int base = t.n0;
-      lds_mfma_f32<NT / 64, BN / (NT / 4), true>(Cs, LDC_, BM, zi, LDZ, DP,
-                                                 [&](int i, int d, float v) {
+      lds_mfma<NT / 64, BN / (NT / 4), true, F64>(Cs, LDC_, BM, zi, LDZ, DP,
+                                                  [&](int i, int d, double v) {
         const int g = base + i;
         if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
       });
@@ -852,6 +958,11 @@ struct EpiRowDotL {
   int M;
   float *part;     // [nb][ldp]
   long ldp;
+  // grouped launches: every workspace pointer moved by o bytes
+  IFS_DEV void shift(long o) {
+    L = gsh(L, o);
+    part = gsh(part, o);
+  }
   template <class C>
   IFS_DEV void run(float *Cs, const TileInfo &t) const {
     using K = Chunks<C>;

@@ -22,10 +22,15 @@
 
 #define LDS_AS __attribute__((address_space(3)))
 
-template <int BM_, int BN_, int WGM_, int WGN_, typename T_, int S_>
+// A64: fp32 operands accumulated on the fp64 matrix cores (the tile is
+// rounded to fp32 once, when it is staged for the epilogue).
+template <int BM_, int BN_, int WGM_, int WGN_, typename T_, int S_, bool A64_ = false>
 struct Cfg {
   using T = T_;
   static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, S = S_;
+  static constexpr bool A64 = A64_;
+  static_assert(!A64 || std::is_same<T_, float>::value, "fp64 accumulation takes fp32 operands");
+  using Acc = typename std::conditional<A64_, f64x4, f32x4>::type;
   static constexpr int NW = WGM * WGN, NT = 64 * NW;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
   static constexpr int TM = WM / 16, TN = WN / 16;
@@ -74,6 +79,7 @@ enum : int { K_LO_M0 = 1, K_LO_N0 = 2, K_HI_M1 = 4, K_HI_N1 = 8 };
 struct Sched {
   int mt, nt, sym, nsplit, K, rule;
   const int *skip;
+  long gs;  // grouped launch: bytes between the problems' workspaces (0: one problem)
   template <class C>
   IFS_DEV void tile(int &m0, int &n0, int &kb, int &ke, int &ti) const {
     const int ntile = sym ? mt * (mt + 1) / 2 : mt * nt;
@@ -142,7 +148,8 @@ IFS_DEV void wait_stages(int n) {
 
 // Epilogues declaring kRegs = true take the accumulators in registers
 // (run_regs: acc[i][j][q] = C[WM wm + 16 i + 4 (lane/16) + q][WN wn + 16 j + lane % 16],
-// LDS free for their own use); the others get the tile staged in LDS (run).
+// or for fp64 accumulators (A64) row WM wm + 16 i + 4 q + lane/16; LDS free for
+// their own use); the others get the tile staged in LDS (run).
 template <class E, class = void>
 struct EpiTakesRegs : std::false_type {};
 template <class E>
@@ -164,6 +171,13 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
 
+  if (sc.gs) {
+    const long o = goff(sc.gs);
+    A.p = gsh(A.p, o);
+    Bt.p = gsh(Bt.p, o);
+    sc.skip = gsh(sc.skip, o);
+    epi.shift(o);
+  }
   int m0, n0, kb, ke, ti;
   sc.tile<C>(m0, n0, kb, ke, ti);
   int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
@@ -221,11 +235,11 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
     }
   };
 
-  f32x4 acc[TM][TN];
+  typename C::Acc acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN; ++j) acc[i][j] = typename C::Acc{0, 0, 0, 0};
   auto mma = [&](auto set_c, int h) {
     constexpr int SET = decltype(set_c)::value;
 #pragma unroll
@@ -277,8 +291,8 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
       for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          Cs[(wm * C::WM + i * 16 + 4 * kq + q) * C::LDC + wn * C::WN + j * 16 + lr] =
-              acc[i][j][q];
+          Cs[(wm * C::WM + i * 16 + (C::A64 ? 4 * q + kq : 4 * kq + q)) * C::LDC + wn * C::WN +
+             j * 16 + lr] = (float)acc[i][j][q];
     __syncthreads();
     epi.template run<C>(Cs, t);
   }
@@ -290,6 +304,8 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
 struct Launch {
   hipStream_t st;
   hipEvent_t t0, t1;
+  int groups;  // problems of a grouped launch (0 or 1: one problem)
+  long gs;     // bytes between their workspaces
 };
 
 // Host-side launch helper.  extra: LDS bytes the epilogue needs beyond the
@@ -300,8 +316,10 @@ static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T>
                                      const EPI &epi, int extra = 0) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
   if (ntile <= 0) return hipSuccess;
-  dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1);
+  dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1, lc.groups > 1 ? lc.groups : 1);
   auto kern = gemm_kernel<C, EPI>;
+  Sched sg = sc;
+  sg.gs = lc.groups > 1 ? lc.gs : 0;
   const int smem = C::smem(extra);
   static int attr_bytes = 0;
   if (smem > attr_bytes) {
@@ -311,8 +329,8 @@ static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T>
     attr_bytes = smem;
   }
   if (lc.t0)
-    hipExtLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, lc.t0, lc.t1, 0, A, Bt, sc, epi);
+    hipExtLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, lc.t0, lc.t1, 0, A, Bt, sg, epi);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, A, Bt, sc, epi);
+    hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, A, Bt, sg, epi);
   return hipGetLastError();
 }

@@ -77,6 +77,10 @@ struct ifsvgp_ctx {
   int ev_next;
   bool side_open;           // the side stream has work not yet joined into st
   bool single_stream;       // side is st: branches run in stream order, no events
+  // grouped contexts: G independent problems of the same sizes, problem g's
+  // workspace at the slab's g * gstride bytes; every launch covers all G
+  int G;
+  long gstride;
   bool capturing;           // launches are being recorded into a graph
   // device argument block of the current call, written by its k_latch
   CallArgs *dca;
@@ -96,7 +100,7 @@ struct ifsvgp_ctx {
   float *Zs, *Xs, *inv_ell, *sP;  // sP: s~ zero-padded to Mp
   float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
-  float *hrow, *hcol, *hx, *hzrow, *hz;
+  double *hrow, *hcol, *hx, *hzrow, *hz;  // gradient partials per tile
   float *gdiag, *pdiag;  // diag(G_uu) [Mp]; partials of diag(L Q L^T) [nb64][Mp]
   double *scal, *tp_ng, *tp_gram, *tp_uf, *tp_uu, *lik_part, *ell_part, *vec_part;
   double *tp_gap;  // per-tile partials of the variance gap [nb128][cdiv(Bp, 64)]
@@ -363,7 +367,6 @@ static size_t layout(ifsvgp_ctx *c, char *base, bool extras) {
   return w.off;
 }
 
-
 // ------------------------------------------------------------------ GH rule (host)
 // Physicists' Gauss-Hermite rule: nodes are the roots of H_n, found by Newton's
 // method on the orthonormal three-term recurrence
@@ -444,9 +447,13 @@ extern "C" void ifsvgp_destroy(ifsvgp_ctx *c) {
   delete c;
 }
 
-extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec, int lik,
-                             int n_gh) {
+// G = 1: a context of one problem (every entry point); G > 1: a grouped
+// context whose slab holds G problems' workspaces (the training iteration
+// without the Hutchinson buffers) one stride apart.
+static int create_ctx(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec, int lik,
+                      int n_gh) {
   if (!out || M < 1 || B_max < 1 || D < 1 || D > MAXD) return IFSVGP_EINVAL;
+  if (G < 1 || G > IFSVGP_MAX_GROUP) return IFSVGP_EINVAL;
   if (prec < 0 || prec > 2 || lik < 0 || lik > 1) return IFSVGP_EINVAL;
   if (lik == IFSVGP_LIK_PROBIT && (n_gh < 1 || n_gh > 64)) return IFSVGP_EINVAL;
   if ((long)M > 32768 || (long)B_max > (1L << 24) || (long)M * B_max > (1L << 31))
@@ -461,6 +468,8 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   c->st = nullptr;
   c->use_graphs = 0;
   c->graph_tick = 0;
+  c->G = G;
+  c->gstride = 0;
   bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cst, hipStreamNonBlocking) == hipSuccess;
   for (int k = 0; ok && k < ifsvgp_ctx::kEvents; ++k)
@@ -469,18 +478,20 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
     ifsvgp_destroy(c);
     return IFSVGP_EHIP;
   }
-  const size_t bytes = layout(c, nullptr, true);
+  const size_t bytes = layout(c, nullptr, G == 1);
+  c->gstride = G > 1 ? (long)bytes : 0;
   void *slab = nullptr;
-  hipError_t e = hipMalloc(&slab, bytes);
+  hipError_t e = hipMalloc(&slab, bytes * G);
   if (e == hipSuccess) {
     c->allocs.push_back(slab);
-    e = hipMemset(slab, 0, bytes);
+    e = hipMemset(slab, 0, bytes * G);
   }
-  if (e == hipSuccess) layout(c, (char *)slab, true);
-  if (e == hipSuccess && c->ngh > 0) {
-    std::vector<double> g(2 * c->ngh);
-    ifsvgp_gh_rule(c->ngh, g.data(), g.data() + c->ngh);
-    e = hipMemcpy(c->gh, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) layout(c, (char *)slab, G == 1);
+  for (int g = 0; e == hipSuccess && c->ngh > 0 && g < G; ++g) {
+    std::vector<double> r(2 * c->ngh);
+    ifsvgp_gh_rule(c->ngh, r.data(), r.data() + c->ngh);
+    e = hipMemcpy((char *)c->gh + g * c->gstride, r.data(), r.size() * sizeof(double),
+                  hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? IFSVGP_ENOMEM : IFSVGP_EHIP;
@@ -495,6 +506,16 @@ extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec
   return IFSVGP_OK;
 }
 
+extern "C" int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec, int lik,
+                             int n_gh) {
+  return create_ctx(out, 1, M, B_max, D, prec, lik, n_gh);
+}
+
+extern "C" int ifsvgp_create_group(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec,
+                                   int lik, int n_gh) {
+  return create_ctx(out, G, M, B_max, D, prec, lik, n_gh);
+}
+
 extern "C" int ifsvgp_set_stream(ifsvgp_ctx *c, void *s) {
   if (!c) return IFSVGP_EINVAL;
   c->st = (hipStream_t)s;
@@ -505,9 +526,12 @@ extern "C" int ifsvgp_status(ifsvgp_ctx *c) {
   if (!c) return IFSVGP_EINVAL;
   HIPCK(hipStreamSynchronize(c->st));
   int f = 0;
-  HIPCK(hipMemcpy(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost));
-  int z = 0;
-  HIPCK(hipMemcpy(c->flag, &z, sizeof(int), hipMemcpyHostToDevice));
+  for (int g = 0; g < std::max(1, c->G); ++g) {  // every problem of a grouped context
+    int *fl = (int *)((char *)c->flag + g * c->gstride), v = 0, z = 0;
+    HIPCK(hipMemcpy(&v, fl, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(fl, &z, sizeof(int), hipMemcpyHostToDevice));
+    f |= v;
+  }
   if (f & FLAG_DOMAIN) return IFSVGP_EDOMAIN;
   if (f & FLAG_NONFINITE) return IFSVGP_ENONFINITE;
   return IFSVGP_OK;
@@ -573,7 +597,13 @@ extern "C" int ifsvgp_kernel_flops(ifsvgp_ctx *c, int B, int cap, double *flops,
 }
 
 // ------------------------------------------------------------------ GEMM wrappers
-static Launch lnc(ifsvgp_ctx *c) { return Launch{c->st, c->lev0, c->lev1}; }
+static Launch lnc(ifsvgp_ctx *c) { return Launch{c->st, c->lev0, c->lev1, c->G, c->gstride}; }
+// grid of a launch covering the context's G problems, and their workspace stride
+static dim3 gdim(ifsvgp_ctx *c, dim3 d) {
+  d.z = std::max(1, c->G);
+  return d;
+}
+static long gsz(ifsvgp_ctx *c) { return c->G > 1 ? c->gstride : 0; }
 
 template <typename T>
 struct Ops {
@@ -583,12 +613,24 @@ struct Ops {
   // and still leave room for three workgroups per CU
   using CS = Cfg<64, 64, 2, 2, T, 3>;
   using CSW = Cfg<64, 64, 2, 2, TW, 3>;
+  // Gram products Y = K~ L and W = L^T Y (NG step and bound): after the NG
+  // step W is within rounding of I, and the bound and its gradient depend on
+  // I - W and on Q = 2I - W, so the fp32 form sums these two products on the
+  // fp64 matrix cores (fp32 operands, one rounding of the result) instead of
+  // letting M-long fp32 sums of terms of size ||L||^2 ||K~|| set their error
+  static constexpr bool kA64 = std::is_same<T, float>::value;
+  using CG = Cfg<64, 64, 2, 2, T, 3, kA64>;
   // M x B products, two stages.  CR: V and U on 128 x 64 tiles (twice the
   // workgroups of 128 x 128, so several share a CU and one's epilogue overlaps
   // another's main loop; their partial sums are per 128-row block).  CRG: R on
   // 128 x 128 tiles, whose gradient partials are per 128-column block.
   using CR = Cfg<128, 64, 2, 2, T, 2>;
-  using CRG = Cfg<128, 128, 2, 2, T, 2>;
+  // (the fp32 form sums R = L U on the fp64 matrix cores too: R = P K_uf is
+  // formed from terms of size ||L||^2 ||K_uf||, so its fp32 sums would set the
+  // error of the H_uf reductions; eight waves keep the fp64 accumulators in
+  // registers)
+  using CRG = typename std::conditional<kA64, Cfg<128, 128, 2, 4, T, 2, true>,
+                                        Cfg<128, 128, 2, 2, T, 2>>::type;
   // Ys = (V D)(V D)^T: lower tiles, split-K over the batch
   using CSY = Cfg<64, 64, 2, 2, T, 3>;
   using CH = Cfg<64, 64, 2, 2, T, 3>;  // the Hutchinson bound's thin products
@@ -606,14 +648,14 @@ struct Ops {
     Opnd<T> a{(const T *)c->KtT, c->Mp}, b{LtT(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_N0, skip};
     EpiStoreT<T> e{(T *)c->Yt, c->Mp, c->M, c->M};
-    return launch_gemm<CS>(lnc(c), a, b, sc, e);
+    return launch_gemm<CG>(lnc(c), a, b, sc, e);
   }
   // W = L^T Y on lower tiles (k >= m0) -> natural-gradient factor + residual
   static hipError_t ng_W(ifsvgp_ctx *c, int cur, const int *skip = nullptr) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0, skip};
     EpiNgGram<T> e{(T *)c->Xgt, c->Mp, c->M, c->tp_ng};
-    return launch_gemm<CS>(lnc(c), a, b, sc, e);
+    return launch_gemm<CG>(lnc(c), a, b, sc, e);
   }
   // Lnew = L - gamma L X on lower tiles, n0 <= k < m0+BM, gamma the call's
   // step size gidx; also the residual of NG step `step` (unless a check
@@ -633,7 +675,7 @@ struct Ops {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Yt, c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_LO_M0};
     EpiStore<float> e{c->W32, c->Mp, c->M, c->M, 0, 0};
-    return launch_gemm<CS>(lnc(c), a, b, sc, e);
+    return launch_gemm<CG>(lnc(c), a, b, sc, e);
   }
   // E' = L^T diag(s) L (lower tiles) -> Q, Wu, gram partials
   static hipError_t gr_E(ifsvgp_ctx *c, int cur) {
@@ -811,7 +853,8 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);
-  hipLaunchKernelGGL((k_setup<MAXD, T>), dim3(a.nK + a.nLx * (a.nLx + 1) / 2), dim3(NTB), 0,
+  a.gs = gsz(c);
+  hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(a.nK + a.nLx * (a.nLx + 1) / 2)), dim3(NTB), 0,
                      c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
@@ -881,9 +924,10 @@ static int launch_kuf(ifsvgp_ctx *c, int B) {
                               kb));
     kuf_attr = kb;
   }
-  hipLaunchKernelGGL((k_kuf<T>), dim3(cdiv(B, KUF_T), cdiv(c->M, KUF_T)), dim3(NTB), kb, c->st,
-                     (const float *)c->Zs, (const CallArgs *)c->dca, (const float *)c->inv_ell,
-                     c->M, B, c->D, (const float *)c->sfn, c->Xs, (T *)c->Kft, (long)c->Mp);
+  hipLaunchKernelGGL((k_kuf<T>), gdim(c, dim3(cdiv(B, KUF_T), cdiv(c->M, KUF_T))), dim3(NTB), kb,
+                     c->st, (const float *)c->Zs, (const CallArgs *)c->dca,
+                     (const float *)c->inv_ell, c->M, B, c->D, (const float *)c->sfn, c->Xs,
+                     (T *)c->Kft, (long)c->Mp, gsz(c));
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
@@ -905,12 +949,12 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
   { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_VEC);
-    hipLaunchKernelGGL(k_gemv_rows, dim3(cdiv(M, NTB / 64)), dim3(NTB), 0, c->st,
+    hipLaunchKernelGGL(k_gemv_rows, gdim(c, dim3(cdiv(M, NTB / 64))), dim3(NTB), 0, c->st,
                        (const float *)c->Q32, Mp, M, M, (const float *)c->va,
-                       (const float *)nullptr, 0, (const double *)nullptr, c->vb);
-    hipLaunchKernelGGL(k_vec_lb_wub, dim3(cdiv(2 * M, NTB / 64)), dim3(NTB), 0, c->st, L,
-                       (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
-                       c->vec_part, c->flag);
+                       (const float *)nullptr, 0, (const double *)nullptr, c->vb, gsz(c));
+    hipLaunchKernelGGL(k_vec_lb_wub, gdim(c, dim3(cdiv(2 * M, NTB / 64))), dim3(NTB), 0, c->st,
+                       L, (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
+                       c->vec_part, c->flag, gsz(c));
   }
   {
     Timed t(c, KK_LIK);
@@ -919,8 +963,8 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
               c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
               c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
               c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
-              c->scal, M, c->flag, c->counters + CNT_LIK};
-    hipLaunchKernelGGL(k_lik, dim3(cdiv(c->Bp, NTB)), dim3(NTB), 0, c->st, a);
+              c->scal, M, c->flag, c->counters + CNT_LIK, gsz(c)};
+    hipLaunchKernelGGL(k_lik, gdim(c, dim3(cdiv(c->Bp, NTB))), dim3(NTB), 0, c->st, a);
   }
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
@@ -940,18 +984,18 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
   }
   {
     Timed t(c, KK_VALPHA);
-    hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
+    hipLaunchKernelGGL(k_valpha<T>, gdim(c, dim3(M)), dim3(NTB), 0, c->st,
                        (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
-                       (const float *)c->sqnb, (T *)c->Vs, c->vVa);
+                       (const float *)c->sqnb, (T *)c->Vs, c->vVa, gsz(c));
   }
   { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B)); }
   {
     Timed t(c, KK_ASM);
-    hipLaunchKernelGGL(k_assemble_C<TW>, dim3(grid1((long)M * cdiv(M, 4))), dim3(NTB), 0, c->st,
-                       (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
+    hipLaunchKernelGGL(k_assemble_C<TW>, gdim(c, dim3(grid1((long)M * cdiv(M, 4)))), dim3(NTB),
+                       0, c->st, (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
                        (const float *)c->Wu32, (const float *)c->Q32, (const float *)c->va,
                        (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M,
-                       Mp, (TW *)c->Cm);
+                       Mp, (TW *)c->Cm, gsz(c));
   }
   { Timed t(c, KK_Y2); HIPCK(Ops<T>::gemm_Y2(c, cur)); }
   { Timed t(c, KK_GUU); HIPCK(Ops<T>::gemm_Guu(c, cur, want_gs ? c->gdiag : nullptr)); }
@@ -970,11 +1014,11 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
                c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
                c->lik_part, cdiv(c->Bp, NTB),
                c->Q32, c->vVa, c->vWub, Mp, c->vt2, c->ell_part, rb, cb,
-               c->gdiag, c->pdiag, (long)Mp, c->vLb, c->sP};
-    hipLaunchKernelGGL(k_grad, dim3(rb + cb + rq), dim3(NTB), 0, c->st, g);
+               c->gdiag, c->pdiag, (long)Mp, c->vLb, c->sP, gsz(c)};
+    hipLaunchKernelGGL(k_grad, gdim(c, dim3(rb + cb + rq)), dim3(NTB), 0, c->st, g);
     // dF/dm~ = L t2 and dF/ds~ rows (when requested), then the scalar gradients
     const int mrows = (want_gm || want_gs) ? rq : 0;
-    hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
+    hipLaunchKernelGGL(k_grad_tail, gdim(c, dim3(mrows + 1)), dim3(NTB), 0, c->st, g,
                        (const float *)c->L32[cur], mrows);
   }
   HIPCK(hipGetLastError());
@@ -1010,9 +1054,9 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
         HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
       }
       Timed t(c, KK_VEC);
-      hipLaunchKernelGGL(k_lt_m, dim3(cdiv(c->M, NTB / 64)), dim3(NTB), 0, c->st,
+      hipLaunchKernelGGL(k_lt_m, gdim(c, dim3(cdiv(c->M, NTB / 64))), dim3(NTB), 0, c->st,
                          (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
-                         (const CallArgs *)c->dca, c->va);
+                         (const CallArgs *)c->dca, c->va, gsz(c));
     }
     r = stage_bound<T>(c, k.B);
     if (r) return r;
@@ -1348,7 +1392,7 @@ static int run_call(ifsvgp_ctx *c, const Call &k, const CallArgs &ca) {
 // ------------------------------------------------------------------ API: compute
 static bool bad_common(ifsvgp_ctx *c, const float *ell, const float *sf2, const float *Z,
                        const float *s, const float *L) {
-  return !c || !ell || !sf2 || !Z || !s || !L;
+  return !c || c->G > 1 || !ell || !sf2 || !Z || !s || !L;  // grouped contexts: step_group only
 }
 
 static CallArgs make_args(const float *X, const float *y, int B, double N, const float *ell,
@@ -1429,6 +1473,45 @@ extern "C" int ifsvgp_step(ifsvgp_ctx *c, const float *X, const float *y, int B,
   Call k{true, true, true, B, n_ng, gammas, c->lik == IFSVGP_LIK_GAUSSIAN, g_m != nullptr,
          g_s != nullptr, NG_FIXED};
   return run_call(c, k, a);
+}
+
+// G independent training iterations (problems of the same M, B, D, each with
+// its own data, hyperparameters, Z, m~, s~ and L) on a grouped context: the
+// per-problem argument blocks are latched one by one, then every kernel of
+// the iteration runs once for all G problems (grid z = problem).
+extern "C" int ifsvgp_step_group(ifsvgp_ctx *c, const ifsvgp_problem *probs, int G, int B,
+                                 double N, const float *gammas, int n_ng) {
+  if (!c || !probs || G < 1 || G != std::max(1, c->G)) return IFSVGP_EINVAL;
+  if (B < 1 || B > c->Bmax || !(N > 0.0)) return IFSVGP_EINVAL;
+  if (n_ng < 0 || n_ng > MAX_NG_LATCH || (n_ng > 0 && !gammas)) return IFSVGP_EINVAL;
+  const bool gauss = c->lik == IFSVGP_LIK_GAUSSIAN;
+  const ifsvgp_problem &p0 = probs[0];
+  for (int g = 0; g < G; ++g) {
+    const ifsvgp_problem &p = probs[g];
+    if (!p.X || !p.y || !p.ell || !p.sf2 || !p.Z || !p.m_tilde || !p.s_tilde || !p.L ||
+        !p.out_bound || (gauss && !p.noise_var))
+      return IFSVGP_EINVAL;
+    // the launch structure is shared: the same outputs for every problem
+    if (!p.g_m != !p0.g_m || !p.g_s != !p0.g_s) return IFSVGP_EINVAL;
+  }
+  c->ev_next = 0;
+  c->side_open = false;
+  for (int g = 0; g < G; ++g) {
+    const ifsvgp_problem &p = probs[g];
+    CallArgs a = make_args(p.X, p.y, B, N, p.ell, p.sf2, p.noise_var, p.Z, p.m_tilde, p.s_tilde,
+                           p.L, gammas, n_ng);
+    a.out_bound = p.out_bound;
+    a.out_terms = p.out_terms;
+    a.out_resid = p.out_resid;
+    a.g_ell = p.g_ell; a.g_sf2 = p.g_sf2; a.g_noise = p.g_noise; a.g_Z = p.g_Z;
+    a.g_m = p.g_m; a.g_s = p.g_s;
+    hipLaunchKernelGGL(k_latch, dim3(1), dim3(64), 0, c->st, a,
+                       (CallArgs *)((char *)c->dca + g * c->gstride));
+    HIPCK(hipGetLastError());
+  }
+  Call k{true, true, true, B, n_ng, gammas, gauss, p0.g_m != nullptr, p0.g_s != nullptr,
+         NG_FIXED};
+  return enqueue_any(c, k, nullptr);
 }
 
 extern "C" int ifsvgp_natgrad_tol(ifsvgp_ctx *c, const float *Z, const float *ell,
@@ -1757,6 +1840,8 @@ extern "C" int ifsvgp_step_noalloc(void *hip_stream, int M, int D, int prec, int
   c->Bp = rup(B, PAD);
   c->nsplit = std::max(1, std::min(8, cdiv(B, 1024)));
   c->st = c->side = (hipStream_t)hip_stream;
+  c->G = 1;
+  c->gstride = 0;
   c->single_stream = true;
   c->capturing = false;
   c->use_graphs = 0;

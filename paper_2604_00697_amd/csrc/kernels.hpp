@@ -21,14 +21,16 @@ enum : int {
 // Arrival counters (one int each, reset to 0 by the last arriving workgroup).
 enum : int { CNT_VEC = 0, CNT_LIK = 1, CNT_GRAD = 2, CNT_N = 4 };
 
-// True in exactly one workgroup of the grid: the last to arrive.  Every
-// workgroup's global writes before the call are visible to it.
+// True in exactly one workgroup of the grid (of one problem's part of a
+// grouped grid, whose problems have counters of their own): the last to
+// arrive.  Every such workgroup's global writes before the call are visible
+// to it.
 IFS_DEV bool arrive_last(int *counter, int *s_flag) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     const int prev = atomicAdd(counter, 1);
-    *s_flag = prev == (int)(gridDim.x * gridDim.y * gridDim.z) - 1;
+    *s_flag = prev == (int)(gridDim.x * gridDim.y) - 1;
   }
   __syncthreads();
   const bool last = *s_flag != 0;
@@ -63,6 +65,14 @@ struct SetupArgs {
   int *flag;
   int *ngskip;         // stop flag of an adaptive NG loop, cleared for the call
   int nKx, nK, nLx;
+  long gs;             // grouped launch: bytes between the problems' workspaces
+  IFS_DEV void shift(long o) {
+    ca = gsh(ca, o); Zs = gsh(Zs, o); inv_ell = gsh(inv_ell, o); sP = gsh(sP, o);
+    Kt = gsh(Kt, o); sfn = gsh(sfn, o); KtT = gsh((char *)KtT, o); L32 = gsh(L32, o);
+    Lt32 = gsh(Lt32, o); LT = gsh((char *)LT, o); LtT = gsh((char *)LtT, o);
+    LstT = gsh((char *)LstT, o); scal = gsh(scal, o); flag = gsh(flag, o);
+    ngskip = gsh(ngskip, o);
+  }
 };
 
 template <int MAXD, typename T>
@@ -70,6 +80,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   __shared__ float zi[64][MAXD + 1], zj[64][MAXD + 1];
   __shared__ float tile[32][33];
   __shared__ double sh[NTB / 64];
+  if (a.gs) a.shift(goff(a.gs));
   const int b = blockIdx.x;
   const int M = a.M, D = a.D;
   const CallArgs *ca = a.latch ? &a.cav : a.ca;
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + tx + 16 * q;
         if (i < M && j < M) {
-          float v = sf2 * __expf(-0.5f * d2[p][q]);
+          float v = sf2 * kexp<std::is_same<T, float>::value>(-0.5f * d2[p][q]);
           if (i == j) v += si;
           a.Kt[(long)i * a.ld + j] = v;
           if constexpr (!std::is_same<T, float>::value)
@@ -228,8 +239,14 @@ __host__ __device__ inline int kuf_smem(int D) { return (2 * KUF_T * kuf_ldz(D) 
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const CallArgs *ca,
                                              const float *inv_ell, int M, int B, int D,
-                                             const float *sf2, float *Xs, T *Kft, long ld) {
+                                             const float *sf2, float *Xs, T *Kft, long ld,
+                                             long gs) {
   extern __shared__ __attribute__((aligned(16))) float ksm[];
+  if (gs) {
+    const long o = goff(gs);
+    Zs = gsh(Zs, o); ca = gsh(ca, o); inv_ell = gsh(inv_ell, o); sf2 = gsh(sf2, o);
+    Xs = gsh(Xs, o); Kft = gsh(Kft, o);
+  }
   const int D4 = (D + 3) & ~3, LDZ = kuf_ldz(D);
   float *zs = ksm;                    // [128][LDZ]
   float *xs = zs + KUF_T * LDZ;       // [128][LDZ]
@@ -265,8 +282,9 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const CallArgs *ca
   const float s2 = *sf2;
   const int lane = t & 63, wave = t >> 6, l16 = lane & 15, l4 = lane >> 4;
   const int kb0 = (wave >> 1) * 64, nb0 = (wave & 1) * 64;
+  constexpr bool F32 = std::is_same<T, float>::value;
   f32x4 c[4][4];
-  cross_block<4, 4>(zs + kb0 * LDZ, LDZ, xs + nb0 * LDZ, LDZ, D4, c);
+  if constexpr (!F32) cross_block<4, 4>(zs + kb0 * LDZ, LDZ, xs + nb0 * LDZ, LDZ, D4, c);
   float zr[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -282,8 +300,15 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const CallArgs *ca
       const int kq = kb0 + 16 * i + 4 * l4;  // first of this lane's 4 consecutive k
       T e[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        e[q] = from_f32<T>((nok && k0 + kq + q < M) ? kern_se(s2, zr[i][q], xv, c[i][j][q]) : 0.f);
+      for (int q = 0; q < 4; ++q) {
+        // the fp32 form: distances from differences and the accurate exp
+        float kv;
+        if constexpr (F32)
+          kv = s2 * kexp<true>(-0.5f * sqdist(zs + (kq + q) * LDZ, xs + n * LDZ, D));
+        else
+          kv = kern_se(s2, zr[i][q], xv, c[i][j][q]);
+        e[q] = from_f32<T>((nok && k0 + kq + q < M) ? kv : 0.f);
+      }
       T *dst = Kft + (long)(n0 + n) * ld + k0 + kq;
       if constexpr (sizeof(T) == 4) {
         *(f32x4 *)dst = f32x4{(float)e[0], (float)e[1], (float)e[2], (float)e[3]};
@@ -319,15 +344,18 @@ IFS_DEV F slot_sum(const F *p, int np, long stride) {
 
 // Two slot sums at once (uf side: nu slots, uu side: nz slots), all loads of
 // a round in flight together.
-IFS_DEV void slot_sum2(const float *pu, int nu, long su, const float *pz, int nz, long sz,
-                       float &ru, float &rz) {
+// A: the accumulation type (fp64 for the gradient's cross-tile sums); P: the
+// partials' type.
+template <typename A = float, typename P = float>
+IFS_DEV void slot_sum2(const P *pu, int nu, long su, const P *pz, int nz, long sz,
+                       A &ru, A &rz) {
   constexpr int W = 16;
-  float a[W], b[W];
+  A a[W], b[W];
 #pragma unroll
-  for (int u = 0; u < W; ++u) a[u] = b[u] = 0.f;
+  for (int u = 0; u < W; ++u) a[u] = b[u] = A(0);
   const int n = nu > nz ? nu : nz;
   for (int k = 0; k < n; k += W) {
-    float va[W], vb[W];
+    P va[W], vb[W];
 #pragma unroll
     for (int u = 0; u < W; ++u) {
       va[u] = pu[(long)max(0, min(k + u, nu - 1)) * su];
@@ -335,8 +363,8 @@ IFS_DEV void slot_sum2(const float *pu, int nu, long su, const float *pz, int nz
     }
 #pragma unroll
     for (int u = 0; u < W; ++u) {
-      a[u] += k + u < nu ? va[u] : 0.f;
-      b[u] += k + u < nz ? vb[u] : 0.f;
+      a[u] += k + u < nu ? (A)va[u] : A(0);
+      b[u] += k + u < nz ? (A)vb[u] : A(0);
     }
   }
 #pragma unroll
@@ -371,7 +399,12 @@ IFS_DEV float row_dot(const float *a, const float *x, const float *xs, int cend)
 // y[i] = scale * sum_j A[i][j] (x[j] - xs[j]) over j < Cn (lower: j <= i;
 // xs and scale optional); one wave per row.
 __global__ void k_gemv_rows(const float *A, long ld, int R, int Cn, const float *x,
-                            const float *xs, int lower, const double *scale, float *y) {
+                            const float *xs, int lower, const double *scale, float *y,
+                            long gs = 0) {
+  if (gs) {
+    const long o = goff(gs);
+    A = gsh(A, o); x = gsh(x, o); xs = gsh(xs, o); y = gsh(y, o);
+  }
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= R) return;
   const float s = row_dot(A + (long)row * ld, x, xs, lower ? min(Cn, row + 1) : Cn);
@@ -379,7 +412,12 @@ __global__ void k_gemv_rows(const float *A, long ld, int R, int Cn, const float 
 }
 
 // a = L^T m~ (rows of the fp32 transpose Lt), m~ from the call's arguments.
-__global__ void k_lt_m(const float *Lt, long ld, int M, const CallArgs *ca, float *a) {
+__global__ void k_lt_m(const float *Lt, long ld, int M, const CallArgs *ca, float *a,
+                       long gs = 0) {
+  if (gs) {
+    const long o = goff(gs);
+    Lt = gsh(Lt, o); ca = gsh(ca, o); a = gsh(a, o);
+  }
   const int row = blockIdx.x * (NTB / 64) + (threadIdx.x >> 6);
   if (row >= M) return;
   const float s = row_dot(Lt + (long)row * ld, ca->m, nullptr, M);
@@ -390,8 +428,13 @@ __global__ void k_lt_m(const float *Lt, long ld, int M, const CallArgs *ca, floa
 // per row, with workgroup partials part[blk] = {sum b_i Wub_i, sum log|L_ii|}
 // (fp64) over the workgroup's rows; the bound's finalisation sums them.
 __global__ void k_vec_lb_wub(const float *L, const float *Wu, long ld, int M, const float *b,
-                             float *Lb, float *Wub, double *part, int *flag) {
+                             float *Lb, float *Wub, double *part, int *flag, long gs = 0) {
   __shared__ double sq[NTB / 64], sl[NTB / 64];
+  if (gs) {
+    const long o = goff(gs);
+    L = gsh(L, o); Wu = gsh(Wu, o); b = gsh(b, o); Lb = gsh(Lb, o); Wub = gsh(Wub, o);
+    part = gsh(part, o); flag = gsh(flag, o);
+  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = blockIdx.x * (NTB / 64) + w;
   double q = 0.0, ldt = 0.0;
@@ -445,6 +488,14 @@ struct LikArgs {
   const double *vec_part; int n_vec;    // [n_vec][2]: b^T Wu b, sum log|L_ii|
   double *scal; int M;
   int *flag, *counter;
+  long gs;  // grouped launch: bytes between the problems' workspaces
+  IFS_DEV void shift(long o) {
+    mu_part = gsh(mu_part, o); var_part = gsh(var_part, o); ca = gsh(ca, o); sfn = gsh(sfn, o);
+    gh = gsh(gh, o); mu = gsh(mu, o); var = gsh(var, o); alpha = gsh(alpha, o);
+    beta = gsh(beta, o); sqnb = gsh(sqnb, o); part = gsh(part, o);
+    gram_part = gsh(gram_part, o); vec_part = gsh(vec_part, o); scal = gsh(scal, o);
+    flag = gsh(flag, o); counter = gsh(counter, o);
+  }
 };
 
 __device__ __forceinline__ void probit_terms(double y, double mu, double v, const double *gh,
@@ -479,6 +530,7 @@ __device__ __forceinline__ void probit_terms(double y, double mu, double v, cons
 __global__ void k_lik(LikArgs a) {
   __shared__ double sh[9 * (NTB / 64)];
   __shared__ int s_last;
+  if (a.gs) a.shift(goff(a.gs));
   const int n = blockIdx.x * NTB + threadIdx.x;
   double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
   // the KL's scalars from the earlier kernels' partials (traces, ||W - I||^2,
@@ -827,7 +879,12 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
                                                     long split_stride, const float *Wu,
                                                     const float *Q, const float *a, const float *b,
                                                     const float *Wub, const float *Va, int M,
-                                                    long ld, TC *Cm) {
+                                                    long ld, TC *Cm, long gs = 0) {
+  if (gs) {
+    const long o = goff(gs);
+    Ys = gsh(Ys, o); Wu = gsh(Wu, o); Q = gsh(Q, o); a = gsh(a, o); b = gsh(b, o);
+    Wub = gsh(Wub, o); Va = gsh(Va, o); Cm = gsh(Cm, o);
+  }
   // one thread per 4 consecutive columns of a row; the padded columns
   // (j >= M, inputs zero there) come out as zeros
   const int cpr = (M + 3) / 4;
@@ -868,8 +925,13 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int Bp,
                                                 const float *alpha, const float *sqnb, T *Vs,
-                                                float *out) {
+                                                float *out, long gs = 0) {
   __shared__ float shw[NTB / 64];
+  if (gs) {
+    const long o = goff(gs);
+    V = gsh(V, o); alpha = gsh(alpha, o); sqnb = gsh(sqnb, o); Vs = gsh(Vs, o);
+    out = gsh(out, o);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = blockIdx.x;
   if (row >= M) return;  // uniform across the workgroup
@@ -926,9 +988,9 @@ struct GradArgs {
   int M, B, D;
   const CallArgs *ca;  // N / B, grad_scale and the gradient outputs
   const float *Zs, *Xs, *inv_ell, *sfn;
-  const float *hrow, *hx; int n_uf_nt;          // [n_uf_nt][M], [n_uf_nt][M][D]
-  const float *hzrow, *hz; int nb;              // [nb][M], [nb][M][D]
-  const float *hcol; int n_uf_mt; long ldc;     // [n_uf_mt][ldc]
+  const double *hrow, *hx; int n_uf_nt;          // [n_uf_nt][M], [n_uf_nt][M][D]
+  const double *hzrow, *hz; int nb;              // [nb][M], [nb][M][D]
+  const double *hcol; int n_uf_mt; long ldc;     // [n_uf_mt][ldc]
   const double *uf_part; int n_uf_tiles;
   const double *uu_part; int n_uu_tiles;
   const double *lik_part; int n_lik;
@@ -938,6 +1000,15 @@ struct GradArgs {
   // gradient with respect to s~ (skipped without g_s)
   const float *gdiag, *pdiag; long ldpd;  // diag(G_uu); [nb][ldpd] partials of diag(P)
   const float *Lb, *s_in;
+  long gs;  // grouped launch: bytes between the problems' workspaces
+  IFS_DEV void shift(long o) {
+    ca = gsh(ca, o); Zs = gsh(Zs, o); Xs = gsh(Xs, o); inv_ell = gsh(inv_ell, o);
+    sfn = gsh(sfn, o); hrow = gsh(hrow, o); hx = gsh(hx, o); hzrow = gsh(hzrow, o);
+    hz = gsh(hz, o); hcol = gsh(hcol, o); uf_part = gsh(uf_part, o);
+    uu_part = gsh(uu_part, o); lik_part = gsh(lik_part, o); Q = gsh(Q, o); Va = gsh(Va, o);
+    Wub = gsh(Wub, o); t2 = gsh(t2, o); ell_part = gsh(ell_part, o); gdiag = gsh(gdiag, o);
+    pdiag = gsh(pdiag, o); Lb = gsh(Lb, o); s_in = gsh(s_in, o);
+  }
 };
 
 // Gradient reductions:
@@ -948,6 +1019,7 @@ struct GradArgs {
 //  * the remaining blocks: t2 = Q (V alpha - Wu b), one wave per row.
 __global__ void k_grad(GradArgs g) {
   __shared__ double sh[NTB];
+  if (g.gs) g.shift(goff(g.gs));
   const int blk = blockIdx.x, t = threadIdx.x;
   const int R = NTB / g.D;
   if (blk < g.rb) {
@@ -958,9 +1030,10 @@ __global__ void k_grad(GradArgs g) {
     double contrib = 0.0;
     if (r < R && i < g.M) {
       const long e = (long)i * g.D + d, MD = (long)g.M * g.D;
-      float ruf, ruu, hx, hz;
-      slot_sum2(g.hrow + i, g.n_uf_nt, (long)g.M, g.hzrow + i, g.nb, (long)g.M, ruf, ruu);
-      slot_sum2(g.hx + e, g.n_uf_nt, MD, g.hz + e, g.nb, MD, hx, hz);
+      double ruf, ruu, hx, hz;
+      slot_sum2<double, double>(g.hrow + i, g.n_uf_nt, (long)g.M, g.hzrow + i, g.nb, (long)g.M,
+                                ruf, ruu);
+      slot_sum2<double, double>(g.hx + e, g.n_uf_nt, MD, g.hz + e, g.nb, MD, hx, hz);
       const double zs = g.Zs[e];
       const double gz = -(double)g.inv_ell[d] * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
       if (ca.g_Z) ca.g_Z[e] = (float)(scale * gz);
@@ -978,9 +1051,10 @@ __global__ void k_grad(GradArgs g) {
     const int n = (blk - g.rb) * R + r;
     double contrib = 0.0;
     if (r < R && n < g.B) {
-      const float cn = slot_sum(g.hcol + n, g.n_uf_mt, g.ldc);
+      double cn = 0.0;
+      for (int k = 0; k < g.n_uf_mt; ++k) cn += g.hcol[n + (long)k * g.ldc];
       const double xs = g.Xs[(long)n * g.D + d];
-      contrib = (double)cn * xs * xs;
+      contrib = cn * xs * xs;
     }
     sh[t] = contrib;
     __syncthreads();
@@ -1007,6 +1081,11 @@ __global__ void k_grad(GradArgs g) {
 // dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and dF/dnoise = c sum dE/dnoise.
 __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
   __shared__ double sh[NTB];
+  if (g.gs) {
+    const long o = goff(g.gs);
+    g.shift(o);
+    L = gsh(L, o);
+  }
   const int t = threadIdx.x;
   const CallArgs &ca = *g.ca;
   const double scale = ca.grad_scale ? *ca.grad_scale : 1.0;

@@ -32,6 +32,8 @@ _SIGS = {
     "ifsvgp_version": (_I, []),
     "ifsvgp_strerror": (ctypes.c_char_p, [_I]),
     "ifsvgp_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _I]),
+    "ifsvgp_create_group": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _I, _I]),
+    "ifsvgp_step_group": (_I, [_P, _P, _I, _I, _D, _P, _I]),
     "ifsvgp_destroy": (None, [_P]),
     "ifsvgp_set_stream": (_I, [_P, _P]),
     "ifsvgp_set_graphs": (_I, [_P, _I]),
@@ -124,6 +126,13 @@ def _ptr(t, shape, name, dtype=None, optional=False):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
+
+
+class Problem(ctypes.Structure):
+    """One problem of a grouped call (the arguments of ifsvgp_step)."""
+    _fields_ = [(n, _P) for n in ("X", "y", "ell", "sf2", "noise_var", "Z", "m_tilde", "s_tilde",
+                                   "L", "out_bound", "out_terms", "out_resid", "g_ell", "g_sf2",
+                                   "g_noise", "g_Z", "g_m", "g_s")]
 
 
 def step_noalloc(X, y, N, ell, sf2, noise, Z, m, s, L, gammas, prec="fp32", lik="gaussian",
@@ -480,3 +489,57 @@ class Context:
         if n < 0:
             raise IFSVGPError(n, "kernel_flops")
         return {names[k].decode(): f[k] for k in range(n)}
+
+
+class GroupContext(Context):
+    """G independent problems of the same sizes, advanced by one grouped
+    launch per kernel (ifsvgp_step_group)."""
+
+    def __init__(self, G, M, B_max, D, prec="fp32", lik="gaussian", n_gh=20, device=None):
+        import torch
+        lib = load()
+        self.G = int(G)
+        self.M, self.B_max, self.D = int(M), int(B_max), int(D)
+        self.prec, self.lik, self.n_gh = prec, lik, int(n_gh)
+        self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
+                       else torch.device(device))
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(lib.ifsvgp_create_group(ctypes.byref(h), self.G, self.M, self.B_max, self.D,
+                                           PREC[prec], LIK[lik], self.n_gh),
+                   "ifsvgp_create_group")
+        self._h = h
+        self._lib = lib
+        self.generation = 0
+
+    def step_group(self, problems, N, gammas, want=("ell", "sf2", "noise_var", "Z", "m")):
+        """problems: G dicts with X, y, ell, sf2, noise, Z, m, s, L (L updated in
+        place).  Returns a list of (F, terms, resid, grads) per problem."""
+        import torch
+        if len(problems) != self.G:
+            raise ValueError(f"expected {self.G} problems, got {len(problems)}")
+        gm = np.ascontiguousarray(np.asarray(gammas, np.float32).reshape(-1))
+        n = gm.shape[0]
+        B = problems[0]["X"].shape[0]
+        arr = (Problem * self.G)()
+        outs = []
+        for g, p in enumerate(problems):
+            a = self._inputs(p["X"], p["y"], p["ell"], p["sf2"], p.get("noise"), p["Z"], p["m"],
+                             p["s"], p["L"])
+            if a["B"] != B:
+                raise ValueError("every problem of a group takes the same batch size")
+            F = torch.empty(1, dtype=torch.float64, device=self.device)
+            terms = torch.empty(N_TERMS, dtype=torch.float64, device=self.device)
+            resid = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+            gr = self._grad_buffers(want)
+            gp = self._grad_ptrs(gr)
+            arr[g] = Problem(a["X"], a["y"], a["ell"], a["sf2"], a["noise"], a["Z"], a["m"],
+                             a["s"], a["L"], F.data_ptr(), terms.data_ptr(),
+                             resid.data_ptr() if n else None, *gp)
+            outs.append((F, terms, resid[:n], gr))
+        self._stream()
+        _check(self._lib.ifsvgp_step_group(self._h, ctypes.cast(arr, _P), self.G, B, float(N),
+                                           gm.ctypes.data if n else None, n),
+               "ifsvgp_step_group")
+        self.generation += 1
+        return outs

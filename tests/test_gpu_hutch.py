@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 from oracle import svgp
-from test_gpu_parity import make_case, to_dev, gate
+from test_gpu_parity import make_case, to_dev, gate, elerr, EL
 
 pytestmark = pytest.mark.gpu
 
@@ -68,14 +68,15 @@ CASES = {
     "fp32_gauss_M2000_B100_K256": ("fp32", "gaussian", 2000, 100, 8, 448, 256, "rademacher"),
 }
 # s~ ranges other than the default (0.05, 0.1): a better-conditioned K~, so
-# that the bf16 gradient gates (4 x the oracle's spread) stay informative
-S_RANGE = {"bf16_gauss_wellcond_M160_B100_K32": (0.5, 1.0)}
+# that the bf16 gradient gates (4 x the oracle's spread) stay informative (at
+# s~ in [0.05, 0.1] and M = 200 bf16 rounding of the inputs alone moves dF/dZ
+# by more than 50 %, which no bf16 evaluation can resolve)
+S_RANGE = {"bf16_gauss_M200_B128_K32": (0.3, 1.0),
+           "bf16_gauss_wellcond_M160_B100_K32": (0.5, 1.0)}
 # At M = 2000 every product is a 2000-long fp32 dot product; as in the M = 4000
 # iteration case of test_gpu_parity.py, the accumulation error that the base
-# covers at the small sizes grows with it, so the base there is 3e-5 and the
-# summation allowance 256 (sums of ~64K terms).
+# covers at the small sizes grows with it, so the base there is 3e-5.
 BASE_CASE = {"fp32_gauss_M2000_B100_K256": 3e-5}
-ACC_CASE = {"fp32_gauss_M2000_B100_K256": 256.0}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -174,6 +175,8 @@ def _grad_spread(c, Om, eps, nsamp=3, seed=5):
         for k in base:
             a, b = np.ravel(out[k]), np.ravel(base[k])
             sp[k] = max(sp[k], float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+            if b.size > 1:
+                sp[k + EL] = max(sp.get(k + EL, 0.0), elerr(a, b))
     return base, sp, cond
 
 
@@ -203,8 +206,7 @@ def test_hutchinson_gradient_parity(require_gpu, name):
     ref, sp, cond = _grad_spread(c, Om, EPS[prec], nsamp=2 if M > 150 else 3)
     if name in BASE_CASE:
         b = BASE_CASE[name]
-        gate(name, prec, gpu, ref, sp, cond, base=dict(F=b, term=b, L=b, grad=b),
-             acc=ACC_CASE[name])
+        gate(name, prec, gpu, ref, sp, cond, base=dict(F=b, term=b, L=b, grad=b))
     else:
         gate(name, prec, gpu, ref, sp, cond)
 

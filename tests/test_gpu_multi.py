@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import svgp
-from test_gpu_parity import make_case, gate, EPS
+from test_gpu_parity import make_case, gate, EPS, elerr, EL
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,8 @@ def _sensitivity(c, eps, nsamp, seed=9):
         out, _ = _oracle(c, pert, scale)
         for k in base:
             sp[k] = max(sp[k], _rel(out[k], base[k], 1.0 if k == "KL" else 0.0))
+            if np.size(base[k]) > 1:
+                sp[k + EL] = max(sp.get(k + EL, 0.0), elerr(out[k], base[k]))
     return base, sp, cond
 
 
@@ -201,6 +203,9 @@ def test_multi_output_full_size_C3(require_gpu, prec):
     gpu = dict(F=F.item(), data=t[0], KL=t[1], sum_var=t[2])
     gpu.update({"grad_" + k: v.double().cpu().numpy() for k, v in gg.items()})
     ref, sp, cond = _sensitivity(c, EPS[prec], nsamp=1)
+    # in bf16 the summed dF/dZ of four outputs moves by about 20 % under
+    # rounding of the inputs alone (spread), so the gate reports it as
+    # unresolved; the fp32 case gates it
     gate(f"multi_full_C3_{prec}", prec, gpu, ref, sp, cond)
     ctx.close()
 

@@ -4,30 +4,29 @@ Both sides receive the same seeded float32 inputs.  The gate for every
 quantity q (the updated L, the NG residuals, F, each term, each gradient
 block) is
 
-    err(q) <= max(base(q), mult * spread(q), acc * 2^-24 * cond(q))
+    tol(q) = max(base(q), mult * spread(q))
 
-where err is the relative error (norm-wise for arrays) against the oracle.
+for the norm-wise relative error ||gpu - ref|| / ||ref||, and the same with
+the spread taken in the element-wise measure for the element-wise error
+max_i |gpu_i - ref_i| / max_i |ref_i| (every coordinate of a gradient block is
+checked against the block's scale, so a wrong small coordinate such as one
+lengthscale fails even when the norm hides it).
 
 spread(q) is the oracle's own relative change when its inputs (X, y, Z, ell,
 sf2, noise, m~, s~, L) and the kernel matrices it forms (K_uu, K_uf) carry
 independent relative rounding of the size of the GPU form's operand precision
 (eps = 2^-24 fp32, 2^-9 bf16, 2^-12 fp16; worst of 3 seeded perturbations,
-1 at the largest size).  W = L^T K~ L and P = L(2I - W)L^T amplify that
-rounding by about kappa = ||L||^2 ||K~||, so no evaluation in that precision
-can beat roughly eps * kappa on them.
-
-cond(q) (gradient blocks only) is the summation condition of the gradient's
-sums, ||sum of |terms| || / ||sum||, from the oracle.  Every form accumulates
-in fp32, and an fp32 sum of n terms with condition cond carries a relative
-error of about sqrt(n) * 2^-24 * cond when the roundings are independent;
-acc = 128 covers sums of about 16K terms (a plain numpy float32 evaluation of
-the same L-space algorithm shows errors of this size, e.g. 6e-4 on dF/dZ at
-M=512, B=1024, D=8 where cond = 327).
+1 at the largest sizes): what rounding the inputs of the computation to that
+precision alone does to the result.  W = L^T K~ L and P = L(2I - W)L^T amplify
+it by about kappa = ||L||^2 ||K~||, so ill-conditioned cases gate above base.
 
   fp32:      base 1e-5 for everything, mult 30
   bf16/fp16: base 1e-3 (F), 1e-2 (terms), 2e-2 (L, gradients), mult 4
-Well-conditioned cases therefore gate at the base tolerance.
-Each check prints "PARITY <case> <quantity> <err> tol <tol> spread <spread> cond <cond>".
+A quantity whose gate would exceed 0.5 (rounding of the inputs to the form's
+precision alone moves it by more than 50 % / mult) is reported as unresolved
+and not gated: no evaluation in that precision resolves it.
+Each check prints "PARITY <case> <quantity> <err> tol <tol> el <elementwise err>
+spread <spread> cond <summation condition of the oracle's gradient sums>".
 """
 import zlib
 
@@ -43,7 +42,7 @@ BASE = {"fp32": dict(F=1e-5, term=1e-5, L=1e-5, grad=1e-5),
         "bf16": dict(F=1e-3, term=1e-2, L=2e-2, grad=2e-2),
         "fp16": dict(F=1e-3, term=1e-2, L=2e-2, grad=2e-2)}
 MULT = {"fp32": 30.0, "bf16": 4.0, "fp16": 4.0}
-ACC = 128.0  # fp32 accumulation: sqrt of the largest sum length covered
+EL = "@el"  # spread key suffix: the spread in the element-wise measure
 GRADS = ("ell", "sf2", "Z", "m", "noise_var", "s")
 
 
@@ -145,21 +144,41 @@ def sensitivity(c, gammas, eps, nsamp=3, seed=99):
         out, _ = oracle_outputs(p, gammas, pert)
         for k in base:
             spread[k] = max(spread[k], relerr(out[k], base[k], 1.0 if k == "KL" else 0.0))
+            if np.size(base[k]) > 1:
+                spread[k + EL] = max(spread.get(k + EL, 0.0), elerr(out[k], base[k]))
     return base, spread, cond
 
 
-def gate(case, prec, gpu, ref, spread, cond, base=None, acc=ACC):
-    """tol = max(base, mult * spread, acc * 2^-24 * summation condition);
-    reports every quantity, then asserts.  base: optional per-class override."""
+def elerr(a, b):
+    """max_i |a_i - b_i| / max_i |b_i| (element-wise error on the block's scale)."""
+    a, b = np.ravel(np.asarray(a, np.float64)), np.ravel(np.asarray(b, np.float64))
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gate(case, prec, gpu, ref, spread, cond, base=None):
+    """tol = max(base, mult * spread); the norm-wise and the element-wise
+    errors must both stay within it.  Reports every quantity, then asserts.
+    base: optional per-class override.  A quantity that rounding of the
+    inputs to this precision alone moves by more than 0.5 / mult (its gate
+    would exceed 50 %) is reported as unresolved and not gated; fp32 gates
+    every quantity."""
     bad = []
     for q in ref:
+        if prec != "fp32" and MULT[prec] * spread[q] > 0.5:
+            print(f"PARITY {case} {q} {relerr(gpu[q], ref[q]):.3e} unresolved spread "
+                  f"{spread[q]:.2e}", flush=True)
+            continue
         b = (base or BASE[prec])[klass(q)]
-        tol = max(b, MULT[prec] * spread[q], acc * 2.0 ** -24 * cond.get(q, 0.0))
+        tol = max(b, MULT[prec] * spread[q])
+        tol_el = max(b, MULT[prec] * spread.get(q + EL, spread[q]))
         err = relerr(gpu[q], ref[q], 1.0 if q == "KL" else 0.0)
-        print(f"PARITY {case} {q} {err:.3e} tol {tol:.2e} spread {spread[q]:.2e} "
-              f"cond {cond.get(q, 1.0):.1f}", flush=True)
+        el = elerr(gpu[q], ref[q]) if np.size(ref[q]) > 1 else err
+        print(f"PARITY {case} {q} {err:.3e} tol {tol:.2e} el {el:.3e} tol_el {tol_el:.2e} "
+              f"spread {spread[q]:.2e} cond {cond.get(q, 1.0):.1f}", flush=True)
         if not err <= tol:
             bad.append(f"{q}: {err:.3e} > {tol:.2e}")
+        if not el <= tol_el:
+            bad.append(f"{q} element-wise: {el:.3e} > {tol_el:.2e}")
     assert not bad, f"{case}: " + "; ".join(bad)
 
 
@@ -184,11 +203,11 @@ def run_gpu(c, prec="fp32", gammas=(1.0,)):
     return out, code
 
 
-def compare(case, c, prec="fp32", gammas=(1.0,), nsamp=3, base=None, acc=ACC):
+def compare(case, c, prec="fp32", gammas=(1.0,), nsamp=3, base=None):
     gpu, code = run_gpu(c, prec, gammas)
     assert code == 0, f"device status {code}"
     ref, spread, cond = sensitivity(c, gammas, EPS[prec], nsamp=nsamp)
-    gate(case, prec, gpu, ref, spread, cond, base, acc)
+    gate(case, prec, gpu, ref, spread, cond, base)
 
 
 CASES_FP32 = {
@@ -219,7 +238,7 @@ CASES_FP32 = {
 def test_uci_size_M4000_B100_fp32(require_gpu):
     c = make_case(4000, 100, 8, seed=4000, s_range=(0.05, 0.1))
     base = dict(BASE["fp32"], F=3e-5, term=3e-5, grad=3e-5)
-    compare("uci_M4000_B100_D8_fp32", c, "fp32", (1.0,), nsamp=1, base=base, acc=256.0)
+    compare("uci_M4000_B100_D8_fp32", c, "fp32", (1.0,), nsamp=1, base=base)
 
 
 @pytest.mark.parametrize("name", list(CASES_FP32))
@@ -285,7 +304,10 @@ def test_autograd_function_matches_oracle(require_gpu):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 def test_low_precision_parity(require_gpu, prec):
-    compare(f"{prec}_M256_B512_D8", make_case(256, 512, 8, seed=21), prec)
+    # bf16 at s~ in [1e-4, 1e-2] leaves the NG residual unresolved (input
+    # rounding alone moves it by 15 %); s~ in [0.01, 0.05] keeps it resolvable
+    sr = (1e-2, 5e-2) if prec == "bf16" else (1e-4, 1e-2)
+    compare(f"{prec}_M256_B512_D8", make_case(256, 512, 8, seed=21, s_range=sr), prec)
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
@@ -295,7 +317,11 @@ def test_low_precision_parity_wellcond(require_gpu, prec):
 
 
 def test_bf16_probit_parity(require_gpu):
-    compare("bf16_probit_M200", make_case(200, 300, 6, seed=23, lik="probit"), "bf16")
+    # at s~ in [1e-4, 1e-2] bf16 rounding of the inputs alone moves this
+    # case's dF/dZ by 350 % (K~ is not resolvable in bf16); s~ in [0.2, 0.5]
+    # keeps every quantity resolvable
+    compare("bf16_probit_M200", make_case(200, 300, 6, seed=23, lik="probit",
+                                          s_range=(0.2, 0.5)), "bf16")
 
 
 def test_argument_errors_and_domain_flag(require_gpu):
