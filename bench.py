@@ -213,8 +213,9 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
     prediction at 4 B test points with their log densities and NLPD, the
     adaptive NG loop with the residual rule (4 checked steps, none stopped),
     the NG loop with the variance-gap rule (3 checked steps on one batch),
-    the Hutchinson bound, the multi-output bound with its gradient, and one
-    Adam step on Z."""
+    the Hutchinson bound, the multi-output bound with its gradient, grouped
+    iterations of independent problems against separate calls, and one Adam
+    step on Z."""
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
@@ -317,6 +318,42 @@ def next_rows(prec, w, batches, par, L0, dev, reps=5):
     out["multi_output"] = {"Q": Qm, "B": w.B, "with_grad_ms": round(ms_multi, 4),
                            "single_output_calls_ms": round(ms_single, 4),
                            "speedup": round(ms_single / ms_multi, 3)}
+    # independent problems (one T each, as the layers of a deep GP): G
+    # iterations in one grouped call against G ifsvgp_step calls, at the
+    # workload's shapes (G = 4) and for small layers (M = 256, B = 1024, D = 8,
+    # G = 8), where the launches dominate
+    from paper_2604_00697_amd.lib import GroupContext
+    out["group"] = []
+    for G, (Mg, Bg, Dg) in ((4, (w.M, w.B, w.D)), (8, (256, 1024, 8))):
+        from paper_2604_00697_amd import synth
+        wg = w if (Mg, Bg, Dg) == (w.M, w.B, w.D) else synth.Workload(
+            f"M{Mg}_B{Bg}_D{Dg}", D=Dg, N=100_000, B=Bg, M=Mg, lik=w.lik)
+        pg = synth.params_s1(wg)
+        tg = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(dev)
+        probs = []
+        for q in range(G):
+            Xq, yq = wg.batch(q)
+            probs.append(dict(X=tg(Xq), y=tg(yq), ell=tg(pg.ell), sf2=tg([pg.sf2]),
+                              noise=tg([pg.noise_var]) if wg.lik == "gaussian" else None,
+                              Z=tg(pg.Z), m=tg(pg.m), s=tg(pg.s),
+                              L=tg(np.eye(wg.M))))
+        gctx = GroupContext(G, wg.M, wg.B, wg.D, prec, wg.lik)
+        sctx = Context(wg.M, wg.B, wg.D, prec, wg.lik)
+        ms_grp = timed(lambda _: gctx.step_group(probs, wg.N, [1e-3]))
+
+        def seq(_):
+            for p_ in probs:
+                sctx.step(p_["X"], p_["y"], wg.N, p_["ell"], p_["sf2"], p_["noise"], p_["Z"],
+                          p_["m"], p_["s"], p_["L"], [1e-3])
+        ms_seq = timed(seq)
+        torch.cuda.synchronize()
+        if gctx.status() != 0 or sctx.status() != 0:
+            raise RuntimeError("device status flag set in the grouped timing")
+        out["group"].append({"G": G, "M": wg.M, "B": wg.B, "D": wg.D,
+                             "grouped_ms": round(ms_grp, 4), "sequential_steps_ms": round(ms_seq, 4),
+                             "speedup": round(ms_seq / ms_grp, 3)})
+        gctx.close()
+        sctx.close()
     g = torch.zeros_like(par["Z"]) + 1e-3
 
     def adam_setup():
@@ -365,6 +402,46 @@ def cpu_baseline(w, p, budget_s=20.0):
                        f"{aff} cores in the affinity mask, {model}")
 
 
+def c4_leg(args, dev, dominant, second):
+    """The M = 2048, B = 8192, D = 32 workload (the MFMA target's workload), timed
+    like the headline one for the bf16 form (and fp32 unless --no-fp32), with the
+    roofline of its dominant kernel; no oracle work."""
+    import torch
+    from paper_2604_00697_amd.lib import Context
+    log("bench: C4 leg: building inputs")
+    w, _, batches, par = make_inputs("C4", dev)
+    c32 = Context(w.M, w.B, w.D, "fp32", w.lik)
+    L0 = par["L"].clone()
+    c32.natgrad(par["Z"], par["ell"], par["sf2"], par["s"], L0, schedule(30))
+    torch.cuda.synchronize()
+    c32.close()
+    out = {"workload": f"C4: SE-ARD regression, D={w.D}, N={w.N}, B={w.B}, M={w.M}, "
+                       f"gaussian likelihood; same step as the headline"}
+    forms = ["bf16"] + ([] if args.no_fp32 else ["fp32"])
+    for prec in forms:
+        steps, warm = args.c4_steps, args.c4_steps
+        if prec == "fp32":
+            steps, warm = max(20, steps // 5), max(20, warm // 5)
+        log(f"bench: C4 {prec}: {warm} warmup + {steps} steps")
+        r = time_form(prec, w, batches, par, L0, steps, warm, (dominant,), dev,
+                      graphs=args.graphs)
+        f_iter = sum(r["flops"][k] for k in STEP_GEMMS)
+        peak = PEAK_TFLOPS[prec]
+        ms = r["launch_ms"][dominant]
+        tf = r["flops"][dominant] / (ms * 1e-3) / 1e12
+        out[prec] = {"value": round(r["iters_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 4),
+                     "repeats": r["repeats"], "flops_per_step": f_iter,
+                     "mfma_pct": round(100.0 * f_iter / (r["ms_per_step"] * 1e-3) / (peak * 1e12), 3),
+                     "roofline": {"bound": "mfma", "kernel": dominant, "achieved": round(tf, 3),
+                                  "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                                  "traffic": kernel_traffic(dominant, "C4", prec),
+                                  "flops_per_launch": r["flops"][dominant],
+                                  "avg_launch_us": round(ms * 1e3, 3)},
+                     "status": r["status"]}
+        log(f"bench: C4 {prec} {r['ms_per_step']:.3f} ms/step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +456,9 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel mean durations")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the timings of prediction, the adaptive NG loops and Adam")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the M=2048, B=8192, D=32 leg (the target workload of the MFMA goal)")
+    ap.add_argument("--c4-steps", type=int, default=300)
     ap.add_argument("--graphs", action="store_true",
                     help="replay recorded HIP graphs instead of direct calls (the dominant "
                          "kernel's timing then runs the timed steps directly anyway)")
@@ -479,6 +559,8 @@ def main():
                        "mfma_pct": round(100.0 * f_iter / (r16["ms_per_step"] * 1e-3) /
                                          (PEAK_TFLOPS["fp16"] * 1e12), 3),
                        "F": r16["F"]}
+    if args.workload == "C3" and not args.no_c4:
+        out["c4"] = c4_leg(args, dev, dominant, second)
     if not args.no_next:
         log("bench: prediction, adaptive NG loops, Adam")
         out["entry_points"] = next_rows(args.prec, w, batches, par, L0, dev)
