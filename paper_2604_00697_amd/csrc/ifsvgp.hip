@@ -605,6 +605,17 @@ static dim3 gdim(ifsvgp_ctx *c, dim3 d) {
 }
 static long gsz(ifsvgp_ctx *c) { return c->G > 1 ? c->gstride : 0; }
 
+// The exact bound's likelihood arguments (partials of U's epilogue, the Gram
+// products' trace partials, the vector kernel's quad / log|T| partials).
+static LikArgs lik_args(ifsvgp_ctx *c, int B, long gs) {
+  const int M = c->M, nb = cdiv(M, 64);
+  return LikArgs{c->mu_part, cdiv(M, 128), c->var_part, cdiv(M, 128), (long)c->Bp,
+                 c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
+                 c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
+                 c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
+                 c->scal, M, c->flag, c->counters + CNT_LIK, gs};
+}
+
 template <typename T>
 struct Ops {
   // TW: operand type of the two products with C (fp32 in the fp16 form)
@@ -782,11 +793,12 @@ struct Ops {
     const int n = cdiv(c->M, CSY::BM), nt = n * (n + 1) / 2;
     return std::max(1, std::min({c->nsplit, cdiv(B, 4 * CSY::BK), cdiv(kSyrkWG, nt)}));
   }
-  static hipError_t syrk(ifsvgp_ctx *c, int B) {
+  // mirror: also store the upper tiles (else the pieces hold lower tiles only)
+  static hipError_t syrk(ifsvgp_ctx *c, int B, bool mirror = true) {
     Opnd<T> a{(const T *)c->Vs, c->Bp}, b{(const T *)c->Vs, c->Bp};
     const int n = cdiv(c->M, CSY::BM);
     Sched sc{n, n, 1, syrk_splits(c, B), B, 0};
-    EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, 1, (long)c->Mp * c->Mp};
+    EpiStore<float> e{c->Ys, c->Mp, c->M, c->M, mirror ? 1 : 0, (long)c->Mp * c->Mp};
     return launch_gemm<CSY>(lnc(c), a, b, sc, e);
   }
   // Y2 = L C (k < m0+BM), C symmetric
@@ -942,11 +954,10 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
   { Timed t(c, KK_GR_Y); HIPCK(Ops<T>::gram_Y(c, cur)); }
   { Timed t(c, KK_GR_W); HIPCK(Ops<T>::gr_W(c, cur)); }
   { Timed t(c, KK_GR_E); HIPCK(Ops<T>::gr_E(c, cur)); }
-  // V = L^T K_uf and a = L^T m~ come from the side stream; U takes the mean
-  // from a, then b = Q a and Lb = L b, Wub = Wu b (with partials of quad and
-  // log|T|)
+  // V = L^T K_uf and a = L^T m~ come from the side stream; b = Q a and
+  // Lb = L b, Wub = Wu b (with partials of quad and log|T|), then U, whose
+  // epilogue takes the mean from a and runs the likelihood and F
   HIPCK(join_side(c));
-  { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_VEC);
     hipLaunchKernelGGL(k_gemv_rows, gdim(c, dim3(cdiv(M, NTB / 64))), dim3(NTB), 0, c->st,
@@ -956,14 +967,10 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
                        L, (const float *)c->Wu32, Mp, M, (const float *)c->vb, c->vLb, c->vWub,
                        c->vec_part, c->flag, gsz(c));
   }
+  { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_LIK);
-    const int nb = cdiv(M, 64);
-    LikArgs a{c->mu_part, cdiv(M, 128), c->var_part, cdiv(M, 128), (long)c->Bp,
-              c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
-              c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
-              c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
-              c->scal, M, c->flag, c->counters + CNT_LIK, gsz(c)};
+    const LikArgs a = lik_args(c, B, gsz(c));
     hipLaunchKernelGGL(k_lik, gdim(c, dim3(cdiv(c->Bp, NTB))), dim3(NTB), 0, c->st, a);
   }
   HIPCK(hipGetLastError());
@@ -988,11 +995,13 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
                        (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                        (const float *)c->sqnb, (T *)c->Vs, c->vVa, gsz(c));
   }
-  { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B)); }
+  // (V D)(V D)^T by split-K on lower tiles; C assembled per lower tile
+  { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B, false)); }
   {
     Timed t(c, KK_ASM);
-    hipLaunchKernelGGL(k_assemble_C<TW>, gdim(c, dim3(grid1((long)M * cdiv(M, 4)))), dim3(NTB),
-                       0, c->st, (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
+    const int nb = cdiv(M, 64);
+    hipLaunchKernelGGL(k_assemble_C<TW>, gdim(c, dim3(nb * (nb + 1) / 2)), dim3(NTB), 0, c->st,
+                       (const float *)c->Ys, Ops<T>::syrk_splits(c, B), Mp * Mp,
                        (const float *)c->Wu32, (const float *)c->Q32, (const float *)c->va,
                        (const float *)c->vb, (const float *)c->vWub, (const float *)c->vVa, M,
                        Mp, (TW *)c->Cm, gsz(c));
@@ -1008,7 +1017,7 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
     Timed t(c, KK_GRAD);
     const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
     const int R = NTB / D;
-    const int rb = cdiv(M, R), cb = cdiv(B, R), rq = cdiv(M, NTB / 64);
+    const int rb = cdiv(M, grad_zrows(D)), cb = cdiv(B, R), rq = cdiv(M, NTB / 64);
     GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
                c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
                c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
@@ -1277,7 +1286,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
   HIPCK(join_side(c));
   const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
   const int R = NTB / D;
-  const int rb = cdiv(M, R), cb = cdiv(B, R);
+  const int rb = cdiv(M, grad_zrows(D)), cb = cdiv(B, R);
   GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
              c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
              c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,
@@ -1696,7 +1705,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
   HIPCK(join_side(c));
   const int ntB = cdiv(B, 128), nb = cdiv(M, 64), nbm = cdiv(M, 128);
   const int R = NTB / D;
-  const int rb = cdiv(M, R), cb = cdiv(B, R);
+  const int rb = cdiv(M, grad_zrows(D)), cb = cdiv(B, R);
   GradArgs g{M, B, D, c->dca, c->Zs, c->Xs, c->inv_ell, c->sfn,
              c->hrow, c->hx, ntB, c->hzrow, c->hz, nb, c->hcol, nbm, (long)c->Bp,
              c->tp_uf, nbm * ntB, c->tp_uu, nb * (nb + 1) / 2,

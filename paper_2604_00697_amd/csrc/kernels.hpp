@@ -527,25 +527,11 @@ __device__ __forceinline__ void probit_terms(double y, double mu, double v, cons
   dv = sd > 0.0 ? dsd / (2.0 * sd) : 0.0;
 }
 
-__global__ void k_lik(LikArgs a) {
-  __shared__ double sh[9 * (NTB / 64)];
-  __shared__ int s_last;
-  if (a.gs) a.shift(goff(a.gs));
-  const int n = blockIdx.x * NTB + threadIdx.x;
-  double e = 0.0, vs = 0.0, dn = 0.0, bs = 0.0;
-  // the KL's scalars from the earlier kernels' partials (traces, ||W - I||^2,
-  // b^T Wu b, log|L_ii|), summed by every workgroup before its arrival so that
-  // the last one's finalisation waits only on this kernel's own partials
-  double trw = 0.0, qwu = 0.0, r2 = 0.0, qd = 0.0, ldt = 0.0;
-  for (int i = threadIdx.x; i < a.n_gram; i += NTB) {
-    trw += a.gram_part[3 * i];
-    qwu += a.gram_part[3 * i + 1];
-    r2 += a.gram_part[3 * i + 2];
-  }
-  for (int i = threadIdx.x; i < a.n_vec; i += NTB) {
-    qd += a.vec_part[2 * i];
-    ldt += a.vec_part[2 * i + 1];
-  }
+// One datum n of the padded batch: mu, var, E_n, alpha, beta, sqrt(-beta)
+// written; contributions to the block sums of [E, var, dE/dnoise, beta]
+// returned (zero for padded entries, whose alpha, beta, sqnb are zeroed).
+IFS_DEV void lik_datum(const LikArgs &a, int n, double &e, double &vs, double &dn, double &bs) {
+  e = vs = dn = bs = 0.0;
   if (n < a.B) {
     float m, vp;
     slot_sum2(a.mu_part + n, a.n_mu, a.ldp, a.var_part + n, a.n_var, a.ldp, m, vp);
@@ -576,26 +562,35 @@ __global__ void k_lik(LikArgs a) {
     a.beta[n] = 0.f;
     a.sqnb[n] = 0.f;
   }
-  double v[9] = {e, vs, dn, bs, trw, qwu, r2, qd, ldt};
-  block_sums<NTB, 9>(v, sh);
-  if (threadIdx.x == 0) {
-    double *p = a.part + 4 * blockIdx.x;
-    p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
+}
+
+// F = c sum E - KL with
+//   KL = 1/2 (-tr(Q Wu) + tr W - M + quad - log|T| - sum log s~)
+// from the likelihood's block partials part[nblk][4] and the earlier kernels'
+// partials (traces, ||W - I||^2, b^T Wu b, log|L_ii|).  Called by every
+// thread of one block of NT threads; sh holds >= 7 * NT / 64 doubles.
+template <int NT>
+IFS_DEV void lik_final(const LikArgs &a, int nblk, double *sh) {
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += NT) {
+    v[0] += a.part[4 * i];
+    v[1] += a.part[4 * i + 1];
   }
-  if (!arrive_last(a.counter, &s_last)) return;
-  double w2[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTB) {
-    w2[0] += a.part[4 * i];
-    w2[1] += a.part[4 * i + 1];
+  for (int i = threadIdx.x; i < a.n_gram; i += NT) {
+    v[2] += a.gram_part[3 * i];
+    v[3] += a.gram_part[3 * i + 1];
+    v[4] += a.gram_part[3 * i + 2];
   }
-  block_sums<NTB, 2>(w2, sh);
+  for (int i = threadIdx.x; i < a.n_vec; i += NT) {
+    v[5] += a.vec_part[2 * i];
+    v[6] += a.vec_part[2 * i + 1];
+  }
+  block_sums<NT, 7>(v, sh);
   if (threadIdx.x == 0) {
-    trw = v[4]; qwu = v[5]; r2 = v[6]; qd = v[7]; ldt = v[8];
-    e = w2[0];
-    vs = w2[1];
-    a.scal[S_QUAD] = qd;
-    a.scal[S_LOGDET] = 2.0 * ldt;
-    const double quad = qd, logdet = 2.0 * ldt, sls = a.scal[S_SUMLOGS];
+    const double e = v[0], vs = v[1], trw = v[2], qwu = v[3], r2 = v[4];
+    const double quad = v[5], logdet = 2.0 * v[6], sls = a.scal[S_SUMLOGS];
+    a.scal[S_QUAD] = quad;
+    a.scal[S_LOGDET] = logdet;
     const double KL = 0.5 * (-qwu + trw - (double)a.M + quad - logdet - sls);
     const double data = a.ca->c * e;
     const double F = data - KL;
@@ -607,6 +602,23 @@ __global__ void k_lik(LikArgs a) {
       o[4] = trw; o[5] = qwu; o[6] = quad; o[7] = logdet;
     }
   }
+}
+
+// Likelihood over the padded batch, one datum per thread; the last block
+// forms F.
+__global__ void k_lik(LikArgs a) {
+  __shared__ double sh[7 * (NTB / 64)];
+  __shared__ int s_last;
+  if (a.gs) a.shift(goff(a.gs));
+  double v[4];
+  lik_datum(a, blockIdx.x * NTB + threadIdx.x, v[0], v[1], v[2], v[3]);
+  block_sums<NTB, 4>(v, sh);
+  if (threadIdx.x == 0) {
+    double *p = a.part + 4 * blockIdx.x;
+    p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
+  }
+  if (!arrive_last(a.counter, &s_last)) return;
+  lik_final<NTB>(a, gridDim.x, sh);
 }
 
 // ---------------------------------------------------------------- prediction
@@ -871,49 +883,78 @@ __global__ void k_hutch_quad(const float *b, const float *Wub, const float *L, l
 
 // ---------------------------------------------------------------- backward
 // C = -sym((V alpha) a^T) + V diag(beta) V^T - 1/2 (Wu + I - Wub a^T - a Wub^T)
-//     + 1/2 (Q - b b^T), with V diag(beta) V^T = -sum_s Ys[s] (split-K pieces of
-// (V D)(V D)^T, D = diag(sqrt(-beta)), stored symmetric), written in the
-// operand type TC over the M x M block.
+//     + 1/2 (Q - b b^T), with V diag(beta) V^T = -sum_s Ys[s] (split-K pieces
+// of (V D)(V D)^T, D = diag(sqrt(-beta)); beta <= 0 for both likelihoods),
+// written in the operand type TC over the M x M block.  The pieces hold the
+// lower 64 x 64 tiles only: one workgroup per lower tile sums them in split
+// order, forms the tile of C from the symmetric inputs and writes it and,
+// through LDS, its mirror.  Entries outside the M x M block are zeros.
+template <typename TC>
+struct alignas(8 * sizeof(TC)) Pack8 {
+  TC v[8];
+};
 template <typename TC>
 __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
                                                     long split_stride, const float *Wu,
                                                     const float *Q, const float *a, const float *b,
                                                     const float *Wub, const float *Va, int M,
                                                     long ld, TC *Cm, long gs = 0) {
+  __shared__ float ct[64][65];
   if (gs) {
     const long o = goff(gs);
     Ys = gsh(Ys, o); Wu = gsh(Wu, o); Q = gsh(Q, o); a = gsh(a, o); b = gsh(b, o);
     Wub = gsh(Wub, o); Va = gsh(Va, o); Cm = gsh(Cm, o);
   }
-  // one thread per 4 consecutive columns of a row; the padded columns
-  // (j >= M, inputs zero there) come out as zeros
-  const int cpr = (M + 3) / 4;
-  const long n = (long)M * cpr;
-  for (long e = blockIdx.x * (long)NTB + threadIdx.x; e < n; e += (long)gridDim.x * NTB) {
-    const int i = (int)(e / cpr), j0 = (int)(e % cpr) * 4;
-    const long ij = (long)i * ld + j0;
-    f32x4 ys = *(const f32x4 *)(Ys + ij);
-#pragma unroll 4
-    for (int s = 1; s < nsplit; ++s) ys += *(const f32x4 *)(Ys + s * split_stride + ij);
-    const f32x4 wu = *(const f32x4 *)(Wu + ij), q = *(const f32x4 *)(Q + ij);
-    const f32x4 aj = *(const f32x4 *)(a + j0), bj = *(const f32x4 *)(b + j0);
-    const f32x4 wj = *(const f32x4 *)(Wub + j0), vj = *(const f32x4 *)(Va + j0);
-    const float ai = a[i], bi = b[i], wi = Wub[i], vi = Va[i];
-    TC out[4];
+  const int t = blockIdx.x;
+  int I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int m0 = I * 64, n0 = J * 64;
+  float cv[2][8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float c = -0.5f * (vi * aj[u] + ai * vj[u]) - ys[u] -
-                      0.5f * (wu[u] + (i == j0 + u ? 1.f : 0.f) - wi * aj[u] - ai * wj[u]) +
-                      0.5f * (q[u] - bi * bj[u]);
-      out[u] = from_f32<TC>(c);
+  for (int k = 0; k < 2; ++k) {
+    const int ch = threadIdx.x + k * NTB, r = ch / 8, c = (ch % 8) * 8;
+    const int gi = m0 + r, gj = n0 + c;
+    const long ij = (long)gi * ld + gj;
+    f32x4 y0 = *(const f32x4 *)(Ys + ij), y1 = *(const f32x4 *)(Ys + ij + 4);
+#pragma unroll 4
+    for (int s = 1; s < nsplit; ++s) {
+      y0 += *(const f32x4 *)(Ys + s * split_stride + ij);
+      y1 += *(const f32x4 *)(Ys + s * split_stride + ij + 4);
     }
-    if constexpr (sizeof(TC) == 4) {
-      *(f32x4 *)(Cm + ij) = f32x4{(float)out[0], (float)out[1], (float)out[2], (float)out[3]};
-    } else {
-      uint2 raw;
-      __builtin_memcpy(&raw, out, 8);
-      *(uint2 *)(Cm + ij) = raw;
+    const f32x4 wu0 = *(const f32x4 *)(Wu + ij), wu1 = *(const f32x4 *)(Wu + ij + 4);
+    const f32x4 q0 = *(const f32x4 *)(Q + ij), q1 = *(const f32x4 *)(Q + ij + 4);
+    const f32x4 a0 = *(const f32x4 *)(a + gj), a1 = *(const f32x4 *)(a + gj + 4);
+    const f32x4 b0 = *(const f32x4 *)(b + gj), b1 = *(const f32x4 *)(b + gj + 4);
+    const f32x4 w0 = *(const f32x4 *)(Wub + gj), w1 = *(const f32x4 *)(Wub + gj + 4);
+    const f32x4 v0 = *(const f32x4 *)(Va + gj), v1 = *(const f32x4 *)(Va + gj + 4);
+    const float ai = a[gi], bi = b[gi], wi = Wub[gi], vi = Va[gi];
+    Pack8<TC> out;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float ys = u < 4 ? y0[u] : y1[u - 4], wu = u < 4 ? wu0[u] : wu1[u - 4];
+      const float q = u < 4 ? q0[u] : q1[u - 4], aj = u < 4 ? a0[u] : a1[u - 4];
+      const float bj = u < 4 ? b0[u] : b1[u - 4], wj = u < 4 ? w0[u] : w1[u - 4];
+      const float vj = u < 4 ? v0[u] : v1[u - 4];
+      const float x = -0.5f * (vi * aj + ai * vj) - ys -
+                      0.5f * (wu + (gi == gj + u ? 1.f : 0.f) - wi * aj - ai * wj) +
+                      0.5f * (q - bi * bj);
+      cv[k][u] = (gi < M && gj + u < M) ? x : 0.f;
+      out.v[u] = from_f32<TC>(cv[k][u]);
+      ct[r][c + u] = cv[k][u];
     }
+    *(Pack8<TC> *)(Cm + ij) = out;
+  }
+  if (I == J) return;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int ch = threadIdx.x + k * NTB, c = ch / 8, r = (ch % 8) * 8;
+    Pack8<TC> out;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) out.v[u] = from_f32<TC>(ct[r + u][c]);
+    *(Pack8<TC> *)(Cm + (long)(n0 + c) * ld + m0 + r) = out;
   }
 }
 
@@ -1011,29 +1052,59 @@ struct GradArgs {
   }
 };
 
+// Z-row blocks of k_grad: GRAD_SLOT_GROUPS threads per (row, d) split the
+// tile slots, grad_zrows(D) rows per block.
+constexpr int GRAD_SLOT_GROUPS = 4;
+__host__ __device__ inline int grad_zrows(int D) { return NTB / (GRAD_SLOT_GROUPS * D); }
+
 // Gradient reductions:
-//  * blocks [0, rb): dF/dZ rows (R = NTB / D rows of D per block) from the
+//  * blocks [0, rb): dF/dZ rows (grad_zrows(D) rows of D per block) from the
 //    per-tile partials of H_uf and H_uu, and lengthscale partials;
 //  * blocks [rb, rb + cb): lengthscale partials of the data side (column sums
 //    of H_uf against Xs^2);
 //  * the remaining blocks: t2 = Q (V alpha - Wu b), one wave per row.
-__global__ void k_grad(GradArgs g) {
+__global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
   __shared__ double sh[NTB];
+  __shared__ double sx[GRAD_SLOT_GROUPS * NTB];
   if (g.gs) g.shift(goff(g.gs));
   const int blk = blockIdx.x, t = threadIdx.x;
   const int R = NTB / g.D;
   if (blk < g.rb) {
-    const int r = t / g.D, d = t % g.D;
-    const int i = blk * R + r;
+    // GRAD_SLOT_GROUPS threads per (row, d), each summing every
+    // GRAD_SLOT_GROUPS-th tile slot, combined in a fixed order
+    constexpr int G = GRAD_SLOT_GROUPS;
+    const int Rz = grad_zrows(g.D), per = Rz * g.D;
+    const int grp = t / per, rem = t % per, r = rem / g.D, d = rem % g.D;
+    const int i = blk * Rz + r;
     const CallArgs &ca = *g.ca;
     const double scale = ca.grad_scale ? *ca.grad_scale : 1.0;
-    double contrib = 0.0;
-    if (r < R && i < g.M) {
+    double ruf = 0.0, ruu = 0.0, hx = 0.0, hz = 0.0;
+    if (grp < G && i < g.M) {
       const long e = (long)i * g.D + d, MD = (long)g.M * g.D;
-      double ruf, ruu, hx, hz;
-      slot_sum2<double, double>(g.hrow + i, g.n_uf_nt, (long)g.M, g.hzrow + i, g.nb, (long)g.M,
-                                ruf, ruu);
-      slot_sum2<double, double>(g.hx + e, g.n_uf_nt, MD, g.hz + e, g.nb, MD, hx, hz);
+      // slots grp, grp + G, ... (a group with no slot keeps slot 0's address,
+      // whose values slot_sum2 reads but discards)
+      const int nuf = g.n_uf_nt > grp ? (g.n_uf_nt - grp + G - 1) / G : 0;
+      const int nuu = g.nb > grp ? (g.nb - grp + G - 1) / G : 0;
+      const long ouf = nuf ? (long)grp : 0, ouu = nuu ? (long)grp : 0;
+      slot_sum2<double, double>(g.hrow + i + ouf * g.M, nuf, (long)G * g.M,
+                                g.hzrow + i + ouu * g.M, nuu, (long)G * g.M, ruf, ruu);
+      slot_sum2<double, double>(g.hx + e + ouf * MD, nuf, G * MD, g.hz + e + ouu * MD, nuu,
+                                G * MD, hx, hz);
+    }
+    sx[t] = ruf;
+    sx[NTB + t] = ruu;
+    sx[2 * NTB + t] = hx;
+    sx[3 * NTB + t] = hz;
+    __syncthreads();
+    double contrib = 0.0;
+    if (t < per && i < g.M) {
+      for (int q = 1; q < G; ++q) {
+        ruf += sx[q * per + t];
+        ruu += sx[NTB + q * per + t];
+        hx += sx[2 * NTB + q * per + t];
+        hz += sx[3 * NTB + q * per + t];
+      }
+      const long e = (long)i * g.D + d;
       const double zs = g.Zs[e];
       const double gz = -(double)g.inv_ell[d] * ((zs * ruf - hx) + 2.0 * (zs * ruu - hz));
       if (ca.g_Z) ca.g_Z[e] = (float)(scale * gz);
@@ -1043,7 +1114,7 @@ __global__ void k_grad(GradArgs g) {
     __syncthreads();
     if (t < g.D) {
       double s = 0.0;
-      for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
+      for (int q = 0; q < Rz; ++q) s += sh[q * g.D + t];
       g.ell_part[(long)blk * g.D + t] = s;
     }
   } else if (blk < g.rb + g.cb) {
@@ -1437,7 +1508,7 @@ struct LikMoArgs {
   double *scal; int *flag; int *counter;
 };
 
-__global__ void k_lik_mo(LikMoArgs a) {
+__global__ __launch_bounds__(NTB) void k_lik_mo(LikMoArgs a) {
   __shared__ double sh[7 * (NTB / 64)];
   __shared__ int s_last;
   const int n = blockIdx.x * NTB + threadIdx.x;
