@@ -60,18 +60,20 @@ struct Chunks {
 // always spans the whole BM x BN block, so the reads are unconditional (and
 // stay in flight together); values outside the valid region (ok false, or
 // index q >= nq along the chunk) are replaced by zero afterwards.
-// lds_get: a read of the staged tile that the compiler may not move into the
-// branch of a later select (volatile), so that guarded uses of staged values
-// compile to selects after reads that are all in flight, not to one
-// branch-and-wait per value.
-IFS_DEV float lds_get(const float *p) { return *(const volatile float *)p; }
-#define CSV(r, c) lds_get(Cs + (r) * C::LDC + (c))
+// pin: an empty asm statement that takes v in a register and hands it back,
+// so a value loaded before it cannot be re-read later inside the branch of a
+// select.  Guarded uses of staged values load every value first (plain LDS
+// reads, all in flight together), pin them, then select.
+IFS_DEV void pin(float &v) { asm volatile("" : "+v"(v)); }
+#define CSV(r, c) Cs[(r) * C::LDC + (c)]
 
 template <class C>
 IFS_DEV void cs_row(const float *Cs, int r, int c, bool ok, int nq, float (&x)[VEC]) {
   float v[VEC];
 #pragma unroll
   for (int q = 0; q < VEC; ++q) v[q] = CSV(r, c + q);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) pin(v[q]);
 #pragma unroll
   for (int q = 0; q < VEC; ++q) x[q] = (ok && q < nq) ? v[q] : 0.f;
 }
@@ -80,6 +82,8 @@ IFS_DEV void cs_col(const float *Cs, int r, int c, bool ok, int nq, float (&x)[V
   float v[VEC];
 #pragma unroll
   for (int q = 0; q < VEC; ++q) v[q] = CSV(r + q, c);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) pin(v[q]);
 #pragma unroll
   for (int q = 0; q < VEC; ++q) x[q] = (ok && q < nq) ? v[q] : 0.f;
 }
@@ -417,12 +421,15 @@ struct EpiNgUpdate {
       int r, c;
       K::row(k, r, c);
       const int gi = t.m0 + r, gj0 = t.n0 + c;
-      float v[VEC];
+      float v[VEC], xs[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) xs[q] = CSV(r, c + q);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) pin(xs[q]);
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
         const int gj = gj0 + q;
-        const float x = CSV(r, c + q);
-        v[q] = (gi < M && gj < M && gi >= gj) ? lv[k][q] - gamma * x : 0.f;
+        v[q] = (gi < M && gj < M && gi >= gj) ? lv[k][q] - gamma * xs[q] : 0.f;
       }
       st_pack(Ln + (long)gi * ld + gj0, v);
       if constexpr (!std::is_same<T, float>::value) st_pack(LnT + (long)gi * ld + gj0, v);
@@ -503,13 +510,18 @@ struct EpiBoundGram {
       int r, c;
       K::row(k, r, c);
       const int gi = t.m0 + r;
+      float es[VEC];
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) es[q] = CSV(r, c + q);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) pin(es[q]);
 #pragma unroll
       for (int q = 0; q < VEC; ++q) {
         const int gj = t.n0 + c + q;
         const bool in = gi < M && gj < M;
         const float w = wv[k][q];
         const float qv = in ? (gi == gj ? 2.f : 0.f) - w : 0.f;
-        const float e = CSV(r, c + q);
+        const float e = es[q];
         const float wu = in ? w - e : 0.f;
         if (in && gi >= gj) {
           const double mult = gi == gj ? 1.0 : 2.0;
@@ -779,17 +791,30 @@ struct EpiGradUf {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int i = ib + 16 * ii + r_of(q);
-          zr[ii][q] = lds_get(zn + i);
-          lr[ii][q] = lds_get(lb + i);
+          zr[ii][q] = zn[i];
+          lr[ii][q] = lb[i];
           rok[ii][q] = t.m0 + i < M;
         }
 #pragma unroll
       for (int jj = 0; jj < C::TN; ++jj) {
         const int n = jb + 16 * jj + l16;
-        xc[jj] = lds_get(xn + n);
-        ac[jj] = lds_get(al + n);
-        bc[jj] = lds_get(be + n);
+        xc[jj] = xn[n];
+        ac[jj] = al[n];
+        bc[jj] = be[n];
         cok[jj] = t.n0 + n < B;
+      }
+#pragma unroll
+      for (int ii = 0; ii < C::TM; ++ii)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          pin(zr[ii][q]);
+          pin(lr[ii][q]);
+        }
+#pragma unroll
+      for (int jj = 0; jj < C::TN; ++jj) {
+        pin(xc[jj]);
+        pin(ac[jj]);
+        pin(bc[jj]);
       }
       // the fp32 form recomputes K_uf from differences with the accurate exp
       // (as its forward does); the others from norms and an MFMA cross term

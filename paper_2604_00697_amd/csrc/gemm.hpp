@@ -160,13 +160,168 @@ struct IC {
   static constexpr int value = v;
 };
 
+// ------------------------------------------------------------------ generated B operand
+// NoGen: both operands are loaded from global memory.
+struct NoGen {
+  static constexpr bool kOn = false;
+  IFS_DEV void shift(long) {}
+  template <class C>
+  struct State {
+    IFS_DEV void init(const NoGen &, int, int) {}
+    IFS_DEV void prefetch(int) {}
+    IFS_DEV void gen(unsigned char *, int) {}
+  };
+};
+
+// KufGen: the B operand of V = L^T K_uf is the kernel-matrix tile
+//   Bt[n][m] = K_uf[m][n] = sf2 exp(-1/2 |zs_m - xs_n|^2),
+// generated in LDS for each k-tile (64 inducing points m) of the
+// workgroup's 64 batch points n; K_uf is never stored.  With the scaling
+// c = sqrt(log2(e) / 2), z' = c zs, x' = c xs:
+//   K = 2^(log2 sf2 - |z'|^2 - |x'|^2 + (2 z') . x'),
+// the dot product on the bf16 matrix cores from hi/lo bf16 splits of 2 z' and
+// x' (hi hi + hi lo + lo hi: about 16 significant bits, below the rounding of
+// the bf16 / fp16 operand it produces), the accumulator started at
+// log2 sf2 - |x'|^2 - |z'|^2 (fp32 norms of the unsplit values), one exp2 per
+// entry, clamped at log2 sf2 (distance >= 0).  Inputs per call (written by the
+// set-up): Zh, Zl [Mp][KW], zc = -|z'|^2 [Mp], Xh, Xl [Bp][KW],
+// xr = log2 sf2 - |x'|^2 [Bp], lsf2 = log2 sf2; KW (16, 32 or 64) >= D, zero
+// beyond D.  KW = 16 contracts with the 16x16x16 bf16 instruction, else
+// 16x16x32 per 32 d.  Each of the 4 waves generates a 32 (m) x 32 (n)
+// quadrant: 2 x 2 blocks of 16 x 16, each lane 4 consecutive m of one n,
+// stored as one 8-byte LDS write into the swizzled stage layout the fragment
+// reads expect.  The z inputs of k-tile j+1 are loaded while tile j is
+// generated.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+template <int KW>
+struct KufOp {  // one lane's share of a row: 8 bf16, or 4 for KW = 16
+  typedef bf16x8 type;
+  static constexpr int NC = KW / 32;  // operands per row and lane
+  static IFS_DEV f32x4 mma(type a, type b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct KufOp<16> {
+  typedef bf16x4 type;
+  static constexpr int NC = 1;
+  static IFS_DEV f32x4 mma(type a, type b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                      __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+  }
+};
+template <typename T, int KW>
+struct KufGen {
+  static constexpr bool kOn = true;
+  using Op = typename KufOp<KW>::type;
+  static constexpr int NC = KufOp<KW>::NC, RW = 4 * NC;  // operands per row
+  const Op *Zh, *Zl;
+  const float *zc;
+  const Op *Xh, *Xl;
+  const float *xr, *lsf2;
+  int M, B;
+  IFS_DEV void shift(long o) {
+    Zh = gsh(Zh, o); Zl = gsh(Zl, o); zc = gsh(zc, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
+    xr = gsh(xr, o); lsf2 = gsh(lsf2, o);
+  }
+  template <class C>
+  struct State {
+    static_assert(C::NW == 4 && C::BN == 64 && C::BK == 64 && C::S == 2,
+                  "generator layout: 4 waves, 64 x 64 k-tiles of the B operand, two stages");
+    const Op *Zh, *Zl;
+    const float *zc;
+    int M, B, n0, kb, gm, gn, l16, l4;
+    float lim;
+    Op xh[2][NC], xl[2][NC], zh[2][NC], zl[2][NC];
+    f32x4 zcv[2];
+    float xrv[2];
+    IFS_DEV void init(const KufGen &g, int n0_, int kb_) {
+      Zh = g.Zh; Zl = g.Zl; zc = g.zc; M = g.M; B = g.B;
+      n0 = n0_;
+      kb = kb_;
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      gm = wave >> 1;
+      gn = wave & 1;
+      l16 = lane & 15;
+      l4 = lane >> 4;
+      lim = *g.lsf2;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const long r = (long)(n0 + gn * 32 + nb * 16 + l16) * RW;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          xh[nb][c] = g.Xh[r + 4 * c + l4];
+          xl[nb][c] = g.Xl[r + 4 * c + l4];
+        }
+        xrv[nb] = g.xr[n0 + gn * 32 + nb * 16 + l16];
+      }
+    }
+    // z inputs of k-tile j
+    IFS_DEV void prefetch(int j) {
+      const int m0 = kb + j * C::BK + gm * 32;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const long r = (long)(m0 + mb * 16 + l16) * RW;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          zh[mb][c] = Zh[r + 4 * c + l4];
+          zl[mb][c] = Zl[r + 4 * c + l4];
+        }
+        zcv[mb] = *(const f32x4 *)(zc + m0 + mb * 16 + 4 * l4);
+      }
+    }
+    // k-tile j into the stage's B rows (bst = stage + BM rows)
+    IFS_DEV void gen(unsigned char *bst, int j) {
+      wait_vm_lgkm0<0>();
+      f32x4 acc[2][2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[mb][nb][q] = zcv[mb][q] + xrv[nb];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            acc[mb][nb] = KufOp<KW>::mma(zh[mb][c], xh[nb][c], acc[mb][nb]);
+            acc[mb][nb] = KufOp<KW>::mma(zh[mb][c], xl[nb][c], acc[mb][nb]);
+            acc[mb][nb] = KufOp<KW>::mma(zl[mb][c], xh[nb][c], acc[mb][nb]);
+          }
+      const int mt = kb + j * C::BK;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int ml = gm * 32 + mb * 16 + 4 * l4, nl = gn * 32 + nb * 16 + l16;
+          const bool nok = n0 + nl < B;
+          T e[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float v = __builtin_amdgcn_exp2f(fminf(acc[mb][nb][q], lim));
+            e[q] = from_f32<T>((nok && mt + ml + q < M) ? v : 0.f);
+          }
+          uint2 raw;
+          __builtin_memcpy(&raw, e, 8);
+          *(uint2 *)(bst + nl * C::ROWB + (((ml >> 3) ^ (nl & 7)) << 4) + (ml & 7) * 2) = raw;
+        }
+    }
+  };
+};
+
 // ------------------------------------------------------------------ kernel
-template <class C, class EPI>
+template <class C, class EPI, class GEN = NoGen>
 __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
-                                                     Opnd<typename C::T> Bt, Sched sc, EPI epi) {
+                                                     Opnd<typename C::T> Bt, Sched sc, EPI epi,
+                                                     GEN gen) {
   using T = typename C::T;
   using V = typename Vec16<T>::type;
-  constexpr int BM = C::BM, BK = C::BK, S = C::S, ROWB = C::ROWB, IPW = C::IPW;
+  constexpr int BM = C::BM, BK = C::BK, S = C::S, ROWB = C::ROWB;
+  // loads per wave and stage: A and B rows, or A rows only when B is generated
+  constexpr int IPW = GEN::kOn ? BM / (8 * C::NW) : C::IPW;
+  static_assert(!GEN::kOn || BM % (8 * C::NW) == 0, "A rows per wave");
   constexpr int TM = C::TM, TN = C::TN;
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -177,6 +332,7 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
     Bt.p = gsh(Bt.p, o);
     sc.skip = gsh(sc.skip, o);
     epi.shift(o);
+    gen.shift(o);
   }
   int m0, n0, kb, ke, ti;
   sc.tile<C>(m0, n0, kb, ke, ti);
@@ -195,7 +351,13 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
   const int dchunk = (lane & 7) ^ (lane >> 3);
   const T *srcA = A.p + (long)(m0 + (lane >> 3)) * A.ld + dchunk * C::KPL + kb;
   const T *srcB = Bt.p + (long)(n0 - BM + (lane >> 3)) * Bt.ld + dchunk * C::KPL + kb;
+  typename GEN::template State<C> gst;
+  if constexpr (GEN::kOn) {
+    gst.init(gen, n0, kb);
+    gst.prefetch(0);
+  }
   auto issue = [&](int j) {
+    if constexpr (GEN::kOn) gst.gen(smem_raw + (j % S) * C::STAGE + BM * ROWB, j);
     unsigned char *dst = smem_raw + (j % S) * C::STAGE + drow0 * ROWB;
     if constexpr (BM % (8 * IPW) == 0) {
       // every wave's rows lie in one operand: one base pointer and stride
@@ -215,6 +377,9 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
         __builtin_amdgcn_global_load_lds((const void *)g, (LDS_AS void *)(dst + i * 8 * ROWB),
                                          16, 0, 0);
       }
+    }
+    if constexpr (GEN::kOn) {
+      if (j + 1 < nk) gst.prefetch(j + 1);
     }
   };
 
@@ -310,14 +475,14 @@ struct Launch {
 
 // Host-side launch helper.  extra: LDS bytes the epilogue needs beyond the
 // staged tile and its scratch.
-template <class C, class EPI>
+template <class C, class EPI, class GEN = NoGen>
 static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T> &A,
                                      const Opnd<typename C::T> &Bt, const Sched &sc,
-                                     const EPI &epi, int extra = 0) {
+                                     const EPI &epi, int extra = 0, const GEN &gen = GEN{}) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
   if (ntile <= 0) return hipSuccess;
   dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1, lc.groups > 1 ? lc.groups : 1);
-  auto kern = gemm_kernel<C, EPI>;
+  auto kern = gemm_kernel<C, EPI, GEN>;
   Sched sg = sc;
   sg.gs = lc.groups > 1 ? lc.gs : 0;
   const int smem = C::smem(extra);
@@ -329,8 +494,9 @@ static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T>
     attr_bytes = smem;
   }
   if (lc.t0)
-    hipExtLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, lc.t0, lc.t1, 0, A, Bt, sg, epi);
+    hipExtLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, lc.t0, lc.t1, 0, A, Bt, sg, epi,
+                          gen);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, A, Bt, sg, epi);
+    hipLaunchKernelGGL(kern, grid, dim3(C::NT), smem, lc.st, A, Bt, sg, epi, gen);
   return hipGetLastError();
 }

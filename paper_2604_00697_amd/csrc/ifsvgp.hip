@@ -98,6 +98,12 @@ struct ifsvgp_ctx {
   // operand-type M x B: Kft, Vt, Ut are [Bp][Mp]; V and Vs = V diag(sqrt(-beta)) are [Mp][Bp]
   void *Kft, *V, *Vt, *Ut, *Vs;
   float *Zs, *Xs, *inv_ell, *sP;  // sP: s~ zero-padded to Mp
+  // inputs of the generated K_uf tiles (bf16 / fp16 forms): hi / lo bf16
+  // rows of 2 z' and x' ([Mp][gldk], [Bp][gldk]), -|z'|^2, log2 sf2 - |x'|^2,
+  // log2 sf2
+  __bf16 *gZh, *gZl, *gXh, *gXl;
+  float *gzc, *gxr, *glsf2;
+  int gldk;
   float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
   double *hrow, *hcol, *hx, *hzrow, *hz;  // gradient partials per tile
@@ -300,6 +306,14 @@ static size_t layout(ifsvgp_ctx *c, char *base, bool extras) {
   c->Vt = w.bytes(MB * os);
   c->Ut = w.bytes(MB * os);
   c->Vs = w.bytes(MB * os);
+  c->gldk = D <= 16 ? 16 : 32 * cdiv(D, 32);
+  c->gZh = (__bf16 *)w.bytes(Mp * c->gldk * 2);
+  c->gZl = (__bf16 *)w.bytes(Mp * c->gldk * 2);
+  c->gXh = (__bf16 *)w.bytes(Bp * c->gldk * 2);
+  c->gXl = (__bf16 *)w.bytes(Bp * c->gldk * 2);
+  w.take(c->gzc, Mp);
+  w.take(c->gxr, Bp);
+  w.take(c->glsf2, (size_t)1);
   w.take(c->Zs, (size_t)M * D);
   w.take(c->Xs, (size_t)B_max * D);
   w.take(c->inv_ell, (size_t)D);
@@ -702,6 +716,30 @@ struct Ops {
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
+  // the same product with the K_uf tiles generated in LDS (bf16 / fp16 forms;
+  // inputs from the set-up), K_uf never stored
+  template <int KW>
+  static hipError_t gemm_Vf_kw(ifsvgp_ctx *c, int cur, int B) {
+    using G = KufGen<T, KW>;
+    using Op = typename G::Op;
+    Opnd<T> a{LtT(c, cur), c->Mp};
+    Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
+    EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
+    G g{(const Op *)c->gZh, (const Op *)c->gZl, c->gzc, (const Op *)c->gXh,
+        (const Op *)c->gXl, c->gxr, c->glsf2, c->M, B};
+    return launch_gemm<CR>(lnc(c), a, a, sc, e, 0, g);
+  }
+  static hipError_t gemm_Vf(ifsvgp_ctx *c, int cur, int B) {
+    if constexpr (std::is_same<T, float>::value) {
+      return hipErrorInvalidValue;  // the fp32 form stores K_uf (k_kuf)
+    } else {
+      switch (c->gldk) {
+        case 16: return gemm_Vf_kw<16>(c, cur, B);
+        case 32: return gemm_Vf_kw<32>(c, cur, B);
+        default: return gemm_Vf_kw<64>(c, cur, B);
+      }
+    }
+  }
   // variance gap: Y = K~ L on all tiles (k >= n0), plain layout, in the Y2
   // buffer (idle outside the backward) ...
   static T *Yfull(ifsvgp_ctx *c) { return (T *)c->Y2; }
@@ -847,8 +885,10 @@ __global__ void k_latch_gammas(CallArgs g, int n, CallArgs *dst) {
 
 // cav non-null: the set-up also writes the call's argument block (direct
 // execution); null: a k_latch has written it (recorded calls).
+// gen_B > 0 (bf16 / fp16 forms): also the inputs of the generated K_uf tiles
+// for a batch of gen_B points, and Xs.
 template <typename T>
-static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
+static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav, int gen_B = 0) {
   const int M = c->M;
   Timed t(c, KK_PREP);
   SetupArgs a;
@@ -865,9 +905,16 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav) {
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * a.nKx;
   a.nLx = cdiv(M, 32);
+  const bool gen = gen_B > 0 && !std::is_same<T, float>::value;
+  a.nGz = gen ? cdiv(M, 64) : 0;
+  a.nG = gen ? a.nGz + cdiv(gen_B, 64) : 0;
+  a.B = gen_B;
+  a.ldk = c->gldk;
+  a.Zh = c->gZh; a.Zl = c->gZl; a.Xh = c->gXh; a.Xl = c->gXl;
+  a.zc = c->gzc; a.xr = c->gxr; a.lsf2 = c->glsf2; a.Xs = c->Xs;
   a.gs = gsz(c);
-  hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(a.nK + a.nLx * (a.nLx + 1) / 2)), dim3(NTB), 0,
-                     c->st, a);
+  hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(a.nK + a.nLx * (a.nLx + 1) / 2 + a.nG)),
+                     dim3(NTB), 0, c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
@@ -1040,17 +1087,22 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
   int r;
   c->ev_next = 0;
   c->side_open = false;
+  // bf16 / fp16: V = L^T K_uf with the K_uf tiles generated in LDS; the fp32
+  // form stores them first (distances from differences, accurate exp)
+  constexpr bool fused_kuf = !std::is_same<T, float>::value;
   if (k.setup) {
-    r = stage_setup<T>(c, k.need_noise, cav);
+    r = stage_setup<T>(c, k.need_noise, cav, k.fwd && fused_kuf ? k.B : 0);
     if (r) return r;
     if (!k.fwd) {
       c->fwd_valid = 0;
       return stage_natgrad<T>(c, k.gammas, k.n_ng, k.adapt, k.B);
     }
-    // side stream: K_uf tiles need only Z / ell and the batch ...
-    HIPCK(fork_side(c));
-    r = launch_kuf<T>(c, k.B);
-    if (r) return r;
+    if constexpr (!fused_kuf) {
+      // side stream: K_uf tiles need only Z / ell and the batch ...
+      HIPCK(fork_side(c));
+      r = launch_kuf<T>(c, k.B);
+      if (r) return r;
+    }
     r = stage_natgrad<T>(c, k.gammas, k.n_ng, NG_FIXED, k.B);
     if (r) return r;
     // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
@@ -1060,7 +1112,8 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
       OnSide side(c);
       {
         Timed t(c, KK_V);
-        HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
+        if constexpr (fused_kuf) HIPCK(Ops<T>::gemm_Vf(c, c->cur, k.B));
+        else HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
       }
       Timed t(c, KK_VEC);
       hipLaunchKernelGGL(k_lt_m, gdim(c, dim3(cdiv(c->M, NTB / 64))), dim3(NTB), 0, c->st,

@@ -65,6 +65,12 @@ struct SetupArgs {
   int *flag;
   int *ngskip;         // stop flag of an adaptive NG loop, cleared for the call
   int nKx, nK, nLx;
+  // inputs of the generated K_uf tiles (KufGen), when nG > 0: blocks
+  // [nK + nL, nK + nL + nGz) take 64 rows of Z each, the remaining nG - nGz
+  // blocks 64 rows of the batch (B rows), which also write Xs = X / ell
+  int nG, nGz, B, ldk;
+  __bf16 *Zh, *Zl, *Xh, *Xl;
+  float *zc, *xr, *lsf2, *Xs;
   long gs;             // grouped launch: bytes between the problems' workspaces
   IFS_DEV void shift(long o) {
     ca = gsh(ca, o); Zs = gsh(Zs, o); inv_ell = gsh(inv_ell, o); sP = gsh(sP, o);
@@ -72,8 +78,38 @@ struct SetupArgs {
     Lt32 = gsh(Lt32, o); LT = gsh((char *)LT, o); LtT = gsh((char *)LtT, o);
     LstT = gsh((char *)LstT, o); scal = gsh(scal, o); flag = gsh(flag, o);
     ngskip = gsh(ngskip, o);
+    Zh = gsh(Zh, o); Zl = gsh(Zl, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o); zc = gsh(zc, o);
+    xr = gsh(xr, o); lsf2 = gsh(lsf2, o); Xs = gsh(Xs, o);
   }
 };
+
+// sqrt(log2(e) / 2): exp(-d^2 / 2) = 2^(-(c d)^2)
+constexpr float KUF_C = 0.84932180028801904272f;
+
+// One row of the generator's inputs: v = c * (row / ell) over d < D, written
+// as the hi / lo bf16 split of s v (s = 2 for Z rows, 1 for batch rows;
+// zeros for D <= d < ldk); returns |v|^2 (fp32) to the row's four threads.
+// Thread q of the row handles d = q, q + 4, ...
+IFS_DEV float gen_row(const float *src, const float *ellc, int D, int ldk, float s, int q,
+                      __bf16 *hi, __bf16 *lo, float *xs_out) {
+  float nrm = 0.f;
+  for (int d = q; d < ldk; d += 4) {
+    float v = 0.f;
+    if (d < D) {
+      const float x = src[d] * (1.0f / ellc[d]);
+      if (xs_out) xs_out[d] = x;
+      v = KUF_C * x;
+    }
+    nrm = fmaf(v, v, nrm);
+    const float w = s * v;
+    const __bf16 h = (__bf16)w;
+    hi[d] = h;
+    lo[d] = (__bf16)(w - (float)h);
+  }
+  nrm += __shfl_xor(nrm, 1);
+  nrm += __shfl_xor(nrm, 2);
+  return nrm;
+}
 
 template <int MAXD, typename T>
 __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
@@ -180,6 +216,31 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
       acc = block_sum<NTB>(acc, sh);
       if (threadIdx.x == 0) a.scal[S_SUMLOGS] = acc;
       if (bad) atomicOr(a.flag, FLAG_DOMAIN);
+    }
+    return;
+  }
+  const int nL = a.nLx * (a.nLx + 1) / 2;
+  if (b >= a.nK + nL) {
+    // generator inputs: 64 rows per block, four threads per row
+    const int g = b - a.nK - nL, r = threadIdx.x >> 2, q = threadIdx.x & 3;
+    if (g < a.nGz) {
+      const int m = g * 64 + r;
+      if (m < M) {
+        const long o = (long)m * a.ldk;
+        const float n = gen_row(Zc + (long)m * D, ellc, D, a.ldk, 2.f, q, a.Zh + o, a.Zl + o,
+                                nullptr);
+        if (q == 0) a.zc[m] = -n;
+      }
+    } else {
+      const int n0 = (g - a.nGz) * 64 + r;
+      if (n0 < a.B) {
+        const long o = (long)n0 * a.ldk;
+        const float n = gen_row(ca->X + (long)n0 * D, ellc, D, a.ldk, 1.f, q, a.Xh + o,
+                                a.Xl + o, a.Xs + (long)n0 * D);
+        const float l2 = log2f(*ca->sf2);
+        if (q == 0) a.xr[n0] = l2 - n;
+        if (n0 == 0 && q == 0) *a.lsf2 = l2;
+      }
     }
     return;
   }
