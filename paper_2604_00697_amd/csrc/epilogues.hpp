@@ -721,6 +721,13 @@ __host__ __device__ inline int graduf_extra(int BM, int BN, int D) {
   const int D4 = d4of(D), LDX = dpof(D) + 1;
   return (BM * (D4 + 1) + BN * LDX + 2 * BM + 3 * BN) * 4;
 }
+//
+// KW > 0 (bf16 / fp16 forms): the K_uf tile comes from the set-up's split
+// inputs exactly as the forward generates it (KufGen: hi/lo bf16 cross term
+// on the matrix cores, accumulator started at the norm terms, one exp2), read
+// straight into registers; Zs is then not staged.  KW = 0: norms and an
+// fp32-MFMA cross term, or (fp32 form) differences and the accurate exp.
+template <int KW>
 struct EpiGradUf {
   const float *Lb, *alpha, *beta;
   const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
@@ -731,6 +738,8 @@ struct EpiGradUf {
   long ldc;
   double *hx;    // [n-tiles][M][D]
   double *part; // [ntiles]
+  const void *Zh, *Zl, *Xh, *Xl;  // generator inputs (KW > 0)
+  const float *zc, *xr, *lsf2;
   static constexpr bool kRegs = true;  // takes the accumulators in registers
   // grouped launches: every workspace pointer moved by o bytes
   IFS_DEV void shift(long o) {
@@ -744,6 +753,8 @@ struct EpiGradUf {
     hcol = gsh(hcol, o);
     hx = gsh(hx, o);
     part = gsh(part, o);
+    Zh = gsh(Zh, o); Zl = gsh(Zl, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
+    zc = gsh(zc, o); xr = gsh(xr, o); lsf2 = gsh(lsf2, o);
   }
   // acc: fp32 or (C::A64) fp64 accumulators; the lane's rows are
   // 16 ii + 4 (lane/16) + q for fp32 and 16 ii + 4 q + lane/16 for fp64
@@ -758,22 +769,26 @@ struct EpiGradUf {
     float *xn = lb + BM;                    // [BN]
     float *al = xn + BN;                    // [BN]
     float *be = al + BN;                    // [BN]
+    constexpr bool F32 = std::is_same<typename C::T, float>::value;
+    constexpr bool GEN = !F32 && KW > 0;
     const int tid = threadIdx.x;
     for (int i = tid; i < BM; i += NT) lb[i] = Lb[t.m0 + i];    // padded to Mp
     for (int i = tid; i < BN; i += NT) {
       al[i] = alpha[t.n0 + i];                                   // padded to Bp
       be[i] = beta[t.n0 + i];
     }
-    stage_rows<NT>(zs, LDZ, Zs, t.m0, BM, M, D, -1);
+    if constexpr (!GEN) stage_rows<NT>(zs, LDZ, Zs, t.m0, BM, M, D, -1);
     stage_rows<NT>(xs, LDX, Xs, t.n0, BN, B, D, -1);
     __syncthreads();
-    for (int i = tid; i < BM + BN; i += NT) {
-      const float *row = i < BM ? zs + i * LDZ : xs + (i - BM) * LDX;
-      float s = 0.f;
-      for (int d = 0; d < D4; ++d) s = fmaf(row[d], row[d], s);
-      (i < BM ? zn : xn)[i < BM ? i : i - BM] = s;
+    if constexpr (!GEN) {
+      for (int i = tid; i < BM + BN; i += NT) {
+        const float *row = i < BM ? zs + i * LDZ : xs + (i - BM) * LDX;
+        float s = 0.f;
+        for (int d = 0; d < D4; ++d) s = fmaf(row[d], row[d], s);
+        (i < BM ? zn : xn)[i < BM ? i : i - BM] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     const float s2f = *sf2;
     double hs = 0.0;
     {
@@ -791,14 +806,14 @@ struct EpiGradUf {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int i = ib + 16 * ii + r_of(q);
-          zr[ii][q] = zn[i];
+          zr[ii][q] = GEN ? 0.f : zn[i];
           lr[ii][q] = lb[i];
           rok[ii][q] = t.m0 + i < M;
         }
 #pragma unroll
       for (int jj = 0; jj < C::TN; ++jj) {
         const int n = jb + 16 * jj + l16;
-        xc[jj] = xn[n];
+        xc[jj] = GEN ? 0.f : xn[n];
         ac[jj] = al[n];
         bc[jj] = be[n];
         cok[jj] = t.n0 + n < B;
@@ -817,11 +832,53 @@ struct EpiGradUf {
         pin(bc[jj]);
       }
       // the fp32 form recomputes K_uf from differences with the accurate exp
-      // (as its forward does); the others from norms and an MFMA cross term
-      constexpr bool F32 = std::is_same<typename C::T, float>::value;
+      // (as its forward does); the others as their forward generates it
       f32x4 c[C::TM][C::TN];
-      if constexpr (!F32)
+      float lim = 0.f;
+      if constexpr (GEN) {
+        using KO = KufOp<(KW > 0 ? KW : 16)>;
+        using Op = typename KO::type;
+        constexpr int NC = KO::NC, RW = 4 * NC;
+        const Op *zh = (const Op *)Zh, *zl = (const Op *)Zl;
+        const Op *xh = (const Op *)Xh, *xl = (const Op *)Xl;
+        lim = *lsf2;
+#pragma unroll
+        for (int ii = 0; ii < C::TM; ++ii) {
+          const f32x4 zcv = *(const f32x4 *)(zc + t.m0 + ib + 16 * ii + 4 * l4);
+#pragma unroll
+          for (int jj = 0; jj < C::TN; ++jj) {
+            const float xrv = xr[t.n0 + jb + 16 * jj + l16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[ii][jj][q] = zcv[q] + xrv;
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          Op a_h[C::TM], a_l[C::TM], b_h[C::TN], b_l[C::TN];
+#pragma unroll
+          for (int ii = 0; ii < C::TM; ++ii) {
+            const long r = (long)(t.m0 + ib + 16 * ii + l16) * RW + 4 * cc + l4;
+            a_h[ii] = zh[r];
+            a_l[ii] = zl[r];
+          }
+#pragma unroll
+          for (int jj = 0; jj < C::TN; ++jj) {
+            const long r = (long)(t.n0 + jb + 16 * jj + l16) * RW + 4 * cc + l4;
+            b_h[jj] = xh[r];
+            b_l[jj] = xl[r];
+          }
+#pragma unroll
+          for (int ii = 0; ii < C::TM; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < C::TN; ++jj) {
+              c[ii][jj] = KO::mma(a_h[ii], b_h[jj], c[ii][jj]);
+              c[ii][jj] = KO::mma(a_h[ii], b_l[jj], c[ii][jj]);
+              c[ii][jj] = KO::mma(a_l[ii], b_h[jj], c[ii][jj]);
+            }
+        }
+      } else if constexpr (!F32) {
         cross_block<C::TM, C::TN, C::A64>(zs + ib * LDZ, LDZ, xs + jb * LDX, LDX, D4, c);
+      }
 #pragma unroll
       for (int ii = 0; ii < C::TM; ++ii)
 #pragma unroll
@@ -833,6 +890,8 @@ struct EpiGradUf {
             float kuf;
             if constexpr (F32)
               kuf = s2f * kexp<true>(-0.5f * sqdist(zs + i * LDZ, xs + n * LDX, D));
+            else if constexpr (GEN)
+              kuf = __builtin_amdgcn_exp2f(fminf(c[ii][jj][q], lim));
             else
               kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
             const float g = lr[ii][q] * ac[jj] - 2.f * (float)acc[ii][jj][q] * bc[jj];

@@ -812,14 +812,29 @@ struct Ops {
   }
   // R = L U (k < m0+BM) -> H_uf reductions
   // (lb, al, be: the epilogue's L b, alpha, beta, by default the context's)
-  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *lb = nullptr,
-                           const float *al = nullptr, const float *be = nullptr) {
+  // (KW: the K_uf recompute from the set-up's split inputs, bf16 / fp16 forms)
+  template <int KW>
+  static hipError_t gemm_R_kw(ifsvgp_ctx *c, int cur, int B, const float *lb, const float *al,
+                              const float *be) {
     const int D = c->D;
     Opnd<T> a{LT(c, cur), c->Mp}, b{(const T *)c->Ut, c->Mp};
     Sched sc{cdiv(c->M, CRG::BM), cdiv(B, CRG::BN), 0, 1, c->M, K_HI_M1};
-    EpiGradUf e{lb ? lb : c->vLb, al ? al : c->alpha, be ? be : c->beta, c->Zs, c->Xs, c->sfn, c->M, B, D,
-                c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf};
+    EpiGradUf<KW> e{lb ? lb : c->vLb, al ? al : c->alpha, be ? be : c->beta, c->Zs, c->Xs,
+                    c->sfn, c->M, B, D, c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf,
+                    c->gZh, c->gZl, c->gXh, c->gXl, c->gzc, c->gxr, c->glsf2};
     return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D));
+  }
+  static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *lb = nullptr,
+                           const float *al = nullptr, const float *be = nullptr) {
+    if constexpr (std::is_same<T, float>::value) {
+      return gemm_R_kw<0>(c, cur, B, lb, al, be);
+    } else {
+      switch (c->gldk) {
+        case 16: return gemm_R_kw<16>(c, cur, B, lb, al, be);
+        case 32: return gemm_R_kw<32>(c, cur, B, lb, al, be);
+        default: return gemm_R_kw<64>(c, cur, B, lb, al, be);
+      }
+    }
   }
   // Ys[s] = (V_s D)(V_s D)^T, D = diag(sqrt(-beta)) (lower tiles mirrored, split-K
   // over the batch); equals -V diag(beta) V^T since beta <= 0 for the
@@ -1230,7 +1245,8 @@ template <typename T>
 static int enqueue_hutch(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *Omt, int K) {
   c->ev_next = 0;
   c->side_open = false;
-  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca);
+  // (with the split inputs of the K_uf tiles, which the backward's R epilogue reads)
+  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca, B);
   if (r) return r;
   c->cur = 0;
   c->fwd_valid = 0;
@@ -1667,7 +1683,8 @@ static int enqueue_multi(ifsvgp_ctx *c, const CallArgs &ca, int B, const float *
                          const float *Mt, int Q) {
   c->ev_next = 0;
   c->side_open = false;
-  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca);
+  // (with the split inputs of the K_uf tiles, which the backward's R epilogue reads)
+  int r = stage_setup<T>(c, c->lik == IFSVGP_LIK_GAUSSIAN, &ca, B);
   if (r) return r;
   c->cur = 0;
   c->fwd_valid = 0;
