@@ -834,14 +834,12 @@ struct EpiGradUf {
       // the fp32 form recomputes K_uf from differences with the accurate exp
       // (as its forward does); the others as their forward generates it
       f32x4 c[C::TM][C::TN];
-      float lim = 0.f;
       if constexpr (GEN) {
         using KO = KufOp<(KW > 0 ? KW : 16)>;
         using Op = typename KO::type;
         constexpr int NC = KO::NC, RW = 4 * NC;
         const Op *zh = (const Op *)Zh, *zl = (const Op *)Zl;
         const Op *xh = (const Op *)Xh, *xl = (const Op *)Xl;
-        lim = *lsf2;
 #pragma unroll
         for (int ii = 0; ii < C::TM; ++ii) {
           const f32x4 zcv = *(const f32x4 *)(zc + t.m0 + ib + 16 * ii + 4 * l4);
@@ -891,7 +889,7 @@ struct EpiGradUf {
             if constexpr (F32)
               kuf = s2f * kexp<true>(-0.5f * sqdist(zs + i * LDZ, xs + n * LDX, D));
             else if constexpr (GEN)
-              kuf = __builtin_amdgcn_exp2f(fminf(c[ii][jj][q], lim));
+              kuf = __builtin_amdgcn_exp2f(c[ii][jj][q]);
             else
               kuf = kern_se(s2f, zr[ii][q], xc[jj], c[ii][jj][q]);
             const float g = lr[ii][q] * ac[jj] - 2.f * (float)acc[ii][jj][q] * bc[jj];

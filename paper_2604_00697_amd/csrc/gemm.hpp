@@ -183,10 +183,12 @@ struct NoGen {
 // x' (hi hi + hi lo + lo hi: about 16 significant bits, below the rounding of
 // the bf16 / fp16 operand it produces), the accumulator started at
 // log2 sf2 - |x'|^2 - |z'|^2 (fp32 norms of the unsplit values), one exp2 per
-// entry, clamped at log2 sf2 (distance >= 0).  Inputs per call (written by the
-// set-up): Zh, Zl [Mp][KW], zc = -|z'|^2 [Mp], Xh, Xl [Bp][KW],
+// entry (the split's rounding can leave a distance of about -1e-5 sf2 relative
+// instead of 0, harmless, so there is no clamp).  Inputs per call (written by
+// the set-up): Zh, Zl [Mp][KW], zc = -|z'|^2 [Mp], Xh, Xl [Bp][KW],
 // xr = log2 sf2 - |x'|^2 [Bp], lsf2 = log2 sf2; KW (16, 32 or 64) >= D, zero
-// beyond D.  KW = 16 contracts with the 16x16x16 bf16 instruction, else
+// beyond D; zc and xr are -1e30 on the rows past M and B that a tile covers,
+// so those entries are exactly 0 without a mask.  KW = 16 contracts with the 16x16x16 bf16 instruction, else
 // 16x16x32 per 32 d.  Each of the 4 waves generates a 32 (m) x 32 (n)
 // quadrant: 2 x 2 blocks of 16 x 16, each lane 4 consecutive m of one n,
 // stored as one 8-byte LDS write into the swizzled stage layout the fragment
@@ -230,13 +232,12 @@ struct KufGen {
                   "generator layout: 4 waves, 64 x 64 k-tiles of the B operand, two stages");
     const Op *Zh, *Zl;
     const float *zc;
-    int M, B, n0, kb, gm, gn, l16, l4;
-    float lim;
+    int n0, kb, gm, gn, l16, l4;
     Op xh[2][NC], xl[2][NC], zh[2][NC], zl[2][NC];
     f32x4 zcv[2];
     float xrv[2];
     IFS_DEV void init(const KufGen &g, int n0_, int kb_) {
-      Zh = g.Zh; Zl = g.Zl; zc = g.zc; M = g.M; B = g.B;
+      Zh = g.Zh; Zl = g.Zl; zc = g.zc;
       n0 = n0_;
       kb = kb_;
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -244,7 +245,6 @@ struct KufGen {
       gn = wave & 1;
       l16 = lane & 15;
       l4 = lane >> 4;
-      lim = *g.lsf2;
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
         const long r = (long)(n0 + gn * 32 + nb * 16 + l16) * RW;
@@ -290,19 +290,14 @@ struct KufGen {
             acc[mb][nb] = KufOp<KW>::mma(zh[mb][c], xl[nb][c], acc[mb][nb]);
             acc[mb][nb] = KufOp<KW>::mma(zl[mb][c], xh[nb][c], acc[mb][nb]);
           }
-      const int mt = kb + j * C::BK;
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           const int ml = gm * 32 + mb * 16 + 4 * l4, nl = gn * 32 + nb * 16 + l16;
-          const bool nok = n0 + nl < B;
           T e[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float v = __builtin_amdgcn_exp2f(fminf(acc[mb][nb][q], lim));
-            e[q] = from_f32<T>((nok && mt + ml + q < M) ? v : 0.f);
-          }
+          for (int q = 0; q < 4; ++q) e[q] = from_f32<T>(__builtin_amdgcn_exp2f(acc[mb][nb][q]));
           uint2 raw;
           __builtin_memcpy(&raw, e, 8);
           *(uint2 *)(bst + nl * C::ROWB + (((ml >> 3) ^ (nl & 7)) << 4) + (ml & 7) * 2) = raw;

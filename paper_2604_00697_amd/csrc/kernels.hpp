@@ -223,6 +223,8 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   if (b >= a.nK + nL) {
     // generator inputs: 64 rows per block, four threads per row
     const int g = b - a.nK - nL, r = threadIdx.x >> 2, q = threadIdx.x & 3;
+    // rows past M (or B) within the last block get norm terms of -1e30, so
+    // that their generated entries come out as exactly 0 with no mask
     if (g < a.nGz) {
       const int m = g * 64 + r;
       if (m < M) {
@@ -230,6 +232,8 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
         const float n = gen_row(Zc + (long)m * D, ellc, D, a.ldk, 2.f, q, a.Zh + o, a.Zl + o,
                                 nullptr);
         if (q == 0) a.zc[m] = -n;
+      } else if (q == 0) {
+        a.zc[m] = -1e30f;
       }
     } else {
       const int n0 = (g - a.nGz) * 64 + r;
@@ -240,6 +244,8 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
         const float l2 = log2f(*ca->sf2);
         if (q == 0) a.xr[n0] = l2 - n;
         if (n0 == 0 && q == 0) *a.lsf2 = l2;
+      } else if (q == 0) {
+        a.xr[n0] = -1e30f;
       }
     }
     return;
