@@ -918,7 +918,7 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav, int g
   a.LstT = c->LstT[0];
   a.scal = c->scal; a.flag = c->flag; a.ngskip = c->ngskip;
   a.nKx = cdiv(M, 64);
-  a.nK = a.nKx * a.nKx;
+  a.nK = a.nKx * (a.nKx + 1) / 2;
   a.nLx = cdiv(M, 32);
   const bool gen = gen_B > 0 && !std::is_same<T, float>::value;
   a.nGz = gen ? cdiv(M, 64) : 0;
@@ -1089,7 +1089,7 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
     hipLaunchKernelGGL(k_grad, gdim(c, dim3(rb + cb + rq)), dim3(NTB), 0, c->st, g);
     // dF/dm~ = L t2 and dF/ds~ rows (when requested), then the scalar gradients
     const int mrows = (want_gm || want_gs) ? rq : 0;
-    hipLaunchKernelGGL(k_grad_tail, gdim(c, dim3(mrows + 1)), dim3(NTB), 0, c->st, g,
+    hipLaunchKernelGGL(k_grad_tail, gdim(c, dim3(mrows + D + 1)), dim3(NTB), 0, c->st, g,
                        (const float *)c->L32[cur], mrows);
   }
   HIPCK(hipGetLastError());
@@ -1364,7 +1364,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
              nullptr, nullptr, (long)Mp, c->vLb, c->sP};
   hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
   const int mrows = want_gm ? cdiv(M, NTB / 64) : 0;
-  hipLaunchKernelGGL(k_grad_tail, dim3(mrows + 1), dim3(NTB), 0, c->st, g,
+  hipLaunchKernelGGL(k_grad_tail, dim3(mrows + D + 1), dim3(NTB), 0, c->st, g,
                      (const float *)c->L32[0], mrows);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
@@ -1783,7 +1783,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
              nullptr, nullptr, nullptr, Mp, nullptr, c->ell_part, rb, cb,
              nullptr, nullptr, (long)Mp, nullptr, c->sP};
   hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
-  hipLaunchKernelGGL(k_grad_tail, dim3(1), dim3(NTB), 0, c->st, g, (const float *)c->L32[0], 0);
+  hipLaunchKernelGGL(k_grad_tail, dim3(D + 1), dim3(NTB), 0, c->st, g, (const float *)c->L32[0], 0);
   HIPCK(hipGetLastError());
   c->fwd_valid = 0;  // U was overwritten in place: one backward per forward
   return IFSVGP_OK;

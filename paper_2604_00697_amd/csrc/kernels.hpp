@@ -43,7 +43,8 @@ IFS_DEV bool arrive_last(int *counter, int *s_flag) {
 
 // ---------------------------------------------------------------- set-up
 // One launch per iteration before any product:
-//  * blocks [0, nK): 64 x 64 tiles of K~ = sf2 exp(-1/2 |zs_i - zs_j|^2) + diag(s~)
+//  * blocks [0, nK): lower 64 x 64 tiles of K~ = sf2 exp(-1/2 |zs_i - zs_j|^2) + diag(s~)
+//    and their mirrors
 //    (fp32, plus the operand type), zs = Z / ell; the first tile column also
 //    writes Zs and the zero-padded copy of s~; block 0 validates ell, sf2,
 //    noise_var, s~ and forms 1/ell and sum log s~;
@@ -127,9 +128,13 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   }
   const float *Zc = ca->Z, *ellc = ca->ell, *sc = ca->s;
   if (b < a.nK) {
-    // 64 x 64 tile; thread (tx, ty) owns rows ty + 16 p and columns tx + 16 q
+    // lower 64 x 64 tile (bi >= bj), its mirror written through LDS; thread
+    // (tx, ty) owns rows ty + 16 p and columns tx + 16 q
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int bi = b / a.nKx, bj = b % a.nKx;
+    int bi = (int)((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    while (bi * (bi + 1) / 2 > b) --bi;
+    const int bj = b - bi * (bi + 1) / 2;
     const int i0 = bi * 64, j0 = bj * 64;
     for (int e0 = 0; e0 < 64 * D; e0 += 4 * NTB) {
       float vi[4], vj[4];
@@ -174,6 +179,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
         }
     }
     const float sf2 = *ca->sf2;
+    float kv[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int i = i0 + ty + 16 * p;
@@ -181,12 +187,37 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + tx + 16 * q;
+        float v = sf2 * kexp<std::is_same<T, float>::value>(-0.5f * d2[p][q]);
+        if (i == j) v += si;
+        kv[p][q] = v;
         if (i < M && j < M) {
-          float v = sf2 * kexp<std::is_same<T, float>::value>(-0.5f * d2[p][q]);
-          if (i == j) v += si;
           a.Kt[(long)i * a.ld + j] = v;
           if constexpr (!std::is_same<T, float>::value)
             ((T *)a.KtT)[(long)i * a.ld + j] = from_f32<T>(v);
+        }
+      }
+    }
+    if (bi != bj) {
+      // the mirror tile [j][i] through LDS (zi is free once the distances are
+      // formed)
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) zi[ty + 16 * p][tx + 16 * q] = kv[p][q];
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int j = j0 + ty + 16 * p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + tx + 16 * q;
+          if (i < M && j < M) {
+            const float v = zi[tx + 16 * q][ty + 16 * p];
+            a.Kt[(long)j * a.ld + i] = v;
+            if constexpr (!std::is_same<T, float>::value)
+              ((T *)a.KtT)[(long)j * a.ld + i] = from_f32<T>(v);
+          }
         }
       }
     }
@@ -1103,7 +1134,7 @@ struct GradArgs {
   const double *uu_part; int n_uu_tiles;
   const double *lik_part; int n_lik;
   const float *Q, *Va, *Wub; long ld; float *t2;
-  double *ell_part;  // [rb + cb][D]
+  double *ell_part;  // [D][rb + cb]
   int rb, cb;
   // gradient with respect to s~ (skipped without g_s)
   const float *gdiag, *pdiag; long ldpd;  // diag(G_uu); [nb][ldpd] partials of diag(P)
@@ -1182,7 +1213,7 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
     if (t < g.D) {
       double s = 0.0;
       for (int q = 0; q < Rz; ++q) s += sh[q * g.D + t];
-      g.ell_part[(long)blk * g.D + t] = s;
+      g.ell_part[(long)t * (g.rb + g.cb) + blk] = s;
     }
   } else if (blk < g.rb + g.cb) {
     const int r = t / g.D, d = t % g.D;
@@ -1199,7 +1230,7 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
     if (t < g.D) {
       double s = 0.0;
       for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
-      g.ell_part[(long)blk * g.D + t] = s;
+      g.ell_part[(long)t * (g.rb + g.cb) + blk] = s;
     }
   } else {
     const int row = (blk - g.rb - g.cb) * (NTB / 64) + (t >> 6);
@@ -1214,9 +1245,10 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
 // dF/ds~ (one wave per row, each when requested):
 //   dF/ds~_i = diag(G_Kt)_i + 1/(2 s~_i),
 //   diag(G_Kt) = diag(G_uu) - diag(P)/2 + (L b)_i^2 / 2,
-// diag(P) summed from the per-tile partials of L Q with J <= i/64; the last
-// block forms dF/dell_d = (1/ell_d) sum of the partials,
-// dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and dF/dnoise = c sum dE/dnoise.
+// diag(P) summed from the per-tile partials of L Q with J <= i/64; blocks
+// [rows, rows + D) form dF/dell_d = (1/ell_d) sum of the partials of d; the
+// last block dF/dsf2 = (sum H_uu + sum H_uf)/sf2 + sum beta and
+// dF/dnoise = c sum dE/dnoise.  Launch with rows + D + 1 blocks.
 __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
   __shared__ double sh[NTB];
   if (g.gs) {
@@ -1248,8 +1280,26 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
     }
     return;
   }
-  // the scalar sums' partials first (their loads overlap the lengthscale
-  // reduction below)
+  const int nparts = g.rb + g.cb;
+  const int blk = (int)blockIdx.x - rows;
+  if (blk < g.D) {
+    // dF/dell_d = (1/ell_d) sum of the block partials of d
+    const int d = blk;
+    const double *pp = g.ell_part + (long)d * nparts;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int p = t;
+    for (; p + 3 * NTB < nparts; p += 4 * NTB) {
+      s0 += pp[p];
+      s1 += pp[p + NTB];
+      s2 += pp[p + 2 * NTB];
+      s3 += pp[p + 3 * NTB];
+    }
+    for (; p < nparts; p += NTB) s0 += pp[p];
+    const double sd = block_sum<NTB>((s0 + s1) + (s2 + s3), sh);
+    if (t == 0 && ca.g_ell) ca.g_ell[d] = (float)(scale * sd * g.inv_ell[d]);
+    return;
+  }
+  // the last block: dF/dsf2 and dF/dnoise
   double huf = 0.0, huu = 0.0, dn = 0.0, bs = 0.0;
   for (int i = t; i < g.n_uf_tiles; i += NTB) huf += g.uf_part[i];
   for (int i = t; i < g.n_uu_tiles; i += NTB) huu += g.uu_part[i];
@@ -1257,30 +1307,6 @@ __global__ void k_grad_tail(GradArgs g, const float *L, int rows) {
     dn += g.lik_part[4 * i + 2];
     bs += g.lik_part[4 * i + 3];
   }
-  // lengthscale partials: thread (slice, d) sums every R-th block partial of d
-  const int nparts = g.rb + g.cb, R = NTB / g.D;
-  {
-    const int slice = t / g.D, d = t % g.D;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (slice < R) {
-      int p = slice;
-      for (; p + 3 * R < nparts; p += 4 * R) {
-        s0 += g.ell_part[(long)p * g.D + d];
-        s1 += g.ell_part[(long)(p + R) * g.D + d];
-        s2 += g.ell_part[(long)(p + 2 * R) * g.D + d];
-        s3 += g.ell_part[(long)(p + 3 * R) * g.D + d];
-      }
-      for (; p < nparts; p += R) s0 += g.ell_part[(long)p * g.D + d];
-    }
-    sh[t] = (s0 + s1) + (s2 + s3);
-  }
-  __syncthreads();
-  if (t < g.D) {
-    double s = 0.0;
-    for (int q = 0; q < R; ++q) s += sh[q * g.D + t];
-    if (ca.g_ell) ca.g_ell[t] = (float)(scale * s * g.inv_ell[t]);
-  }
-  __syncthreads();
   double v4[4] = {huf, huu, dn, bs};
   block_sums<NTB, 4>(v4, sh);
   huf = v4[0]; huu = v4[1]; dn = v4[2]; bs = v4[3];
