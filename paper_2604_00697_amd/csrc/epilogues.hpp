@@ -733,11 +733,13 @@ struct EpiGradUf {
   const float *Zs, *Xs;  // [M][D], [B][D]  (inputs / lengthscales)
   const float *sf2;
   int M, B, D;
-  double *hrow;  // [n-tiles][M]
-  double *hcol;  // [m-tiles][ldc]
+  // per-tile partials, fp64 in the fp32 form and fp32 in the others (whose
+  // tile reductions run in fp32)
+  void *hrow;    // [n-tiles][M]
+  void *hcol;    // [m-tiles][ldc]
   long ldc;
-  double *hx;    // [n-tiles][M][D]
-  double *part; // [ntiles]
+  void *hx;      // [n-tiles][M][D]
+  double *part;  // [ntiles]
   const void *Zh, *Zl, *Xh, *Xl;  // generator inputs (KW > 0)
   const float *zc, *xr, *lsf2;
   static constexpr bool kRegs = true;  // takes the accumulators in registers
@@ -904,24 +906,26 @@ struct EpiGradUf {
     if (tid == 0) part[t.ti] = hs;
     const int nti = t.n0 / BN, mti = t.m0 / BM;
     // the fp32 form sums on the fp64 matrix cores (the gradient's sums of
-    // these partials cancel), the others in fp32; partials are kept in fp64
+    // these partials cancel) and keeps fp64 partials; the others sum in fp32
+    // and keep fp32 partials
     constexpr bool F64 = std::is_same<typename C::T, float>::value;
+    using P = typename std::conditional<F64, double, float>::type;
     {
       const double s = tile_colsum<C, double>(Cs);
       const int cl = tid % BN, gj = t.n0 + cl;
-      if (tid < BN && gj < B) hcol[(long)mti * ldc + gj] = s;
+      if (tid < BN && gj < B) ((P *)hcol)[(long)mti * ldc + gj] = (P)s;
     }
     {
       const double s = tile_rowsum<C, double>(Cs);
       const int gi = t.m0 + tid % BM;
-      if (tid < BM && gi < M) hrow[(long)nti * M + gi] = s;
+      if (tid < BM && gi < M) ((P *)hrow)[(long)nti * M + gi] = (P)s;
     }
     const int D_ = D, M_ = M;
-    double *hx_ = hx + (long)nti * M * D;
+    P *hx_ = (P *)hx + (long)nti * M * D;
     lds_mfma<NT / 64, BM / (NT / 4), false, F64>(Cs, C::LDC, BN, xs, LDX, DP,
                                                 [&](int i, int d, double v) {
       const int gi = t.m0 + i;
-      if (gi < M_ && d < D_) hx_[(long)gi * D_ + d] = v;
+      if (gi < M_ && d < D_) hx_[(long)gi * D_ + d] = (P)v;
     });
   }
 };
@@ -931,13 +935,17 @@ struct EpiGradUf {
 // For rows of block I (slot J): hz[i][d] = sum_j H_ij Zs_jd and hzrow[i] = sum_j H_ij;
 // for an off-diagonal tile also rows of block J (slot I) through H^T.  The
 // products with Zs run on fp32 MFMA; the row / column sums come from LDS.
+// P: the partials' type, which the form sets (not the product's operand
+// type: the fp16 form runs this product with fp32 operands): fp64 partials
+// and fp64-MFMA reductions in the fp32 form, fp32 in the others.
 // Extra LDS: 2 * BM * (DP + 1) floats (DP: dpof).
+template <typename P>
 struct EpiGradUu {
   const float *Kt, *s, *Zs;
   long ld;
   int M, D;
-  double *hz;     // [nb][M][D]
-  double *hzrow;  // [nb][M]
+  void *hz;       // [nb][M][D]  (fp64 in the fp32 form, else fp32)
+  void *hzrow;    // [nb][M]
   double *part;  // [ntiles]
   float *gdiag;  // [M]: diagonal of G_uu from the diagonal tiles, or null
   // grouped launches: every workspace pointer moved by o bytes
@@ -998,19 +1006,18 @@ struct EpiGradUu {
     hs = tile_sum<C>(hs, Cs);
     if (threadIdx.x == 0) part[t.ti] = hs;
     const int I = t.m0 / BM, J = t.n0 / BN, D_ = D, M_ = M;
-    // fp64 partials; the fp32 form's reduction products on the fp64 matrix cores
-    constexpr bool F64 = std::is_same<typename C::T, float>::value;
+    constexpr bool F64 = std::is_same<P, double>::value;
     {
       // rows of block I (slot J): row sums and H Zs_J
       const double rs = tile_rowsum<C, double>(Cs);
       const int gi = t.m0 + threadIdx.x % BM;
-      if (threadIdx.x < BM && gi < M) hzrow[(long)J * M + gi] = rs;
-      double *hz_ = hz + (long)J * M * D;
+      if (threadIdx.x < BM && gi < M) ((P *)hzrow)[(long)J * M + gi] = (P)rs;
+      P *hz_ = (P *)hz + (long)J * M * D;
       const int base = t.m0;
       lds_mfma<NT / 64, BM / (NT / 4), false, F64>(Cs, LDC_, BN, zj, LDZ, DP,
                                                    [&](int i, int d, double v) {
         const int g = base + i;
-        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
+        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = (P)v;
       });
     }
     if (!off) return;
@@ -1018,13 +1025,13 @@ struct EpiGradUu {
       // rows of block J (slot I) through H^T: column sums and H^T Zs_I
       const double cs = tile_colsum<C, double>(Cs);
       const int gj = t.n0 + threadIdx.x % BN;
-      if (threadIdx.x < BN && gj < M) hzrow[(long)I * M + gj] = cs;
-      double *hz_ = hz + (long)I * M * D;
+      if (threadIdx.x < BN && gj < M) ((P *)hzrow)[(long)I * M + gj] = (P)cs;
+      P *hz_ = (P *)hz + (long)I * M * D;
       const int base = t.n0;
       lds_mfma<NT / 64, BN / (NT / 4), true, F64>(Cs, LDC_, BM, zi, LDZ, DP,
                                                   [&](int i, int d, double v) {
         const int g = base + i;
-        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = v;
+        if (g < M_ && d < D_) hz_[(long)g * D_ + d] = (P)v;
       });
     }
   }

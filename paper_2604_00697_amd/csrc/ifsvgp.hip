@@ -630,6 +630,10 @@ static LikArgs lik_args(ifsvgp_ctx *c, int B, long gs) {
                  c->scal, M, c->flag, c->counters + CNT_LIK, gs};
 }
 
+// element type of the per-tile gradient partials (the epilogues' P)
+template <typename T>
+using GradPartial = typename std::conditional<std::is_same<T, float>::value, double, float>::type;
+
 template <typename T>
 struct Ops {
   // TW: operand type of the two products with C (fp32 in the fp16 form)
@@ -799,7 +803,8 @@ struct Ops {
     const int D = c->D;
     Opnd<TW> a{(const TW *)c->hy1, ldr(c)}, b{(const TW *)c->hy2, ldr(c)};
     Sched sc{nb(c), nb(c), 1, 1, r, 0};
-    EpiGradUu e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, nullptr};
+    EpiGradUu<GradPartial<T>> e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu,
+                                nullptr};
     return launch_gemm<CSW>(lnc(c), a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
   // U = Q V -> Ut, sigma^2 partials
@@ -866,7 +871,8 @@ struct Ops {
     const int D = c->D;
     Opnd<TW> a{(const TW *)c->Y2, c->Mp}, b{LW(c, cur), c->Mp};
     Sched sc{nb(c), nb(c), 1, 1, c->M, K_HI_N1};
-    EpiGradUu e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu, gdiag};
+    EpiGradUu<GradPartial<T>> e{c->Kt, c->sP, c->Zs, c->Mp, c->M, D, c->hz, c->hzrow, c->tp_uu,
+                                gdiag};
     return launch_gemm<CSW>(lnc(c), a, b, sc, e, 2 * CSW::BM * (dpof(D) + 1) * 4);
   }
   // L Q on lower tiles (k < m0+BM) -> partials of diag(L Q L^T) = diag(P)
@@ -1086,7 +1092,7 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
                c->lik_part, cdiv(c->Bp, NTB),
                c->Q32, c->vVa, c->vWub, Mp, c->vt2, c->ell_part, rb, cb,
                c->gdiag, c->pdiag, (long)Mp, c->vLb, c->sP, gsz(c)};
-    hipLaunchKernelGGL(k_grad, gdim(c, dim3(rb + cb + rq)), dim3(NTB), 0, c->st, g);
+    hipLaunchKernelGGL(k_grad<GradPartial<T>>, gdim(c, dim3(rb + cb + rq)), dim3(NTB), 0, c->st, g);
     // dF/dm~ = L t2 and dF/ds~ rows (when requested), then the scalar gradients
     const int mrows = (want_gm || want_gs) ? rq : 0;
     hipLaunchKernelGGL(k_grad_tail, gdim(c, dim3(mrows + D + 1)), dim3(NTB), 0, c->st, g,
@@ -1362,7 +1368,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
              c->lik_part, cdiv(c->Bp, NTB),
              nullptr, c->vVa, c->vWub, Mp, c->vt2, c->ell_part, rb, cb,
              nullptr, nullptr, (long)Mp, c->vLb, c->sP};
-  hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
+  hipLaunchKernelGGL(k_grad<GradPartial<T>>, dim3(rb + cb), dim3(NTB), 0, c->st, g);
   const int mrows = want_gm ? cdiv(M, NTB / 64) : 0;
   hipLaunchKernelGGL(k_grad_tail, dim3(mrows + D + 1), dim3(NTB), 0, c->st, g,
                      (const float *)c->L32[0], mrows);
@@ -1782,7 +1788,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
              c->lik_part, cdiv(c->Bp, NTB),
              nullptr, nullptr, nullptr, Mp, nullptr, c->ell_part, rb, cb,
              nullptr, nullptr, (long)Mp, nullptr, c->sP};
-  hipLaunchKernelGGL(k_grad, dim3(rb + cb), dim3(NTB), 0, c->st, g);
+  hipLaunchKernelGGL(k_grad<GradPartial<T>>, dim3(rb + cb), dim3(NTB), 0, c->st, g);
   hipLaunchKernelGGL(k_grad_tail, dim3(D + 1), dim3(NTB), 0, c->st, g, (const float *)c->L32[0], 0);
   HIPCK(hipGetLastError());
   c->fwd_valid = 0;  // U was overwritten in place: one backward per forward

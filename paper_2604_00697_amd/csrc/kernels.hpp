@@ -1127,9 +1127,10 @@ struct GradArgs {
   int M, B, D;
   const CallArgs *ca;  // N / B, grad_scale and the gradient outputs
   const float *Zs, *Xs, *inv_ell, *sfn;
-  const double *hrow, *hx; int n_uf_nt;          // [n_uf_nt][M], [n_uf_nt][M][D]
-  const double *hzrow, *hz; int nb;              // [nb][M], [nb][M][D]
-  const double *hcol; int n_uf_mt; long ldc;     // [n_uf_mt][ldc]
+  // per-tile partials (element type P of k_grad: fp64 in the fp32 form, else fp32)
+  const void *hrow, *hx; int n_uf_nt;            // [n_uf_nt][M], [n_uf_nt][M][D]
+  const void *hzrow, *hz; int nb;                // [nb][M], [nb][M][D]
+  const void *hcol; int n_uf_mt; long ldc;       // [n_uf_mt][ldc]
   const double *uf_part; int n_uf_tiles;
   const double *uu_part; int n_uu_tiles;
   const double *lik_part; int n_lik;
@@ -1161,6 +1162,7 @@ __host__ __device__ inline int grad_zrows(int D) { return NTB / (GRAD_SLOT_GROUP
 //  * blocks [rb, rb + cb): lengthscale partials of the data side (column sums
 //    of H_uf against Xs^2);
 //  * the remaining blocks: t2 = Q (V alpha - Wu b), one wave per row.
+template <typename P>
 __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
   __shared__ double sh[NTB];
   __shared__ double sx[GRAD_SLOT_GROUPS * NTB];
@@ -1184,10 +1186,12 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
       const int nuf = g.n_uf_nt > grp ? (g.n_uf_nt - grp + G - 1) / G : 0;
       const int nuu = g.nb > grp ? (g.nb - grp + G - 1) / G : 0;
       const long ouf = nuf ? (long)grp : 0, ouu = nuu ? (long)grp : 0;
-      slot_sum2<double, double>(g.hrow + i + ouf * g.M, nuf, (long)G * g.M,
-                                g.hzrow + i + ouu * g.M, nuu, (long)G * g.M, ruf, ruu);
-      slot_sum2<double, double>(g.hx + e + ouf * MD, nuf, G * MD, g.hz + e + ouu * MD, nuu,
-                                G * MD, hx, hz);
+      const P *hrow = (const P *)g.hrow, *hzrow = (const P *)g.hzrow;
+      const P *hxp = (const P *)g.hx, *hzp = (const P *)g.hz;
+      slot_sum2<double, P>(hrow + i + ouf * g.M, nuf, (long)G * g.M,
+                           hzrow + i + ouu * g.M, nuu, (long)G * g.M, ruf, ruu);
+      slot_sum2<double, P>(hxp + e + ouf * MD, nuf, G * MD, hzp + e + ouu * MD, nuu, G * MD,
+                           hx, hz);
     }
     sx[t] = ruf;
     sx[NTB + t] = ruu;
@@ -1221,7 +1225,7 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
     double contrib = 0.0;
     if (r < R && n < g.B) {
       double cn = 0.0;
-      for (int k = 0; k < g.n_uf_mt; ++k) cn += g.hcol[n + (long)k * g.ldc];
+      for (int k = 0; k < g.n_uf_mt; ++k) cn += ((const P *)g.hcol)[n + (long)k * g.ldc];
       const double xs = g.Xs[(long)n * g.D + d];
       contrib = cn * xs * xs;
     }
