@@ -233,7 +233,9 @@ static hipError_t fork_side(ifsvgp_ctx *c) {
 struct OnSide {
   ifsvgp_ctx *c;
   hipStream_t saved;
-  explicit OnSide(ifsvgp_ctx *c_) : c(c_), saved(c_->st) { c->st = c->side; }
+  explicit OnSide(ifsvgp_ctx *c_) : c(c_), saved(c_->st) {
+    if (!c->single_stream) c->st = c->side;
+  }
   ~OnSide() { c->st = saved; }
 };
 
@@ -484,6 +486,11 @@ static int create_ctx(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec
   c->graph_tick = 0;
   c->G = G;
   c->gstride = 0;
+#ifdef IFSVGP_SERIAL_SIDE
+  // profiling builds: the side branches run in order on the context's stream
+  // (kernel durations without the overlap)
+  c->single_stream = true;
+#endif
   bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cst, hipStreamNonBlocking) == hipSuccess;
   for (int k = 0; ok && k < ifsvgp_ctx::kEvents; ++k)
@@ -621,13 +628,13 @@ static long gsz(ifsvgp_ctx *c) { return c->G > 1 ? c->gstride : 0; }
 
 // The exact bound's likelihood arguments (partials of U's epilogue, the Gram
 // products' trace partials, the vector kernel's quad / log|T| partials).
-static LikArgs lik_args(ifsvgp_ctx *c, int B, long gs) {
+static LikArgs lik_args(ifsvgp_ctx *c, int B, long gs, int defer_final = 0) {
   const int M = c->M, nb = cdiv(M, 64);
   return LikArgs{c->mu_part, cdiv(M, 128), c->var_part, cdiv(M, 128), (long)c->Bp,
                  c->dca, B, c->Bp, c->sfn, c->lik, c->gh, c->ngh,
                  c->mu, c->var, c->alpha, c->beta, c->sqnb, c->lik_part,
                  c->tp_gram, nb * (nb + 1) / 2, c->vec_part, cdiv(2 * M, NTB / 64),
-                 c->scal, M, c->flag, c->counters + CNT_LIK, gs};
+                 c->scal, M, c->flag, c->counters + CNT_LIK, gs, defer_final};
 }
 
 // element type of the per-tile gradient partials (the epilogues' P)
@@ -1014,8 +1021,9 @@ static int launch_kuf(ifsvgp_ctx *c, int B) {
 
 // Bound at c->cur.  V = L^T K_uf and a = L^T m~ have been enqueued on the
 // side stream (forked after the last update of L).
+// defer_final: the backward follows in the same call and its k_valpha forms F.
 template <typename T>
-static int stage_bound(ifsvgp_ctx *c, int B) {
+static int stage_bound(ifsvgp_ctx *c, int B, bool defer_final) {
   const int M = c->M, cur = c->cur;
   const float *L = c->L32[cur];
   const long Mp = c->Mp;
@@ -1038,15 +1046,16 @@ static int stage_bound(ifsvgp_ctx *c, int B) {
   { Timed t(c, KK_U); HIPCK(Ops<T>::gemm_U(c, B)); }
   {
     Timed t(c, KK_LIK);
-    const LikArgs a = lik_args(c, B, gsz(c));
+    const LikArgs a = lik_args(c, B, gsz(c), defer_final ? 1 : 0);
     hipLaunchKernelGGL(k_lik, gdim(c, dim3(cdiv(c->Bp, NTB))), dim3(NTB), 0, c->st, a);
   }
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }
 
+// lik_final: the forward of the same call deferred F to k_valpha.
 template <typename T>
-static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
+static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs, bool lik_final) {
   using TW = typename Ops<T>::TW;
   const int M = c->M, D = c->D, cur = c->cur;
   const long Mp = c->Mp;
@@ -1059,9 +1068,11 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs) {
   }
   {
     Timed t(c, KK_VALPHA);
-    hipLaunchKernelGGL(k_valpha<T>, gdim(c, dim3(M)), dim3(NTB), 0, c->st,
+    const int nlik = lik_final ? cdiv(c->Bp, NTB) : 0;
+    hipLaunchKernelGGL(k_valpha<T>, gdim(c, dim3(M + (nlik ? 1 : 0))), dim3(NTB), 0, c->st,
                        (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
-                       (const float *)c->sqnb, (T *)c->Vs, c->vVa, gsz(c));
+                       (const float *)c->sqnb, (T *)c->Vs, c->vVa, gsz(c),
+                       lik_args(c, B, 0), nlik);
   }
   // (V D)(V D)^T by split-K on lower tiles; C assembled per lower tile
   { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B, false)); }
@@ -1141,13 +1152,13 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
                          (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
                          (const CallArgs *)c->dca, c->va, gsz(c));
     }
-    r = stage_bound<T>(c, k.B);
+    r = stage_bound<T>(c, k.B, k.bwd);
     if (r) return r;
     c->fwd_valid = 1;
     c->fwd_B = k.B;
   }
   if (k.bwd) {
-    r = stage_backward<T>(c, k.B, k.want_gm, k.want_gs);
+    r = stage_backward<T>(c, k.B, k.want_gm, k.want_gs, k.setup && k.fwd);
     if (r) return r;
   }
   return IFSVGP_OK;
@@ -1334,7 +1345,7 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
   }
   hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
-                     (const float *)c->sqnb, (T *)c->Vs, c->vVa);
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0);
   hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), std::min(rup(nr, 64), kMaxGridY)),
                      dim3(NTB), 0, c->st, (const T *)c->Vt, Omt, (const float *)c->hwx,
                      (const float *)c->hex, (const float *)c->vVa, (const float *)c->vWub,
@@ -1760,7 +1771,7 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
   }
   hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->alpha,
-                     (const float *)c->sqnb, (T *)c->Vs, c->vVa);
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0);
   HIPCK(Ops<T>::syrk(c, B));
   hipLaunchKernelGGL((k_mo_x<T>), dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->mo_al, Bp, Q,

@@ -587,6 +587,7 @@ struct LikArgs {
   double *scal; int M;
   int *flag, *counter;
   long gs;  // grouped launch: bytes between the problems' workspaces
+  int defer_final;  // 1: F is formed by the next kernel (k_valpha), not here
   IFS_DEV void shift(long o) {
     mu_part = gsh(mu_part, o); var_part = gsh(var_part, o); ca = gsh(ca, o); sfn = gsh(sfn, o);
     gh = gsh(gh, o); mu = gsh(mu, o); var = gsh(var, o); alpha = gsh(alpha, o);
@@ -715,6 +716,7 @@ __global__ void k_lik(LikArgs a) {
     double *p = a.part + 4 * blockIdx.x;
     p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
   }
+  if (a.defer_final) return;
   if (!arrive_last(a.counter, &s_last)) return;
   lik_final<NTB>(a, gridDim.x, sh);
 }
@@ -1061,19 +1063,27 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
 // padded row, the operand of the batch product (V D)(V D)^T.  alpha and sqnb
 // are zero for n >= B (set by the likelihood kernel), so padded entries
 // contribute nothing and Vs is zero there.  Launch with M workgroups.
+// With nlik > 0 one more workgroup (index M) forms F from the likelihood
+// kernel's nlik block partials (lik_final), when that kernel deferred it:
+// the kernel boundary orders the partials, so no arrival fence is needed.
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int Bp,
                                                 const float *alpha, const float *sqnb, T *Vs,
-                                                float *out, long gs = 0) {
+                                                float *out, long gs, LikArgs la, int nlik) {
   __shared__ float shw[NTB / 64];
+  __shared__ double shl[7 * (NTB / 64)];
   if (gs) {
     const long o = goff(gs);
     V = gsh(V, o); alpha = gsh(alpha, o); sqnb = gsh(sqnb, o); Vs = gsh(Vs, o);
     out = gsh(out, o);
+    if (nlik) la.shift(o);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = blockIdx.x;
-  if (row >= M) return;  // uniform across the workgroup
+  if (row >= M) {  // uniform across the workgroup
+    if (nlik && row == M) lik_final<NTB>(la, nlik, shl);
+    return;
+  }
   constexpr int KPL = 16 / (int)sizeof(T);
   const T *v = V + (long)row * ld;
   T *vs = Vs + (long)row * ld;
