@@ -933,7 +933,7 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav, int g
   a.scal = c->scal; a.flag = c->flag; a.ngskip = c->ngskip;
   a.nKx = cdiv(M, 64);
   a.nK = a.nKx * (a.nKx + 1) / 2;
-  a.nLx = cdiv(M, 32);
+  a.nLx = cdiv(M, 64);
   const bool gen = gen_B > 0 && !std::is_same<T, float>::value;
   a.nGz = gen ? cdiv(M, 64) : 0;
   a.nG = gen ? a.nGz + cdiv(gen_B, 64) : 0;

@@ -48,7 +48,7 @@ IFS_DEV bool arrive_last(int *counter, int *s_flag) {
 //    (fp32, plus the operand type), zs = Z / ell; the first tile column also
 //    writes Zs and the zero-padded copy of s~; block 0 validates ell, sf2,
 //    noise_var, s~ and forms 1/ell and sum log s~;
-//  * blocks [nK, nK + nL): 32 x 32 tiles of the caller's L: fp32 master (lower
+//  * blocks [nK, nK + nL): 64 x 64 tiles of the caller's L: fp32 master (lower
 //    triangle, strict upper 0), operand copy, both transposes, and the
 //    transpose scaled by s~ along k (operand of L^T S~ L).
 struct SetupArgs {
@@ -115,7 +115,6 @@ IFS_DEV float gen_row(const float *src, const float *ellc, int D, int ldk, float
 template <int MAXD, typename T>
 __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   __shared__ float zi[64][MAXD + 1], zj[64][MAXD + 1];
-  __shared__ float tile[32][33];
   __shared__ double sh[NTB / 64];
   if (a.gs) a.shift(goff(a.gs));
   const int b = blockIdx.x;
@@ -281,28 +280,28 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
     }
     return;
   }
-  // caller's L -> L32, LT, LtT, Lt32, LstT on the 32 x 32 tiles with I >= J
-  // only: the strictly upper tiles of L (and the strictly lower ones of the
-  // transposes) are zero from the workspace's allocation and no kernel ever
-  // writes them
+  // caller's L -> L32, LT, LtT, Lt32, LstT on the 64 x 64 tiles with I >= J
+  // only (zi serves as the transpose buffer): the strictly upper tiles of L
+  // (and the strictly lower ones of the transposes) are zero from the
+  // workspace's allocation and no kernel ever writes them
   const int bl = b - a.nK;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
   int I = (int)((sqrtf(8.0f * bl + 1.0f) - 1.0f) * 0.5f);
   while ((I + 1) * (I + 2) / 2 <= bl) ++I;
   while (I * (I + 1) / 2 > bl) --I;
-  const int i0 = I * 32, j0 = (bl - I * (I + 1) / 2) * 32;
-  float lv[4];
+  const int i0 = I * 64, j0 = (bl - I * (I + 1) / 2) * 64;
+  float lv[16];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = i0 + ty + 8 * u, j = j0 + tx;
+  for (int u = 0; u < 16; ++u) {
+    const int i = i0 + ty + 4 * u, j = j0 + tx;
     lv[u] = ld_or0((const float *)ca->L, (long)i * M + j, i < M && j < M && i >= j);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = ty + 8 * u;
+  for (int u = 0; u < 16; ++u) {
+    const int r = ty + 4 * u;
     const int i = i0 + r, j = j0 + tx;
     const float v = lv[u];
-    tile[r][tx] = v;
+    zi[r][tx] = v;
     if (i < M && j < M) {
       a.L32[(long)i * a.ld + j] = v;
       if constexpr (!std::is_same<T, float>::value) ((T *)a.LT)[(long)i * a.ld + j] = from_f32<T>(v);
@@ -310,10 +309,10 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   }
   __syncthreads();
   const float si = ld_or0(sc, i0 + tx, i0 + tx < M);
-  for (int r = ty; r < 32; r += 8) {
+  for (int r = ty; r < 64; r += 4) {
     const int j = j0 + r, i = i0 + tx;  // transposes: [j][i] = L[i][j]
     if (i < M && j < M) {
-      const float v = tile[tx][r];
+      const float v = zi[tx][r];
       ((T *)a.LtT)[(long)j * a.ld + i] = from_f32<T>(v);
       ((T *)a.LstT)[(long)j * a.ld + i] = from_f32<T>(v * si);
       if constexpr (!std::is_same<T, float>::value) a.Lt32[(long)j * a.ld + i] = v;
