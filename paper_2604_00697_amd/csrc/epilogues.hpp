@@ -742,7 +742,7 @@ struct EpiGradUf {
   void *hx;      // [n-tiles][M][D]
   double *part;  // [ntiles]
   const void *Zh, *Zl, *Xh, *Xl;  // generator inputs (KW > 0)
-  const float *zc, *xr, *lsf2;
+  const float *zc, *xr;
   static constexpr bool kRegs = true;  // takes the accumulators in registers
   // grouped launches: every workspace pointer moved by o bytes
   IFS_DEV void shift(long o) {
@@ -757,7 +757,7 @@ struct EpiGradUf {
     hx = gsh(hx, o);
     part = gsh(part, o);
     Zh = gsh(Zh, o); Zl = gsh(Zl, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
-    zc = gsh(zc, o); xr = gsh(xr, o); lsf2 = gsh(lsf2, o);
+    zc = gsh(zc, o); xr = gsh(xr, o);
   }
   // acc: fp32 or (C::A64) fp64 accumulators; the lane's rows are
   // 16 ii + 4 (lane/16) + q for fp32 and 16 ii + 4 q + lane/16 for fp64

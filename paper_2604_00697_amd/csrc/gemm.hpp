@@ -186,7 +186,7 @@ struct NoGen {
 // entry (the split's rounding can leave a distance of about -1e-5 sf2 relative
 // instead of 0, harmless, so there is no clamp).  Inputs per call (written by
 // the set-up): Zh, Zl [Mp][KW], zc = -|z'|^2 [Mp], Xh, Xl [Bp][KW],
-// xr = log2 sf2 - |x'|^2 [Bp], lsf2 = log2 sf2; KW (16, 32 or 64) >= D, zero
+// xr = log2 sf2 - |x'|^2 [Bp]; KW (16, 32 or 64) >= D, zero
 // beyond D; zc and xr are -1e30 on the rows past M and B that a tile covers,
 // so those entries are exactly 0 without a mask.  KW = 16 contracts with the 16x16x16 bf16 instruction, else
 // 16x16x32 per 32 d.  Each of the 4 waves generates a 32 (m) x 32 (n)
@@ -220,11 +220,11 @@ struct KufGen {
   const Op *Zh, *Zl;
   const float *zc;
   const Op *Xh, *Xl;
-  const float *xr, *lsf2;
+  const float *xr;
   int M, B;
   IFS_DEV void shift(long o) {
     Zh = gsh(Zh, o); Zl = gsh(Zl, o); zc = gsh(zc, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
-    xr = gsh(xr, o); lsf2 = gsh(lsf2, o);
+    xr = gsh(xr, o);
   }
   template <class C>
   struct State {

@@ -99,10 +99,9 @@ struct ifsvgp_ctx {
   void *Kft, *V, *Vt, *Ut, *Vs;
   float *Zs, *Xs, *inv_ell, *sP;  // sP: s~ zero-padded to Mp
   // inputs of the generated K_uf tiles (bf16 / fp16 forms): hi / lo bf16
-  // rows of 2 z' and x' ([Mp][gldk], [Bp][gldk]), -|z'|^2, log2 sf2 - |x'|^2,
-  // log2 sf2
+  // rows of 2 z' and x' ([Mp][gldk], [Bp][gldk]), -|z'|^2, log2 sf2 - |x'|^2
   __bf16 *gZh, *gZl, *gXh, *gXl;
-  float *gzc, *gxr, *glsf2;
+  float *gzc, *gxr;
   int gldk;
   float *va, *vb, *vLb, *vWub, *vVa, *vt2;
   float *mu_part, *var_part, *mu, *var, *alpha, *beta, *sqnb;
@@ -315,7 +314,6 @@ static size_t layout(ifsvgp_ctx *c, char *base, bool extras) {
   c->gXl = (__bf16 *)w.bytes(Bp * c->gldk * 2);
   w.take(c->gzc, Mp);
   w.take(c->gxr, Bp);
-  w.take(c->glsf2, (size_t)1);
   w.take(c->Zs, (size_t)M * D);
   w.take(c->Xs, (size_t)B_max * D);
   w.take(c->inv_ell, (size_t)D);
@@ -737,7 +735,7 @@ struct Ops {
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
     G g{(const Op *)c->gZh, (const Op *)c->gZl, c->gzc, (const Op *)c->gXh,
-        (const Op *)c->gXl, c->gxr, c->glsf2, c->M, B};
+        (const Op *)c->gXl, c->gxr, c->M, B};
     return launch_gemm<CR>(lnc(c), a, a, sc, e, 0, g);
   }
   static hipError_t gemm_Vf(ifsvgp_ctx *c, int cur, int B) {
@@ -833,7 +831,7 @@ struct Ops {
     Sched sc{cdiv(c->M, CRG::BM), cdiv(B, CRG::BN), 0, 1, c->M, K_HI_M1};
     EpiGradUf<KW> e{lb ? lb : c->vLb, al ? al : c->alpha, be ? be : c->beta, c->Zs, c->Xs,
                     c->sfn, c->M, B, D, c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf,
-                    c->gZh, c->gZl, c->gXh, c->gXl, c->gzc, c->gxr, c->glsf2};
+                    c->gZh, c->gZl, c->gXh, c->gXl, c->gzc, c->gxr};
     constexpr bool gen = KW > 0 && !std::is_same<T, float>::value;
     return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D, gen));
   }
@@ -940,7 +938,7 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav, int g
   a.B = gen_B;
   a.ldk = c->gldk;
   a.Zh = c->gZh; a.Zl = c->gZl; a.Xh = c->gXh; a.Xl = c->gXl;
-  a.zc = c->gzc; a.xr = c->gxr; a.lsf2 = c->glsf2; a.Xs = c->Xs;
+  a.zc = c->gzc; a.xr = c->gxr; a.Xs = c->Xs;
   a.gs = gsz(c);
   hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(a.nK + a.nLx * (a.nLx + 1) / 2 + a.nG)),
                      dim3(NTB), 0, c->st, a);

@@ -71,7 +71,7 @@ struct SetupArgs {
   // blocks 64 rows of the batch (B rows), which also write Xs = X / ell
   int nG, nGz, B, ldk;
   __bf16 *Zh, *Zl, *Xh, *Xl;
-  float *zc, *xr, *lsf2, *Xs;
+  float *zc, *xr, *Xs;
   long gs;             // grouped launch: bytes between the problems' workspaces
   IFS_DEV void shift(long o) {
     ca = gsh(ca, o); Zs = gsh(Zs, o); inv_ell = gsh(inv_ell, o); sP = gsh(sP, o);
@@ -80,7 +80,7 @@ struct SetupArgs {
     LstT = gsh((char *)LstT, o); scal = gsh(scal, o); flag = gsh(flag, o);
     ngskip = gsh(ngskip, o);
     Zh = gsh(Zh, o); Zl = gsh(Zl, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o); zc = gsh(zc, o);
-    xr = gsh(xr, o); lsf2 = gsh(lsf2, o); Xs = gsh(Xs, o);
+    xr = gsh(xr, o); Xs = gsh(Xs, o);
   }
 };
 
@@ -273,7 +273,6 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
                                 a.Xl + o, a.Xs + (long)n0 * D);
         const float l2 = log2f(*ca->sf2);
         if (q == 0) a.xr[n0] = l2 - n;
-        if (n0 == 0 && q == 0) *a.lsf2 = l2;
       } else if (q == 0) {
         a.xr[n0] = -1e30f;
       }
