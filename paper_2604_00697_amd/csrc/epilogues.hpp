@@ -716,11 +716,13 @@ __host__ __device__ inline int dpof(int D) { return (D + 15) / 16 * 16; }
 //   hx[i][d]   = sum_n H_in Xs_nd           (per n-tile partial)
 //   sum H                                   (per tile partial)
 // hx comes from an fp32 MFMA product H Xs, the row and column sums from LDS.
-// Extra LDS: graduf_extra(BM, BN, D, gen) bytes (gen: the K_uf tile from the
-// split inputs, so no staged Zs rows).
-__host__ __device__ inline int graduf_extra(int BM, int BN, int D, bool gen) {
+// Extra LDS: graduf_extra(BM, BN, D) bytes (the Zs rows' region stays in the
+// budget when the tile is generated and Zs is not staged: at one workgroup per
+// CU R's launches are shorter beside the main stream's backward chain than at
+// two, with the same step time).
+__host__ __device__ inline int graduf_extra(int BM, int BN, int D) {
   const int D4 = d4of(D), LDX = dpof(D) + 1;
-  return ((gen ? 0 : BM * (D4 + 1)) + BN * LDX + 2 * BM + 3 * BN) * 4;
+  return (BM * (D4 + 1) + BN * LDX + 2 * BM + 3 * BN) * 4;
 }
 //
 // KW > 0 (bf16 / fp16 forms): the K_uf tile comes from the set-up's split
@@ -765,15 +767,15 @@ struct EpiGradUf {
   IFS_DEV void run_regs(const Acc (&acc)[C::TM][C::TN], float *Cs, const TileInfo &t) const {
     constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
     const int D4 = d4of(D), DP = dpof(D), LDZ = D4 + 1, LDX = DP + 1;
+    float *zs = Cs + BM * C::LDC + 4 * NT;  // [BM][LDZ]
+    float *xs = zs + BM * LDZ;              // [BN][LDX]
+    float *zn = xs + BN * LDX;              // [BM]
+    float *lb = zn + BM;                    // [BM]
+    float *xn = lb + BM;                    // [BN]
+    float *al = xn + BN;                    // [BN]
+    float *be = al + BN;                    // [BN]
     constexpr bool F32 = std::is_same<typename C::T, float>::value;
     constexpr bool GEN = !F32 && KW > 0;
-    float *zs = Cs + BM * C::LDC + 4 * NT;      // [BM][LDZ] (not with GEN)
-    float *xs = GEN ? zs : zs + BM * LDZ;       // [BN][LDX]
-    float *zn = xs + BN * LDX;                  // [BM]
-    float *lb = zn + BM;                        // [BM]
-    float *xn = lb + BM;                        // [BN]
-    float *al = xn + BN;                        // [BN]
-    float *be = al + BN;                        // [BN]
     const int tid = threadIdx.x;
     for (int i = tid; i < BM; i += NT) lb[i] = Lb[t.m0 + i];    // padded to Mp
     for (int i = tid; i < BN; i += NT) {

@@ -832,8 +832,7 @@ struct Ops {
     EpiGradUf<KW> e{lb ? lb : c->vLb, al ? al : c->alpha, be ? be : c->beta, c->Zs, c->Xs,
                     c->sfn, c->M, B, D, c->hrow, c->hcol, (long)c->Bp, c->hx, c->tp_uf,
                     c->gZh, c->gZl, c->gXh, c->gXl, c->gzc, c->gxr};
-    constexpr bool gen = KW > 0 && !std::is_same<T, float>::value;
-    return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D, gen));
+    return launch_gemm<CRG>(lnc(c), a, b, sc, e, graduf_extra(CRG::BM, CRG::BN, D));
   }
   static hipError_t gemm_R(ifsvgp_ctx *c, int cur, int B, const float *lb = nullptr,
                            const float *al = nullptr, const float *be = nullptr) {
