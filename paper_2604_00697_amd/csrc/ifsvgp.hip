@@ -939,8 +939,8 @@ static int stage_setup(ifsvgp_ctx *c, int need_noise, const CallArgs *cav, int g
   a.Zh = c->gZh; a.Zl = c->gZl; a.Xh = c->gXh; a.Xl = c->gXl;
   a.zc = c->gzc; a.xr = c->gxr; a.Xs = c->Xs;
   a.gs = gsz(c);
-  hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(a.nK + a.nLx * (a.nLx + 1) / 2 + a.nG)),
-                     dim3(NTB), 0, c->st, a);
+  const int nblk = 1 + a.nK + a.nLx * (a.nLx + 1) / 2 + a.nG;
+  hipLaunchKernelGGL((k_setup<MAXD, T>), gdim(c, dim3(nblk)), dim3(NTB), 0, c->st, a);
   HIPCK(hipGetLastError());
   return IFSVGP_OK;
 }

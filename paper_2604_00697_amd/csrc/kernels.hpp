@@ -66,9 +66,10 @@ struct SetupArgs {
   int *flag;
   int *ngskip;         // stop flag of an adaptive NG loop, cleared for the call
   int nKx, nK, nLx;
-  // inputs of the generated K_uf tiles (KufGen), when nG > 0: blocks
-  // [nK + nL, nK + nL + nGz) take 64 rows of Z each, the remaining nG - nGz
-  // blocks 64 rows of the batch (B rows), which also write Xs = X / ell
+  // inputs of the generated K_uf tiles (KufGen), when nG > 0: the blocks
+  // after workgroup 0, the nK K~ tiles and the nL tiles of L take first
+  // 64 rows of Z each (nGz blocks), then 64 rows of the batch (B rows), which
+  // also write Xs = X / ell
   int nG, nGz, B, ldk;
   __bf16 *Zh, *Zl, *Xh, *Xl;
   float *zc, *xr, *Xs;
@@ -112,20 +113,60 @@ IFS_DEV float gen_row(const float *src, const float *ellc, int D, int ldk, float
   return nrm;
 }
 
+// The call's inputs that the set-up reads, taken by value: a pointer into
+// the kernel's argument block would make the compiler keep a private copy of
+// the whole block in scratch memory.
+struct SetupIn {
+  const float *X, *ell, *sf2, *noise, *Z, *s, *L;
+};
+IFS_DEV SetupIn setup_in(const CallArgs &c) {
+  return {c.X, c.ell, c.sf2, c.noise, c.Z, c.s, c.L};
+}
+
 template <int MAXD, typename T>
 __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
   __shared__ float zi[64][MAXD + 1], zj[64][MAXD + 1];
   __shared__ double sh[NTB / 64];
   if (a.gs) a.shift(goff(a.gs));
-  const int b = blockIdx.x;
-  const int M = a.M, D = a.D;
-  const CallArgs *ca = a.latch ? &a.cav : a.ca;
-  if (b == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (a.latch) *a.ca = a.cav;
     // a stop of an earlier call must not skip this call's first products
     *a.ngskip = 0;
   }
-  const float *Zc = ca->Z, *ellc = ca->ell, *sc = ca->s;
+  const int M = a.M, D = a.D;
+  const SetupIn ca = a.latch ? setup_in(a.cav) : setup_in(*a.ca);
+  const float *Zc = ca.Z, *ellc = ca.ell, *sc = ca.s;
+  // workgroup 0: the call's scalars, 1/ell, the domain checks and sum log s~
+  // (dispatched first, beside the tiles)
+  if (blockIdx.x == 0) {
+    int bad = 0;
+    for (int d = threadIdx.x; d < D; d += NTB) {
+      const float l = ellc[d];
+      if (!(l > 0.f) || !isfinite(l)) bad = 1;
+      a.inv_ell[d] = 1.0f / l;
+    }
+    if (threadIdx.x == 0) {
+      const float v = *ca.sf2;
+      if (!(v > 0.f) || !isfinite(v)) bad = 1;
+      a.sfn[0] = v;
+      if (a.need_noise) {
+        const float n = *ca.noise;
+        if (!(n > 0.f) || !isfinite(n)) bad = 1;
+        a.sfn[1] = n;
+      }
+    }
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < M; q += NTB) {
+      const float v = sc[q];
+      if (!(v > 0.f) || !isfinite(v)) bad = 1;
+      acc += log((double)v);
+    }
+    acc = block_sum<NTB>(acc, sh);
+    if (threadIdx.x == 0) a.scal[S_SUMLOGS] = acc;
+    if (bad) atomicOr(a.flag, FLAG_DOMAIN);
+    return;
+  }
+  const int b = (int)blockIdx.x - 1;
   if (b < a.nK) {
     // lower 64 x 64 tile (bi >= bj), its mirror written through LDS; thread
     // (tx, ty) owns rows ty + 16 p and columns tx + 16 q
@@ -177,7 +218,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
           d2[p][q] = fmaf(df, df, d2[p][q]);
         }
     }
-    const float sf2 = *ca->sf2;
+    const float sf2 = *ca.sf2;
     float kv[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -220,33 +261,6 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
         }
       }
     }
-    if (b == 0) {
-      int bad = 0;
-      for (int d = threadIdx.x; d < D; d += NTB) {
-        const float l = ellc[d];
-        if (!(l > 0.f) || !isfinite(l)) bad = 1;
-        a.inv_ell[d] = 1.0f / l;
-      }
-      if (threadIdx.x == 0) {
-        const float v = *ca->sf2;
-        if (!(v > 0.f) || !isfinite(v)) bad = 1;
-        a.sfn[0] = v;
-        if (a.need_noise) {
-          const float n = *ca->noise;
-          if (!(n > 0.f) || !isfinite(n)) bad = 1;
-          a.sfn[1] = n;
-        }
-      }
-      double acc = 0.0;
-      for (int q = threadIdx.x; q < M; q += NTB) {
-        const float v = sc[q];
-        if (!(v > 0.f) || !isfinite(v)) bad = 1;
-        acc += log((double)v);
-      }
-      acc = block_sum<NTB>(acc, sh);
-      if (threadIdx.x == 0) a.scal[S_SUMLOGS] = acc;
-      if (bad) atomicOr(a.flag, FLAG_DOMAIN);
-    }
     return;
   }
   const int nL = a.nLx * (a.nLx + 1) / 2;
@@ -269,9 +283,9 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
       const int n0 = (g - a.nGz) * 64 + r;
       if (n0 < a.B) {
         const long o = (long)n0 * a.ldk;
-        const float n = gen_row(ca->X + (long)n0 * D, ellc, D, a.ldk, 1.f, q, a.Xh + o,
+        const float n = gen_row(ca.X + (long)n0 * D, ellc, D, a.ldk, 1.f, q, a.Xh + o,
                                 a.Xl + o, a.Xs + (long)n0 * D);
-        const float l2 = log2f(*ca->sf2);
+        const float l2 = log2f(*ca.sf2);
         if (q == 0) a.xr[n0] = l2 - n;
       } else if (q == 0) {
         a.xr[n0] = -1e30f;
@@ -293,7 +307,7 @@ __global__ __launch_bounds__(NTB) void k_setup(SetupArgs a) {
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int i = i0 + ty + 4 * u, j = j0 + tx;
-    lv[u] = ld_or0((const float *)ca->L, (long)i * M + j, i < M && j < M && i >= j);
+    lv[u] = ld_or0(ca.L, (long)i * M + j, i < M && j < M && i >= j);
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -417,11 +431,12 @@ __global__ __launch_bounds__(NTB) void k_kuf(const float *Zs, const CallArgs *ca
   }
 }
 
-// sum_{k < np} p[k * stride]: each round issues W loads (clamped to an
-// in-bounds slot, masked afterwards) before the first add uses them.
-template <int W = 16, typename F>
-IFS_DEV F slot_sum(const F *p, int np, long stride) {
-  F a[W];
+// sum_{k < np} p[k * stride], accumulated in A: each round issues W loads
+// (clamped to an in-bounds slot, masked afterwards) before the first add uses
+// them.
+template <int W = 16, typename F, typename A = F>
+IFS_DEV A slot_sum(const F *p, int np, long stride) {
+  A a[W];
 #pragma unroll
   for (int u = 0; u < W; ++u) a[u] = 0;
   for (int k = 0; k < np; k += W) {
@@ -429,7 +444,7 @@ IFS_DEV F slot_sum(const F *p, int np, long stride) {
 #pragma unroll
     for (int u = 0; u < W; ++u) v[u] = p[(long)min(k + u, np - 1) * stride];
 #pragma unroll
-    for (int u = 0; u < W; ++u) a[u] += k + u < np ? v[u] : F(0);
+    for (int u = 0; u < W; ++u) a[u] += k + u < np ? (A)v[u] : A(0);
   }
 #pragma unroll
   for (int w = W / 2; w > 0; w /= 2)
@@ -478,18 +493,44 @@ IFS_DEV void slot_sum2(const P *pu, int nu, long su, const P *pz, int nz, long s
 // Row dot product of one wave: sum_{j < cend} a[j] (x[j] - xs[j]) (xs optional),
 // 4 floats per lane per load.
 IFS_DEV float row_dot(const float *a, const float *x, const float *xs, int cend) {
+  // U 16-byte chunks per lane in flight together (one round trip for rows of
+  // up to 2048); a chunk past the last whole one re-reads chunk 0 and is
+  // skipped, which needs cend >= 4 (true whenever the loop runs)
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63;
-  float s = 0.f;
-  int j = lane * 4;
-  for (; j + 3 < cend; j += 256) {
-    const f32x4 v = *(const f32x4 *)(a + j);
-    f32x4 u = *(const f32x4 *)(x + j);
-    if (xs) u -= *(const f32x4 *)(xs + j);
-    s = fmaf(v[0], u[0], s); s = fmaf(v[1], u[1], s);
-    s = fmaf(v[2], u[2], s); s = fmaf(v[3], u[3], s);
+  const int c4 = cend & ~3;  // whole chunks end here
+  float t = 0.f;             // the last cend - c4 elements, one per lane
+  if (c4 + lane < cend) t = a[c4 + lane] * (x[c4 + lane] - (xs ? xs[c4 + lane] : 0.f));
+  float s[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) s[q] = 0.f;
+  for (int j0 = 4 * lane; j0 < c4 + 4 * lane; j0 += 256 * U) {
+    f32x4 v[U], u[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + 256 * q, jc = j < c4 ? j : 0;
+      v[q] = *(const f32x4 *)(a + jc);
+      u[q] = *(const f32x4 *)(x + jc);
+    }
+    if (xs) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int j = j0 + 256 * q, jc = j < c4 ? j : 0;
+        u[q] -= *(const f32x4 *)(xs + jc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+      if (j0 + 256 * q < c4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[q] = fmaf(v[q][e], u[q][e], s[q]);
+      }
   }
-  for (; j < cend; ++j) s = fmaf(a[j], x[j] - (xs ? xs[j] : 0.f), s);  // tail
-  return wave_sum(s);
+#pragma unroll
+  for (int w = U / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int q = 0; q < w; ++q) s[q] += s[q + w];
+  return wave_sum(s[0] + t);
 }
 
 // y[i] = scale * sum_j A[i][j] (x[j] - xs[j]) over j < Cn (lower: j <= i;
@@ -1232,8 +1273,7 @@ __global__ __launch_bounds__(NTB) void k_grad(GradArgs g) {
     const int n = (blk - g.rb) * R + r;
     double contrib = 0.0;
     if (r < R && n < g.B) {
-      double cn = 0.0;
-      for (int k = 0; k < g.n_uf_mt; ++k) cn += ((const P *)g.hcol)[n + (long)k * g.ldc];
+      const double cn = slot_sum<8, P, double>((const P *)g.hcol + n, g.n_uf_mt, g.ldc);
       const double xs = g.Xs[(long)n * g.D + d];
       contrib = cn * xs * xs;
     }
