@@ -97,6 +97,49 @@ IFS_DEV double wave_sum(double v) {
   return v;
 }
 
+// Row dot product of one wave: sum_{j < cend} a[j] (x[j] - xs[j]) (xs optional),
+// 4 floats per lane per load.
+IFS_DEV float row_dot(const float *a, const float *x, const float *xs, int cend) {
+  // U 16-byte chunks per lane in flight together (one round trip for rows of
+  // up to 2048); a chunk past the last whole one re-reads chunk 0 and is
+  // skipped, which needs cend >= 4 (true whenever the loop runs)
+  constexpr int U = 8;
+  const int lane = threadIdx.x & 63;
+  const int c4 = cend & ~3;  // whole chunks end here
+  float t = 0.f;             // the last cend - c4 elements, one per lane
+  if (c4 + lane < cend) t = a[c4 + lane] * (x[c4 + lane] - (xs ? xs[c4 + lane] : 0.f));
+  float s[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) s[q] = 0.f;
+  for (int j0 = 4 * lane; j0 < c4 + 4 * lane; j0 += 256 * U) {
+    f32x4 v[U], u[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + 256 * q, jc = j < c4 ? j : 0;
+      v[q] = *(const f32x4 *)(a + jc);
+      u[q] = *(const f32x4 *)(x + jc);
+    }
+    if (xs) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int j = j0 + 256 * q, jc = j < c4 ? j : 0;
+        u[q] -= *(const f32x4 *)(xs + jc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+      if (j0 + 256 * q < c4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[q] = fmaf(v[q][e], u[q][e], s[q]);
+      }
+  }
+#pragma unroll
+  for (int w = U / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int q = 0; q < w; ++q) s[q] += s[q + w];
+  return wave_sum(s[0] + t);
+}
+
 // Block-wide sums of N doubles per thread with one LDS exchange (the same
 // summation order as N separate block_sum calls); results valid in thread 0.
 template <int NT, int N>

@@ -64,7 +64,7 @@ struct Opnd {
 // ------------------------------------------------------------------ schedule
 enum : int { K_LO_M0 = 1, K_LO_N0 = 2, K_HI_M1 = 4, K_HI_N1 = 8 };
 
-// Maps blockIdx.x to an output tile and its k-range.
+// Maps a workgroup index b (blockIdx.x) to an output tile and its k-range.
 //   sym = 0: rectangular grid of mt x nt tiles;
 //   sym = 1: lower-triangular tiles (I >= J) of an mt x mt grid.
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -80,10 +80,10 @@ struct Sched {
   int mt, nt, sym, nsplit, K, rule;
   const int *skip;
   long gs;  // grouped launch: bytes between the problems' workspaces (0: one problem)
+  // b: the workgroup's index among the tiles
   template <class C>
-  IFS_DEV void tile(int &m0, int &n0, int &kb, int &ke, int &ti) const {
+  IFS_DEV void tile(int b, int &m0, int &n0, int &kb, int &ke, int &ti) const {
     const int ntile = sym ? mt * (mt + 1) / 2 : mt * nt;
-    const int b = blockIdx.x;
     // XCD-contiguous renumbering: blocks b, b+8, b+16, ... share XCD b % 8
     const int per = (ntile + 7) / 8, rem = ntile % 8;
     const int x = b % 8, q = b / 8;
@@ -164,6 +164,7 @@ struct IC {
 // NoGen: both operands are loaded from global memory.
 struct NoGen {
   static constexpr bool kOn = false;
+  int side_blocks() const { return 0; }
   IFS_DEV void shift(long) {}
   template <class C>
   struct State {
@@ -194,6 +195,10 @@ struct NoGen {
 // stored as one 8-byte LDS write into the swizzled stage layout the fragment
 // reads expect.  The z inputs of k-tile j+1 are loaded while tile j is
 // generated.
+// Side role (nside > 0): nside workgroups after the tiles form a = L^T m~
+// (one wave per row, from the fp32 transpose Lt of the same L); they start as
+// the short tiles of the triangular product finish, so the matrix-vector
+// product runs beside the product's tail instead of after it.
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 template <int KW>
 struct KufOp {  // one lane's share of a row: 8 bf16, or 4 for KW = 16
@@ -222,9 +227,23 @@ struct KufGen {
   const Op *Xh, *Xl;
   const float *xr;
   int M, B;
+  // side role: a = L^T m~ over rows [0, M) (m~ from the call's arguments)
+  const float *Lt;
+  long ldl;
+  const CallArgs *ca;
+  float *a;
+  int nside;
+  int side_blocks() const { return nside; }
   IFS_DEV void shift(long o) {
     Zh = gsh(Zh, o); Zl = gsh(Zl, o); zc = gsh(zc, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
     xr = gsh(xr, o);
+    Lt = gsh(Lt, o); ca = gsh(ca, o); a = gsh(a, o);
+  }
+  IFS_DEV void side(int blk) const {
+    const int row = blk * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (row >= M) return;
+    const float s = row_dot(Lt + (long)row * ldl, ca->m, nullptr, M);
+    if ((threadIdx.x & 63) == 0) a[row] = s;
   }
   template <class C>
   struct State {
@@ -329,8 +348,15 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
     epi.shift(o);
     gen.shift(o);
   }
+  if constexpr (GEN::kOn) {
+    const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
+    if ((int)blockIdx.x >= ntile) {  // uniform across the workgroup
+      gen.side((int)blockIdx.x - ntile);
+      return;
+    }
+  }
   int m0, n0, kb, ke, ti;
-  sc.tile<C>(m0, n0, kb, ke, ti);
+  sc.tile<C>(blockIdx.x, m0, n0, kb, ke, ti);
   int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (sc.skip && *sc.skip) nk = 0;
 
@@ -476,7 +502,8 @@ static inline hipError_t launch_gemm(const Launch &lc, const Opnd<typename C::T>
                                      const EPI &epi, int extra = 0, const GEN &gen = GEN{}) {
   const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
   if (ntile <= 0) return hipSuccess;
-  dim3 grid(ntile, sc.nsplit > 1 ? sc.nsplit : 1, lc.groups > 1 ? lc.groups : 1);
+  dim3 grid(ntile + gen.side_blocks(), sc.nsplit > 1 ? sc.nsplit : 1,
+            lc.groups > 1 ? lc.groups : 1);
   auto kern = gemm_kernel<C, EPI, GEN>;
   Sched sg = sc;
   sg.gs = lc.groups > 1 ? lc.gs : 0;

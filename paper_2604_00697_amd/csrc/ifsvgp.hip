@@ -726,26 +726,29 @@ struct Ops {
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // the same product with the K_uf tiles generated in LDS (bf16 / fp16 forms;
-  // inputs from the set-up), K_uf never stored
+  // inputs from the set-up), K_uf never stored; with va non-null workgroups
+  // after the tiles also form va = L^T m~ from the same L
   template <int KW>
-  static hipError_t gemm_Vf_kw(ifsvgp_ctx *c, int cur, int B) {
+  static hipError_t gemm_Vf_kw(ifsvgp_ctx *c, int cur, int B, float *va) {
     using G = KufGen<T, KW>;
     using Op = typename G::Op;
     Opnd<T> a{LtT(c, cur), c->Mp};
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
     G g{(const Op *)c->gZh, (const Op *)c->gZl, c->gzc, (const Op *)c->gXh,
-        (const Op *)c->gXl, c->gxr, c->M, B};
+        (const Op *)c->gXl, c->gxr, c->M, B,
+        (const float *)c->Lt32[cur], (long)c->Mp, (const CallArgs *)c->dca, va,
+        va ? cdiv(c->M, CR::NT / 64) : 0};
     return launch_gemm<CR>(lnc(c), a, a, sc, e, 0, g);
   }
-  static hipError_t gemm_Vf(ifsvgp_ctx *c, int cur, int B) {
+  static hipError_t gemm_Vf(ifsvgp_ctx *c, int cur, int B, float *va) {
     if constexpr (std::is_same<T, float>::value) {
       return hipErrorInvalidValue;  // the fp32 form stores K_uf (k_kuf)
     } else {
       switch (c->gldk) {
-        case 16: return gemm_Vf_kw<16>(c, cur, B);
-        case 32: return gemm_Vf_kw<32>(c, cur, B);
-        default: return gemm_Vf_kw<64>(c, cur, B);
+        case 16: return gemm_Vf_kw<16>(c, cur, B, va);
+        case 32: return gemm_Vf_kw<32>(c, cur, B, va);
+        default: return gemm_Vf_kw<64>(c, cur, B, va);
       }
     }
   }
@@ -1136,19 +1139,22 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
     r = stage_natgrad<T>(c, k.gammas, k.n_ng, NG_FIXED, k.B);
     if (r) return r;
     // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
-    // K_uf tiles first), so all of them run beside the Gram products
+    // K_uf tiles first), so all of them run beside the Gram products; with
+    // the generated K_uf tiles, a comes from extra workgroups of V's launch
     HIPCK(fork_side(c));
     {
       OnSide side(c);
       {
         Timed t(c, KK_V);
-        if constexpr (fused_kuf) HIPCK(Ops<T>::gemm_Vf(c, c->cur, k.B));
+        if constexpr (fused_kuf) HIPCK(Ops<T>::gemm_Vf(c, c->cur, k.B, c->va));
         else HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
       }
-      Timed t(c, KK_VEC);
-      hipLaunchKernelGGL(k_lt_m, gdim(c, dim3(cdiv(c->M, NTB / 64))), dim3(NTB), 0, c->st,
-                         (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
-                         (const CallArgs *)c->dca, c->va, gsz(c));
+      if constexpr (!fused_kuf) {
+        Timed t(c, KK_VEC);
+        hipLaunchKernelGGL(k_lt_m, gdim(c, dim3(cdiv(c->M, NTB / 64))), dim3(NTB), 0, c->st,
+                           (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
+                           (const CallArgs *)c->dca, c->va, gsz(c));
+      }
     }
     r = stage_bound<T>(c, k.B, k.bwd);
     if (r) return r;
