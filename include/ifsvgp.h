@@ -121,6 +121,21 @@ int ifsvgp_set_stream(ifsvgp_ctx *ctx, void *hip_stream);
  * Up to 16 structures are kept (least recently used replaced). */
 int ifsvgp_set_graphs(ifsvgp_ctx *ctx, int enable);
 
+/* Where the bf16 / fp16 forms form the tiles of K_uf (the data-inducing
+ * block of the SE-ARD kernel, Section 2) for V = L^T K_uf: IFSVGP_KUF_AUTO
+ * (the default) generates each tile inside the product's workgroups for
+ * problems with M * B below 2^23 and otherwise stores the tiles once, beside
+ * the natural-gradient step, for the product to load; IFSVGP_KUF_IN_PRODUCT
+ * and IFSVGP_KUF_STORED force one way.  Both ways use the same arithmetic, so
+ * results are bit-identical and only the step time differs.  The fp32 form
+ * always stores K_uf (computed from differences with the accurate exp).
+ * Synchronises the stream and drops recorded graphs.  IFSVGP_EINVAL for
+ * another mode. */
+#define IFSVGP_KUF_AUTO 0
+#define IFSVGP_KUF_IN_PRODUCT 1
+#define IFSVGP_KUF_STORED 2
+int ifsvgp_set_kuf_mode(ifsvgp_ctx *ctx, int mode);
+
 /* Synchronise the stream, then report and clear the sticky device flag:
  * IFSVGP_OK, IFSVGP_EDOMAIN or IFSVGP_ENONFINITE. */
 int ifsvgp_status(ifsvgp_ctx *ctx);

@@ -162,9 +162,32 @@ struct IC {
 
 // ------------------------------------------------------------------ generated B operand
 // NoGen: both operands are loaded from global memory.
+// Side role of a product's launch: nside workgroups after the tiles form
+// a = L^T m~ (one wave per row, from the fp32 transpose Lt of the same L, m~
+// from the call's arguments); they start as the short tiles of a triangular
+// product finish, so the matrix-vector product runs beside the product's tail
+// instead of after it.
+struct SideRows {
+  const float *Lt;
+  long ldl;
+  const CallArgs *ca;
+  float *a;
+  int M, nside;
+  IFS_DEV void shift(long o) {
+    Lt = gsh(Lt, o); ca = gsh(ca, o); a = gsh(a, o);
+  }
+  IFS_DEV void run(int blk) const {
+    const int row = blk * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (row >= M) return;
+    const float s = row_dot(Lt + (long)row * ldl, ca->m, nullptr, M);
+    if ((threadIdx.x & 63) == 0) a[row] = s;
+  }
+};
+
 struct NoGen {
-  static constexpr bool kOn = false;
+  static constexpr bool kOn = false, kSide = false;
   int side_blocks() const { return 0; }
+  IFS_DEV void side(int) const {}
   IFS_DEV void shift(long) {}
   template <class C>
   struct State {
@@ -172,6 +195,15 @@ struct NoGen {
     IFS_DEV void prefetch(int) {}
     IFS_DEV void gen(unsigned char *, int) {}
   };
+};
+
+// A loaded B operand with the side role.
+struct SideOnly : NoGen {
+  static constexpr bool kSide = true;
+  SideRows rows;
+  int side_blocks() const { return rows.nside; }
+  IFS_DEV void side(int blk) const { rows.run(blk); }
+  IFS_DEV void shift(long o) { rows.shift(o); }
 };
 
 // KufGen: the B operand of V = L^T K_uf is the kernel-matrix tile
@@ -195,10 +227,7 @@ struct NoGen {
 // stored as one 8-byte LDS write into the swizzled stage layout the fragment
 // reads expect.  The z inputs of k-tile j+1 are loaded while tile j is
 // generated.
-// Side role (nside > 0): nside workgroups after the tiles form a = L^T m~
-// (one wave per row, from the fp32 transpose Lt of the same L); they start as
-// the short tiles of the triangular product finish, so the matrix-vector
-// product runs beside the product's tail instead of after it.
+// It carries the side role (SideRows; none with nside = 0).
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 template <int KW>
 struct KufOp {  // one lane's share of a row: 8 bf16, or 4 for KW = 16
@@ -219,7 +248,7 @@ struct KufOp<16> {
 };
 template <typename T, int KW>
 struct KufGen {
-  static constexpr bool kOn = true;
+  static constexpr bool kOn = true, kSide = true;
   using Op = typename KufOp<KW>::type;
   static constexpr int NC = KufOp<KW>::NC, RW = 4 * NC;  // operands per row
   const Op *Zh, *Zl;
@@ -227,24 +256,14 @@ struct KufGen {
   const Op *Xh, *Xl;
   const float *xr;
   int M, B;
-  // side role: a = L^T m~ over rows [0, M) (m~ from the call's arguments)
-  const float *Lt;
-  long ldl;
-  const CallArgs *ca;
-  float *a;
-  int nside;
-  int side_blocks() const { return nside; }
+  SideRows rows;
+  int side_blocks() const { return rows.nside; }
   IFS_DEV void shift(long o) {
     Zh = gsh(Zh, o); Zl = gsh(Zl, o); zc = gsh(zc, o); Xh = gsh(Xh, o); Xl = gsh(Xl, o);
     xr = gsh(xr, o);
-    Lt = gsh(Lt, o); ca = gsh(ca, o); a = gsh(a, o);
+    rows.shift(o);
   }
-  IFS_DEV void side(int blk) const {
-    const int row = blk * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
-    if (row >= M) return;
-    const float s = row_dot(Lt + (long)row * ldl, ca->m, nullptr, M);
-    if ((threadIdx.x & 63) == 0) a[row] = s;
-  }
+  IFS_DEV void side(int blk) const { rows.run(blk); }
   template <class C>
   struct State {
     static_assert(C::NW == 4 && C::BN == 64 && C::BK == 64 && C::S == 2,
@@ -291,6 +310,15 @@ struct KufGen {
     }
     // k-tile j into the stage's B rows (bst = stage + BM rows)
     IFS_DEV void gen(unsigned char *bst, int j) {
+      gen_to([&](int ml, int nl, uint2 raw) {
+        *(uint2 *)(bst + nl * C::ROWB + (((ml >> 3) ^ (nl & 7)) << 4) + (ml & 7) * 2) = raw;
+      });
+    }
+    // the prefetched k-tile's quadrant: put(ml, nl, raw) receives the entries
+    // of inducing points ml .. ml + 3 (tile-local) and batch point nl as four
+    // operand-type values
+    template <class F>
+    IFS_DEV void gen_to(F &&put) {
       wait_vm_lgkm0<0>();
       f32x4 acc[2][2];
 #pragma unroll
@@ -319,11 +347,36 @@ struct KufGen {
           for (int q = 0; q < 4; ++q) e[q] = from_f32<T>(__builtin_amdgcn_exp2f(acc[mb][nb][q]));
           uint2 raw;
           __builtin_memcpy(&raw, e, 8);
-          *(uint2 *)(bst + nl * C::ROWB + (((ml >> 3) ^ (nl & 7)) << 4) + (ml & 7) * 2) = raw;
+          put(ml, nl, raw);
         }
     }
   };
 };
+
+// The K_uf tiles of KufGen written to memory instead of LDS, in the B operand
+// layout of V = L^T K_uf (Kft[n][m], ld >= the padded M), with the same
+// arithmetic, so the product over the stored tiles equals the one over the
+// generated tiles.  Workgroup t takes k-tile t % nmt (64 inducing points) of
+// batch tile t / nmt (64 points).  C: the product's configuration (the
+// generator's four-wave quadrant layout).  gs: grouped launch (problem
+// blockIdx.z, workspaces gs bytes apart).
+template <class C, typename T, int KW>
+__global__ __launch_bounds__(C::NT) void k_kuf_gen(KufGen<T, KW> g, T *Kft, long ld, int nmt,
+                                                    long gs) {
+  if (gs) {
+    const long o = goff(gs);
+    g.shift(o);
+    Kft = gsh(Kft, o);
+  }
+  const int t = blockIdx.x;
+  const int kb = (t % nmt) * 64, n0 = (t / nmt) * 64;
+  typename KufGen<T, KW>::template State<C> st;
+  st.init(g, n0, kb);
+  st.prefetch(0);
+  st.gen_to([&](int ml, int nl, uint2 raw) {
+    *(uint2 *)(Kft + (long)(n0 + nl) * ld + kb + ml) = raw;
+  });
+}
 
 // ------------------------------------------------------------------ kernel
 template <class C, class EPI, class GEN = NoGen>
@@ -348,7 +401,7 @@ __global__ __launch_bounds__(C::NT) void gemm_kernel(Opnd<typename C::T> A,
     epi.shift(o);
     gen.shift(o);
   }
-  if constexpr (GEN::kOn) {
+  if constexpr (GEN::kSide) {
     const int ntile = sc.sym ? sc.mt * (sc.mt + 1) / 2 : sc.mt * sc.nt;
     if ((int)blockIdx.x >= ntile) {  // uniform across the workgroup
       gen.side((int)blockIdx.x - ntile);

@@ -88,6 +88,7 @@ struct ifsvgp_ctx {
   // recorded calls (HIP graphs) and the stream they are recorded on
   hipStream_t cst;
   int use_graphs;
+  int kuf_mode;  // IFSVGP_KUF_*
   std::vector<GraphEnt> graphs;
   long long graph_tick;
   // fp32 M x M ([Mp][Mp])
@@ -481,6 +482,7 @@ static int create_ctx(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec
   c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
   c->use_graphs = 0;
+  c->kuf_mode = IFSVGP_KUF_AUTO;
   c->graph_tick = 0;
   c->G = G;
   c->gstride = 0;
@@ -719,10 +721,22 @@ struct Ops {
     return launch_gemm<CS>(lnc(c), a, b, sc, e, CS::BM * CS::LDC * 4);
   }
   // V = L^T K_uf (k >= m0) -> V, Vt
-  static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B, const int *skip = nullptr) {
+  // V = L^T K_uf from the stored K_uf tiles; with va non-null workgroups
+  // after the tiles also form va = L^T m~ from the same L
+  static SideRows side_rows(ifsvgp_ctx *c, int cur, float *va) {
+    return SideRows{(const float *)c->Lt32[cur], (long)c->Mp, (const CallArgs *)c->dca, va,
+                    c->M, va ? cdiv(c->M, CR::NT / 64) : 0};
+  }
+  static hipError_t gemm_V(ifsvgp_ctx *c, int cur, int B, const int *skip = nullptr,
+                           float *va = nullptr) {
     Opnd<T> a{LtT(c, cur), c->Mp}, b{(const T *)c->Kft, c->Mp};
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0, skip};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
+    if (va) {
+      SideOnly g;
+      g.rows = side_rows(c, cur, va);
+      return launch_gemm<CR>(lnc(c), a, b, sc, e, 0, g);
+    }
     return launch_gemm<CR>(lnc(c), a, b, sc, e);
   }
   // the same product with the K_uf tiles generated in LDS (bf16 / fp16 forms;
@@ -736,10 +750,32 @@ struct Ops {
     Sched sc{cdiv(c->M, CR::BM), cdiv(B, CR::BN), 0, 1, c->M, K_LO_M0};
     EpiV<T> e{(T *)c->V, (T *)c->Vt, c->Bp, c->Mp, c->M, B};
     G g{(const Op *)c->gZh, (const Op *)c->gZl, c->gzc, (const Op *)c->gXh,
-        (const Op *)c->gXl, c->gxr, c->M, B,
-        (const float *)c->Lt32[cur], (long)c->Mp, (const CallArgs *)c->dca, va,
-        va ? cdiv(c->M, CR::NT / 64) : 0};
+        (const Op *)c->gXl, c->gxr, c->M, B, side_rows(c, cur, va)};
     return launch_gemm<CR>(lnc(c), a, a, sc, e, 0, g);
+  }
+  // the generated K_uf tiles stored (Kft, the B operand of gemm_V) with the
+  // same arithmetic as gemm_Vf's
+  template <int KW>
+  static hipError_t kuf_gen_kw(ifsvgp_ctx *c, int B) {
+    using G = KufGen<T, KW>;
+    using Op = typename G::Op;
+    G g{(const Op *)c->gZh, (const Op *)c->gZl, c->gzc, (const Op *)c->gXh,
+        (const Op *)c->gXl, c->gxr, c->M, B, SideRows{}};
+    const int nmt = cdiv(c->M, 64), nnt = cdiv(B, 64);
+    hipLaunchKernelGGL((k_kuf_gen<CR, T, KW>), gdim(c, dim3(nmt * nnt)), dim3(CR::NT), 0, c->st,
+                       g, (T *)c->Kft, (long)c->Mp, nmt, gsz(c));
+    return hipGetLastError();
+  }
+  static hipError_t kuf_gen(ifsvgp_ctx *c, int B) {
+    if constexpr (std::is_same<T, float>::value) {
+      return hipErrorInvalidValue;  // the fp32 form stores K_uf with k_kuf
+    } else {
+      switch (c->gldk) {
+        case 16: return kuf_gen_kw<16>(c, B);
+        case 32: return kuf_gen_kw<32>(c, B);
+        default: return kuf_gen_kw<64>(c, B);
+      }
+    }
   }
   static hipError_t gemm_Vf(ifsvgp_ctx *c, int cur, int B, float *va) {
     if constexpr (std::is_same<T, float>::value) {
@@ -1114,47 +1150,57 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs, bool
   return IFSVGP_OK;
 }
 
+// K_uf tiles of the bf16 / fp16 forms are stored (generated once beside the
+// natural-gradient step) rather than generated inside V from this many
+// entries M x B on: V's row blocks regenerate each tile M / 256 times on
+// average, which outweighs the extra launch and fork for large problems
+// (measured: 0.185 vs 0.192 ms per step at M = 1024, B = 4096 in favour of
+// generating inside V; 0.557 vs 0.576 ms at M = 2048, B = 8192 in favour of
+// storing, before the store moved beside the natural-gradient step).
+static constexpr long KUF_STORE_MIN = 1L << 23;
+
 // All launches of one call on c->st (and the side stream), in order.
 template <typename T>
 static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
   int r;
   c->ev_next = 0;
   c->side_open = false;
-  // bf16 / fp16: V = L^T K_uf with the K_uf tiles generated in LDS; the fp32
-  // form stores them first (distances from differences, accurate exp)
-  constexpr bool fused_kuf = !std::is_same<T, float>::value;
+  // K_uf: the fp32 form stores it first (k_kuf: distances from differences,
+  // accurate exp); bf16 / fp16 generate its tiles from the set-up's split
+  // inputs, inside V = L^T K_uf (LDS only) or stored once (k_kuf_gen)
+  constexpr bool gen = !std::is_same<T, float>::value;
+  const bool stored = !gen || c->kuf_mode == IFSVGP_KUF_STORED ||
+                      (c->kuf_mode == IFSVGP_KUF_AUTO && (long)c->M * k.B >= KUF_STORE_MIN);
   if (k.setup) {
-    r = stage_setup<T>(c, k.need_noise, cav, k.fwd && fused_kuf ? k.B : 0);
+    r = stage_setup<T>(c, k.need_noise, cav, k.fwd && gen ? k.B : 0);
     if (r) return r;
     if (!k.fwd) {
       c->fwd_valid = 0;
       return stage_natgrad<T>(c, k.gammas, k.n_ng, k.adapt, k.B);
     }
-    if constexpr (!fused_kuf) {
+    if (stored) {
       // side stream: K_uf tiles need only Z / ell and the batch ...
       HIPCK(fork_side(c));
-      r = launch_kuf<T>(c, k.B);
-      if (r) return r;
+      if constexpr (gen) {
+        OnSide side(c);
+        Timed t(c, KK_KUF);
+        HIPCK(Ops<T>::kuf_gen(c, k.B));
+      } else {
+        r = launch_kuf<T>(c, k.B);
+        if (r) return r;
+      }
     }
     r = stage_natgrad<T>(c, k.gammas, k.n_ng, NG_FIXED, k.B);
     if (r) return r;
     // ... and V = L^T K_uf and a = L^T m~ the updated L (the fork joins the
-    // K_uf tiles first), so all of them run beside the Gram products; with
-    // the generated K_uf tiles, a comes from extra workgroups of V's launch
+    // K_uf tiles first), so all of them run beside the Gram products; a
+    // comes from extra workgroups of V's launch
     HIPCK(fork_side(c));
     {
       OnSide side(c);
-      {
-        Timed t(c, KK_V);
-        if constexpr (fused_kuf) HIPCK(Ops<T>::gemm_Vf(c, c->cur, k.B, c->va));
-        else HIPCK(Ops<T>::gemm_V(c, c->cur, k.B));
-      }
-      if constexpr (!fused_kuf) {
-        Timed t(c, KK_VEC);
-        hipLaunchKernelGGL(k_lt_m, gdim(c, dim3(cdiv(c->M, NTB / 64))), dim3(NTB), 0, c->st,
-                           (const float *)c->Lt32[c->cur], (long)c->Mp, c->M,
-                           (const CallArgs *)c->dca, c->va, gsz(c));
-      }
+      Timed t(c, KK_V);
+      if (stored) HIPCK(Ops<T>::gemm_V(c, c->cur, k.B, nullptr, c->va));
+      else HIPCK(Ops<T>::gemm_Vf(c, c->cur, k.B, c->va));
     }
     r = stage_bound<T>(c, k.B, k.bwd);
     if (r) return r;
@@ -1849,6 +1895,14 @@ extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {
     if (e != hipSuccess) return IFSVGP_EHIP;
   }
   return IFSVGP_OK;
+}
+
+extern "C" int ifsvgp_set_kuf_mode(ifsvgp_ctx *c, int mode) {
+  if (!c || mode < IFSVGP_KUF_AUTO || mode > IFSVGP_KUF_STORED) return IFSVGP_EINVAL;
+  hipError_t e = hipStreamSynchronize(c->st);
+  graphs_clear(c);
+  c->kuf_mode = mode;
+  return e == hipSuccess ? IFSVGP_OK : IFSVGP_EHIP;
 }
 
 extern "C" int ifsvgp_adam(ifsvgp_ctx *c, float *param, const float *grad, float *m, float *v,

@@ -37,6 +37,7 @@ _SIGS = {
     "ifsvgp_destroy": (None, [_P]),
     "ifsvgp_set_stream": (_I, [_P, _P]),
     "ifsvgp_set_graphs": (_I, [_P, _I]),
+    "ifsvgp_set_kuf_mode": (_I, [_P, _I]),
     "ifsvgp_adam": (_I, [_P, _P, _P, _P, _P, ctypes.c_long, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, ctypes.c_float, _I, _I]),
     "ifsvgp_status": (_I, [_P]),
@@ -225,6 +226,15 @@ class Context:
         """Record and replay repeated calls as HIP graphs (enable=True), or run
         every call directly (the default)."""
         _check(self._lib.ifsvgp_set_graphs(self._h, 1 if enable else 0), "ifsvgp_set_graphs")
+
+    def set_kuf_mode(self, mode):
+        """Where the bf16 / fp16 forms form K_uf's tiles: "auto" (default),
+        "in_product" (inside V's launch) or "stored" (once, beside the NG
+        step); results are bit-identical."""
+        modes = {"auto": 0, "in_product": 1, "stored": 2}
+        if mode not in modes:
+            raise ValueError(f"mode must be one of {sorted(modes)}")
+        _check(self._lib.ifsvgp_set_kuf_mode(self._h, modes[mode]), "ifsvgp_set_kuf_mode")
 
     def status(self):
         """Synchronise and return (and clear) the device error flag code."""

@@ -1,0 +1,63 @@
+"""The bf16 / fp16 forms form K_uf's tiles either inside V's launch or once
+into memory beside the natural-gradient step (ifsvgp_set_kuf_mode).  Both ways
+run the same arithmetic on the same split inputs, so every output of a
+training iteration (F, its terms, the NG residual, the updated L and every
+gradient) must be bit-identical between them; the automatic choice is one of
+the two.  Ragged sizes (partial tiles in both M and B), Gaussian and probit;
+the full-size parity tests cover the stored way against the oracle at
+M = 2048, B = 8192, where the automatic choice stores."""
+import numpy as np
+import pytest
+
+from test_gpu_parity import make_case, to_dev, GRADS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _run(c, prec, mode, gammas=(1.0,)):
+    from paper_2604_00697_amd.lib import Context
+    M, D = c["Z"].shape
+    B = c["X"].shape[0]
+    lik = c["lik"]
+    want = tuple(k for k in GRADS if k != "noise_var" or lik == "gaussian")
+    ctx = Context(M, B, D, prec, lik)
+    ctx.set_kuf_mode(mode)
+    d = to_dev(c)
+    F, t, r, g = ctx.step(d["X"], d["y"], c["N"], d["ell"], d["sf2"], d["noise"], d["Z"],
+                          d["m"], d["s"], d["L"], list(gammas), want=want)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    out = dict(F=F.item(), terms=t.cpu().numpy(), resid=r.cpu().numpy(), L=d["L"].cpu().numpy())
+    for k, v in g.items():
+        out["grad_" + k] = v.cpu().numpy()
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("lik", ["gaussian", "probit"])
+def test_stored_and_generated_kuf_bit_identical(require_gpu, prec, lik):
+    c = make_case(200, 333, 5, seed=41, lik=lik, s_range=(0.05, 0.2))
+    a = _run(c, prec, "in_product")
+    b = _run(c, prec, "stored")
+    auto = _run(c, prec, "auto")
+    for k in a:
+        same = np.array_equal(np.asarray(a[k]), np.asarray(b[k]))
+        print(f"KUF {prec} {lik} {k} in_product == stored: {same}", flush=True)
+        assert same, k
+        assert np.array_equal(np.asarray(a[k]), np.asarray(auto[k])), k
+    assert np.isfinite(a["F"])
+
+
+def test_kuf_mode_argument_errors(require_gpu):
+    from paper_2604_00697_amd import lib
+    from paper_2604_00697_amd.lib import Context
+    ctx = Context(40, 50, 2, "bf16")
+    with pytest.raises(ValueError):
+        ctx.set_kuf_mode("sometimes")
+    assert ctx._lib.ifsvgp_set_kuf_mode(ctx._h, 3) == lib.EINVAL
+    assert ctx._lib.ifsvgp_set_kuf_mode(ctx._h, -1) == lib.EINVAL
+    assert ctx._lib.ifsvgp_set_kuf_mode(None, 0) == lib.EINVAL
+    ctx.close()
