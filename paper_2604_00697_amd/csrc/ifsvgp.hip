@@ -1154,9 +1154,9 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs, bool
 // natural-gradient step) rather than generated inside V from this many
 // entries M x B on: V's row blocks regenerate each tile M / 256 times on
 // average, which outweighs the extra launch and fork for large problems
-// (measured: 0.185 vs 0.192 ms per step at M = 1024, B = 4096 in favour of
-// generating inside V; 0.557 vs 0.576 ms at M = 2048, B = 8192 in favour of
-// storing, before the store moved beside the natural-gradient step).
+// (measured per training step: 0.188 ms generating inside V against 0.190 to
+// 0.192 ms storing at M = 1024, B = 4096; 0.585 against 0.559 ms at
+// M = 2048, B = 8192).
 static constexpr long KUF_STORE_MIN = 1L << 23;
 
 // All launches of one call on c->st (and the side stream), in order.
