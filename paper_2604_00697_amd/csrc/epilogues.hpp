@@ -190,6 +190,72 @@ IFS_DEV void lds_mfma(const float *H, int ldh, int K, const float *Z, int ldz, i
   }
 }
 
+// The same product on the bf16 matrix cores (the reduced-precision forms):
+// both fp32 operands are split into bf16 hi + lo parts as their fragments are
+// read, and each 16 x 16 x 32 block takes hi hi + hi lo + lo hi (products to
+// about 16 significant bits, fp32 sums: far below the bf16 / fp16 rounding of
+// the GEMM operands that produced H), three instructions where the fp32
+// instruction needs eight.  K a multiple of 32, DP a multiple of 16 up to 64;
+// each of the workgroup's waves owns TI row tiles of 16; Out to
+// sink(i, d, value).
+IFS_DEV void split_bf16(const float (&x)[8], bf16x8 &hi, bf16x8 &lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = (__bf16)x[j];
+    hi[j] = h;
+    lo[j] = (__bf16)(x[j] - (float)h);
+  }
+}
+template <int TI, class F>
+IFS_DEV void lds_mfma_split(const float *H, int ldh, int K, const float *Z, int ldz, int DP,
+                            F &&sink) {
+  constexpr int MAXDT = 4;  // d tiles of 16 (DP <= 64)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int ib = wave * TI * 16;
+  f32x4 acc[TI][MAXDT];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int t = 0; t < MAXDT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    // A fragments: row ib + 16 i + l16, k = k0 + 8 l4 + j; each is read and
+    // split once for all d tiles
+    float ha[TI][8];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ha[i][j] = H[(ib + 16 * i + l16) * ldh + k0 + 8 * l4 + j];
+    bf16x8 ah[TI], al[TI];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) split_bf16(ha[i], ah[i], al[i]);
+#pragma unroll
+    for (int t = 0; t < MAXDT; ++t) {
+      if (16 * t >= DP) break;
+      // B fragment: column 16 t + l16, k = k0 + 8 l4 + j
+      float zb[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) zb[j] = Z[(k0 + 8 * l4 + j) * ldz + 16 * t + l16];
+      bf16x8 bh, bl;
+      split_bf16(zb, bh, bl);
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        acc[i][t] = mfma16(ah[i], bh, acc[i][t]);
+        acc[i][t] = mfma16(ah[i], bl, acc[i][t]);
+        acc[i][t] = mfma16(al[i], bh, acc[i][t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < MAXDT; ++t) {
+    if (16 * t >= DP) break;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sink(ib + 16 * i + 4 * l4 + q, 16 * t + l16, (double)acc[i][t][q]);
+  }
+}
+
 // Row sums of the staged tile over its BN columns (NT / BM threads per row,
 // partials combined in the scratch LDS), accumulated in A.  Valid for threads
 // with threadIdx.x < BM, where the row is threadIdx.x.
@@ -910,7 +976,7 @@ struct EpiGradUf {
     const int nti = t.n0 / BN, mti = t.m0 / BM;
     // the fp32 form sums on the fp64 matrix cores (the gradient's sums of
     // these partials cancel) and keeps fp64 partials; the others sum in fp32
-    // and keep fp32 partials
+    // (H Xs from split-bf16 products) and keep fp32 partials
     constexpr bool F64 = std::is_same<typename C::T, float>::value;
     using P = typename std::conditional<F64, double, float>::type;
     {
@@ -925,11 +991,14 @@ struct EpiGradUf {
     }
     const int D_ = D, M_ = M;
     P *hx_ = (P *)hx + (long)nti * M * D;
-    lds_mfma<NT / 64, BM / (NT / 4), false, F64>(Cs, C::LDC, BN, xs, LDX, DP,
-                                                [&](int i, int d, double v) {
+    auto sink = [&](int i, int d, double v) {
       const int gi = t.m0 + i;
       if (gi < M_ && d < D_) hx_[(long)gi * D_ + d] = (P)v;
-    });
+    };
+    if constexpr (F64)
+      lds_mfma<NT / 64, BM / (NT / 4), false, true>(Cs, C::LDC, BN, xs, LDX, DP, sink);
+    else
+      lds_mfma_split<BM / (NT / 4)>(Cs, C::LDC, BN, xs, LDX, DP, sink);
   }
 };
 
