@@ -1106,10 +1106,13 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs, bool
   {
     Timed t(c, KK_VALPHA);
     const int nlik = lik_final ? cdiv(c->Bp, NTB) : 0;
-    hipLaunchKernelGGL(k_valpha<T>, gdim(c, dim3(M + (nlik ? 1 : 0))), dim3(NTB), 0, c->st,
-                       (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
+    // (measured: one row per workgroup 0.184 against four 0.188 ms per step
+    // at M = 1024; four 0.551 against one 0.554 ms at M = 2048)
+    const int rpw = va_rows(M);
+    hipLaunchKernelGGL(k_valpha<T>, gdim(c, dim3(cdiv(M, rpw) + (nlik ? 1 : 0))), dim3(NTB), 0,
+                       c->st, (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
                        (const float *)c->sqnb, (T *)c->Vs, c->vVa, gsz(c),
-                       lik_args(c, B, 0), nlik);
+                       lik_args(c, B, 0), nlik, rpw);
   }
   // (V D)(V D)^T by split-K on lower tiles; C assembled per lower tile
   { Timed t(c, KK_SYRK); HIPCK(Ops<T>::syrk(c, B, false)); }
@@ -1393,9 +1396,9 @@ static int enqueue_hutch_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, const flo
     Timed t(c, KK_R);
     HIPCK(Ops<T>::gemm_R(c, 0, B));
   }
-  hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, va_rows(M))), dim3(NTB), 0, c->st,
                      (const T *)c->V, (long)c->Bp, M, c->Bp, (const float *)c->alpha,
-                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0);
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0, va_rows(M));
   hipLaunchKernelGGL((k_hutch_X<T>), dim3(cdiv(c->Mp, NTB), std::min(rup(nr, 64), kMaxGridY)),
                      dim3(NTB), 0, c->st, (const T *)c->Vt, Omt, (const float *)c->hwx,
                      (const float *)c->hex, (const float *)c->vVa, (const float *)c->vWub,
@@ -1819,9 +1822,9 @@ static int enqueue_multi_bwd(ifsvgp_ctx *c, const CallArgs &ca, int B, int Q, fl
     OnSide side(c);
     HIPCK(Ops<T>::gemm_R(c, 0, B, c->mo_zero, c->mo_half, c->mo_half));
   }
-  hipLaunchKernelGGL(k_valpha<T>, dim3(M), dim3(NTB), 0, c->st,
+  hipLaunchKernelGGL(k_valpha<T>, dim3(cdiv(M, va_rows(M))), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->alpha,
-                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0);
+                     (const float *)c->sqnb, (T *)c->Vs, c->vVa, 0L, LikArgs{}, 0, va_rows(M));
   HIPCK(Ops<T>::syrk(c, B));
   hipLaunchKernelGGL((k_mo_x<T>), dim3(M), dim3(NTB), 0, c->st,
                      (const T *)c->V, Bp, M, c->Bp, (const float *)c->mo_al, Bp, Q,

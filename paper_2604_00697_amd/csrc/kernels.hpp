@@ -1054,19 +1054,25 @@ __global__ __launch_bounds__(NTB) void k_assemble_C(const float *Ys, int nsplit,
   }
 }
 
-// One workgroup per row of the operand-type V (its four waves split the row):
+// rpw (1..VA_ROWS) rows of the operand-type V per workgroup (its four waves
+// split the rows, each alpha / sqnb chunk loaded once for all of them):
 // (V alpha)_i and the scaled copy Vs[i][n] = V[i][n] sqnb[n] over the whole
 // padded row, the operand of the batch product (V D)(V D)^T.  alpha and sqnb
 // are zero for n >= B (set by the likelihood kernel), so padded entries
-// contribute nothing and Vs is zero there.  Launch with M workgroups.
-// With nlik > 0 one more workgroup (index M) forms F from the likelihood
-// kernel's nlik block partials (lik_final), when that kernel deferred it:
-// the kernel boundary orders the partials, so no arrival fence is needed.
+// contribute nothing and Vs is zero there.  Launch with cdiv(M, rpw)
+// workgroups.  With nlik > 0 one more workgroup (the last) forms F from the
+// likelihood kernel's nlik block partials (lik_final), when that kernel
+// deferred it: the kernel boundary orders the partials, so no arrival fence
+// is needed.  Several rows per workgroup save re-reads of alpha and sqnb when
+// there are rows enough to fill the chip regardless (va_rows).
+constexpr int VA_ROWS = 4;
+__host__ __device__ inline int va_rows(int M) { return M >= 2048 ? VA_ROWS : 1; }
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int Bp,
                                                 const float *alpha, const float *sqnb, T *Vs,
-                                                float *out, long gs, LikArgs la, int nlik) {
-  __shared__ float shw[NTB / 64];
+                                                float *out, long gs, LikArgs la, int nlik,
+                                                int rpw) {
+  __shared__ float shw[VA_ROWS][NTB / 64];
   __shared__ double shl[7 * (NTB / 64)];
   if (gs) {
     const long o = goff(gs);
@@ -1075,18 +1081,17 @@ __global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int 
     if (nlik) la.shift(o);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = blockIdx.x;
-  if (row >= M) {  // uniform across the workgroup
-    if (nlik && row == M) lik_final<NTB>(la, nlik, shl);
+  const int nrb = (M + rpw - 1) / rpw, rb = blockIdx.x;
+  if (rb >= nrb) {  // uniform across the workgroup
+    if (nlik && rb == nrb) lik_final<NTB>(la, nlik, shl);
     return;
   }
+  const int r0 = rb * rpw, nr = min(rpw, M - r0);
   constexpr int KPL = 16 / (int)sizeof(T);
-  const T *v = V + (long)row * ld;
-  T *vs = Vs + (long)row * ld;
-  float s = 0.f;
+  float s[VA_ROWS];
+#pragma unroll
+  for (int r = 0; r < VA_ROWS; ++r) s[r] = 0.f;
   for (int n = (int)threadIdx.x * KPL; n < Bp; n += NTB * KPL) {  // Bp is a multiple of KPL
-    const uint4 raw = *(const uint4 *)(v + n);
-    const T *e = (const T *)&raw;
     float al[KPL], sq[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; q += 4) {
@@ -1097,24 +1102,36 @@ __global__ __launch_bounds__(NTB) void k_valpha(const T *V, long ld, int M, int 
         sq[q + u] = s4[u];
       }
     }
-    uint4 sraw;
-    T *se = (T *)&sraw;
+    uint4 raw[VA_ROWS];
 #pragma unroll
-    for (int q = 0; q < KPL; ++q) {
-      const float x = to_f32(e[q]);
-      s = fmaf(x, al[q], s);
-      se[q] = from_f32<T>(x * sq[q]);
+    for (int r = 0; r < VA_ROWS; ++r)
+      if (r < nr) raw[r] = *(const uint4 *)(V + (long)(r0 + r) * ld + n);
+#pragma unroll
+    for (int r = 0; r < VA_ROWS; ++r) {
+      if (r >= nr) break;
+      const T *e = (const T *)&raw[r];
+      uint4 sraw;
+      T *se = (T *)&sraw;
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) {
+        const float x = to_f32(e[q]);
+        s[r] = fmaf(x, al[q], s[r]);
+        se[q] = from_f32<T>(x * sq[q]);
+      }
+      *(uint4 *)(Vs + (long)(r0 + r) * ld + n) = sraw;
     }
-    *(uint4 *)(vs + n) = sraw;
   }
-  s = wave_sum(s);
-  if (lane == 0) shw[wave] = s;
+#pragma unroll
+  for (int r = 0; r < VA_ROWS; ++r) {
+    const float w = wave_sum(s[r]);
+    if (lane == 0) shw[r][wave] = w;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if ((int)threadIdx.x < nr) {
     float t = 0.f;
 #pragma unroll
-    for (int w = 0; w < NTB / 64; ++w) t += shw[w];
-    out[row] = t;
+    for (int w = 0; w < NTB / 64; ++w) t += shw[threadIdx.x][w];
+    out[r0 + threadIdx.x] = t;
   }
 }
 
