@@ -92,11 +92,13 @@ def schedule(n, g0=1e-5, g1=1.0, ramp=10):
     return out
 
 
-def time_form(prec, w, batches, par, L0, steps, warmup, kinds, dev, graphs=False):
+def time_form(prec, w, batches, par, L0, steps, warmup, kinds, dev, graphs=False, kuf_mode=None):
     import torch
     from paper_2604_00697_amd.lib import Context
     ctx = Context(w.M, w.B, w.D, prec, w.lik)
     ctx.set_graphs(graphs)
+    if kuf_mode:
+        ctx.set_kuf_mode(kuf_mode)
     L = L0.clone()
     F = torch.empty(1, dtype=torch.float64, device=dev)
     terms = torch.empty(8, dtype=torch.float64, device=dev)
@@ -438,6 +440,15 @@ def c4_leg(args, dev, dominant, second):
                                   "flops_per_launch": r["flops"][dominant],
                                   "avg_launch_us": round(ms * 1e3, 3)},
                      "status": r["status"]}
+        if prec == "bf16":
+            # the same step with K_uf's tiles stored once beside the NG step
+            # instead of generated inside V's launch (bit-identical results)
+            log(f"bench: C4 bf16, K_uf stored: {warm} warmup + {steps} steps")
+            rs = time_form(prec, w, batches, par, L0, steps, warm, (dominant,), dev,
+                           graphs=args.graphs, kuf_mode="stored")
+            out["bf16_kuf_stored"] = {"value": round(rs["iters_per_s"], 3),
+                                      "ms_per_step": round(rs["ms_per_step"], 4),
+                                      "repeats": rs["repeats"], "status": rs["status"]}
         log(f"bench: C4 {prec} {r['ms_per_step']:.3f} ms/step")
     return out
 

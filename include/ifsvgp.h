@@ -122,18 +122,22 @@ int ifsvgp_set_stream(ifsvgp_ctx *ctx, void *hip_stream);
 int ifsvgp_set_graphs(ifsvgp_ctx *ctx, int enable);
 
 /* Where the bf16 / fp16 forms form the tiles of K_uf (the data-inducing
- * block of the SE-ARD kernel, Section 2) for V = L^T K_uf: IFSVGP_KUF_AUTO
- * (the default) generates each tile inside the product's workgroups for
- * problems with M * B below 2^23 and otherwise stores the tiles once, beside
- * the natural-gradient step, for the product to load; IFSVGP_KUF_IN_PRODUCT
- * and IFSVGP_KUF_STORED force one way.  Both ways use the same arithmetic, so
- * results are bit-identical and only the step time differs.  The fp32 form
- * always stores K_uf (computed from differences with the accurate exp).
+ * block of the SE-ARD kernel, Section 2) for V = L^T K_uf.
+ * IFSVGP_KUF_IN_PRODUCT (the default): each tile is generated in LDS inside
+ * the product's workgroups and K_uf is never stored.  IFSVGP_KUF_STORED: the
+ * same generator writes the tiles once into the workspace, beside the
+ * natural-gradient step, and the product loads them (faster for large
+ * problems, whose triangular product otherwise regenerates every tile
+ * M / 256 times on average, at the cost of an M x B store).
+ * IFSVGP_KUF_AUTO: stored from M * B = 2^23 on.  All modes use the same
+ * arithmetic, so results are bit-identical and only the step time differs;
+ * the backward recomputes its tiles in every mode.  The fp32 form always
+ * stores K_uf (computed from differences with the accurate exp).
  * Synchronises the stream and drops recorded graphs.  IFSVGP_EINVAL for
  * another mode. */
-#define IFSVGP_KUF_AUTO 0
-#define IFSVGP_KUF_IN_PRODUCT 1
-#define IFSVGP_KUF_STORED 2
+#define IFSVGP_KUF_IN_PRODUCT 0
+#define IFSVGP_KUF_STORED 1
+#define IFSVGP_KUF_AUTO 2
 int ifsvgp_set_kuf_mode(ifsvgp_ctx *ctx, int mode);
 
 /* Synchronise the stream, then report and clear the sticky device flag:

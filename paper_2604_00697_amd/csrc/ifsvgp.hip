@@ -482,7 +482,7 @@ static int create_ctx(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec
   c->nsplit = std::max(1, std::min(8, cdiv(B_max, 1024)));
   c->st = nullptr;
   c->use_graphs = 0;
-  c->kuf_mode = IFSVGP_KUF_AUTO;
+  c->kuf_mode = IFSVGP_KUF_IN_PRODUCT;
   c->graph_tick = 0;
   c->G = G;
   c->gstride = 0;
@@ -1153,13 +1153,13 @@ static int stage_backward(ifsvgp_ctx *c, int B, bool want_gm, bool want_gs, bool
   return IFSVGP_OK;
 }
 
-// K_uf tiles of the bf16 / fp16 forms are stored (generated once beside the
-// natural-gradient step) rather than generated inside V from this many
-// entries M x B on: V's row blocks regenerate each tile M / 256 times on
-// average, which outweighs the extra launch and fork for large problems
-// (measured per training step: 0.188 ms generating inside V against 0.190 to
-// 0.192 ms storing at M = 1024, B = 4096; 0.585 against 0.559 ms at
-// M = 2048, B = 8192).
+// IFSVGP_KUF_AUTO stores the K_uf tiles of the bf16 / fp16 forms (generated
+// once beside the natural-gradient step) rather than generating them inside
+// V from this many entries M x B on: V's row blocks regenerate each tile
+// M / 256 times on average, which outweighs the extra launch and fork for
+// large problems (measured per training step: 0.188 ms generating inside V
+// against 0.190 to 0.192 ms storing at M = 1024, B = 4096; 0.585 against
+// 0.559 ms at M = 2048, B = 8192).
 static constexpr long KUF_STORE_MIN = 1L << 23;
 
 // All launches of one call on c->st (and the side stream), in order.
@@ -1170,7 +1170,8 @@ static int enqueue(ifsvgp_ctx *c, const Call &k, const CallArgs *cav) {
   c->side_open = false;
   // K_uf: the fp32 form stores it first (k_kuf: distances from differences,
   // accurate exp); bf16 / fp16 generate its tiles from the set-up's split
-  // inputs, inside V = L^T K_uf (LDS only) or stored once (k_kuf_gen)
+  // inputs, inside V = L^T K_uf (LDS only, the default) or, as the context's
+  // K_uf mode asks, stored once (k_kuf_gen)
   constexpr bool gen = !std::is_same<T, float>::value;
   const bool stored = !gen || c->kuf_mode == IFSVGP_KUF_STORED ||
                       (c->kuf_mode == IFSVGP_KUF_AUTO && (long)c->M * k.B >= KUF_STORE_MIN);
@@ -1901,7 +1902,9 @@ extern "C" int ifsvgp_set_graphs(ifsvgp_ctx *c, int enable) {
 }
 
 extern "C" int ifsvgp_set_kuf_mode(ifsvgp_ctx *c, int mode) {
-  if (!c || mode < IFSVGP_KUF_AUTO || mode > IFSVGP_KUF_STORED) return IFSVGP_EINVAL;
+  if (!c || (mode != IFSVGP_KUF_IN_PRODUCT && mode != IFSVGP_KUF_STORED &&
+             mode != IFSVGP_KUF_AUTO))
+    return IFSVGP_EINVAL;
   hipError_t e = hipStreamSynchronize(c->st);
   graphs_clear(c);
   c->kuf_mode = mode;

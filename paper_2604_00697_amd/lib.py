@@ -228,10 +228,11 @@ class Context:
         _check(self._lib.ifsvgp_set_graphs(self._h, 1 if enable else 0), "ifsvgp_set_graphs")
 
     def set_kuf_mode(self, mode):
-        """Where the bf16 / fp16 forms form K_uf's tiles: "auto" (default),
-        "in_product" (inside V's launch) or "stored" (once, beside the NG
-        step); results are bit-identical."""
-        modes = {"auto": 0, "in_product": 1, "stored": 2}
+        """Where the bf16 / fp16 forms form K_uf's tiles: "in_product" (the
+        default: inside V's launch, never stored), "stored" (once, beside the
+        NG step) or "auto" (stored from M * B = 2^23 on); results are
+        bit-identical."""
+        modes = {"in_product": 0, "stored": 1, "auto": 2}
         if mode not in modes:
             raise ValueError(f"mode must be one of {sorted(modes)}")
         _check(self._lib.ifsvgp_set_kuf_mode(self._h, modes[mode]), "ifsvgp_set_kuf_mode")

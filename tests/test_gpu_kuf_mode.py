@@ -1,11 +1,12 @@
-"""The bf16 / fp16 forms form K_uf's tiles either inside V's launch or once
-into memory beside the natural-gradient step (ifsvgp_set_kuf_mode).  Both ways
-run the same arithmetic on the same split inputs, so every output of a
-training iteration (F, its terms, the NG residual, the updated L and every
-gradient) must be bit-identical between them; the automatic choice is one of
-the two.  Ragged sizes (partial tiles in both M and B), Gaussian and probit;
-the full-size parity tests cover the stored way against the oracle at
-M = 2048, B = 8192, where the automatic choice stores."""
+"""The bf16 / fp16 forms form K_uf's tiles either inside V's launch (the
+default, K_uf never stored) or once into memory beside the natural-gradient
+step (ifsvgp_set_kuf_mode).  Both ways run the same arithmetic on the same
+split inputs, so every output of a training iteration (F, its terms, the NG
+residual, the updated L and every gradient) must be bit-identical between
+them; the automatic choice is one of the two.  Ragged sizes (partial tiles in
+both M and B), Gaussian and probit; the parity tests cover the default way
+against the oracle at every size, so the stored way inherits them through
+this identity."""
 import numpy as np
 import pytest
 
