@@ -90,17 +90,24 @@ struct Sched {
     int t;
     if (rem == 0 || x < rem) t = x * per + q;
     else t = rem * per + (x - rem) * (per - 1) + q;
+    // k-ranges bounded above by the row or column block (a lower-triangular
+    // operand) grow with I (and J <= I): such tiles run longest first, so the
+    // launch does not end on a long tile started last.  ti stays the tile's
+    // position in the canonical order, which indexes per-tile partials.
     int I, J;
     if (sym) {
+      if ((rule & (K_HI_M1 | K_HI_N1)) && !(rule & (K_LO_M0 | K_LO_N0))) t = ntile - 1 - t;
       I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
       while (I * (I + 1) / 2 > t) --I;
       J = t - I * (I + 1) / 2;
+      ti = t;
     } else {
       J = t / mt;
       I = t - J * mt;
+      if (rule & K_HI_M1) I = mt - 1 - I;
+      ti = J * mt + I;
     }
-    ti = t;
     m0 = I * C::BM;
     n0 = J * C::BN;
     int lo = 0, hi = K;
