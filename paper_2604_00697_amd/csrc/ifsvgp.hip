@@ -493,8 +493,13 @@ static int create_ctx(ifsvgp_ctx **out, int G, int M, int B_max, int D, int prec
 #endif
   bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&c->cst, hipStreamNonBlocking) == hipSuccess;
+  // fork / join events only order the two streams on the device (each
+  // kernel's own end-of-dispatch release makes its writes visible there), so
+  // they skip the system-scope fence an event record otherwise performs (a
+  // probe on the box: fork + join of two streams 24.9 -> 19.8 us)
   for (int k = 0; ok && k < ifsvgp_ctx::kEvents; ++k)
-    ok = hipEventCreateWithFlags(&c->evs[k], hipEventDisableTiming) == hipSuccess;
+    ok = hipEventCreateWithFlags(&c->evs[k], hipEventDisableTiming |
+                                                 hipEventDisableSystemFence) == hipSuccess;
   if (!ok) {
     ifsvgp_destroy(c);
     return IFSVGP_EHIP;
