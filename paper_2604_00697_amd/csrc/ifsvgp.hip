@@ -193,8 +193,10 @@ struct Timed {
       c->pool.pop_back();
       return e;
     }
+    // timing only: no system-scope fence when the event is reached, so the
+    // stamps do not add a cache write-back to the launches they time
     hipEvent_t e;
-    hipEventCreate(&e);
+    hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
   }
 };
