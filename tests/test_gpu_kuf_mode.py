@@ -52,6 +52,14 @@ def test_stored_and_generated_kuf_bit_identical_wide_inputs(require_gpu, D):
     _compare(c, "bf16", "gaussian")
 
 
+def test_auto_mode_above_its_threshold(require_gpu):
+    """M B of at least 2^23 entries, where the automatic choice stores the
+    tiles; ragged M and B (partial tiles in both)."""
+    c = make_case(1030, 8200, 8, seed=47, s_range=(0.05, 0.2))
+    assert 1030 * 8200 >= 1 << 23
+    _compare(c, "bf16", "gaussian")
+
+
 def test_stored_and_generated_kuf_bit_identical_grouped(require_gpu):
     """Two problems in one grouped context (the store kernel's grouped launch
     with per-problem workspaces)."""
