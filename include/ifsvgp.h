@@ -96,7 +96,9 @@ const char *ifsvgp_strerror(int code);
  * enum ifsvgp_lik.  n_gh: Gauss-Hermite points for the probit likelihood
  * (1..64; ignored for Gaussian).  Allocates the whole device workspace on the
  * current device (sizes grow as M^2 + M*B_max).  Stream: the null stream
- * until ifsvgp_set_stream.  *out is set only on IFSVGP_OK. */
+ * until ifsvgp_set_stream.  *out is set only on IFSVGP_OK.  Sizes outside
+ * 1 <= M <= 32768, 1 <= B_max <= 2^24, M*B_max <= 2^31, 1 <= D <= 64 return
+ * IFSVGP_EINVAL before the device is touched. */
 int ifsvgp_create(ifsvgp_ctx **out, int M, int B_max, int D, int prec, int lik, int n_gh);
 
 /* Release the workspace.  The caller must make sure queued work has finished

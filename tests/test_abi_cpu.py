@@ -73,7 +73,10 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     h = ctypes.c_void_p()
     for args in [(0, 10, 2, 0, 0, 20), (10, 0, 2, 0, 0, 20), (10, 10, 0, 0, 0, 20),
                  (10, 10, 65, 0, 0, 20), (10, 10, 2, 3, 0, 20), (10, 10, 2, 0, 2, 20),
-                 (10, 10, 2, 0, 1, 0), (10, 10, 2, 0, 1, 65)]:
+                 (10, 10, 2, 0, 1, 0), (10, 10, 2, 0, 1, 65),
+                 # the size limits: M, B_max and M * B_max
+                 (32769, 10, 2, 0, 0, 20), (10, (1 << 24) + 1, 2, 0, 0, 20),
+                 (32768, (1 << 16) + 1, 2, 0, 0, 20)]:
         assert L.ifsvgp_create(ctypes.byref(h), *args) == lib.EINVAL
     assert L.ifsvgp_natgrad(None, None, None, None, None, None, None, 1, None) == lib.EINVAL
     assert L.ifsvgp_status(None) == lib.EINVAL
